@@ -1,0 +1,251 @@
+"""Pins of the oracle's multigrid pieces (Sec. 3) against dense linear
+algebra, library routines and exact special cases."""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import amg, dirac as od
+
+BC_AP = (1, 1, 1, -1)
+DIMS = (4, 4, 4, 4)
+BLOCK = (2, 2, 2, 2)
+
+
+@pytest.fixture(scope='module')
+def small():
+    U = syn.gauge_field(DIMS, 0.5, 1)
+    kappa, csw = 0.124, 1.0
+    Fb = od.clover_blocks(U, kappa, csw)
+    op = amg.FineOp(U, Fb, kappa, BC_AP, BLOCK)
+    D = od.dense_D(U, Fb, kappa, BC_AP, DIMS)
+    return op, D
+
+
+def _colour_index(dims, block):
+    col = np.broadcast_to(amg.domain_colour(dims, block), syn.shape_of(dims) + (4, 3))
+    return col.reshape(-1)
+
+
+def test_block_roundtrip():
+    v = syn.gaussian_vectors((4, 2, 6, 4), 3, 1)
+    b = amg.to_blocks(v, (4, 2, 6, 4), (2, 2, 3, 2))
+    assert b.shape == (3, 2 * 1 * 2 * 2, 2, 6 * 24)
+    assert np.array_equal(amg.from_blocks(b, (4, 2, 6, 4), (2, 2, 3, 2)), v)
+
+
+def test_mr_step_is_minimal_residual(small):
+    """One MR step minimises ||b - alpha A b|| over alpha in every domain, so
+    the new residual is orthogonal to A b domain by domain; the residual
+    norm never grows, and r = b - D_SAP x is kept exactly."""
+    op, _ = small
+    b = syn.gaussian_vectors(DIMS, 1, 3)[0]
+    x1, r1 = amg.mr_domains(op, b, 1)
+    Ab = op.Dsap(b)
+    ortho = amg.domain_sums(np.conj(Ab) * r1, DIMS, BLOCK)
+    assert np.abs(ortho).max() < 1e-12
+    prev = amg.domain_sums(np.abs(b) ** 2, DIMS, BLOCK).real
+    for k in range(1, 7):
+        x, r = amg.mr_domains(op, b, k)
+        now = amg.domain_sums(np.abs(r) ** 2, DIMS, BLOCK).real
+        assert np.all(now <= prev * (1 + 1e-13))
+        prev = now
+        assert np.abs(r - (b - op.Dsap(x))).max() < 1e-12
+    # A = c 1 (kappa = 0, no clover): MR is exact after one step
+    U = syn.unit_gauge(DIMS)
+    op0 = amg.FineOp(U, np.zeros(syn.shape_of(DIMS) + (2, 6, 6), complex), 0.0, BC_AP, BLOCK)
+    x, r = amg.mr_domains(op0, b, 1)
+    assert np.abs(r).max() < 1e-14 and np.abs(x - b).max() < 1e-14
+
+
+def test_sap_is_red_black_block_gauss_seidel(small):
+    """With exact block solves, the SAP listing is multiplicative Schwarz on
+    the two colours: e <- (1 - S_o D)(1 - S_e D) e with S_c the inverse of
+    D restricted to the colour-c domains, written here from dense matrices."""
+    op, D = small
+    n = D.shape[0]
+    col = _colour_index(DIMS, BLOCK)
+    S = []
+    for c in (0, 1):
+        idx = np.where(col == c)[0]
+        Sc = np.zeros((n, n), complex)
+        Sc[np.ix_(idx, idx)] = np.linalg.inv(D[np.ix_(idx, idx)])
+        S.append(Sc)
+    E = (np.eye(n) - S[1] @ D) @ (np.eye(n) - S[0] @ D)
+    b = syn.gaussian_vectors(DIMS, 1, 4)[0]
+    Dinv_b = np.linalg.solve(D, b.reshape(-1))
+    sweeps = 3
+    want = Dinv_b - np.linalg.matrix_power(E, sweeps) @ Dinv_b
+
+    Ds = od.dense_D(op.U, op.Fb, op.kappa, BC_AP, DIMS, block=BLOCK)
+
+    def exact_block(rc):
+        return np.linalg.solve(Ds, rc.reshape(-1)).reshape(rc.shape)
+
+    got = amg.sap(op, b, sweeps, block_solver=exact_block)
+    assert np.abs(got.reshape(-1) - want).max() < 1e-11 * np.abs(want).max()
+
+
+def test_sap_converges_for_small_kappa():
+    U = syn.gauge_field(DIMS, 0.5, 2)
+    kappa = 0.06
+    Fb = od.clover_blocks(U, kappa, 1.0)
+    op = amg.FineOp(U, Fb, kappa, BC_AP, BLOCK)
+    b = syn.gaussian_vectors(DIMS, 1, 5)[0]
+    x = amg.sap(op, b, sweeps=12, mr_iters=12)
+    res = np.linalg.norm(b - op.D(x)) / np.linalg.norm(b)
+    assert res < 1e-8
+
+
+def _dense_P(V, dims, block):
+    nv = V.shape[0]
+    nX = amg.n_blocks(dims, block)
+    cols = []
+    for X in range(nX):
+        for k in range(2 * nv):
+            e = np.zeros((nX, 2 * nv), complex)
+            e[X, k] = 1.0
+            cols.append(amg.prolong(V, e, dims, block).reshape(-1))
+    return np.array(cols).T
+
+
+def test_orthonormalisation_matches_library_qr():
+    V = syn.gaussian_vectors(DIMS, 6, 8)
+    Q = amg.block_orthonormalize(V, DIMS, BLOCK)
+    Vb = amg.to_blocks(V, DIMS, BLOCK)
+    Qb = amg.to_blocks(Q, DIMS, BLOCK)
+    for X in (0, 5, 15):
+        for s in (0, 1):
+            A = Vb[:, X, s, :].T
+            q, r = np.linalg.qr(A)
+            q = q * (np.diag(r) / np.abs(np.diag(r)))
+            assert np.abs(Qb[:, X, s, :].T - q).max() < 1e-13
+    P = _dense_P(Q, DIMS, BLOCK)
+    assert np.abs(P.conj().T @ P - np.eye(P.shape[1])).max() < 1e-13
+
+
+def test_restrict_prolong_identities():
+    V = amg.block_orthonormalize(syn.gaussian_vectors(DIMS, 4, 9), DIMS, BLOCK)
+    P = _dense_P(V, DIMS, BLOCK)
+    x = syn.gaussian_vectors(DIMS, 2, 10)
+    xc = amg.restrict(V, x, DIMS, BLOCK)
+    assert np.abs(xc.reshape(2, -1) - (P.conj().T @ x.reshape(2, -1).T).T).max() < 1e-13
+    yc = syn.gaussian_coarse(16, 8, 1, 3)[0]
+    assert np.abs(amg.restrict(V, amg.prolong(V, yc, DIMS, BLOCK), DIMS, BLOCK) - yc).max() < 1e-13
+    PR = P @ P.conj().T
+    assert np.abs(PR @ PR - PR).max() < 1e-13 and np.abs(PR - PR.conj().T).max() < 1e-14
+
+
+@pytest.mark.parametrize('block', [(2, 2, 2, 2), (2, 4, 2, 2)])
+def test_coarse_operator_is_galerkin(small, block):
+    """eq. (7): Dc = P^dag D P, checked against dense brute force, including a
+    direction with a single block (no crossing) and extent-2 coarse
+    directions (forward and backward blocks reach the same neighbour)."""
+    op0, D = small
+    op = amg.FineOp(op0.U, op0.Fb, op0.kappa, BC_AP, block)
+    V = amg.block_orthonormalize(syn.gaussian_vectors(DIMS, 3, 12), DIMS, block)
+    Dc = amg.coarse_operator(op, V)
+    cd = amg.coarse_dims(DIMS, block)
+    P = _dense_P(V, DIMS, block)
+    M = amg.coarse_dense(Dc, cd)
+    assert np.abs(M - P.conj().T @ D @ P).max() < 1e-13
+    xc = syn.gaussian_coarse(M.shape[0] // 6, 6, 1, 4)[0]
+    assert np.abs(amg.coarse_apply(Dc, xc, cd).reshape(-1) - M @ xc.reshape(-1)).max() < 1e-13
+    # coarse gamma_5-hermiticity: Gamma Dc Gamma = Dc^dag, Gamma = diag(1_Nv, -1_Nv)
+    G = np.kron(np.eye(M.shape[0] // 6), np.diag([1, 1, 1, -1, -1, -1]))
+    assert np.abs(G @ M @ G - M.conj().T).max() < 1e-13
+
+
+def test_full_basis_coarse_correction_is_exact(small):
+    """N_v = 6|X|: P is unitary, so P Dc^-1 P^dag = D^-1 (the coarse step of
+    the V-cycle alone solves the system)."""
+    op, D = small
+    V = amg.block_orthonormalize(syn.gaussian_vectors(DIMS, 96, 13), DIMS, BLOCK)
+    mg = amg.TwoLevel(op, V, sap_sweeps=0, coarse='exact')
+    b = syn.gaussian_vectors(DIMS, 1, 14)
+    x = mg.vcycle(b)
+    want = np.linalg.solve(D, b.reshape(-1))
+    assert np.abs(x.reshape(-1) - want).max() < 1e-11 * np.abs(want).max()
+
+
+def test_bicgstab_converges_to_dense_solution(small):
+    op, _ = small
+    V = amg.block_orthonormalize(syn.gaussian_vectors(DIMS, 4, 15), DIMS, BLOCK)
+    Dc = amg.coarse_operator(op, V)
+    cd = amg.coarse_dims(DIMS, BLOCK)
+    M = amg.coarse_dense(Dc, cd)
+    b = syn.gaussian_coarse(16, 8, 1, 5)[0]
+    x, its = amg.bicgstab(lambda z: amg.coarse_apply(Dc, z[None], cd)[0], b, 200, 1e-13)
+    want = np.linalg.solve(M, b.reshape(-1))
+    assert its < 200
+    assert np.abs(x.reshape(-1) - want).max() < 1e-10 * np.abs(want).max()
+    # a non-normal test matrix where the omega stabilisation engages
+    rng = np.random.default_rng(0)
+    A = np.eye(60) * 2 + np.diag(rng.standard_normal(59) * 3, 1) + 0.3j * rng.standard_normal((60, 60))
+    bb = rng.standard_normal(60) + 0j
+    x, its = amg.bicgstab(lambda z: A @ z, bb, 500, 1e-12)
+    assert np.linalg.norm(A @ x - bb) <= 1e-11 * np.linalg.norm(bb)
+
+
+def test_vcycle_error_propagator(small):
+    """With an exact coarse solve and exact block solves in SAP (both linear),
+    the preconditioner satisfies 1 - M D = (1 - S D)(1 - P Dc^-1 P^dag D)."""
+    op, D = small
+    n = D.shape[0]
+    V = amg.block_orthonormalize(syn.gaussian_vectors(DIMS, 4, 16), DIMS, BLOCK)
+    mg = amg.TwoLevel(op, V, sap_sweeps=2, coarse='exact')
+    Ds = od.dense_D(op.U, op.Fb, op.kappa, BC_AP, DIMS, block=BLOCK)
+    mg.smoother = lambda r: amg.sap(op, r, 2, block_solver=lambda rc: np.linalg.solve(
+        Ds, rc.reshape(-1)).reshape(rc.shape))
+    col = _colour_index(DIMS, BLOCK)
+    Sc = []
+    for c in (0, 1):
+        idx = np.where(col == c)[0]
+        S = np.zeros((n, n), complex)
+        S[np.ix_(idx, idx)] = np.linalg.inv(D[np.ix_(idx, idx)])
+        Sc.append(S)
+    Esap = np.linalg.matrix_power((np.eye(n) - Sc[1] @ D) @ (np.eye(n) - Sc[0] @ D), 2)
+    P = _dense_P(V, DIMS, BLOCK)
+    Cc = P @ np.linalg.inv(P.conj().T @ D @ P) @ P.conj().T
+    E = Esap @ (np.eye(n) - Cc @ D)
+    v = syn.gaussian_vectors(DIMS, 1, 17)
+    Mv = mg.vcycle(v).reshape(-1)
+    want = (np.eye(n) - E) @ np.linalg.solve(D, v.reshape(-1))
+    assert np.abs(Mv - want).max() < 1e-10 * np.abs(want).max()
+
+
+def test_fgmres_is_gmres_without_preconditioner(small):
+    """With M = 1 and no restart, the k-th FGMRES iterate minimises
+    ||b - D y|| over the Krylov space span{b, Db, ..., D^{k-1} b}."""
+    op, D = small
+    b = syn.z2_source(DIMS, 1)[0]
+    for k in (3, 7):
+        x, its, _ = amg.fgmres(op.D, lambda v: v, b, tol=0.0, restart=50, max_iters=k)
+        assert its == k
+        Kr = [b.reshape(-1)]
+        for _ in range(k - 1):
+            Kr.append(D @ Kr[-1])
+        Q, _ = np.linalg.qr(np.array(Kr).T)
+        y, *_ = np.linalg.lstsq(D @ Q, b.reshape(-1), rcond=None)
+        best = np.linalg.norm(b.reshape(-1) - D @ Q @ y)
+        got = np.linalg.norm(b.reshape(-1) - D @ x.reshape(-1))
+        assert abs(got - best) < 1e-9 * best
+
+
+def test_two_level_solve_matches_dense_lu(small):
+    """Config-1-like: setup then AMG-preconditioned FGMRES(16) to 1e-10; the
+    solution agrees with dense LU; the paper's flexible BiCGStab as well."""
+    op, D = small
+    V0 = syn.gaussian_vectors(DIMS, 8, 1)
+    mg = amg.setup(op, V0, n_init=3, n_adapt=3, coarse_iters=50, coarse_tol=0.1)
+    P = _dense_P(mg.V, DIMS, BLOCK)
+    assert np.abs(P.conj().T @ P - np.eye(P.shape[1])).max() < 1e-12
+    b = syn.z2_source(DIMS, 1)[0]
+    want = np.linalg.solve(D, b.reshape(-1))
+    x, its, res = amg.fgmres(op.D, mg.vcycle, b, tol=1e-10, restart=16)
+    assert res <= 1e-10
+    cond = np.linalg.cond(D)
+    assert np.linalg.norm(x.reshape(-1) - want) <= cond * 1e-10 * np.linalg.norm(want)
+    _, its_plain, _ = amg.fgmres(op.D, lambda v: v, b, tol=1e-10, restart=16)
+    assert its < its_plain
+    x2, _, res2 = amg.flexible_bicgstab(op.D, mg.vcycle, b, tol=1e-10)
+    assert res2 <= 1e-10
