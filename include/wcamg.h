@@ -1,0 +1,209 @@
+/*
+ * wcamg.h -- C ABI of libwcamg, an algebraic multigrid (AMG) solver for the
+ * Wilson-clover Dirac equation D x = b on one AMD MI355X (gfx950).
+ *
+ * The operator is eq. (1) of Kanamori, Ishikawa, Matsufuru, arXiv:2111.05012
+ * (Sec. 2):
+ *   D psi(x) = (1 + F(x)) psi(x)
+ *              - kappa sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                             + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
+ * and the solver is the paper's multigrid preconditioner (Sec. 3: setup
+ * (0-a)/(0-b), restriction eq. (5), coarse solve of eq. (4) with the coarse
+ * operator eq. (7), prolongation eq. (6), SAP smoother) inside an outer
+ * flexible GMRES in FP64.
+ *
+ * Conventions (fixed by this ABI):
+ *  - Lattice extents dims = {Lx, Ly, Lz, Lt}; canonical site index
+ *    x + Lx*(y + Ly*(z + Lz*t)).
+ *  - Spinor fields: complex128 [nrhs][V][4 spin][3 colour] (interleaved re, im).
+ *  - Gauge fields:  complex128 [4 mu = x,y,z,t][V][3][3], U_mu(x) links x to
+ *    x+mu, row-major.  Boundary phases are NOT folded into U.
+ *  - Clover fields: complex128 [V][2][6][6]: the two diagonal 6x6 blocks of
+ *    the 12x12 matrix F(x) in the chiral basis (block b holds spins 2b, 2b+1;
+ *    index spin_in_block*3 + colour).  F excludes the identity.
+ *  - Gamma matrices, chiral basis: gamma_k = [[0, -i s_k], [i s_k, 0]]
+ *    (k = 1,2,3 with Pauli matrices s_k), gamma_4 = [[0, -1], [-1, 0]], so
+ *    gamma_5 = -gamma_1 gamma_2 gamma_3 gamma_4 = diag(1, 1, -1, -1) (eq. (2)).
+ *  - Clover term: F = i c_sw kappa sum_{mu<nu} sigma_{mu nu} (x) Fhat_{mu nu},
+ *    sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu], Fhat = (Q - Q^dag)/8 with Q the
+ *    four plaquette leaves at x in the (mu, nu) plane.
+ *  - Multigrid blocks (= SAP domains, Sec. 3) of extents block[4] divide dims.
+ *    Coarse vectors: complex128 [nrhs][NC][2 nv], NC = prod(dims/block) coarse
+ *    sites ordered like fine sites, internal index s*nv + i (s = 0: spins 0,1;
+ *    s = 1: spins 2,3).  Coarse operator: complex128 [NC][9][2nv][2nv],
+ *    Dc[X][d][n][m] = <X, n| D |X + e_d, m>, d = 0 self, 1 + mu forward,
+ *    5 + mu backward neighbour.
+ *
+ * Pointers: "where" selects WCAMG_DEVICE (device memory, read/written in
+ * order on the context's stream, asynchronously) or WCAMG_HOST (host memory,
+ * the call is synchronous).  The caller owns every buffer it passes; the
+ * library keeps no caller pointer after a call returns (device reads of a
+ * device input may still be in flight on the stream).  The library owns its
+ * internal copies (gauge, clover, test vectors, coarse operators,
+ * workspaces), all freed by wcamg_destroy.
+ *
+ * Errors: every int function returns WCAMG_OK (0), a negative error code or
+ * a positive warning; no C++ exception crosses the ABI.  The message of the
+ * last failure is returned by wcamg_last_error.  A context is not
+ * thread-safe: use one context per host thread / stream.
+ */
+#ifndef WCAMG_H
+#define WCAMG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WCAMG_OK 0
+#define WCAMG_NOT_CONVERGED 1 /* solve: some right-hand side missed the tolerance */
+#define WCAMG_EINVAL (-1)     /* invalid argument (checked before any device call) */
+#define WCAMG_ENOMEM (-2)     /* device allocation failed */
+#define WCAMG_EHIP (-3)       /* HIP runtime error */
+#define WCAMG_ESTATE (-4)     /* call out of order (e.g. no gauge field, no setup) */
+#define WCAMG_ENUMERIC (-5)   /* NaN/Inf or breakdown detected */
+
+#define WCAMG_DEVICE 0
+#define WCAMG_HOST 1
+
+#define WCAMG_PREC_FP64 0  /* everything in FP64 */
+#define WCAMG_PREC_MIXED 1 /* FP16 links/clover/test vectors, FP32 arithmetic, FP64 outer solver */
+
+typedef struct wcamg_ctx wcamg_ctx;
+
+typedef struct {
+  int dims[4];  /* Lx, Ly, Lz, Lt: each even and >= 2 */
+  int block[4]; /* multigrid block = SAP domain extents; must divide dims */
+  int bc[4];    /* +1 periodic, -1 antiperiodic, per direction */
+  double kappa; /* hopping parameter of eq. (1) */
+  double csw;   /* clover coefficient */
+} wcamg_lattice;
+
+/* Create a context on the current HIP device.  hip_stream: a hipStream_t to
+ * issue all work on (e.g. torch.cuda.current_stream().cuda_stream), or NULL
+ * for a library-owned stream.  Validates the lattice (EINVAL) before touching
+ * the device. */
+int wcamg_create(wcamg_ctx** out, const wcamg_lattice* lat, void* hip_stream);
+/* Free everything the context owns.  NULL is accepted. */
+void wcamg_destroy(wcamg_ctx* ctx);
+/* Message of the last failed call on ctx ("" if none); valid until the next call. */
+const char* wcamg_last_error(const wcamg_ctx* ctx);
+/* Synchronise the context's stream. */
+int wcamg_sync(wcamg_ctx* ctx);
+
+/* Load the gauge field U (canonical layout), convert it to the internal
+ * blocked layout in FP64 and FP16, and build the clover term F (Sec. 2).
+ * Invalidates any previous setup. */
+int wcamg_load_gauge(wcamg_ctx* ctx, const void* U, int where);
+/* Override the clover term with F (canonical clover layout; Hermitian blocks
+ * expected, only the upper triangles and real diagonals are read). */
+int wcamg_load_clover(wcamg_ctx* ctx, const void* F, int where);
+/* Copy the FP64 clover term out (canonical clover layout). */
+int wcamg_get_clover(wcamg_ctx* ctx, void* F, int where);
+
+/* out = D in for nrhs spinor fields, eq. (1).  prec = WCAMG_PREC_FP64
+ * (FP64 throughout) or WCAMG_PREC_MIXED (FP32 arithmetic on FP32-rounded
+ * input, FP16 links and clover).  in and out must not alias. */
+int wcamg_apply_D(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int prec, int where);
+/* out = D_SAP in: eq. (1) with every hop between distinct blocks removed
+ * (Sec. 3, SAP paragraph). */
+int wcamg_apply_Dsap(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int prec, int where);
+/* x = SAP(b): the Schwarz alternating procedure with fixed iterations
+ * (Sec. 3 listing): x = 0, r = b; per sweep, even then odd domains
+ * (colour = parity of the sum of block coordinates) get x += M r with M
+ * mr_iters minimal-residual iterations on D_SAP of the domain, and
+ * r = b - D x.  Needs an even number of blocks per direction (EINVAL). */
+int wcamg_sap(wcamg_ctx* ctx, const void* b, void* x, int nrhs, int sweeps, int mr_iters, int prec, int where);
+
+typedef struct {
+  int nv;            /* test vectors N_v (<= 64) */
+  int n_init;        /* (0-a): SAP applications to the start vectors */
+  int n_adapt;       /* (0-b): adaptive refinement passes */
+  int sap_sweeps;    /* SAP sweeps n (paper: 4) */
+  int mr_iters;      /* MR iterations per block solve (paper: 6) */
+  int coarse_iters;  /* coarse BiCGStab: maximum iterations */
+  double coarse_tol; /* coarse BiCGStab: relative residual tolerance */
+  int prec;          /* WCAMG_PREC_FP64 or WCAMG_PREC_MIXED */
+  const void* init_vectors; /* nv start vectors (canonical spinor layout), required */
+  int init_where;    /* WCAMG_DEVICE or WCAMG_HOST for init_vectors */
+} wcamg_setup_params;
+
+/* Setup stage (0) of Sec. 3: (0-a) SAP applied n_init times to the start
+ * vectors, block orthonormalisation (<I|J> = delta_IJ), coarse operator
+ * eq. (7); (0-b) n_adapt times: every vector replaced by M v (the V-cycle
+ * with the current hierarchy), re-orthonormalised, coarse operator rebuilt.
+ * Synchronous. */
+int wcamg_setup(wcamg_ctx* ctx, const wcamg_setup_params* p);
+
+/* Install nv test vectors as given (canonical spinor layout; the caller
+ * orthonormalises them), with the preconditioner parameters of p (its
+ * init_vectors / n_init / n_adapt are ignored), and build the coarse
+ * operator.  Component test hook. */
+int wcamg_set_test_vectors(wcamg_ctx* ctx, const void* V, const wcamg_setup_params* p, int where);
+/* Copy the stored test vectors out (canonical spinor layout, nv fields). */
+int wcamg_get_test_vectors(wcamg_ctx* ctx, void* V, int where);
+/* Block-orthonormalise nv fields (canonical layout) per block and
+ * chirality in the order i = 1..nv, positive real diagonal (CholQR2). */
+int wcamg_orthonormalize(wcamg_ctx* ctx, const void* in, void* out, int nv, int prec, int where);
+/* eq. (5): out[r][X][s nv + i] = <X, s, i | in_r>, with the stored vectors. */
+int wcamg_restrict(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int where);
+/* eq. (6): out_r = sum_I in[r][I] |I>. */
+int wcamg_prolong(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int where);
+/* Copy the coarse operator out (complex128 [NC][9][2nv][2nv], see above). */
+int wcamg_get_coarse_op(wcamg_ctx* ctx, void* Dc, int where);
+/* out = Dc in on coarse vectors (the 9-point block stencil). */
+int wcamg_apply_coarse(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int where);
+/* x = coarse solve of Dc x = b: BiCGStab from x = 0 with the stabilised
+ * omega (Sec. 3 step (1b)), at most iters iterations, stopping per
+ * right-hand side at ||r|| <= tol ||b||. */
+int wcamg_coarse_solve(wcamg_ctx* ctx, const void* b, void* x, int nrhs, int iters, double tol, int where);
+/* out = M in: one application of the multigrid preconditioner, Sec. 3
+ * steps (1a)-(1c) then (2). */
+int wcamg_vcycle(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int where);
+
+typedef struct {
+  int restart;   /* FGMRES restart length m (1..32) */
+  double tol;    /* relative residual ||b - D x|| / ||b|| per right-hand side */
+  int max_iters; /* total Arnoldi steps per right-hand side */
+  int rhs_chunk; /* right-hand sides per batch (0: all) */
+  int use_graph; /* capture the V-cycle in a HIP graph and replay it */
+} wcamg_solve_params;
+
+#define WCAMG_MAX_RHS 64
+typedef struct {
+  int iters[WCAMG_MAX_RHS];        /* outer iterations per right-hand side */
+  double relres[WCAMG_MAX_RHS];    /* final ||b - D x|| / ||b||, recomputed with FP64 D */
+  int converged[WCAMG_MAX_RHS];
+  int vcycles;                     /* preconditioner applications (batched) */
+  double t_solve;                  /* seconds, wall clock of the whole solve */
+} wcamg_solve_info;
+
+/* Solve D x = b for nrhs right-hand sides (canonical layout, DEVICE
+ * pointers b and x; synchronous) with flexible
+ * GMRES(restart) in FP64, right-preconditioned by the multigrid V-cycle,
+ * from x = 0.  Returns WCAMG_NOT_CONVERGED if some right-hand side missed
+ * tol within max_iters (info filled either way). */
+int wcamg_solve(wcamg_ctx* ctx, const void* b, void* x, int nrhs, const wcamg_solve_params* p,
+                wcamg_solve_info* info);
+
+/* Per-kernel-class timing with HIP events on the context stream, for
+ * roofline measurements: enable (1) / disable (0, also clears nothing).
+ * When enabled, the work of each class is bracketed by events: "dslash64",
+ * "dslash32" (one launch of the fine operator), "sap" (one smoother
+ * application, all half-sweeps), "restrict", "prolong", "coarse_mv",
+ * "coarse_solve" (one whole coarse BiCGStab), "coarse_build" (one coarse
+ * operator construction), "ortho" (one block orthonormalisation).  Classes
+ * nest ("coarse_mv" launches inside "coarse_solve" are recorded in both),
+ * except that nothing inside "coarse_build" or "ortho" is recorded
+ * separately.  Graph replay is disabled while timing is on. */
+int wcamg_kernel_timing(wcamg_ctx* ctx, int enable);
+/* Accumulated time (ms), launch count, algorithmic bytes and flops (the
+ * compulsory traffic / arithmetic of the work, 0 when not defined for the
+ * class) and right-hand-side units of a class since timing was enabled.
+ * bytes, flops, units may be NULL. */
+int wcamg_kernel_stats(wcamg_ctx* ctx, const char* name, double* total_ms, int* count, double* bytes,
+                       double* flops, double* units);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WCAMG_H */

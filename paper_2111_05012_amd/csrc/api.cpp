@@ -1,0 +1,1181 @@
+// libwcamg: C ABI entry points and the solver orchestration (V-cycle, setup,
+// outer FGMRES) on top of the HIP kernels.  All device work is issued on the
+// context's stream; host synchronisation happens only where a host decision
+// needs device data (Givens rotations of FGMRES, coarse-solve early exit
+// outside graph capture) or at the end of synchronous calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/wcamg.h"
+#include "wc_kernels.h"
+
+using namespace wc;
+using cd = std::complex<double>;
+
+namespace {
+
+struct WcError : std::runtime_error {
+  int code;
+  WcError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                                \
+  do {                                                                                           \
+    hipError_t e_ = (x);                                                                         \
+    if (e_ != hipSuccess)                                                                        \
+      throw WcError(e_ == hipErrorOutOfMemory ? WCAMG_ENOMEM : WCAMG_EHIP,                       \
+                    std::string(#x) + ": " + hipGetErrorString(e_));                              \
+  } while (0)
+
+void require(bool c, const std::string& m, int code = WCAMG_EINVAL) {
+  if (!c) throw WcError(code, m);
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  void* ensure(size_t bytes, bool frozen) {
+    if (bytes <= n) return p;
+    require(!frozen, "internal: workspace growth during graph capture", WCAMG_ESTATE);
+    if (p) HIPCHK(hipFree(p));
+    p = nullptr;
+    n = 0;
+    HIPCHK(hipMalloc(&p, bytes));
+    n = bytes;
+    return p;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+struct Hier {
+  int prec = -1;  // WCAMG_PREC_*
+  int nv = 0, N = 0;
+  CGeo cg{};
+  int sap_sweeps = 4, mr_iters = 6, coarse_iters = 50;
+  double coarse_tol = 0.1;
+  DevBuf V;   // stored test vectors [nv][12][V]
+  DevBuf Dc;  // [NC][9][N][N]
+};
+
+struct KStat {
+  double ms = 0, bytes = 0, flops = 0, units = 0;
+  int count = 0;
+};
+
+// sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu] in the chiral basis, as its two
+// diagonal 2x2 blocks per plane (mu<nu), [6][2][2][2][re,im].
+std::vector<double> sigma_table() {
+  cd I(0, 1);
+  cd g[4][4][4] = {};
+  // gamma_k = [[0, -i s_k], [i s_k, 0]], gamma_4 = [[0, -1], [-1, 0]]
+  cd s[3][2][2] = {{{0, 1}, {1, 0}}, {{0, -I}, {I, 0}}, {{1, 0}, {0, -1}}};
+  for (int k = 0; k < 3; ++k)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        g[k][a][2 + b] = -I * s[k][a][b];
+        g[k][2 + a][b] = I * s[k][a][b];
+      }
+  for (int a = 0; a < 2; ++a) {
+    g[3][a][2 + a] = -1;
+    g[3][2 + a][a] = -1;
+  }
+  std::vector<double> t(6 * 2 * 2 * 2 * 2);
+  int pl = 0;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int nu = mu + 1; nu < 4; ++nu, ++pl) {
+      cd sg[4][4];
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          cd c = 0;
+          for (int k = 0; k < 4; ++k) c += g[mu][a][k] * g[nu][k][b] - g[nu][a][k] * g[mu][k][b];
+          sg[a][b] = 0.5 * I * c;
+        }
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          if (std::abs(sg[a][2 + b]) > 1e-14 || std::abs(sg[2 + a][b]) > 1e-14)
+            throw WcError(WCAMG_EHIP, "internal: sigma not block diagonal");
+      for (int ch = 0; ch < 2; ++ch)
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) {
+            cd v = sg[2 * ch + a][2 * ch + b];
+            size_t o = ((((size_t)pl * 2 + ch) * 2 + a) * 2 + b) * 2;
+            t[o] = v.real();
+            t[o + 1] = v.imag();
+          }
+    }
+  return t;
+}
+
+}  // namespace
+
+struct wcamg_ctx {
+  Geo g{};
+  double kappa = 0, csw = 0;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  bool have_gauge = false;
+  DevBuf U64, U16, Cl64, Cl16;
+  Hier h;
+  bool have_hier = false;
+  std::map<std::string, std::unique_ptr<DevBuf>> ws;
+  std::string err;
+  bool capturing = false;
+  // kernel timing
+  bool timing = false;
+  struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes, flops, units;
+  };
+  int timing_excl = 0;  // > 0 inside an exclusive scope: inner scopes are not recorded
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> evpool;
+  std::map<std::string, KStat> kstats;
+  // graphs: key (slot, nrhs) -> exec
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  int graph_prec = -1;
+  hipStream_t cap_st = nullptr;  // library-owned stream used for graph capture
+  size_t lds_max = 0;            // LDS bytes available to one workgroup
+
+  ~wcamg_ctx() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : evpool) (void)hipEventDestroy(e);
+    if (own_stream && st) (void)hipStreamDestroy(st);
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+  }
+
+  void* W(const std::string& name, size_t bytes) {
+    auto& b = ws[name];
+    if (!b) b.reset(new DevBuf());
+    return b->ensure(bytes, capturing);
+  }
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
+
+  // ---- kernel timing
+  hipEvent_t ev() {
+    if (!evpool.empty()) {
+      hipEvent_t e = evpool.back();
+      evpool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+  // Brackets the launches of one kernel class with events (when timing is
+  // on and no graph is being captured), with the algorithmic bytes / flops /
+  // right-hand-side units of the work, for roofline accounting.
+  struct Timed {
+    wcamg_ctx* c;
+    const char* name;
+    double bytes, flops, units;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool excl;
+    Timed(wcamg_ctx* c_, const char* n, double by = 0, double fl = 0, double un = 0, bool exclusive = false)
+        : c(c_), name(n), bytes(by), flops(fl), units(un), excl(exclusive) {
+      if (c->timing && !c->capturing && c->timing_excl == 0) {
+        a = c->ev();
+        b = c->ev();
+        HIPCHK(hipEventRecord(a, c->st));
+      }
+      if (excl) c->timing_excl++;
+    }
+    ~Timed() {
+      if (excl) c->timing_excl--;
+      if (a) {
+        (void)hipEventRecord(b, c->st);
+        c->pending.push_back({name, a, b, bytes, flops, units});
+      }
+    }
+  };
+  void collect_timing() {
+    if (pending.empty()) return;
+    HIPCHK(hipStreamSynchronize(st));
+    for (auto& p : pending) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+      auto& k = kstats[p.name];
+      k.ms += ms;
+      k.count += 1;
+      k.bytes += p.bytes;
+      k.flops += p.flops;
+      k.units += p.units;
+      evpool.push_back(p.a);
+      evpool.push_back(p.b);
+    }
+    pending.clear();
+  }
+
+  // ---- precision helpers
+  int spin_t(int prec) const { return prec == WCAMG_PREC_MIXED ? C64 : C128; }
+  size_t fsz(int nrhs, int prec) const { return (size_t)nrhs * 12 * g.V * ct_size(spin_t(prec)); }
+  size_t frs() const { return (size_t)12 * g.V; }
+
+  // ---- D family on internal fields
+  void dslash(const void* in, int in_t, void* out, int out_t, int nrhs, int op, int prec, const void* b = nullptr,
+              int hopdir = 0, int chir = -1) {
+    DslashArgs a;
+    a.g = g;
+    a.op = op;
+    a.hopdir = hopdir;
+    a.chir = chir;
+    a.nrhs = nrhs;
+    a.in = in;
+    a.in_t = in_t;
+    a.in_rs = frs();
+    a.out = out;
+    a.out_t = out_t;
+    a.out_rs = frs();
+    a.b = b;
+    a.kappa = kappa;
+    if (prec == WCAMG_PREC_MIXED) {
+      a.U = U16.p;
+      a.C = Cl16.p;
+      a.fields16 = 1;
+      a.compute32 = 1;
+    } else {
+      a.U = U64.p;
+      a.C = Cl64.p;
+    }
+    double site = (double)g.V;
+    double fld = 4.0 * 9 * (a.fields16 ? 4 : 16) + 36.0 * (a.fields16 ? 4 : 16);
+    double by = site * (fld + nrhs * 12.0 * (ct_size(in_t) + ct_size(out_t) * (b ? 2 : 1)));
+    Timed t(this, a.compute32 ? "dslash32" : "dslash64", by, 1920.0 * site * nrhs, nrhs);
+    launch_dslash(a, st);
+  }
+
+  void sap(const void* b, void* x, const void* xinit, int nrhs, int sweeps, int mr, int prec) {
+    SapArgs a;
+    a.g = g;
+    a.nrhs = nrhs;
+    a.sweeps = sweeps;
+    a.mr = mr;
+    a.mixed = prec == WCAMG_PREC_MIXED;
+    a.kappa = kappa;
+    a.b = b;
+    a.x = x;
+    a.xinit = xinit;
+    a.r = W("sap_r", fsz(nrhs, prec));
+    a.delta = W("sap_d", fsz(nrhs, prec));
+    a.rs = frs();
+    a.U = a.mixed ? U16.p : U64.p;
+    a.C = a.mixed ? Cl16.p : Cl64.p;
+    if (sweeps <= 0) {
+      // x = xinit (or 0)
+      if (xinit)
+        HIPCHK(hipMemcpyAsync(x, xinit, fsz(nrhs, prec), hipMemcpyDeviceToDevice, st));
+      else
+        launch_zero(x, fsz(nrhs, prec), st);
+      return;
+    }
+    require((size_t)sap_lds_bytes(g, a.mixed) <= lds_max,
+            "block volume too large for the SAP kernel's LDS at this precision");
+    double sb = a.mixed ? 8 : 16, fld = a.mixed ? 4 * 9 * 4 + 36 * 4 : 4 * 9 * 16 + 36 * 16;
+    double by = (double)g.V * (sweeps * fld + nrhs * 12.0 * sb * (4.0 * sweeps + (sweeps - 1) + (xinit ? 1 : 0)));
+    double fl = (double)g.V * sweeps * nrhs * (mr * 2200.0 + 400.0);
+    Timed t(this, "sap", by, fl, nrhs);
+    launch_sap(a, st);
+  }
+
+  // ---- coarse level
+  int vec_t() const { return h.prec == WCAMG_PREC_MIXED ? C32H : C128; }
+  int crs_t() const { return h.prec == WCAMG_PREC_MIXED ? C64 : C128; }
+  size_t crs_n() const { return (size_t)h.cg.NC * h.N; }
+  size_t csz(int nrhs) const { return (size_t)nrhs * crs_n() * ct_size(crs_t()); }
+
+  void restrict_(const void* in, void* out, int nrhs) {
+    double by = (double)g.V * 12 * (h.nv * ct_size(vec_t()) + nrhs * ct_size(spin_t(h.prec))) +
+                (double)nrhs * crs_n() * ct_size(crs_t());
+    Timed t(this, "restrict", by, 96.0 * g.V * h.nv * nrhs, nrhs);
+    launch_restrict(g, h.nv, nrhs, h.V.p, vec_t(), in, spin_t(h.prec), frs(), out, crs_t(), crs_n(), h.N, 0, st);
+  }
+  void prolong_(const void* xc, void* out, int nrhs) {
+    double by = (double)g.V * 12 * (h.nv * ct_size(vec_t()) + nrhs * ct_size(spin_t(h.prec))) +
+                (double)nrhs * crs_n() * ct_size(crs_t());
+    Timed t(this, "prolong", by, 96.0 * g.V * h.nv * nrhs, nrhs);
+    launch_prolong(g, h.nv, nrhs, h.V.p, vec_t(), xc, crs_t(), crs_n(), h.N, out, spin_t(h.prec), frs(), 0,
+                   h.prec == WCAMG_PREC_MIXED, st);
+  }
+  void coarse_mv(const void* x, void* y, const void* b, int nrhs) {
+    double nc = h.cg.NC, N = h.N, cb = ct_size(crs_t());
+    double by = nc * 9 * N * N * cb + nrhs * nc * N * cb * (b ? 3 : 2);
+    Timed t(this, "coarse_mv", by, 8.0 * 9 * N * N * nc * nrhs, nrhs);
+    launch_coarse_mv(h.cg, h.N, h.Dc.p, x, y, b, nrhs, crs_n(), h.prec == WCAMG_PREC_MIXED, st);
+  }
+
+  // BiCGStab with the stabilised omega; early exit checks only outside capture
+  void coarse_solve(const void* b, void* x, int nrhs, int iters, double tol) {
+    int t = crs_t();
+    Timed tc(this, "coarse_solve", 0, 0, nrhs);
+    size_t n = crs_n();
+    size_t bytes = csz(nrhs);
+    void* r = W("cg_r", bytes);
+    void* rt = W("cg_rt", bytes);
+    void* p = W("cg_p", bytes);
+    void* v = W("cg_v", bytes);
+    void* s = W("cg_s", bytes);
+    void* tt = W("cg_t", bytes);
+    double2* part = (double2*)W("cg_part", (size_t)nrhs * reduce_nwg(n) * 3 * sizeof(double2));
+    BicgScal* sc = (BicgScal*)W("cg_sc", (size_t)nrhs * sizeof(BicgScal));
+    launch_bicg_init(b, x, r, rt, p, v, t, n, n, nrhs, tol, part, sc, st);
+    std::vector<BicgScal> hs(nrhs);
+    for (int it = 0; it < iters; ++it) {
+      launch_bicg_p(p, r, v, t, n, n, nrhs, sc, st);
+      coarse_mv(p, v, nullptr, nrhs);
+      launch_bicg_alpha(rt, v, t, n, n, nrhs, part, sc, st);
+      launch_bicg_s(s, r, v, t, n, n, nrhs, sc, st);
+      coarse_mv(s, tt, nullptr, nrhs);
+      launch_bicg_omega(tt, s, t, n, n, nrhs, part, sc, 0.7, st);
+      launch_bicg_xr(x, r, p, s, tt, rt, t, n, n, nrhs, part, sc, st);
+      if (!capturing && (it % 4 == 3) && it + 1 < iters) {
+        HIPCHK(hipMemcpyAsync(hs.data(), sc, nrhs * sizeof(BicgScal), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool any = false;
+        for (auto& q : hs) any |= q.active != 0;
+        if (!any) break;
+      }
+    }
+  }
+
+  // M v: restrict, coarse solve, prolong, residual, SAP started from the prolonged vector
+  void vcycle(const void* in, void* out, int nrhs) {
+    int prec = h.prec;
+    void* vc = W("vc_b", csz(nrhs));
+    void* xc = W("vc_x", csz(nrhs));
+    void* x1 = W("vc_x1", fsz(nrhs, prec));
+    void* r = W("vc_r", fsz(nrhs, prec));
+    restrict_(in, vc, nrhs);
+    coarse_solve(vc, xc, nrhs, h.coarse_iters, h.coarse_tol);
+    prolong_(xc, x1, nrhs);
+    dslash(x1, spin_t(prec), r, spin_t(prec), nrhs, OP_D, prec, in);
+    sap(r, out, x1, nrhs, h.sap_sweeps, h.mr_iters, prec);
+  }
+
+  // block orthonormalisation (CholQR, twice) of nv working fields in place
+  void orthonormalize(void* Vw, int nv, int prec) {
+    int t = spin_t(prec);
+    Timed tb(this, "ortho", 0, 0, 1, true);
+    size_t gbytes = (size_t)nv * g.nblk * 2 * nv * sizeof(double2);
+    double2* G = (double2*)W("or_G", gbytes);
+    void* coef = W("or_c", (size_t)nv * g.nblk * 2 * nv * ct_size(t));
+    void* tmp = W("or_tmp", fsz(nv, prec));
+    int* bad = (int*)W("or_bad", sizeof(int));
+    launch_zero(bad, sizeof(int), st);
+    size_t grs = (size_t)g.nblk * 2 * nv;
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_restrict(g, nv, nv, Vw, t, Vw, t, frs(), G, C128, grs, 2 * nv, 1, st);
+      launch_cholesky_coef(g.nblk, nv, G, grs, coef, t, grs, bad, st);
+      launch_prolong(g, nv, nv, Vw, t, coef, t, grs, 2 * nv, tmp, t, frs(), 0, prec == WCAMG_PREC_MIXED, st);
+      HIPCHK(hipMemcpyAsync(Vw, tmp, fsz(nv, prec), hipMemcpyDeviceToDevice, st));
+    }
+    int hb = 0;
+    HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    require(hb == 0, "orthonormalisation: test vectors linearly dependent on a block", WCAMG_ENUMERIC);
+  }
+
+  // coarse operator eq.(7) from the stored vectors
+  void build_coarse() {
+    int prec = h.prec;
+    int nv = h.nv, N = h.N;
+    Timed tb(this, "coarse_build", 0, 0, 1, true);
+    void* Y = W("bc_Y", fsz(nv, prec));
+    h.Dc.ensure((size_t)h.cg.NC * 9 * N * N * ct_size(crs_t()), capturing);
+    for (int sp = 0; sp < 2; ++sp) {
+      for (int d = 0; d < 9; ++d) {
+        int op = d == 0 ? OP_DSAP : OP_HOP;
+        int hopdir = d == 0 ? 0 : (d <= 4 ? d - 1 : d - 1);
+        dslash(h.V.p, vec_t(), Y, spin_t(prec), nv, op, prec, nullptr, hopdir, sp);
+        char* base = (char*)h.Dc.p + ((size_t)d * N * N + (size_t)sp * nv * N) * ct_size(crs_t());
+        launch_restrict(g, nv, nv, h.V.p, vec_t(), Y, spin_t(prec), frs(), base, crs_t(), N, (size_t)9 * N * N, 0,
+                        st);
+      }
+    }
+  }
+
+  void store_vectors(const void* Vw, int nv) {
+    h.V.ensure((size_t)nv * 12 * g.V * ct_size(vec_t()), capturing);
+    launch_convert(Vw, spin_t(h.prec), h.V.p, vec_t(), (size_t)nv * 12 * g.V, st);
+  }
+
+  void set_params(const wcamg_setup_params* p) {
+    require(p->nv >= 1 && p->nv <= 64, "nv must be in [1, 64]");
+    require(p->prec == WCAMG_PREC_FP64 || p->prec == WCAMG_PREC_MIXED, "invalid prec");
+    require(p->sap_sweeps >= 0 && p->mr_iters >= 0 && p->coarse_iters >= 0 && p->n_init >= 0 && p->n_adapt >= 0,
+            "negative iteration count");
+    require(p->sap_sweeps == 0 || (g.NB[0] % 2 == 0 && g.NB[1] % 2 == 0 && g.NB[2] % 2 == 0 && g.NB[3] % 2 == 0),
+            "SAP needs an even number of blocks per direction");
+    require(std::isfinite(p->coarse_tol) && p->coarse_tol >= 0, "invalid coarse_tol");
+    h.prec = p->prec;
+    h.nv = p->nv;
+    h.N = 2 * p->nv;
+    h.cg = make_cgeo(g.NB);
+    h.sap_sweeps = p->sap_sweeps;
+    h.mr_iters = p->mr_iters;
+    h.coarse_iters = p->coarse_iters;
+    h.coarse_tol = p->coarse_tol;
+    drop_graphs();
+  }
+};
+
+// ---------------------------------------------------------------------------
+// helpers for the ABI wrappers
+// ---------------------------------------------------------------------------
+namespace {
+
+int guard(wcamg_ctx* c, const std::function<void()>& f);
+
+struct HostIO {
+  // stage host buffers through device memory
+  wcamg_ctx* c;
+  HostIO(wcamg_ctx* c_) : c(c_) {}
+  const void* in(const void* p, size_t bytes, int where, const char* name) {
+    if (where == WCAMG_DEVICE) return p;
+    void* d = c->W(name, bytes);
+    HIPCHK(hipMemcpyAsync(d, p, bytes, hipMemcpyHostToDevice, c->st));
+    return d;
+  }
+  void* out(void* p, size_t bytes, int where, const char* name) {
+    if (where == WCAMG_DEVICE) return p;
+    return c->W(name, bytes);
+  }
+  void finish(void* host, const void* dev, size_t bytes, int where) {
+    if (where == WCAMG_DEVICE) return;
+    HIPCHK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+  }
+};
+
+int guard(wcamg_ctx* c, const std::function<void()>& f) {
+  try {
+    if (c) c->err.clear();
+    f();
+    return WCAMG_OK;
+  } catch (const WcError& e) {
+    if (c) {
+      c->err = e.what();
+      c->capturing = false;
+    }
+    return e.code;
+  } catch (const std::exception& e) {
+    if (c) {
+      c->err = e.what();
+      c->capturing = false;
+    }
+    return WCAMG_EHIP;
+  } catch (...) {
+    if (c) c->err = "unknown error";
+    return WCAMG_EHIP;
+  }
+}
+
+void check_where(int where) { require(where == WCAMG_DEVICE || where == WCAMG_HOST, "invalid 'where'"); }
+void check_nrhs(int n) { require(n >= 1 && n <= WCAMG_MAX_RHS, "nrhs must be in [1, 64]"); }
+void check_prec(int p) { require(p == WCAMG_PREC_FP64 || p == WCAMG_PREC_MIXED, "invalid prec"); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int wcamg_create(wcamg_ctx** out, const wcamg_lattice* lat, void* hip_stream) {
+  if (!out || !lat) return WCAMG_EINVAL;
+  *out = nullptr;
+  for (int m = 0; m < 4; ++m) {
+    if (lat->dims[m] < 2 || lat->dims[m] % 2) return WCAMG_EINVAL;
+    if (lat->block[m] < 1 || lat->dims[m] % lat->block[m]) return WCAMG_EINVAL;
+    if (lat->bc[m] != 1 && lat->bc[m] != -1) return WCAMG_EINVAL;
+  }
+  if (!std::isfinite(lat->kappa) || !std::isfinite(lat->csw)) return WCAMG_EINVAL;
+  long long V = 1;
+  for (int m = 0; m < 4; ++m) V *= lat->dims[m];
+  if (V > (1LL << 28)) return WCAMG_EINVAL;
+  int vb = lat->block[0] * lat->block[1] * lat->block[2] * lat->block[3];
+  if (vb > 512) return WCAMG_EINVAL;  // one SAP workgroup (<= 512 threads) per domain
+  wcamg_ctx* c = new (std::nothrow) wcamg_ctx();
+  if (!c) return WCAMG_ENOMEM;
+  int rc = guard(c, [&] {
+    c->g = make_geo(lat->dims, lat->block, lat->bc);
+    c->kappa = lat->kappa;
+    c->csw = lat->csw;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (hip_stream) {
+      c->st = (hipStream_t)hip_stream;
+    } else {
+      // a blocking stream: ordered with work on the legacy default stream
+      HIPCHK(hipStreamCreateWithFlags(&c->st, hipStreamDefault));
+      c->own_stream = true;
+    }
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    c->lds_max = prop.sharedMemPerBlock;
+  });
+  if (rc != WCAMG_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return WCAMG_OK;
+}
+
+void wcamg_destroy(wcamg_ctx* c) {
+  if (!c) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  delete c;
+}
+
+const char* wcamg_last_error(const wcamg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int wcamg_sync(wcamg_ctx* c) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] { HIPCHK(hipStreamSynchronize(c->st)); });
+}
+
+int wcamg_load_gauge(wcamg_ctx* c, const void* U, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(U != nullptr, "null gauge pointer");
+    const Geo& g = c->g;
+    size_t bytes = (size_t)4 * g.V * 9 * sizeof(double2);
+    HostIO io(c);
+    const double2* Ud = (const double2*)io.in(U, bytes, where, "io_in");
+    c->U64.ensure((size_t)4 * 9 * g.V * sizeof(double2), false);
+    c->U16.ensure((size_t)4 * 9 * g.V * sizeof(half2_t), false);
+    c->Cl64.ensure((size_t)36 * g.V * sizeof(double2), false);
+    c->Cl16.ensure((size_t)36 * g.V * sizeof(half2_t), false);
+    launch_pack_gauge(g, Ud, (double2*)c->U64.p, (half2_t*)c->U16.p, c->st);
+    std::vector<double> sig = sigma_table();
+    launch_clover_build(g, (const double2*)c->U64.p, c->kappa, c->csw, sig.data(), (double2*)c->Cl64.p,
+                        (half2_t*)c->Cl16.p, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    c->have_gauge = true;
+    c->have_hier = false;
+    c->drop_graphs();
+  });
+}
+
+int wcamg_load_clover(wcamg_ctx* c, const void* F, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(F != nullptr, "null clover pointer");
+    require(c->have_gauge, "load the gauge field first", WCAMG_ESTATE);
+    const Geo& g = c->g;
+    HostIO io(c);
+    const double2* Fd = (const double2*)io.in(F, (size_t)g.V * 72 * sizeof(double2), where, "io_in");
+    launch_pack_clover(g, Fd, (double2*)c->Cl64.p, (half2_t*)c->Cl16.p, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    c->have_hier = false;
+    c->drop_graphs();
+  });
+}
+
+int wcamg_get_clover(wcamg_ctx* c, void* F, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(F != nullptr, "null pointer");
+    require(c->have_gauge, "no gauge field", WCAMG_ESTATE);
+    const Geo& g = c->g;
+    size_t bytes = (size_t)g.V * 72 * sizeof(double2);
+    HostIO io(c);
+    double2* Fd = (double2*)io.out(F, bytes, where, "io_out");
+    launch_unpack_clover(g, (const double2*)c->Cl64.p, Fd, c->st);
+    HIPCHK(hipGetLastError());
+    io.finish(F, Fd, bytes, where);
+  });
+}
+
+static int apply_op(wcamg_ctx* c, const void* in, void* out, int nrhs, int prec, int where, int op) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    check_nrhs(nrhs);
+    check_prec(prec);
+    require(in && out && in != out, "null or aliasing pointers");
+    require(c->have_gauge, "no gauge field", WCAMG_ESTATE);
+    const Geo& g = c->g;
+    size_t cbytes = (size_t)nrhs * g.V * 12 * sizeof(double2);
+    HostIO io(c);
+    const double2* ind = (const double2*)io.in(in, cbytes, where, "io_in");
+    double2* outd = (double2*)io.out(out, cbytes, where, "io_out");
+    int t = c->spin_t(prec);
+    void* a = c->W("ap_a", c->fsz(nrhs, prec));
+    void* b = c->W("ap_b", c->fsz(nrhs, prec));
+    launch_pack_spinor(g, ind, a, t, c->frs(), nrhs, c->st);
+    c->dslash(a, t, b, t, nrhs, op, prec);
+    launch_unpack_spinor(g, b, t, c->frs(), outd, nrhs, c->st);
+    HIPCHK(hipGetLastError());
+    io.finish(out, outd, cbytes, where);
+  });
+}
+
+int wcamg_apply_D(wcamg_ctx* c, const void* in, void* out, int nrhs, int prec, int where) {
+  return apply_op(c, in, out, nrhs, prec, where, OP_D);
+}
+int wcamg_apply_Dsap(wcamg_ctx* c, const void* in, void* out, int nrhs, int prec, int where) {
+  return apply_op(c, in, out, nrhs, prec, where, OP_DSAP);
+}
+
+int wcamg_sap(wcamg_ctx* c, const void* b, void* x, int nrhs, int sweeps, int mr_iters, int prec, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    check_nrhs(nrhs);
+    check_prec(prec);
+    require(b && x, "null pointer");
+    require(sweeps >= 0 && mr_iters >= 0, "negative iteration count");
+    require(c->have_gauge, "no gauge field", WCAMG_ESTATE);
+    const Geo& g = c->g;
+    require(g.NB[0] % 2 == 0 && g.NB[1] % 2 == 0 && g.NB[2] % 2 == 0 && g.NB[3] % 2 == 0,
+            "SAP needs an even number of blocks per direction");
+    size_t cbytes = (size_t)nrhs * g.V * 12 * sizeof(double2);
+    HostIO io(c);
+    const double2* bd = (const double2*)io.in(b, cbytes, where, "io_in");
+    double2* xd = (double2*)io.out(x, cbytes, where, "io_out");
+    int t = c->spin_t(prec);
+    void* bi = c->W("ap_a", c->fsz(nrhs, prec));
+    void* xi = c->W("ap_b", c->fsz(nrhs, prec));
+    launch_pack_spinor(g, bd, bi, t, c->frs(), nrhs, c->st);
+    c->sap(bi, xi, nullptr, nrhs, sweeps, mr_iters, prec);
+    launch_unpack_spinor(g, xi, t, c->frs(), xd, nrhs, c->st);
+    HIPCHK(hipGetLastError());
+    io.finish(x, xd, cbytes, where);
+  });
+}
+
+static void install_vectors(wcamg_ctx* c, const void* V, int where, const wcamg_setup_params* p) {
+  c->set_params(p);
+  const Geo& g = c->g;
+  size_t cbytes = (size_t)p->nv * g.V * 12 * sizeof(double2);
+  HostIO io(c);
+  const double2* Vd = (const double2*)io.in(V, cbytes, where, "io_in");
+  c->h.V.ensure((size_t)p->nv * 12 * g.V * ct_size(c->vec_t()), false);
+  launch_pack_spinor(g, Vd, c->h.V.p, c->vec_t(), c->frs(), p->nv, c->st);
+}
+
+int wcamg_set_test_vectors(wcamg_ctx* c, const void* V, const wcamg_setup_params* p, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(V && p, "null pointer");
+    require(c->have_gauge, "no gauge field", WCAMG_ESTATE);
+    c->have_hier = false;
+    install_vectors(c, V, where, p);
+    c->build_coarse();
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    c->have_hier = true;
+  });
+}
+
+int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    require(p && p->init_vectors, "setup needs init_vectors");
+    check_where(p->init_where);
+    require(c->have_gauge, "no gauge field", WCAMG_ESTATE);
+    c->have_hier = false;
+    c->set_params(p);
+    const Geo& g = c->g;
+    int nv = p->nv, prec = p->prec, t = c->spin_t(prec);
+    size_t cbytes = (size_t)nv * g.V * 12 * sizeof(double2);
+    HostIO io(c);
+    const double2* Vd = (const double2*)io.in(p->init_vectors, cbytes, p->init_where, "io_in");
+    void* Vw = c->W("su_w", c->fsz(nv, prec));
+    void* Vt = c->W("su_t", c->fsz(nv, prec));
+    launch_pack_spinor(g, Vd, Vw, t, c->frs(), nv, c->st);
+    for (int k = 0; k < p->n_init; ++k) {
+      c->sap(Vw, Vt, nullptr, nv, p->sap_sweeps, p->mr_iters, prec);
+      std::swap(Vw, Vt);
+    }
+    c->orthonormalize(Vw, nv, prec);
+    c->store_vectors(Vw, nv);
+    c->build_coarse();
+    for (int k = 0; k < p->n_adapt; ++k) {
+      c->vcycle(Vw, Vt, nv);
+      std::swap(Vw, Vt);
+      c->orthonormalize(Vw, nv, prec);
+      c->store_vectors(Vw, nv);
+      c->build_coarse();
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    c->have_hier = true;
+  });
+}
+
+int wcamg_get_test_vectors(wcamg_ctx* c, void* V, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(V, "null pointer");
+    require(c->have_hier, "no hierarchy", WCAMG_ESTATE);
+    size_t cbytes = (size_t)c->h.nv * c->g.V * 12 * sizeof(double2);
+    HostIO io(c);
+    double2* Vd = (double2*)io.out(V, cbytes, where, "io_out");
+    launch_unpack_spinor(c->g, c->h.V.p, c->vec_t(), c->frs(), Vd, c->h.nv, c->st);
+    HIPCHK(hipGetLastError());
+    io.finish(V, Vd, cbytes, where);
+  });
+}
+
+int wcamg_orthonormalize(wcamg_ctx* c, const void* in, void* out, int nv, int prec, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    check_prec(prec);
+    require(in && out, "null pointer");
+    require(nv >= 1 && nv <= 64, "nv must be in [1, 64]");
+    const Geo& g = c->g;
+    size_t cbytes = (size_t)nv * g.V * 12 * sizeof(double2);
+    HostIO io(c);
+    const double2* ind = (const double2*)io.in(in, cbytes, where, "io_in");
+    double2* outd = (double2*)io.out(out, cbytes, where, "io_out");
+    int t = c->spin_t(prec);
+    void* Vw = c->W("ap_a", c->fsz(nv, prec));
+    launch_pack_spinor(g, ind, Vw, t, c->frs(), nv, c->st);
+    c->orthonormalize(Vw, nv, prec);
+    launch_unpack_spinor(g, Vw, t, c->frs(), outd, nv, c->st);
+    HIPCHK(hipGetLastError());
+    io.finish(out, outd, cbytes, where);
+  });
+}
+
+int wcamg_restrict(wcamg_ctx* c, const void* in, void* out, int nrhs, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    check_nrhs(nrhs);
+    require(in && out, "null pointer");
+    require(c->have_hier, "no hierarchy", WCAMG_ESTATE);
+    const Geo& g = c->g;
+    size_t fb = (size_t)nrhs * g.V * 12 * sizeof(double2);
+    size_t cb = (size_t)nrhs * c->crs_n() * sizeof(double2);
+    HostIO io(c);
+    const double2* ind = (const double2*)io.in(in, fb, where, "io_in");
+    double2* outd = (double2*)io.out(out, cb, where, "io_out");
+    int t = c->spin_t(c->h.prec);
+    void* a = c->W("ap_a", c->fsz(nrhs, c->h.prec));
+    void* xc = c->W("ap_c", c->csz(nrhs));
+    launch_pack_spinor(g, ind, a, t, c->frs(), nrhs, c->st);
+    c->restrict_(a, xc, nrhs);
+    launch_convert(xc, c->crs_t(), outd, C128, (size_t)nrhs * c->crs_n(), c->st);
+    HIPCHK(hipGetLastError());
+    io.finish(out, outd, cb, where);
+  });
+}
+
+int wcamg_prolong(wcamg_ctx* c, const void* in, void* out, int nrhs, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    check_nrhs(nrhs);
+    require(in && out, "null pointer");
+    require(c->have_hier, "no hierarchy", WCAMG_ESTATE);
+    const Geo& g = c->g;
+    size_t fb = (size_t)nrhs * g.V * 12 * sizeof(double2);
+    size_t cb = (size_t)nrhs * c->crs_n() * sizeof(double2);
+    HostIO io(c);
+    const double2* ind = (const double2*)io.in(in, cb, where, "io_in");
+    double2* outd = (double2*)io.out(out, fb, where, "io_out");
+    int t = c->spin_t(c->h.prec);
+    void* xc = c->W("ap_c", c->csz(nrhs));
+    void* a = c->W("ap_a", c->fsz(nrhs, c->h.prec));
+    launch_convert(ind, C128, xc, c->crs_t(), (size_t)nrhs * c->crs_n(), c->st);
+    c->prolong_(xc, a, nrhs);
+    launch_unpack_spinor(g, a, t, c->frs(), outd, nrhs, c->st);
+    HIPCHK(hipGetLastError());
+    io.finish(out, outd, fb, where);
+  });
+}
+
+int wcamg_get_coarse_op(wcamg_ctx* c, void* Dc, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(Dc, "null pointer");
+    require(c->have_hier, "no hierarchy", WCAMG_ESTATE);
+    int N = c->h.N;
+    size_t nel = (size_t)c->h.cg.NC * 9 * N * N;
+    void* tmp = c->W("gc_tmp", nel * sizeof(double2));
+    launch_convert(c->h.Dc.p, c->crs_t(), tmp, C128, nel, c->st);
+    std::vector<double2> hst(nel), tr(nel);
+    HIPCHK(hipMemcpyAsync(hst.data(), tmp, nel * sizeof(double2), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    // internal [X][d][m][n] -> [X][d][n][m]
+    for (size_t xd = 0; xd < (size_t)c->h.cg.NC * 9; ++xd)
+      for (int m = 0; m < N; ++m)
+        for (int n = 0; n < N; ++n) tr[(xd * N + n) * N + m] = hst[(xd * N + m) * N + n];
+    HIPCHK(hipMemcpy(Dc, tr.data(), nel * sizeof(double2),
+                     where == WCAMG_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+  });
+}
+
+int wcamg_apply_coarse(wcamg_ctx* c, const void* in, void* out, int nrhs, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    check_nrhs(nrhs);
+    require(in && out && in != out, "null or aliasing pointers");
+    require(c->have_hier, "no hierarchy", WCAMG_ESTATE);
+    size_t cb = (size_t)nrhs * c->crs_n() * sizeof(double2);
+    HostIO io(c);
+    const double2* ind = (const double2*)io.in(in, cb, where, "io_in");
+    double2* outd = (double2*)io.out(out, cb, where, "io_out");
+    void* a = c->W("ap_c", c->csz(nrhs));
+    void* b = c->W("ap_c2", c->csz(nrhs));
+    launch_convert(ind, C128, a, c->crs_t(), (size_t)nrhs * c->crs_n(), c->st);
+    c->coarse_mv(a, b, nullptr, nrhs);
+    launch_convert(b, c->crs_t(), outd, C128, (size_t)nrhs * c->crs_n(), c->st);
+    HIPCHK(hipGetLastError());
+    io.finish(out, outd, cb, where);
+  });
+}
+
+int wcamg_coarse_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, int iters, double tol, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    check_nrhs(nrhs);
+    require(b && x && b != x, "null or aliasing pointers");
+    require(iters >= 0 && std::isfinite(tol) && tol >= 0, "invalid iteration count or tolerance");
+    require(c->have_hier, "no hierarchy", WCAMG_ESTATE);
+    size_t cb = (size_t)nrhs * c->crs_n() * sizeof(double2);
+    HostIO io(c);
+    const double2* bd = (const double2*)io.in(b, cb, where, "io_in");
+    double2* xd = (double2*)io.out(x, cb, where, "io_out");
+    void* a = c->W("ap_c", c->csz(nrhs));
+    void* y = c->W("ap_c2", c->csz(nrhs));
+    launch_convert(bd, C128, a, c->crs_t(), (size_t)nrhs * c->crs_n(), c->st);
+    c->coarse_solve(a, y, nrhs, iters, tol);
+    launch_convert(y, c->crs_t(), xd, C128, (size_t)nrhs * c->crs_n(), c->st);
+    HIPCHK(hipGetLastError());
+    io.finish(x, xd, cb, where);
+  });
+}
+
+int wcamg_vcycle(wcamg_ctx* c, const void* in, void* out, int nrhs, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    check_nrhs(nrhs);
+    require(in && out, "null pointer");
+    require(c->have_hier, "no hierarchy", WCAMG_ESTATE);
+    const Geo& g = c->g;
+    size_t fb = (size_t)nrhs * g.V * 12 * sizeof(double2);
+    HostIO io(c);
+    const double2* ind = (const double2*)io.in(in, fb, where, "io_in");
+    double2* outd = (double2*)io.out(out, fb, where, "io_out");
+    int prec = c->h.prec, t = c->spin_t(prec);
+    void* a = c->W("ap_a", c->fsz(nrhs, prec));
+    void* b = c->W("ap_b", c->fsz(nrhs, prec));
+    launch_pack_spinor(g, ind, a, t, c->frs(), nrhs, c->st);
+    c->vcycle(a, b, nrhs);
+    launch_unpack_spinor(g, b, t, c->frs(), outd, nrhs, c->st);
+    HIPCHK(hipGetLastError());
+    io.finish(out, outd, fb, where);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Outer solver: FGMRES(m), FP64, right preconditioning with the V-cycle
+// ---------------------------------------------------------------------------
+static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs, const wcamg_solve_params* p,
+                         int* iters, double* relres, int* conv, int* vcycles) {
+  const Geo& g = c->g;
+  const int m = p->restart;
+  const int prec = c->h.prec;
+  const size_t n = (size_t)12 * g.V;  // complex numbers per rhs
+  const size_t rs = n;
+  const size_t vs = (size_t)nrhs * n;  // stride between basis vectors
+  int zt = c->spin_t(prec);
+  double2* V = (double2*)c->W("fg_V", (size_t)(m + 1) * vs * sizeof(double2));
+  void* Z = c->W("fg_Z", (size_t)m * vs * ct_size(zt));
+  void* vin = prec == WCAMG_PREC_MIXED ? c->W("fg_vin", vs * sizeof(float2)) : nullptr;
+  double2* part = (double2*)c->W("fg_part", (size_t)nrhs * reduce_nwg(n) * 8 * sizeof(double2));
+  double2* h1 = (double2*)c->W("fg_h1", (size_t)(m + 1) * nrhs * sizeof(double2));
+  double2* h2 = (double2*)c->W("fg_h2", (size_t)(m + 1) * nrhs * sizeof(double2));
+  double* nrm = (double*)c->W("fg_nrm", (size_t)nrhs * sizeof(double));
+  double* scl = (double*)c->W("fg_scl", (size_t)nrhs * sizeof(double));
+  double2* ycoef = (double2*)c->W("fg_y", (size_t)m * nrhs * sizeof(double2));
+
+  auto sync_get = [&](void* host, const void* dev, size_t bytes) {
+    HIPCHK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+  };
+
+  std::vector<double> bn2(nrhs), hn(nrhs), hs(nrhs);
+  launch_norm2(bb, C128, n, rs, nrhs, part, nrm, c->st);
+  sync_get(bn2.data(), nrm, nrhs * sizeof(double));
+  for (int r = 0; r < nrhs; ++r) require(std::isfinite(bn2[r]), "non-finite right-hand side", WCAMG_ENUMERIC);
+  launch_zero(xx, vs * sizeof(double2), c->st);
+  std::vector<int> its(nrhs, 0), done(nrhs, 0);
+  for (int r = 0; r < nrhs; ++r)
+    if (bn2[r] == 0.0) done[r] = 1;
+
+  // graph per Z slot (mixed precision only: the V-cycle input is the fixed FP32 buffer)
+  auto run_vcycle = [&](int j) {
+    void* zj = (char*)Z + (size_t)j * vs * ct_size(zt);
+    const void* in = prec == WCAMG_PREC_MIXED ? vin : (const void*)(V + (size_t)j * vs);
+    if (!p->use_graph || c->timing) {
+      c->vcycle(in, zj, nrhs);
+      return;
+    }
+    auto key = std::make_pair(j, nrhs);
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end() || c->graph_prec != prec) {
+      if (c->graph_prec != prec) c->drop_graphs();
+      // allocate every workspace first with an uncaptured run
+      if (c->graphs.empty()) c->vcycle(in, zj, nrhs);
+      // capture on a library-owned stream (the caller's stream may be one
+      // that cannot be captured), replay on the caller's stream
+      if (!c->cap_st) HIPCHK(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+      HIPCHK(hipStreamSynchronize(c->st));
+      hipGraph_t gr;
+      hipStream_t user = c->st;
+      c->st = c->cap_st;
+      c->capturing = true;
+      try {
+        HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+        c->vcycle(in, zj, nrhs);
+        HIPCHK(hipStreamEndCapture(c->st, &gr));
+      } catch (...) {
+        hipGraph_t junk;
+        (void)hipStreamEndCapture(c->st, &junk);
+        c->st = user;
+        c->capturing = false;
+        throw;
+      }
+      c->st = user;
+      c->capturing = false;
+      hipGraphExec_t ex;
+      HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+      HIPCHK(hipGraphDestroy(gr));
+      c->graphs[key] = ex;
+      c->graph_prec = prec;
+      it = c->graphs.find(key);
+    }
+    HIPCHK(hipGraphLaunch(it->second, c->st));
+  };
+
+  std::vector<cd> H((size_t)(m + 1) * m * nrhs), gvec((size_t)(m + 1) * nrhs), cs((size_t)m * nrhs),
+      sn((size_t)m * nrhs);
+  std::vector<double2> hh1((size_t)(m + 1) * nrhs), hh2((size_t)(m + 1) * nrhs);
+  std::vector<int> kcols(nrhs);
+  std::vector<double2> yhost((size_t)m * nrhs);
+  auto Hc = [&](int i, int j, int r) -> cd& { return H[((size_t)i * m + j) * nrhs + r]; };
+
+  while (true) {
+    // r = b - D x (FP64), into V_0
+    c->dslash(xx, C128, V, C128, nrhs, OP_D, WCAMG_PREC_FP64, bb);
+    launch_norm2(V, C128, n, rs, nrhs, part, nrm, c->st);
+    std::vector<double> rn2(nrhs);
+    sync_get(rn2.data(), nrm, nrhs * sizeof(double));
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+      require(std::isfinite(rn2[r]), "non-finite residual", WCAMG_ENUMERIC);
+      relres[r] = bn2[r] > 0 ? std::sqrt(rn2[r] / bn2[r]) : 0.0;
+      if (!done[r] && (relres[r] <= p->tol || its[r] >= p->max_iters)) done[r] = 1;
+      all = all && done[r];
+    }
+    if (all) break;
+    std::vector<double> sc(nrhs);
+    std::vector<int> act(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+      act[r] = !done[r];
+      double beta = std::sqrt(rn2[r]);
+      sc[r] = act[r] && beta > 0 ? 1.0 / beta : 0.0;
+      for (int i = 0; i <= m; ++i) gvec[(size_t)i * nrhs + r] = 0;
+      gvec[r] = act[r] ? beta : 0.0;
+      kcols[r] = 0;
+    }
+    HIPCHK(hipMemcpyAsync(scl, sc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
+    launch_scale(V, scl, V, (float2*)vin, n, rs, nrhs, c->st);
+    std::vector<int> ext = act;  // still extending its Krylov space in this cycle
+    for (int j = 0; j < m; ++j) {
+      run_vcycle(j);
+      *vcycles += 1;
+      void* zj = (char*)Z + (size_t)j * vs * ct_size(zt);
+      double2* w = V + (size_t)(j + 1) * vs;
+      c->dslash(zj, zt, w, C128, nrhs, OP_D, WCAMG_PREC_FP64);
+      launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h1, c->st);
+      launch_multiaxpy(V, vs, j + 1, h1, w, n, rs, nrhs, part, nullptr, c->st);
+      launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h2, c->st);
+      launch_multiaxpy(V, vs, j + 1, h2, w, n, rs, nrhs, part, nrm, c->st);
+      HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
+                            c->st));
+      HIPCHK(hipMemcpyAsync(hh2.data(), h2, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
+                            c->st));
+      sync_get(hn.data(), nrm, nrhs * sizeof(double));
+      bool any = false;
+      for (int r = 0; r < nrhs; ++r) {
+        hs[r] = 0.0;
+        if (!ext[r]) continue;
+        for (int i = 0; i <= j; ++i) {
+          size_t o = (size_t)i * nrhs + r;
+          Hc(i, j, r) = cd(hh1[o].x + hh2[o].x, hh1[o].y + hh2[o].y);
+        }
+        double hnr = std::sqrt(std::max(hn[r], 0.0));
+        require(std::isfinite(hnr), "non-finite Arnoldi norm", WCAMG_ENUMERIC);
+        Hc(j + 1, j, r) = hnr;
+        hs[r] = hnr > 0 ? 1.0 / hnr : 0.0;
+        // apply previous rotations, then a new one (c real, s complex)
+        for (int i = 0; i < j; ++i) {
+          cd ci = cs[(size_t)i * nrhs + r], si = sn[(size_t)i * nrhs + r];
+          cd t = ci * Hc(i, j, r) + si * Hc(i + 1, j, r);
+          Hc(i + 1, j, r) = -std::conj(si) * Hc(i, j, r) + ci * Hc(i + 1, j, r);
+          Hc(i, j, r) = t;
+        }
+        cd a = Hc(j, j, r), bq = Hc(j + 1, j, r);
+        double den = std::sqrt(std::norm(a) + std::norm(bq));
+        cd cj_, sj;
+        if (den == 0) {
+          cj_ = 1;
+          sj = 0;
+        } else if (std::abs(a) == 0) {
+          cj_ = 0;
+          sj = std::conj(bq) / std::abs(bq);
+        } else {
+          cj_ = std::abs(a) / den;
+          sj = (a / std::abs(a)) * std::conj(bq) / den;
+        }
+        cs[(size_t)j * nrhs + r] = cj_;
+        sn[(size_t)j * nrhs + r] = sj;
+        Hc(j, j, r) = cj_ * Hc(j, j, r) + sj * Hc(j + 1, j, r);
+        Hc(j + 1, j, r) = 0;
+        cd gj = gvec[(size_t)j * nrhs + r];
+        gvec[(size_t)(j + 1) * nrhs + r] = -std::conj(sj) * gj;
+        gvec[(size_t)j * nrhs + r] = cj_ * gj;
+        its[r] += 1;
+        kcols[r] = j + 1;
+        double est = std::abs(gvec[(size_t)(j + 1) * nrhs + r]);
+        if (est <= p->tol * std::sqrt(bn2[r]) || hnr == 0 || its[r] >= p->max_iters) ext[r] = 0;
+        any = any || ext[r];
+      }
+      if (!any || j == m - 1) break;
+      HIPCHK(hipMemcpyAsync(scl, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
+      launch_scale(w, scl, w, (float2*)vin, n, rs, nrhs, c->st);
+    }
+    // y = H^{-1} g per rhs, x += Z y
+    int kmax = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      int k = kcols[r];
+      kmax = std::max(kmax, k);
+      std::vector<cd> y(k);
+      for (int i = k - 1; i >= 0; --i) {
+        cd s = gvec[(size_t)i * nrhs + r];
+        for (int l = i + 1; l < k; ++l) s -= Hc(i, l, r) * y[l];
+        y[i] = Hc(i, i, r) != cd(0) ? s / Hc(i, i, r) : cd(0);
+      }
+      for (int i = 0; i < m; ++i) {
+        cd v = i < k ? y[i] : cd(0);
+        yhost[(size_t)i * nrhs + r] = make_double2(v.real(), v.imag());
+      }
+    }
+    if (kmax > 0) {
+      HIPCHK(hipMemcpyAsync(ycoef, yhost.data(), (size_t)m * nrhs * sizeof(double2), hipMemcpyHostToDevice, c->st));
+      launch_update_x(xx, Z, zt, vs, kmax, ycoef, n, rs, nrhs, c->st);
+    }
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    iters[r] = its[r];
+    conv[r] = relres[r] <= p->tol;
+  }
+}
+
+int wcamg_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, const wcamg_solve_params* p,
+                wcamg_solve_info* info) {
+  if (!c) return WCAMG_EINVAL;
+  int status = WCAMG_OK;
+  int rc = guard(c, [&] {
+    require(b && x && p, "null pointer");
+    check_nrhs(nrhs);
+    require(p->restart >= 1 && p->restart <= 32, "restart must be in [1, 32]");
+    require(std::isfinite(p->tol) && p->tol >= 0, "invalid tol");
+    require(p->max_iters >= 0, "invalid max_iters");
+    require(c->have_hier, "no hierarchy: call wcamg_setup first", WCAMG_ESTATE);
+    auto t0 = std::chrono::steady_clock::now();
+    const Geo& g = c->g;
+    size_t n = (size_t)12 * g.V;
+    int chunk = p->rhs_chunk > 0 ? std::min(p->rhs_chunk, nrhs) : nrhs;
+    wcamg_solve_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+      int nr = std::min(chunk, nrhs - r0);
+      double2* bb = (double2*)c->W("sv_b", (size_t)nr * n * sizeof(double2));
+      double2* xx = (double2*)c->W("sv_x", (size_t)nr * n * sizeof(double2));
+      launch_pack_spinor(g, (const double2*)b + (size_t)r0 * n, bb, C128, n, nr, c->st);
+      fgmres_batch(c, bb, xx, nr, p, inf.iters + r0, inf.relres + r0, inf.converged + r0, &inf.vcycles);
+      launch_unpack_spinor(g, xx, C128, n, (double2*)x + (size_t)r0 * n, nr, c->st);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    inf.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int r = 0; r < nrhs; ++r)
+      if (!inf.converged[r]) status = WCAMG_NOT_CONVERGED;
+    if (info) *info = inf;
+  });
+  return rc != WCAMG_OK ? rc : status;
+}
+
+int wcamg_kernel_timing(wcamg_ctx* c, int enable) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    c->collect_timing();
+    c->timing = enable != 0;
+    if (enable) c->kstats.clear();
+  });
+}
+
+int wcamg_kernel_stats(wcamg_ctx* c, const char* name, double* total_ms, int* count, double* bytes,
+                       double* flops, double* units) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    require(name && total_ms && count, "null pointer");
+    c->collect_timing();
+    auto it = c->kstats.find(name);
+    KStat k = it == c->kstats.end() ? KStat() : it->second;
+    *total_ms = k.ms;
+    *count = k.count;
+    if (bytes) *bytes = k.bytes;
+    if (flops) *flops = k.flops;
+    if (units) *units = k.units;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,376 @@
+// Coarse-level kernels: restriction eq. (5), prolongation eq. (6), the
+// coarse 9-point block stencil of eq. (7) and the per-block Cholesky factor
+// used to orthonormalise the test vectors (<I|J> = delta_IJ, Sec. 3).
+//
+// Test vectors are stored like spinor fields, [nv][12][V] (blocked site order),
+// so that block X's part of one (vector, component) row is contiguous.
+// Coarse vectors are [rhs][X][N] with N = 2 nv and n = s*nv + i.  The coarse
+// operator is stored [X][d][m][n] (each 2nv x 2nv block column-major) with
+// d = 0 self, 1+mu forward, 5+mu backward neighbour.
+#include <stdexcept>
+
+#include "wc_kernels.h"
+
+namespace wc {
+
+// ---------------------------------------------------------------------------
+// Restriction.  One workgroup per block X.  Thread t owns the outputs
+// (s, i, rhs group of RB); tiles of TS sites of V and of the input are staged
+// in LDS (V in its storage type, the input in the accumulation type).
+// ---------------------------------------------------------------------------
+template <class RA, class TV, class TI, class TO, int RB>
+__global__ __launch_bounds__(256) void k_restrict(Geo g, int nv, int nrhs, int TS, const TV* __restrict__ V,
+                                                  const TI* __restrict__ in, size_t in_rs, TO* __restrict__ out,
+                                                  size_t out_rs, size_t out_xs) {
+  extern __shared__ __align__(16) char smem[];
+  TV* sv = (TV*)smem;                                                           // [TS][nv][12]
+  cplx<RA>* si = (cplx<RA>*)(smem + (((size_t)TS * nv * 12 * sizeof(TV) + 15) & ~(size_t)15));  // [TS][nrhs][12]
+  const int X = blockIdx.x;
+  const int t = threadIdx.x;
+  const int nrg = (nrhs + RB - 1) / RB;
+  const int nout = 2 * nv * nrg;
+  const int sc = t / (nv * nrg);
+  const int rem = t - sc * nv * nrg;
+  const int i = rem / nrg;
+  const int rg = rem - i * nrg;
+  const int V_ = g.V;
+  const size_t base = (size_t)X * g.Vb;
+  cplx<RA> acc[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q) acc[q] = {0, 0};
+
+  for (int s0 = 0; s0 < g.Vb; s0 += TS) {
+    for (int e = t; e < TS * nv * 12; e += 256) {
+      int st_ = e % TS;
+      int row = e / TS;  // i*12 + a
+      int ii = row / 12, a = row - ii * 12;
+      sv[(st_ * nv + ii) * 12 + a] = V[(size_t)row * V_ + base + s0 + st_];
+    }
+    for (int e = t; e < TS * nrhs * 12; e += 256) {
+      int st_ = e % TS;
+      int row = e / TS;  // r*12 + a
+      int r = row / 12, a = row - r * 12;
+      si[(st_ * nrhs + r) * 12 + a] = ld<RA>(in, r * in_rs + (size_t)a * V_ + base + s0 + st_);
+    }
+    __syncthreads();
+    if (t < nout) {
+      for (int st_ = 0; st_ < TS; ++st_) {
+#pragma unroll
+        for (int a6 = 0; a6 < 6; ++a6) {
+          int a = 6 * sc + a6;
+          cplx<RA> vv = ld<RA>(sv, (size_t)(st_ * nv + i) * 12 + a);
+#pragma unroll
+          for (int q = 0; q < RB; ++q) {
+            int r = rg * RB + q;
+            if (r < nrhs) cjmac(acc[q], vv, si[(st_ * nrhs + r) * 12 + a]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (t < nout) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      int r = rg * RB + q;
+      if (r < nrhs) st(out, r * out_rs + X * out_xs + sc * nv + i, acc[q]);
+    }
+  }
+}
+
+template <class RA, class TV, class TI, class TO, int RB>
+static void restrict_run(const Geo& g, int nv, int nrhs, const void* V, const void* in, size_t in_rs, void* out,
+                         size_t out_rs, size_t out_xs, hipStream_t st) {
+  int nrg = (nrhs + RB - 1) / RB;
+  if (2 * nv * nrg > 256) throw std::runtime_error("restrict: too many outputs per block");
+  // largest power-of-two tile (dividing Vb) with LDS <= 48 KiB
+  int TS = 1;
+  auto bytes = [&](int ts) {
+    return (((size_t)ts * nv * 12 * sizeof(TV) + 15) & ~(size_t)15) + (size_t)ts * nrhs * 12 * sizeof(cplx<RA>);
+  };
+  while (TS * 2 <= 32 && g.Vb % (TS * 2) == 0 && bytes(TS * 2) <= 48 * 1024) TS *= 2;
+  k_restrict<RA, TV, TI, TO, RB><<<g.nblk, 256, bytes(TS), st>>>(g, nv, nrhs, TS, (const TV*)V, (const TI*)in,
+                                                                in_rs, (TO*)out, out_rs, out_xs);
+}
+
+template <class RA, class TV, class TI, class TO>
+static void restrict_rb(const Geo& g, int nv, int nrhs, const void* V, const void* in, size_t in_rs, void* out,
+                        size_t out_rs, size_t out_xs, hipStream_t st) {
+  // choose the rhs group so that 2 nv ceil(nrhs/RB) <= 256
+  int need = (2 * nv * nrhs + 255) / 256;
+  if (need <= 1)
+    restrict_run<RA, TV, TI, TO, 1>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+  else if (need <= 2)
+    restrict_run<RA, TV, TI, TO, 2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+  else if (need <= 4)
+    restrict_run<RA, TV, TI, TO, 4>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+  else if (need <= 8)
+    restrict_run<RA, TV, TI, TO, 8>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+  else
+    restrict_run<RA, TV, TI, TO, 16>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+}
+
+void launch_restrict(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* in, int in_t,
+                     size_t in_rs, void* out, int out_t, size_t out_rs, size_t out_xs, int acc64,
+                     hipStream_t st) {
+  if (v_t == C128 && in_t == C128 && out_t == C128)
+    return restrict_rb<double, double2, double2, double2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+  if (v_t == C32H && in_t == C64 && out_t == C64 && !acc64)
+    return restrict_rb<float, half2_t, float2, float2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+  if (v_t == C32H && in_t == C32H && out_t == C64 && !acc64)
+    return restrict_rb<float, half2_t, half2_t, float2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+  if (v_t == C64 && in_t == C64 && out_t == C128 && acc64)
+    return restrict_rb<double, float2, float2, double2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+  throw std::runtime_error("launch_restrict: unsupported type combination");
+}
+
+// ---------------------------------------------------------------------------
+// Prolongation.  One thread per (colour, site) (a wavefront holds one colour
+// and consecutive sites); accumulators for the 4 spins x RB right-hand sides.
+// ---------------------------------------------------------------------------
+template <class R, class TV, class TC, class TO, int RB>
+__global__ __launch_bounds__(256) void k_prolong(Geo g, int nv, int nrhs, const TV* __restrict__ V,
+                                                 const TC* __restrict__ xc, size_t xc_rs, size_t xc_xs,
+                                                 TO* __restrict__ out, size_t out_rs, int accumulate) {
+  const int V_ = g.V;
+  int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= 3 * V_) return;
+  int col = t / V_;
+  int s = t - col * V_;
+  int X = s / g.Vb;
+  for (int r0 = 0; r0 < nrhs; r0 += RB) {
+    cplx<R> acc[4][RB];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int q = 0; q < RB; ++q) acc[sp][q] = {0, 0};
+    for (int i = 0; i < nv; ++i) {
+      cplx<R> v[4];
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) v[sp] = ld<R>(V, (size_t)(i * 12 + sp * 3 + col) * V_ + s);
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        int r = r0 + q;
+        if (r < nrhs) {
+          cplx<R> c0 = ld<R>(xc, r * xc_rs + X * xc_xs + i);
+          cplx<R> c1 = ld<R>(xc, r * xc_rs + X * xc_xs + nv + i);
+          cmac(acc[0][q], v[0], c0);
+          cmac(acc[1][q], v[1], c0);
+          cmac(acc[2][q], v[2], c1);
+          cmac(acc[3][q], v[3], c1);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      int r = r0 + q;
+      if (r < nrhs) {
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+          size_t o = r * out_rs + (size_t)(sp * 3 + col) * V_ + s;
+          cplx<R> val = acc[sp][q];
+          if (accumulate) val = val + ld<R>(out, o);
+          st(out, o, val);
+        }
+      }
+    }
+  }
+}
+
+template <class R, class TV, class TC, class TO>
+static void prolong_run(const Geo& g, int nv, int nrhs, const void* V, const void* xc, size_t xc_rs, size_t xc_xs,
+                        void* out, size_t out_rs, int accumulate, hipStream_t st) {
+  int nb = (3 * g.V + 255) / 256;
+  auto go = [&](auto rbtag) {
+    constexpr int RB = decltype(rbtag)::value;
+    k_prolong<R, TV, TC, TO, RB><<<nb, 256, 0, st>>>(g, nv, nrhs, (const TV*)V, (const TC*)xc, xc_rs, xc_xs,
+                                                     (TO*)out, out_rs, accumulate);
+  };
+  if (nrhs <= 1)
+    go(std::integral_constant<int, 1>());
+  else if (nrhs <= 4)
+    go(std::integral_constant<int, 4>());
+  else if (nrhs <= 8)
+    go(std::integral_constant<int, 8>());
+  else if (nrhs <= 12)
+    go(std::integral_constant<int, 12>());
+  else
+    go(std::integral_constant<int, 16>());
+}
+
+void launch_prolong(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* xc, int xc_t, size_t xc_rs,
+                    size_t xc_xs, void* out, int out_t, size_t out_rs, int accumulate, int compute32,
+                    hipStream_t st) {
+  if (!compute32 && v_t == C128 && xc_t == C128 && out_t == C128)
+    return prolong_run<double, double2, double2, double2>(g, nv, nrhs, V, xc, xc_rs, xc_xs, out, out_rs,
+                                                          accumulate, st);
+  if (compute32 && v_t == C32H && xc_t == C64 && out_t == C64)
+    return prolong_run<float, half2_t, float2, float2>(g, nv, nrhs, V, xc, xc_rs, xc_xs, out, out_rs, accumulate,
+                                                       st);
+  if (compute32 && v_t == C64 && xc_t == C64 && out_t == C64)
+    return prolong_run<float, float2, float2, float2>(g, nv, nrhs, V, xc, xc_rs, xc_xs, out, out_rs, accumulate,
+                                                      st);
+  if (!compute32 && v_t == C64 && xc_t == C128 && out_t == C64)
+    return prolong_run<double, float2, double2, float2>(g, nv, nrhs, V, xc, xc_rs, xc_xs, out, out_rs, accumulate,
+                                                        st);
+  throw std::runtime_error("launch_prolong: unsupported type combination");
+}
+
+// ---------------------------------------------------------------------------
+// Coarse 9-point block stencil.  One thread per (coarse site X, row n); the
+// NR right-hand sides of a launch row share each loaded matrix element.
+// ---------------------------------------------------------------------------
+template <class R, class TC, class TX, int NR>
+__global__ __launch_bounds__(256) void k_coarse_mv(CGeo cg, int N, const TC* __restrict__ Dc,
+                                                   const TX* __restrict__ x, TX* __restrict__ y,
+                                                   const TX* __restrict__ b, size_t rs, int nrhs) {
+  int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= cg.NC * N) return;
+  int X = t / N, n = t - X * N;
+  int r0 = blockIdx.y * NR;
+  int c[4];
+  {
+    int q = X;
+    for (int m = 0; m < 3; ++m) {
+      c[m] = q % cg.N[m];
+      q /= cg.N[m];
+    }
+    c[3] = q;
+  }
+  cplx<R> acc[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) acc[q] = {0, 0};
+  for (int d = 0; d < 9; ++d) {
+    int Y = X;
+    if (d > 0) {
+      int mu = (d - 1) & 3;
+      int step = d <= 4 ? 1 : -1;
+      int cc = c[mu] + step;
+      if (cc == cg.N[mu]) cc = 0;
+      if (cc < 0) cc = cg.N[mu] - 1;
+      Y = X + (cc - c[mu]) * cg.sN[mu];
+    }
+    const TC* B = Dc + ((size_t)(X * 9 + d) * N) * N + n;
+    const TX* xy = x + (size_t)Y * N;
+    for (int m = 0; m < N; ++m) {
+      cplx<R> bb = ld<R>(B, (size_t)m * N);
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (r0 + q < nrhs) cmac(acc[q], bb, ld<R>(xy, (r0 + q) * rs + m));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    int r = r0 + q;
+    if (r < nrhs) {
+      size_t o = r * rs + (size_t)X * N + n;
+      if (b)
+        st(y, o, ld<R>(b, o) - acc[q]);
+      else
+        st(y, o, acc[q]);
+    }
+  }
+}
+
+template <class R, class TC, class TX>
+static void coarse_mv_run(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
+                          size_t rs, hipStream_t st) {
+  int nb = (cg.NC * N + 255) / 256;
+  auto go = [&](auto tag) {
+    constexpr int NR = decltype(tag)::value;
+    dim3 grid(nb, (nrhs + NR - 1) / NR);
+    k_coarse_mv<R, TC, TX, NR><<<grid, 256, 0, st>>>(cg, N, (const TC*)Dc, (const TX*)x, (TX*)y, (const TX*)b, rs,
+                                                     nrhs);
+  };
+  if (nrhs == 1)
+    go(std::integral_constant<int, 1>());
+  else if (nrhs <= 4)
+    go(std::integral_constant<int, 4>());
+  else if (nrhs <= 8)
+    go(std::integral_constant<int, 8>());
+  else if (nrhs <= 12)
+    go(std::integral_constant<int, 12>());
+  else
+    go(std::integral_constant<int, 16>());
+}
+
+void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
+                      size_t rs, int prec32, hipStream_t st) {
+  if (prec32)
+    coarse_mv_run<float, float2, float2>(cg, N, Dc, x, y, b, nrhs, rs, st);
+  else
+    coarse_mv_run<double, double2, double2>(cg, N, Dc, x, y, b, nrhs, rs, st);
+}
+
+// ---------------------------------------------------------------------------
+// Block orthonormalisation coefficients.  One wavefront per (block X,
+// chirality s): G = L L^H by a right-looking Cholesky (lane = row), then
+// M = L^{-1} by forward substitution (lane = column), coef = M^H = L^{-H}
+// (upper triangular, positive real diagonal).
+// ---------------------------------------------------------------------------
+template <class TCo>
+__global__ __launch_bounds__(64) void k_cholesky_coef(int nblk, int nv, const double2* __restrict__ G, size_t g_rs,
+                                                      TCo* __restrict__ coef, size_t coef_rs, int* bad) {
+  extern __shared__ __align__(16) char smem[];
+  cplx<double>* A = (cplx<double>*)smem;  // [nv][nv] (row i, col k)
+  cplx<double>* M = A + nv * nv;          // [nv][nv]
+  const int X = blockIdx.x >> 1, s = blockIdx.x & 1;
+  const int lane = threadIdx.x;
+  const size_t xs = 2 * (size_t)nv;
+  // A[i][j] = <v_i, v_j> = G[j][X][s*nv+i]
+  for (int e = lane; e < nv * nv; e += 64) {
+    int i = e % nv, j = e / nv;
+    A[i * nv + j] = ld<double>(G, j * g_rs + X * xs + s * nv + i);
+  }
+  __syncthreads();
+  int fail = 0;
+  for (int j = 0; j < nv; ++j) {
+    double d = A[j * nv + j].x;
+    if (!(d > 0.0)) fail = 1;
+    double piv = sqrt(fmax(d, 1e-300));
+    __syncthreads();
+    if (lane == j) A[j * nv + j] = {piv, 0.0};
+    if (lane > j && lane < nv) A[lane * nv + j] = (1.0 / piv) * A[lane * nv + j];
+    __syncthreads();
+    if (lane > j && lane < nv) {
+      cplx<double> lij = A[lane * nv + j];
+      for (int k = j + 1; k <= lane; ++k) {
+        cplx<double> lkj = A[k * nv + j];
+        A[lane * nv + k] = A[lane * nv + k] - lij * cj(lkj);
+      }
+    }
+    __syncthreads();
+  }
+  // M = L^{-1}: column j = lane, rows i >= j
+  if (lane < nv) {
+    int j = lane;
+    for (int i = 0; i < nv; ++i) M[i * nv + j] = {0.0, 0.0};
+    M[j * nv + j] = {1.0 / A[j * nv + j].x, 0.0};
+    for (int i = j + 1; i < nv; ++i) {
+      cplx<double> acc = {0.0, 0.0};
+      for (int k = j; k < i; ++k) cmac(acc, A[i * nv + k], M[k * nv + j]);
+      M[i * nv + j] = (-1.0 / A[i * nv + i].x) * acc;
+    }
+  }
+  __syncthreads();
+  // coef[j][X][s*nv+i] = conj(M[j][i]) for i <= j
+  for (int e = lane; e < nv * nv; e += 64) {
+    int i = e % nv, j = e / nv;
+    cplx<double> val = {0.0, 0.0};
+    if (i <= j) val = cj(M[j * nv + i]);
+    st(coef, j * coef_rs + X * xs + s * nv + i, val);
+  }
+  if (fail && lane == 0) atomicOr(bad, 1);
+}
+
+void launch_cholesky_coef(int nblk, int nv, const double2* G, size_t g_rs, void* coef, int coef_t, size_t coef_rs,
+                          int* bad, hipStream_t st) {
+  if (nv > 64) throw std::runtime_error("cholesky: nv > 64");
+  size_t lds = 2 * (size_t)nv * nv * sizeof(double2);
+  if (coef_t == C128)
+    k_cholesky_coef<double2><<<2 * nblk, 64, lds, st>>>(nblk, nv, G, g_rs, (double2*)coef, coef_rs, bad);
+  else
+    k_cholesky_coef<float2><<<2 * nblk, 64, lds, st>>>(nblk, nv, G, g_rs, (float2*)coef, coef_rs, bad);
+}
+
+}  // namespace wc

@@ -1,0 +1,702 @@
+// Fine-level kernels: layout conversion, clover construction, the
+// Wilson-clover operator of eq. (1) (full, domain-decomposed D_SAP and single
+// domain-crossing hops) and the SAP smoother (Sec. 3) with minimal-residual
+// block solves.
+//
+// Internal layouts (blocked site order, see wc_common.h):
+//   spinor  [rhs][12 = spin*3 + colour][V]         complex (double2 / float2)
+//   links   [4 mu][9 = row*3 + col][V]            complex (double2 / half2)
+//   clover  [36 pairs][V]: per chirality b (pairs 18b..18b+17) the Hermitian
+//           6x6 block as 6 real diagonal entries (pairs 0..2) followed by the
+//           15 upper entries (i<j, row-major) as complex numbers.
+#include "wc_kernels.h"
+
+namespace wc {
+
+// ---------------------------------------------------------------------------
+// Spin projection in the chiral basis.  For a hop in direction mu the factor
+// (1 -/+ gamma_mu) has rank 2: with u = spins (0,1), l = spins (2,3),
+//   h_k = u_k + tau_k l_{pi(k)},   result = [h ; sigma_k h_{pi(k)}]
+// where pi swaps (mu = x, y) or keeps (mu = z, t) the two spins and tau,
+// sigma are units in {1, i, -1, -i}; the backward sign flips both.  Units are
+// coded 0: 1, 1: i, 2: -1, 3: -i.
+// ---------------------------------------------------------------------------
+template <int MU>
+struct Proj;
+template <>
+struct Proj<0> {
+  static constexpr int pi0 = 1, pi1 = 0, t0 = 1, t1 = 1, s0 = 3, s1 = 3;
+};
+template <>
+struct Proj<1> {
+  static constexpr int pi0 = 1, pi1 = 0, t0 = 0, t1 = 2, s0 = 2, s1 = 0;
+};
+template <>
+struct Proj<2> {
+  static constexpr int pi0 = 0, pi1 = 1, t0 = 1, t1 = 3, s0 = 3, s1 = 1;
+};
+template <>
+struct Proj<3> {
+  static constexpr int pi0 = 0, pi1 = 1, t0 = 0, t1 = 0, s0 = 0, s1 = 0;
+};
+
+// acc += coef * (1 -/+ gamma_mu) W psi with W = U (FWD) or U^dag (backward).
+template <int MU, bool FWD, class R>
+__device__ __forceinline__ void hop_accum(const cplx<R> (&psi)[12], const cplx<R> (&u)[9], R coef,
+                                          cplx<R> (&acc)[12]) {
+  using P = Proj<MU>;
+  constexpr int T0 = FWD ? P::t0 : (P::t0 ^ 2);
+  constexpr int T1 = FWD ? P::t1 : (P::t1 ^ 2);
+  constexpr int S0 = FWD ? P::s0 : (P::s0 ^ 2);
+  constexpr int S1 = FWD ? P::s1 : (P::s1 ^ 2);
+  cplx<R> h0[3], h1[3], g0[3], g1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    h0[c] = psi[c] + unit<T0>(psi[(2 + P::pi0) * 3 + c]);
+    h1[c] = psi[3 + c] + unit<T1>(psi[(2 + P::pi1) * 3 + c]);
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    cplx<R> a = {0, 0}, b = {0, 0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (FWD) {
+        cmac(a, u[r * 3 + c], h0[c]);
+        cmac(b, u[r * 3 + c], h1[c]);
+      } else {
+        cjmac(a, u[c * 3 + r], h0[c]);
+        cjmac(b, u[c * 3 + r], h1[c]);
+      }
+    }
+    g0[r] = coef * a;
+    g1[r] = coef * b;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    acc[c] = acc[c] + g0[c];
+    acc[3 + c] = acc[3 + c] + g1[c];
+    acc[6 + c] = acc[6 + c] + unit<S0>(P::pi0 == 0 ? g0[c] : g1[c]);
+    acc[9 + c] = acc[9 + c] + unit<S1>(P::pi1 == 0 ? g0[c] : g1[c]);
+  }
+}
+
+template <int MU, bool FWD, class R>
+__device__ __forceinline__ void hop_dispatch(int mu, const cplx<R> (&psi)[12], const cplx<R> (&u)[9], R coef,
+                                             cplx<R> (&acc)[12]);
+
+template <bool FWD, class R>
+__device__ __forceinline__ void hop_any(int mu, const cplx<R> (&psi)[12], const cplx<R> (&u)[9], R coef,
+                                        cplx<R> (&acc)[12]) {
+  switch (mu) {
+    case 0: hop_accum<0, FWD>(psi, u, coef, acc); break;
+    case 1: hop_accum<1, FWD>(psi, u, coef, acc); break;
+    case 2: hop_accum<2, FWD>(psi, u, coef, acc); break;
+    default: hop_accum<3, FWD>(psi, u, coef, acc); break;
+  }
+}
+
+template <class R, class TL>
+__device__ __forceinline__ void load_link(const TL* __restrict__ U, int V, int mu, int s, cplx<R> (&u)[9]) {
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = ld<R>(U, (size_t)(mu * 9 + e) * V + s);
+}
+
+template <class R, class TS>
+__device__ __forceinline__ void load_spinor(const TS* __restrict__ p, int V, int s, cplx<R> (&psi)[12]) {
+#pragma unroll
+  for (int a = 0; a < 12; ++a) psi[a] = ld<R>(p, (size_t)a * V + s);
+}
+
+// acc += F(x) psi for the packed clover field.
+template <class R, class TC>
+__device__ __forceinline__ void clover_accum(const TC* __restrict__ C, int V, int s, const cplx<R> (&psi)[12],
+                                             cplx<R> (&acc)[12]) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    cplx<R> p[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) p[k] = ld<R>(C, (size_t)(18 * b + k) * V + s);
+    R d[6] = {p[0].x, p[0].y, p[1].x, p[1].y, p[2].x, p[2].y};
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[6 * b + i] = acc[6 * b + i] + d[i] * psi[6 * b + i];
+    int k = 3;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+      for (int j = i + 1; j < 6; ++j) {
+        cmac(acc[6 * b + i], p[k], psi[6 * b + j]);
+        cjmac(acc[6 * b + j], p[k], psi[6 * b + i]);
+        ++k;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int blocked_index(const Geo& g, int cs) {
+  int x = cs % g.L[0];
+  int r = cs / g.L[0];
+  int y = r % g.L[1];
+  r /= g.L[1];
+  int z = r % g.L[2];
+  int t = r / g.L[2];
+  int c[4] = {x, y, z, t};
+  int blk = 0, loc = 0;
+#pragma unroll
+  for (int m = 3; m >= 0; --m) {
+    blk = blk * g.NB[m] + c[m] / g.B[m];
+    loc = loc * g.B[m] + c[m] % g.B[m];
+  }
+  return blk * g.Vb + loc;
+}
+
+template <class TO>
+__global__ __launch_bounds__(256) void k_pack_spinor(Geo g, const double2* __restrict__ canon, TO* __restrict__ out,
+                                                     size_t out_rs) {
+  int cs = blockIdx.x * 256 + threadIdx.x;
+  if (cs >= g.V) return;
+  int r = blockIdx.y;
+  int s = blocked_index(g, cs);
+  const double2* src = canon + ((size_t)r * g.V + cs) * 12;
+  TO* dst = out + r * out_rs;
+#pragma unroll
+  for (int a = 0; a < 12; ++a) st(dst, (size_t)a * g.V + s, ld<double>(src, a));
+}
+
+template <class TI>
+__global__ __launch_bounds__(256) void k_unpack_spinor(Geo g, const TI* __restrict__ in, size_t in_rs,
+                                                       double2* __restrict__ canon) {
+  int cs = blockIdx.x * 256 + threadIdx.x;
+  if (cs >= g.V) return;
+  int r = blockIdx.y;
+  int s = blocked_index(g, cs);
+  double2* dst = canon + ((size_t)r * g.V + cs) * 12;
+  const TI* src = in + r * in_rs;
+#pragma unroll
+  for (int a = 0; a < 12; ++a) st(dst, a, ld<double>(src, (size_t)a * g.V + s));
+}
+
+__global__ __launch_bounds__(256) void k_pack_gauge(Geo g, const double2* __restrict__ canon,
+                                                    double2* __restrict__ U64, half2_t* __restrict__ U16) {
+  int cs = blockIdx.x * 256 + threadIdx.x;
+  if (cs >= g.V) return;
+  int mu = blockIdx.y;
+  int s = blocked_index(g, cs);
+  const double2* src = canon + ((size_t)mu * g.V + cs) * 9;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    double2 v = src[e];
+    size_t o = (size_t)(mu * 9 + e) * g.V + s;
+    U64[o] = v;
+    st(U16, o, cplx<double>{v.x, v.y});
+  }
+}
+
+// pack a full Hermitian 6x6 chiral block pair (canonical [2][6][6]) into 36 pairs
+__device__ __forceinline__ void clover_pack_site(const double2 (&f)[2][6][6], int V, int s, double2* C64,
+                                                 half2_t* C16) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    double d[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) d[i] = f[b][i][i].x;
+    double2 pr[18];
+    pr[0] = make_double2(d[0], d[1]);
+    pr[1] = make_double2(d[2], d[3]);
+    pr[2] = make_double2(d[4], d[5]);
+    int k = 3;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 6; ++j) pr[k++] = f[b][i][j];
+#pragma unroll
+    for (int q = 0; q < 18; ++q) {
+      size_t o = (size_t)(18 * b + q) * V + s;
+      C64[o] = pr[q];
+      if (C16) st(C16, o, cplx<double>{pr[q].x, pr[q].y});
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pack_clover(Geo g, const double2* __restrict__ canon,
+                                                     double2* __restrict__ C64, half2_t* __restrict__ C16) {
+  int cs = blockIdx.x * 256 + threadIdx.x;
+  if (cs >= g.V) return;
+  int s = blocked_index(g, cs);
+  double2 f[2][6][6];
+  const double2* src = canon + (size_t)cs * 72;
+  for (int b = 0; b < 2; ++b)
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) f[b][i][j] = src[(b * 6 + i) * 6 + j];
+  clover_pack_site(f, g.V, s, C64, C16);
+}
+
+__global__ __launch_bounds__(256) void k_unpack_clover(Geo g, const double2* __restrict__ C64,
+                                                       double2* __restrict__ canon) {
+  int cs = blockIdx.x * 256 + threadIdx.x;
+  if (cs >= g.V) return;
+  int s = blocked_index(g, cs);
+  double2* dst = canon + (size_t)cs * 72;
+  for (int b = 0; b < 2; ++b) {
+    double2 pr[18];
+    for (int q = 0; q < 18; ++q) pr[q] = C64[(size_t)(18 * b + q) * g.V + s];
+    double d[6] = {pr[0].x, pr[0].y, pr[1].x, pr[1].y, pr[2].x, pr[2].y};
+    int k = 3;
+    for (int i = 0; i < 6; ++i) {
+      dst[(b * 6 + i) * 6 + i] = make_double2(d[i], 0.0);
+      for (int j = i + 1; j < 6; ++j) {
+        double2 u = pr[k++];
+        dst[(b * 6 + i) * 6 + j] = u;
+        dst[(b * 6 + j) * 6 + i] = make_double2(u.x, -u.y);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Clover construction: F(x) = i c_sw kappa sum_{mu<nu} sigma_{mu nu} (x) Fhat_{mu nu}(x),
+// Fhat = (Q - Q^dag) / 8, Q = sum of the four plaquette leaves at x in the
+// (mu, nu) plane (each traversed mu then nu).  FP64, once per gauge field.
+// ---------------------------------------------------------------------------
+struct Su3 {
+  cplx<double> a[9];
+};
+__device__ __forceinline__ Su3 su3_load(const double2* U, int V, int mu, int s) {
+  Su3 m;
+  for (int e = 0; e < 9; ++e) m.a[e] = ld<double>(U, (size_t)(mu * 9 + e) * V + s);
+  return m;
+}
+__device__ __forceinline__ Su3 su3_mul(const Su3& x, const Su3& y) {
+  Su3 z;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      cplx<double> acc = {0, 0};
+      for (int k = 0; k < 3; ++k) cmac(acc, x.a[i * 3 + k], y.a[k * 3 + j]);
+      z.a[i * 3 + j] = acc;
+    }
+  return z;
+}
+__device__ __forceinline__ Su3 su3_dag(const Su3& x) {
+  Su3 z;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) z.a[i * 3 + j] = cj(x.a[j * 3 + i]);
+  return z;
+}
+
+// site index of x + da*e_a + db*e_b (da, db in {-1, 0, 1}) on the periodic lattice
+__device__ __forceinline__ int shifted(const Geo& g, int s, int a, int da, int b, int db) {
+  int sign;
+  bool inb;
+  if (da != 0) {
+    SiteCoord c = decompose(g, s);
+    s = da > 0 ? neighbour<true>(g, s, c, a, sign, inb) : neighbour<false>(g, s, c, a, sign, inb);
+  }
+  if (db != 0) {
+    SiteCoord c = decompose(g, s);
+    s = db > 0 ? neighbour<true>(g, s, c, b, sign, inb) : neighbour<false>(g, s, c, b, sign, inb);
+  }
+  return s;
+}
+
+struct SigmaTab {
+  double v[6][2][2][2][2];  // [plane][chirality][row][col][re/im]
+};
+
+__global__ __launch_bounds__(128) void k_clover_build(Geo g, const double2* __restrict__ U, double kappa,
+                                                      double csw, SigmaTab sig, double2* __restrict__ C64,
+                                                      half2_t* __restrict__ C16) {
+  int s = blockIdx.x * 128 + threadIdx.x;
+  if (s >= g.V) return;
+  double2 f[2][6][6];
+  for (int b = 0; b < 2; ++b)
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) f[b][i][j] = make_double2(0.0, 0.0);
+  int plane = 0;
+  for (int mu = 0; mu < 4; ++mu) {
+    for (int nu = mu + 1; nu < 4; ++nu, ++plane) {
+      // leaf 1: U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+      Su3 l1 = su3_mul(su3_mul(su3_load(U, g.V, mu, s), su3_load(U, g.V, nu, shifted(g, s, mu, 1, nu, 0))),
+                       su3_mul(su3_dag(su3_load(U, g.V, mu, shifted(g, s, nu, 1, mu, 0))),
+                               su3_dag(su3_load(U, g.V, nu, s))));
+      // leaf 2: U_nu(x) U_mu(x-mu+nu)^dag U_nu(x-mu)^dag U_mu(x-mu)
+      int xm = shifted(g, s, mu, -1, nu, 0);
+      Su3 l2 = su3_mul(su3_mul(su3_load(U, g.V, nu, s), su3_dag(su3_load(U, g.V, mu, shifted(g, s, mu, -1, nu, 1)))),
+                       su3_mul(su3_dag(su3_load(U, g.V, nu, xm)), su3_load(U, g.V, mu, xm)));
+      // leaf 3: U_mu(x-mu)^dag U_nu(x-mu-nu)^dag U_mu(x-mu-nu) U_nu(x-nu)
+      int xmn = shifted(g, s, mu, -1, nu, -1);
+      int xn = shifted(g, s, nu, -1, mu, 0);
+      Su3 l3 = su3_mul(su3_mul(su3_dag(su3_load(U, g.V, mu, xm)), su3_dag(su3_load(U, g.V, nu, xmn))),
+                       su3_mul(su3_load(U, g.V, mu, xmn), su3_load(U, g.V, nu, xn)));
+      // leaf 4: U_nu(x-nu)^dag U_mu(x-nu) U_nu(x+mu-nu) U_mu(x)^dag
+      Su3 l4 = su3_mul(su3_mul(su3_dag(su3_load(U, g.V, nu, xn)), su3_load(U, g.V, mu, xn)),
+                       su3_mul(su3_load(U, g.V, nu, shifted(g, s, mu, 1, nu, -1)), su3_dag(su3_load(U, g.V, mu, s))));
+      Su3 fh;
+      for (int e = 0; e < 9; ++e) {
+        int i = e / 3, j = e % 3;
+        cplx<double> q = l1.a[e] + l2.a[e] + l3.a[e] + l4.a[e];
+        cplx<double> qt = l1.a[j * 3 + i] + l2.a[j * 3 + i] + l3.a[j * 3 + i] + l4.a[j * 3 + i];
+        fh.a[e] = 0.125 * (q - cj(qt));
+      }
+      // F_b[(s1,c1),(s2,c2)] += i csw kappa sigma_b[s1][s2] Fhat[c1][c2]
+      for (int b = 0; b < 2; ++b)
+        for (int s1 = 0; s1 < 2; ++s1)
+          for (int s2 = 0; s2 < 2; ++s2) {
+            cplx<double> sg = {sig.v[plane][b][s1][s2][0], sig.v[plane][b][s1][s2][1]};
+            cplx<double> fac = cplx<double>{0.0, csw * kappa} * sg;
+            for (int c1 = 0; c1 < 3; ++c1)
+              for (int c2 = 0; c2 < 3; ++c2) {
+                cplx<double> add = fac * fh.a[c1 * 3 + c2];
+                double2& e = f[b][s1 * 3 + c1][s2 * 3 + c2];
+                e.x += add.x;
+                e.y += add.y;
+              }
+          }
+    }
+  }
+  clover_pack_site(f, g.V, s, C64, C16);
+}
+
+// ---------------------------------------------------------------------------
+// Dslash family
+// ---------------------------------------------------------------------------
+template <class R, class TI, class TO, class TL, class TC, int OP>
+__global__ __launch_bounds__(256) void k_dslash(Geo g, const TI* __restrict__ in, size_t in_rs, TO* __restrict__ out,
+                                                size_t out_rs, const TO* __restrict__ b, const TL* __restrict__ U,
+                                                const TC* __restrict__ C, R kappa, int hopdir, int chir) {
+  int ntile = (g.V + 255) >> 8;
+  int tile = xcd_remap(blockIdx.x, ntile);
+  if (tile >= ntile) return;
+  int s = tile * 256 + threadIdx.x;
+  if (s >= g.V) return;
+  int r = blockIdx.y;
+  const TI* inr = in + r * in_rs;
+  const int V = g.V;
+  SiteCoord c = decompose(g, s);
+  cplx<R> acc[12];
+  cplx<R> psi[12];
+  cplx<R> u[9];
+  const int a0 = chir == 1 ? 6 : 0, a1 = chir == 0 ? 6 : 12;  // components kept by the chirality projection
+  if (OP != OP_HOP) {
+    load_spinor<R>(inr, V, s, psi);
+#pragma unroll
+    for (int a = 0; a < 12; ++a)
+      if (a < a0 || a >= a1) psi[a] = {0, 0};
+#pragma unroll
+    for (int a = 0; a < 12; ++a) acc[a] = psi[a];
+    clover_accum<R>(C, V, s, psi, acc);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 12; ++a) acc[a] = {0, 0};
+  }
+  // one hop at a time (not unrolled): keeps a single neighbour spinor live
+#pragma unroll 1
+  for (int dir = 0; dir < 8; ++dir) {
+    const int mu = dir & 3;
+    const bool fw = dir < 4;
+    if (OP == OP_HOP && dir != hopdir) continue;
+    int sign;
+    bool inb;
+    int nb = fw ? neighbour<true>(g, s, c, mu, sign, inb) : neighbour<false>(g, s, c, mu, sign, inb);
+    if (OP == OP_DSAP && !inb) continue;
+    if (OP == OP_HOP && inb) continue;
+    load_spinor<R>(inr, V, nb, psi);
+#pragma unroll
+    for (int a = 0; a < 12; ++a)
+      if (a < a0 || a >= a1) psi[a] = {0, 0};
+    R coef = -kappa * (R)sign;
+    if (fw) {
+      load_link<R>(U, V, mu, s, u);
+      hop_any<true>(mu, psi, u, coef, acc);
+    } else {
+      load_link<R>(U, V, mu, nb, u);
+      hop_any<false>(mu, psi, u, coef, acc);
+    }
+  }
+  TO* outr = out + r * out_rs;
+  if (b) {
+    const TO* br = b + r * out_rs;
+#pragma unroll
+    for (int a = 0; a < 12; ++a) st(outr, (size_t)a * V + s, ld<R>(br, (size_t)a * V + s) - acc[a]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 12; ++a) st(outr, (size_t)a * V + s, acc[a]);
+  }
+}
+
+template <class R, class TI, class TO, class TL, class TC>
+static void dslash_dispatch(const DslashArgs& a, hipStream_t st) {
+  int ntile = (a.g.V + 255) / 256;
+  dim3 grid(round8(ntile), a.nrhs);
+  const TI* in = (const TI*)a.in;
+  TO* out = (TO*)a.out;
+  const TO* b = (const TO*)a.b;
+  const TL* U = (const TL*)a.U;
+  const TC* C = (const TC*)a.C;
+  R kappa = (R)a.kappa;
+  switch (a.op) {
+    case OP_D:
+      k_dslash<R, TI, TO, TL, TC, OP_D><<<grid, 256, 0, st>>>(a.g, in, a.in_rs, out, a.out_rs, b, U, C, kappa, 0,
+                                                              a.chir);
+      break;
+    case OP_DSAP:
+      k_dslash<R, TI, TO, TL, TC, OP_DSAP><<<grid, 256, 0, st>>>(a.g, in, a.in_rs, out, a.out_rs, b, U, C, kappa,
+                                                                 0, a.chir);
+      break;
+    default:
+      k_dslash<R, TI, TO, TL, TC, OP_HOP><<<grid, 256, 0, st>>>(a.g, in, a.in_rs, out, a.out_rs, b, U, C, kappa,
+                                                                a.hopdir, a.chir);
+      break;
+  }
+}
+
+void launch_dslash(const DslashArgs& a, hipStream_t st) {
+  if (!a.fields16 && !a.compute32) {
+    if (a.in_t == C128 && a.out_t == C128)
+      return dslash_dispatch<double, double2, double2, double2, double2>(a, st);
+    if (a.in_t == C64 && a.out_t == C128)
+      return dslash_dispatch<double, float2, double2, double2, double2>(a, st);
+  }
+  if (a.fields16 && a.compute32) {
+    if (a.in_t == C64 && a.out_t == C64) return dslash_dispatch<float, float2, float2, half2_t, half2_t>(a, st);
+    if (a.in_t == C32H && a.out_t == C64) return dslash_dispatch<float, half2_t, float2, half2_t, half2_t>(a, st);
+  }
+  throw std::runtime_error("launch_dslash: unsupported precision combination");
+}
+
+// ---------------------------------------------------------------------------
+// SAP smoother.  One workgroup per domain of the active colour and right-hand
+// side, one thread per site.  Each half-sweep:
+//   1. r_X = (first visit ? b_X : r_X) + kappa * (domain-crossing hops of the
+//      other colour's latest correction delta)  -- i.e. r -= D delta restricted
+//      to this domain, which equals r = b - D x there (neighbouring domains all
+//      have the other colour);
+//   2. MR(mr) on D_SAP restricted to the domain from 0 (residual through LDS);
+//   3. x_X += correction, r_X = MR residual, delta_X = correction.
+// ---------------------------------------------------------------------------
+enum { SAP_FIRST = 1, SAP_DELTA = 2 };
+
+template <class R>
+__device__ __forceinline__ R wave_sum(R v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <class R, class TS, class TL, class TC>
+__global__ __launch_bounds__(512) void k_sap_half(Geo g, int colour, int flags, int mr, R kappa,
+                                                   const TS* __restrict__ b, TS* __restrict__ r, TS* __restrict__ x,
+                                                   TS* __restrict__ delta, const TS* __restrict__ xinit, size_t rs,
+                                                   const TL* __restrict__ U, const TC* __restrict__ C) {
+  extern __shared__ __align__(16) char smem[];
+  const int Vb = g.Vb;
+  cplx<R>* lds = (cplx<R>*)smem;  // [12][Vb]
+  R* red = (R*)(lds + 12 * Vb);   // [nwaves][3]
+  // the k-th domain of this colour
+  const int half = g.NB[0] >> 1;
+  int k = blockIdx.x;
+  int row = k / half, j = k - row * half;
+  int by = row % g.NB[1];
+  int rz = row / g.NB[1];
+  int bz = rz % g.NB[2];
+  int bt = rz / g.NB[2];
+  int bx = 2 * j + ((colour + by + bz + bt) & 1);
+  int blk = bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
+  const int l = threadIdx.x;
+  const bool act = l < Vb;
+  const int s = blk * Vb + (act ? l : 0);
+  const size_t off = blockIdx.y * rs;
+  const int V = g.V;
+  const int nw = (blockDim.x + 63) >> 6;
+  SiteCoord c = decompose(g, s);
+
+  cplx<R> rho[12], xm[12], p[12], psi[12], u[9];
+  if (act) {
+    load_spinor<R>((flags & SAP_FIRST) ? b + off : r + off, V, s, rho);
+    if (flags & SAP_DELTA) {
+#pragma unroll 1
+      for (int mu = 0; mu < 4; ++mu) {
+        int sign;
+        bool inb;
+        int nb = neighbour<true>(g, s, c, mu, sign, inb);
+        if (!inb) {
+          load_spinor<R>(delta + off, V, nb, psi);
+          load_link<R>(U, V, mu, s, u);
+          hop_any<true>(mu, psi, u, kappa * (R)sign, rho);
+        }
+        nb = neighbour<false>(g, s, c, mu, sign, inb);
+        if (!inb) {
+          load_spinor<R>(delta + off, V, nb, psi);
+          load_link<R>(U, V, mu, nb, u);
+          hop_any<false>(mu, psi, u, kappa * (R)sign, rho);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 12; ++a) xm[a] = {0, 0};
+
+  for (int it = 0; it < mr; ++it) {
+    if (act) {
+#pragma unroll
+      for (int a = 0; a < 12; ++a) lds[a * Vb + l] = rho[a];
+    }
+    __syncthreads();
+    R pr_re = 0, pr_im = 0, pp = 0;
+    if (act) {
+#pragma unroll
+      for (int a = 0; a < 12; ++a) p[a] = rho[a];
+      clover_accum<R>(C, V, s, rho, p);
+#pragma unroll 1
+      for (int mu = 0; mu < 4; ++mu) {
+        int sign;
+        bool inb;
+        int nb = neighbour<true>(g, s, c, mu, sign, inb);
+        if (inb) {
+          int nl = nb - blk * Vb;
+#pragma unroll
+          for (int a = 0; a < 12; ++a) psi[a] = lds[a * Vb + nl];
+          load_link<R>(U, V, mu, s, u);
+          hop_any<true>(mu, psi, u, -kappa * (R)sign, p);
+        }
+        nb = neighbour<false>(g, s, c, mu, sign, inb);
+        if (inb) {
+          int nl = nb - blk * Vb;
+#pragma unroll
+          for (int a = 0; a < 12; ++a) psi[a] = lds[a * Vb + nl];
+          load_link<R>(U, V, mu, nb, u);
+          hop_any<false>(mu, psi, u, -kappa * (R)sign, p);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 12; ++a) {
+        pr_re += p[a].x * rho[a].x + p[a].y * rho[a].y;
+        pr_im += p[a].x * rho[a].y - p[a].y * rho[a].x;
+        pp += p[a].x * p[a].x + p[a].y * p[a].y;
+      }
+    }
+    pr_re = wave_sum(pr_re);
+    pr_im = wave_sum(pr_im);
+    pp = wave_sum(pp);
+    if ((l & 63) == 0) {
+      red[(l >> 6) * 3 + 0] = pr_re;
+      red[(l >> 6) * 3 + 1] = pr_im;
+      red[(l >> 6) * 3 + 2] = pp;
+    }
+    __syncthreads();
+    R sre = 0, sim = 0, spp = 0;
+    for (int w = 0; w < nw; ++w) {
+      sre += red[w * 3 + 0];
+      sim += red[w * 3 + 1];
+      spp += red[w * 3 + 2];
+    }
+    cplx<R> alpha = {0, 0};
+    if (spp > 0) alpha = {sre / spp, sim / spp};
+    if (act) {
+#pragma unroll
+      for (int a = 0; a < 12; ++a) {
+        xm[a] = xm[a] + alpha * rho[a];
+        rho[a] = rho[a] - alpha * p[a];
+      }
+    }
+  }
+  if (act) {
+    TS* xr = x + off;
+    TS* rr = r + off;
+    TS* dr = delta + off;
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      size_t o = (size_t)a * V + s;
+      cplx<R> x0 = {0, 0};
+      if (!(flags & SAP_FIRST)) x0 = ld<R>(xr, o);
+      else if (xinit) x0 = ld<R>(xinit + off, o);
+      st(xr, o, x0 + xm[a]);
+      st(rr, o, rho[a]);
+      st(dr, o, xm[a]);
+    }
+  }
+}
+
+int sap_lds_bytes(const Geo& g, int mixed) {
+  int rsz = mixed ? 4 : 8;
+  int nthr = ((g.Vb + 63) / 64) * 64;
+  return 12 * g.Vb * 2 * rsz + (nthr / 64) * 3 * rsz;
+}
+
+template <class R, class TS, class TL, class TC>
+static void sap_run(const SapArgs& a, hipStream_t st) {
+  const Geo& g = a.g;
+  int nthr = ((g.Vb + 63) / 64) * 64;
+  int lds = sap_lds_bytes(g, sizeof(R) == 4);
+  dim3 grid(g.nblk / 2, a.nrhs);
+  auto kern = k_sap_half<R, TS, TL, TC>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  for (int sw = 0; sw < a.sweeps; ++sw) {
+    for (int col = 0; col < 2; ++col) {
+      int flags = (sw == 0 ? SAP_FIRST : 0) | ((sw > 0 || col == 1) ? SAP_DELTA : 0);
+      kern<<<grid, nthr, lds, st>>>(g, col, flags, a.mr, (R)a.kappa, (const TS*)a.b, (TS*)a.r, (TS*)a.x,
+                                    (TS*)a.delta, (const TS*)a.xinit, a.rs, (const TL*)a.U, (const TC*)a.C);
+    }
+  }
+}
+
+void launch_sap(const SapArgs& a, hipStream_t st) {
+  if (a.mixed)
+    sap_run<float, float2, half2_t, half2_t>(a, st);
+  else
+    sap_run<double, double2, double2, double2>(a, st);
+}
+
+// ---------------------------------------------------------------------------
+// launchers for layout / clover kernels
+// ---------------------------------------------------------------------------
+void launch_pack_spinor(const Geo& g, const double2* canon, void* out, int out_t, size_t out_rs, int nrhs,
+                        hipStream_t st) {
+  dim3 grid((g.V + 255) / 256, nrhs);
+  if (out_t == C128)
+    k_pack_spinor<double2><<<grid, 256, 0, st>>>(g, canon, (double2*)out, out_rs);
+  else if (out_t == C64)
+    k_pack_spinor<float2><<<grid, 256, 0, st>>>(g, canon, (float2*)out, out_rs);
+  else
+    k_pack_spinor<half2_t><<<grid, 256, 0, st>>>(g, canon, (half2_t*)out, out_rs);
+}
+
+void launch_unpack_spinor(const Geo& g, const void* in, int in_t, size_t in_rs, double2* canon, int nrhs,
+                          hipStream_t st) {
+  dim3 grid((g.V + 255) / 256, nrhs);
+  if (in_t == C128)
+    k_unpack_spinor<double2><<<grid, 256, 0, st>>>(g, (const double2*)in, in_rs, canon);
+  else if (in_t == C64)
+    k_unpack_spinor<float2><<<grid, 256, 0, st>>>(g, (const float2*)in, in_rs, canon);
+  else
+    k_unpack_spinor<half2_t><<<grid, 256, 0, st>>>(g, (const half2_t*)in, in_rs, canon);
+}
+
+void launch_pack_gauge(const Geo& g, const double2* canon, double2* U64, half2_t* U16, hipStream_t st) {
+  dim3 grid((g.V + 255) / 256, 4);
+  k_pack_gauge<<<grid, 256, 0, st>>>(g, canon, U64, U16);
+}
+
+void launch_clover_build(const Geo& g, const double2* U64, double kappa, double csw, const double* sigma,
+                         double2* C64, half2_t* C16, hipStream_t st) {
+  SigmaTab t;
+  const double* src = sigma;
+  double* dst = &t.v[0][0][0][0][0];
+  for (int i = 0; i < 6 * 2 * 2 * 2 * 2; ++i) dst[i] = src[i];
+  k_clover_build<<<(g.V + 127) / 128, 128, 0, st>>>(g, U64, kappa, csw, t, C64, C16);
+}
+
+void launch_pack_clover(const Geo& g, const double2* canon, double2* C64, half2_t* C16, hipStream_t st) {
+  k_pack_clover<<<(g.V + 255) / 256, 256, 0, st>>>(g, canon, C64, C16);
+}
+
+void launch_unpack_clover(const Geo& g, const double2* C64, double2* canon, hipStream_t st) {
+  k_unpack_clover<<<(g.V + 255) / 256, 256, 0, st>>>(g, C64, canon);
+}
+
+}  // namespace wc

@@ -1,0 +1,154 @@
+// Host-side launchers of the libwcamg kernels (internal interface between
+// the solver orchestration and the HIP kernels).
+#pragma once
+#include "wc_common.h"
+
+namespace wc {
+
+// Storage type of a complex field.
+enum CT { C128 = 0, C64 = 1, C32H = 2 };  // double2, float2, half2_t
+inline size_t ct_size(int t) { return t == C128 ? 16 : (t == C64 ? 8 : 4); }
+
+inline int round8(int n) { return ((n + 7) / 8) * 8; }
+
+// ---------------------------------------------------------------- layout
+// canonical complex128 [nrhs][V][4][3]  <->  internal [nrhs][12][V] (blocked site order)
+void launch_pack_spinor(const Geo& g, const double2* canon, void* out, int out_t, size_t out_rs, int nrhs,
+                        hipStream_t st);
+void launch_unpack_spinor(const Geo& g, const void* in, int in_t, size_t in_rs, double2* canon, int nrhs,
+                          hipStream_t st);
+// canonical complex128 [4][V][3][3] -> internal [4][9][V] in FP64 and FP16
+void launch_pack_gauge(const Geo& g, const double2* canon, double2* U64, half2_t* U16, hipStream_t st);
+// clover F(x) from the FP64 links: packed Hermitian chiral blocks [36 pairs][V] in FP64 and FP16.
+// sigma: the chiral 2x2 blocks of sigma_{mu nu}, [6 planes][2 chiralities][2][2] complex (re, im).
+void launch_clover_build(const Geo& g, const double2* U64, double kappa, double csw, const double* sigma,
+                         double2* C64, half2_t* C16, hipStream_t st);
+// canonical clover complex128 [V][2][6][6] <-> packed
+void launch_pack_clover(const Geo& g, const double2* canon, double2* C64, half2_t* C16, hipStream_t st);
+void launch_unpack_clover(const Geo& g, const double2* C64, double2* canon, hipStream_t st);
+
+// ---------------------------------------------------------------- Dslash family
+enum { OP_D = 0, OP_DSAP = 1, OP_HOP = 2 };
+struct DslashArgs {
+  Geo g;
+  int op = OP_D;      // OP_D: full eq.(1); OP_DSAP: in-block hops only; OP_HOP: one crossing hop
+  int hopdir = 0;     // OP_HOP: 0..3 = +mu, 4..7 = -mu
+  int chir = -1;      // >= 0: input projected on chirality chir (spins 2chir, 2chir+1)
+  int nrhs = 1;
+  const void* in = nullptr;
+  int in_t = C128;
+  size_t in_rs = 0;
+  void* out = nullptr;
+  int out_t = C128;
+  size_t out_rs = 0;
+  const void* b = nullptr;  // non-null: out = b - D in  (b has out's type and stride)
+  const void* U = nullptr;
+  const void* C = nullptr;
+  int fields16 = 0;  // 0: FP64 links/clover, 1: FP16
+  int compute32 = 0; // 0: FP64 arithmetic, 1: FP32
+  double kappa = 0;
+};
+void launch_dslash(const DslashArgs& a, hipStream_t st);
+
+// ---------------------------------------------------------------- SAP smoother
+struct SapArgs {
+  Geo g;
+  int nrhs = 1, sweeps = 4, mr = 6;
+  int mixed = 0;  // 0: FP64 everything; 1: FP32 spinors and arithmetic, FP16 links/clover
+  double kappa = 0;
+  const void* b = nullptr;      // source
+  void* x = nullptr;            // solution (output)
+  const void* xinit = nullptr;  // optional: x starts from xinit instead of 0 (x = xinit + SAP(b))
+  void* r = nullptr;            // workspace residual
+  void* delta = nullptr;        // workspace last block corrections
+  size_t rs = 0;                // per-rhs stride of all spinor fields
+  const void* U = nullptr;
+  const void* C = nullptr;
+};
+void launch_sap(const SapArgs& a, hipStream_t st);
+int sap_lds_bytes(const Geo& g, int mixed);
+
+// ---------------------------------------------------------------- coarse level
+struct CGeo {
+  int N[4];
+  int sN[4];
+  int NC;
+};
+inline CGeo make_cgeo(const int* n) {
+  CGeo c;
+  for (int m = 0; m < 4; ++m) c.N[m] = n[m];
+  c.sN[0] = 1;
+  for (int m = 1; m < 4; ++m) c.sN[m] = c.sN[m - 1] * n[m - 1];
+  c.NC = n[0] * n[1] * n[2] * n[3];
+  return c;
+}
+
+// restriction eq.(5): out[r][X][s*nv+i] = sum_{y in X, a in s} conj(V_i(y,a)) in_r(y,a)
+// V: [nv][12][V] of type v_t; in: [nrhs][12][V] (in_rs); out element (r, X, n) at
+// r*out_rs + X*out_xs + n.  acc64: accumulate in FP64.
+void launch_restrict(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* in, int in_t,
+                     size_t in_rs, void* out, int out_t, size_t out_rs, size_t out_xs, int acc64,
+                     hipStream_t st);
+// prolongation eq.(6): out_r(y,a) (+)= sum_i V_i(y,a) xc[r][X(y)][s(a)*nv+i]
+void launch_prolong(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* xc, int xc_t,
+                    size_t xc_rs, size_t xc_xs, void* out, int out_t, size_t out_rs, int accumulate,
+                    int compute32, hipStream_t st);
+// coarse 9-point stencil: y[r][X] = sum_d Dc[X][d] x[r][X+e_d]   (or y = b - Dc x)
+// Dc stored [X][d][m][n] (column-major blocks), vectors [nrhs][NC][N]
+void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
+                      size_t rs, int prec32, hipStream_t st);
+// Cholesky-based coefficients for block orthonormalisation: given the Gram
+// matrices G[j][X][s*nv+i] = <v_i, v_j>_{X,s} (FP64), write
+// coef[j][X][s*nv+i] = (L^{-H})_{ij} with G = L L^H.  Returns nonzero via
+// *bad (device int) when a pivot is not positive.
+void launch_cholesky_coef(int nblk, int nv, const double2* G, size_t g_rs, void* coef, int coef_t,
+                          size_t coef_rs, int* bad, hipStream_t st);
+
+// ---------------------------------------------------------------- vector kernels
+void launch_convert(const void* in, int in_t, void* out, int out_t, size_t n, hipStream_t st);
+void launch_zero(void* p, size_t bytes, hipStream_t st);
+
+// per-rhs reductions: for r < nrhs over vectors of n complex numbers (stride rs):
+// result[r*nd + k] for k < nd dots (a_k, b_k) -- see blas.hip for the sets
+int reduce_nwg(size_t n);
+// partial sums of up to 3 inner products <a_k, b_k> per rhs: part[r][wg][k] (complex)
+void launch_dots_partial(int nd, const void* const* a, const void* const* b, int t, size_t n, size_t rs,
+                         int nrhs, double2* part, hipStream_t st);
+
+// BiCGStab on device-resident per-rhs scalars (coarse solve)
+struct BicgScal {
+  double2 rho, rho_old, alpha, omega, beta;  // complex scalars
+  double bnorm2, rnorm2, tol2;
+  int active, iters, final_step, pad;
+};
+void launch_bicg_init(const void* b, void* x, void* r, void* rt, void* p, void* v, int t, size_t n, size_t rs,
+                      int nrhs, double tol, double2* part, BicgScal* sc, hipStream_t st);
+void launch_bicg_p(void* p, const void* r, const void* v, int t, size_t n, size_t rs, int nrhs,
+                   const BicgScal* sc, hipStream_t st);
+void launch_bicg_alpha(const void* rt, const void* v, int t, size_t n, size_t rs, int nrhs, double2* part,
+                       BicgScal* sc, hipStream_t st);
+void launch_bicg_s(void* s, const void* r, const void* v, int t, size_t n, size_t rs, int nrhs,
+                   const BicgScal* sc, hipStream_t st);
+void launch_bicg_omega(const void* tt, const void* s, int t, size_t n, size_t rs, int nrhs, double2* part,
+                       BicgScal* sc, double stab, hipStream_t st);
+void launch_bicg_xr(void* x, void* r, const void* p, const void* s, const void* tt, const void* rt, int t,
+                    size_t n, size_t rs, int nrhs, double2* part, BicgScal* sc, hipStream_t st);
+
+// FGMRES helpers (FP64 basis)
+// h[k][r] = <V_k[r], w[r]> for k < nk;  V_k at V + k*vs
+void launch_multidot(const double2* V, size_t vs, int nk, const double2* w, size_t n, size_t rs, int nrhs,
+                     double2* part, double2* h, hipStream_t st);
+// w[r] -= sum_k h[k][r] V_k[r]; then norm2[r] = ||w[r]||^2 (if norm2 != null)
+void launch_multiaxpy(const double2* V, size_t vs, int nk, const double2* h, double2* w, size_t n, size_t rs,
+                      int nrhs, double2* part, double* norm2, hipStream_t st);
+// out[r] = w[r] * scale[r]; optional FP32 copy out32
+void launch_scale(const double2* w, const double* scale, double2* out, float2* out32, size_t n, size_t rs, int nrhs,
+                  hipStream_t st);
+// x[r] += sum_k y[k][r] Z_k[r]   (Z of type z_t)
+void launch_update_x(double2* x, const void* Z, int z_t, size_t zs, int nk, const double2* y, size_t n, size_t rs,
+                     int nrhs, hipStream_t st);
+// norm2[r] = ||v[r]||^2
+void launch_norm2(const void* v, int t, size_t n, size_t rs, int nrhs, double2* part, double* norm2,
+                  hipStream_t st);
+
+}  // namespace wc

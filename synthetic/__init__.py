@@ -50,12 +50,36 @@ def _herm_traceless(draws):
     return h
 
 
-def _expi(h, eps):
-    """exp(i eps H) for Hermitian H via its eigen-decomposition (unitary, det 1
-    when H is traceless)."""
-    w, q = np.linalg.eigh(h)
-    ph = np.exp(1j * eps * w)
-    return np.einsum('...ik,...k,...jk->...ij', q, ph, np.conj(q))
+def _mm(a, b):
+    """Product of two batches of 3x3 matrices stored component-major [3][3][N]."""
+    return np.array([[a[i, 0] * b[0, j] + a[i, 1] * b[1, j] + a[i, 2] * b[2, j] for j in range(3)]
+                     for i in range(3)])
+
+
+def _expi(h, eps, chunk=1 << 16):
+    """exp(i eps H) for Hermitian 3x3 H by scaling and squaring: A = i eps H
+    is scaled by 2^-k (one k for the whole batch, so every matrix sees the
+    same operations) until its Frobenius norm is <= 1/2, exponentiated by its
+    Taylor series to order 16 (truncation below 1e-19), and squared k times.
+    Unitary to rounding; det 1 when H is traceless."""
+    shp = h.shape
+    hf = h.reshape(-1, 3, 3)
+    nrm = eps * np.sqrt((np.abs(hf) ** 2).sum(axis=(1, 2))).max() if hf.size else 0.0
+    k = max(0, int(np.ceil(np.log2(nrm / 0.5)))) if nrm > 0 else 0
+    out = np.empty_like(hf, dtype=np.complex128)
+    for c0 in range(0, hf.shape[0], chunk):
+        b = np.moveaxis((1j * eps / 2.0 ** k) * hf[c0:c0 + chunk], 0, -1)  # [3][3][n]
+        n = b.shape[-1]
+        eye = np.zeros((3, 3, n), np.complex128)
+        for i in range(3):
+            eye[i, i] = 1.0
+        e = eye.copy()
+        for m in range(16, 0, -1):
+            e = eye + _mm(b, e) / m
+        for _ in range(k):
+            e = _mm(e, e)
+        out[c0:c0 + chunk] = np.moveaxis(e, -1, 0)
+    return out.reshape(shp)
 
 
 def gauge_field(dims, eps, seed):

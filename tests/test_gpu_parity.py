@@ -1,0 +1,193 @@
+"""Parity of each HIP step with the CPU oracle on the same seeded inputs
+(FP64 to rounding; mixed precision within its FP16/FP32 bound)."""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import amg, dirac as od
+from gpu_common import Problem, rel, BC_AP
+
+pytestmark = pytest.mark.gpu
+
+# lattices: a 4^4 with 2^4 blocks (coarse extent 2), a ragged volume (V = 576
+# is not a multiple of the 256-site tile) and an 8^4 with 4^4 blocks
+GEOMS = [((4, 4, 4, 4), (2, 2, 2, 2)), ((6, 4, 4, 6), (2, 2, 2, 2)), ((8, 8, 8, 8), (4, 4, 4, 4))]
+
+
+@pytest.fixture(scope='module', params=GEOMS, ids=lambda g: 'x'.join(map(str, g[0])))
+def prob(request):
+    dims, block = request.param
+    return Problem(dims, block, eps=0.5, seed=1, kappa=0.124, csw=1.1)
+
+
+def test_clover_matches_oracle(prob):
+    F = prob.zeros((syn.volume(prob.dims), 2, 6, 6))
+    prob.ctx.get_clover(F)
+    want = prob.Fb.reshape(-1, 2, 6, 6)
+    assert rel(prob.N(F), want) < 1e-13
+
+
+@pytest.mark.parametrize('nrhs', [1, 3])
+def test_apply_D_fp64(prob, nrhs):
+    from paper_2111_05012_amd import PREC_FP64
+    psi = syn.gaussian_vectors(prob.dims, nrhs, 11)
+    out = prob.zeros(psi.shape)
+    prob.ctx.apply_D(prob.T(psi), out, nrhs, PREC_FP64)
+    want = prob.op.D(psi)
+    assert rel(prob.N(out), want) < 1e-13
+
+
+def test_apply_D_mixed(prob):
+    """FP16 links/clover, FP32 spinors: relative error of order the FP16 unit
+    roundoff 2^-11 times the few terms summed per component."""
+    from paper_2111_05012_amd import PREC_MIXED
+    psi = syn.gaussian_vectors(prob.dims, 2, 12)
+    out = prob.zeros(psi.shape)
+    prob.ctx.apply_D(prob.T(psi), out, 2, PREC_MIXED)
+    want = prob.op.D(psi)
+    assert rel(prob.N(out), want) < 2e-3
+
+
+def test_apply_Dsap_fp64(prob):
+    from paper_2111_05012_amd import PREC_FP64
+    psi = syn.gaussian_vectors(prob.dims, 2, 13)
+    out = prob.zeros(psi.shape)
+    prob.ctx.apply_Dsap(prob.T(psi), out, 2, PREC_FP64)
+    assert rel(prob.N(out), prob.op.Dsap(psi)) < 1e-13
+
+
+def test_sap_fp64(prob):
+    from paper_2111_05012_amd import PREC_FP64
+    if any((d // b) % 2 for d, b in zip(prob.dims, prob.block)):
+        pytest.skip('SAP colouring needs an even number of domains per direction')
+    b = syn.gaussian_vectors(prob.dims, 2, 14)
+    x = prob.zeros(b.shape)
+    prob.ctx.sap(prob.T(b), x, 2, 4, 6, PREC_FP64)
+    want = amg.sap(prob.op, b, 4, 6)
+    assert rel(prob.N(x), want) < 1e-11
+
+
+def test_sap_mixed(prob):
+    from paper_2111_05012_amd import PREC_MIXED
+    if any((d // b) % 2 for d, b in zip(prob.dims, prob.block)):
+        pytest.skip('SAP colouring needs an even number of domains per direction')
+    b = syn.gaussian_vectors(prob.dims, 1, 15)
+    x = prob.zeros(b.shape)
+    prob.ctx.sap(prob.T(b), x, 1, 4, 6, PREC_MIXED)
+    want = amg.sap(prob.op, b, 4, 6)
+    assert rel(prob.N(x), want) < 1e-2
+
+
+def test_orthonormalize_fp64(prob):
+    from paper_2111_05012_amd import PREC_FP64
+    V = syn.gaussian_vectors(prob.dims, 6, 16)
+    out = prob.zeros(V.shape)
+    prob.ctx.orthonormalize(prob.T(V), out, 6, PREC_FP64)
+    want = amg.block_orthonormalize(V, prob.dims, prob.block)
+    assert rel(prob.N(out), want) < 1e-12
+
+
+def _hier(prob, nv=4, prec=0, coarse_iters=20, coarse_tol=0.0, seed=17):
+    V = amg.block_orthonormalize(syn.gaussian_vectors(prob.dims, nv, seed), prob.dims, prob.block)
+    odd = any((d // b) % 2 for d, b in zip(prob.dims, prob.block))
+    p = prob.ctx.setup_params(nv, prec, coarse_iters=coarse_iters, coarse_tol=coarse_tol,
+                              sap_sweeps=0 if odd else 4)
+    prob.ctx.set_test_vectors(prob.T(V), p)
+    return V
+
+
+def test_restrict_prolong_fp64(prob):
+    V = _hier(prob)
+    x = syn.gaussian_vectors(prob.dims, 2, 18)
+    nX = amg.n_blocks(prob.dims, prob.block)
+    xc = prob.zeros((2, nX, 8))
+    prob.ctx.restrict(prob.T(x), xc, 2)
+    assert rel(prob.N(xc), amg.restrict(V, x, prob.dims, prob.block)) < 1e-13
+    yc = syn.gaussian_coarse(nX, 8, 2, 19)
+    y = prob.zeros(x.shape)
+    prob.ctx.prolong(prob.T(yc), y, 2)
+    assert rel(prob.N(y), amg.prolong(V, yc, prob.dims, prob.block)) < 1e-13
+
+
+def test_coarse_operator_fp64(prob):
+    V = _hier(prob)
+    nX = amg.n_blocks(prob.dims, prob.block)
+    Dc = prob.zeros((nX, 9, 8, 8))
+    prob.ctx.get_coarse_op(Dc)
+    want = amg.coarse_operator(prob.op, V)
+    assert rel(prob.N(Dc), want) < 1e-13
+    x = syn.gaussian_coarse(nX, 8, 3, 20)
+    y = prob.zeros(x.shape)
+    prob.ctx.apply_coarse(prob.T(x), y, 3)
+    cd = amg.coarse_dims(prob.dims, prob.block)
+    assert rel(prob.N(y), amg.coarse_apply(want, x, cd)) < 1e-13
+
+
+def test_coarse_solve_fp64(prob):
+    V = _hier(prob)
+    nX = amg.n_blocks(prob.dims, prob.block)
+    cd = amg.coarse_dims(prob.dims, prob.block)
+    Dc = amg.coarse_operator(prob.op, V)
+    b = syn.gaussian_coarse(nX, 8, 2, 21)
+    x = prob.zeros(b.shape)
+    prob.ctx.coarse_solve(prob.T(b), x, 2, 12, 0.0)
+    for k in range(2):
+        want, _ = amg.bicgstab(lambda z: amg.coarse_apply(Dc, z, cd), b[k], 12, 0.0)
+        assert rel(prob.N(x)[k], want) < 1e-10
+
+
+def test_vcycle_fp64(prob):
+    if any((d // b) % 2 for d, b in zip(prob.dims, prob.block)):
+        pytest.skip('SAP colouring needs an even number of domains per direction')
+    V = _hier(prob, coarse_iters=10, coarse_tol=0.0)
+    mg = amg.TwoLevel(prob.op, V, 4, 6, coarse_iters=10, coarse_tol=0.0)
+    v = syn.gaussian_vectors(prob.dims, 2, 22)
+    out = prob.zeros(v.shape)
+    prob.ctx.vcycle(prob.T(v), out, 2)
+    assert rel(prob.N(out), mg.vcycle(v)) < 1e-10
+
+
+def test_setup_and_solve_fp64_c1():
+    """Config-1 workload: setup from the same start vectors as the oracle,
+    then FGMRES(16) to 1e-10; residual recomputed by the oracle's D and the
+    solution checked against dense LU."""
+    from paper_2111_05012_amd import PREC_FP64
+    c = syn.CONFIGS['c1']
+    prob = Problem(c['dims'], c['block'], c['eps'], c['seed'], c['kappa'], c['csw'])
+    V0 = syn.gaussian_vectors(prob.dims, c['nv'], c['seed'])
+    p = prob.ctx.setup_params(c['nv'], PREC_FP64, n_init=3, n_adapt=3, coarse_iters=50, coarse_tol=0.1,
+                              init_vectors=prob.T(V0))
+    prob.ctx.setup(p)
+    mg = amg.setup(prob.op, V0, n_init=3, n_adapt=3, coarse_iters=50, coarse_tol=0.1)
+    Vg = prob.zeros(V0.shape)
+    prob.ctx.get_test_vectors(Vg)
+    # same setup, same inputs: equal up to rounding
+    assert rel(prob.N(Vg), mg.V) < 1e-8
+    b = syn.z2_source(prob.dims, c['seed'])
+    x = prob.zeros(b.shape)
+    rc, info = prob.ctx.solve(prob.T(b), x, 1, restart=16, tol=1e-10)
+    assert rc == 0 and info.converged[0]
+    xg = prob.N(x)
+    res = np.linalg.norm(b - prob.op.D(xg)) / np.linalg.norm(b)
+    assert res <= 1e-10
+    D = od.dense_D(prob.U, prob.Fb, prob.kappa, BC_AP, prob.dims)
+    xs = np.linalg.solve(D, b.reshape(-1))
+    assert np.linalg.norm(xg.reshape(-1) - xs) / np.linalg.norm(xs) <= 1e-9
+    _, its_oracle, _ = amg.fgmres(prob.op.D, mg.vcycle, b[0], tol=1e-10, restart=16)
+    assert abs(info.iters[0] - its_oracle) <= 1
+
+
+def test_setup_and_solve_mixed_c1():
+    from paper_2111_05012_amd import PREC_MIXED
+    c = syn.CONFIGS['c1']
+    prob = Problem(c['dims'], c['block'], c['eps'], c['seed'], c['kappa'], c['csw'])
+    V0 = syn.gaussian_vectors(prob.dims, c['nv'], c['seed'])
+    p = prob.ctx.setup_params(c['nv'], PREC_MIXED, init_vectors=prob.T(V0))
+    prob.ctx.setup(p)
+    b = syn.z2_source(prob.dims, c['seed'], nrhs=2)
+    x = prob.zeros(b.shape)
+    rc, info = prob.ctx.solve(prob.T(b), x, 2, restart=16, tol=1e-10)
+    assert rc == 0
+    xg = prob.N(x)
+    for k in range(2):
+        assert np.linalg.norm(b[k] - prob.op.D(xg[k])) / np.linalg.norm(b[k]) <= 1e-10
