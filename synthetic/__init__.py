@@ -147,3 +147,43 @@ CONFIGS = {
     'c3': dict(dims=(32, 32, 32, 64), eps=0.3, seed=1, kappa=0.1365, csw=1.1, block=(4, 4, 4, 8),
                nv=32, nrhs=12, source='point'),
 }
+
+
+# ----------------------------------------------------------------------------
+# Device-side generation for large lattices (same recipe, evaluated with torch
+# on the GPU; agrees with the NumPy arrays above to rounding).  Used where a
+# 32^3x64-sized input would take minutes on the host.
+# ----------------------------------------------------------------------------
+def gauge_field_torch(dims, eps, seed, device, chunk=1 << 22):
+    """gauge_field() with the same Gaussian draws and the same scaling and
+    squaring Taylor evaluation, carried out in complex128 on `device`."""
+    import torch
+    g = rng(seed, STREAM_GAUGE)
+    draws = g.standard_normal((4,) + shape_of(dims) + (9,))
+    h = _herm_traceless(draws).reshape(-1, 3, 3)
+    del draws
+    nrm = eps * np.sqrt((np.abs(h) ** 2).sum(axis=(1, 2))).max()
+    k = max(0, int(np.ceil(np.log2(nrm / 0.5)))) if nrm > 0 else 0
+    out = torch.empty((h.shape[0], 3, 3), dtype=torch.complex128, device=device)
+    eye = torch.eye(3, dtype=torch.complex128, device=device)
+    for c0 in range(0, h.shape[0], chunk):
+        b = torch.from_numpy(h[c0:c0 + chunk]).to(device) * (1j * eps / 2.0 ** k)
+        e = eye.expand_as(b).clone()
+        for m in range(16, 0, -1):
+            e = eye + torch.matmul(b, e) / m
+        for _ in range(k):
+            e = torch.matmul(e, e)
+        out[c0:c0 + chunk] = e
+    return out.reshape((4,) + shape_of(dims) + (3, 3))
+
+
+def gaussian_vectors_torch(dims, n, seed, device):
+    """n complex Gaussian fields drawn on the device from a seeded torch
+    generator (deterministic for a given seed and device type)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) * 1000003 + STREAM_SETUP)
+    shp = (n,) + shape_of(dims) + (4, 3)
+    re = torch.randn(shp, generator=gen, dtype=torch.float64, device=device)
+    im = torch.randn(shp, generator=gen, dtype=torch.float64, device=device)
+    return torch.complex(re, im)
