@@ -67,9 +67,9 @@ def run_step(ctx, U, b, x, V0, w, prec, rhs_chunk=0, nrhs=None):
     return t1 - t0, t2 - t1, info, rc
 
 
-CLASSES = ['dslash64', 'dslash32', 'sap', 'restrict', 'prolong', 'coarse_solve', 'coarse_mv', 'coarse_build',
+CLASSES = ['dslash64', 'dslash32', 'sap_half', 'restrict', 'prolong', 'coarse_solve', 'coarse_mv', 'coarse_build',
            'ortho']
-LEAVES = ['dslash64', 'dslash32', 'sap', 'restrict', 'prolong', 'coarse_mv', 'coarse_build', 'ortho']
+LEAVES = ['dslash64', 'dslash32', 'sap_half', 'restrict', 'prolong', 'coarse_mv', 'coarse_build', 'ortho']
 
 
 def kernel_profile(ctx, U, b, x, V0, w, prec):
@@ -150,9 +150,11 @@ def cpu_baseline(w, units, gpu_iters):
     cpu = time.process_time() - t_cpu0
     est = 0.0
     parts = {}
-    for cls, key in (('dslash64', 'dslash'), ('dslash32', 'dslash'), ('sap', 'sap'), ('restrict', 'restrict'),
+    for cls, key in (('dslash64', 'dslash'), ('dslash32', 'dslash'), ('restrict', 'restrict'),
                      ('prolong', 'prolong'), ('coarse_mv', 'coarse_mv')):
         parts[cls] = units[cls]['units'] * cost[key] * scale
+    # one oracle SAP application = 2 * sweeps half-sweeps
+    parts['sap_half'] = units['sap_half']['units'] * cost['sap'] / (2 * SETUP['sap_sweeps']) * scale
     parts['coarse_build'] = units['coarse_build']['units'] * cost['coarse_build'] * scale
     parts['ortho'] = units['ortho']['units'] * cost['ortho'] * scale
     est = sum(parts.values())
@@ -166,6 +168,33 @@ def cpu_baseline(w, units, gpu_iters):
                 parts={k: round(v, 2) for k, v in parts.items()})
 
 
+def profile_kernels(ctx, U, b, x, V0, w, dev):
+    """Kernel-only program for counter collection: a plain copy of 1 GiB
+    (reads 1 GiB, writes 1 GiB: the scale of FETCH_SIZE / WRITE_SIZE), then
+    the fine FP64 D (1 RHS), one SAP application and one V-cycle on all RHS."""
+    import torch
+    from paper_2111_05012_amd import PREC_FP64, PREC_MIXED
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ctx.load_gauge(U)
+    prm = ctx.setup_params(w['nv'], PREC_MIXED, init_vectors=V0, **SETUP)
+    ctx.setup(prm)
+    psi = b[:1].contiguous()
+    out = torch.empty_like(psi)
+    for _ in range(5):
+        ctx.apply_D(psi, out, 1, PREC_FP64)
+    xs = torch.empty_like(b)
+    for _ in range(2):
+        ctx.sap(b, xs, w['nrhs'], SETUP['sap_sweeps'], SETUP['mr_iters'], PREC_MIXED)
+    for _ in range(2):
+        ctx.vcycle(b, xs, w['nrhs'])
+    torch.cuda.synchronize()
+    log('profile-kernels done')
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -174,6 +203,8 @@ def main():
     ap.add_argument('--workload', default='c3', choices=sorted(WORKLOADS))
     ap.add_argument('--plain-rhs', type=int, default=1, help='RHS solved by the plain FP64 comparison (0: skip)')
     ap.add_argument('--no-cpu', action='store_true')
+    ap.add_argument('--profile-kernels', action='store_true',
+                    help='short kernel-only run for hardware counters: a 1 GiB copy, then D, SAP, V-cycle')
     args = ap.parse_args()
     if args.gpus != 1:
         print('bench.py: this build runs on one GPU only (--gpus %d requested); the multi-GPU path is a '
@@ -189,6 +220,9 @@ def main():
     U, b, V0 = make_inputs(w, dev)
     x = torch.zeros_like(b)
     ctx = Context(w['dims'], w['block'], (1, 1, 1, -1), w['kappa'], w['csw'])
+    if args.profile_kernels:
+        profile_kernels(ctx, U, b, x, V0, w, dev)
+        return
 
     for k in range(args.warmup):
         s, v, info, rc = run_step(ctx, U, b, x, V0, w, PREC_MIXED)

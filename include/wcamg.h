@@ -188,8 +188,8 @@ int wcamg_solve(wcamg_ctx* ctx, const void* b, void* x, int nrhs, const wcamg_so
 /* Per-kernel-class timing with HIP events on the context stream, for
  * roofline measurements: enable (1) / disable (0, also clears nothing).
  * When enabled, the work of each class is bracketed by events: "dslash64",
- * "dslash32" (one launch of the fine operator), "sap" (one smoother
- * application, all half-sweeps), "restrict", "prolong", "coarse_mv",
+ * "dslash32" (one launch of the fine operator), "sap_half" (one SAP
+ * half-sweep launch), "restrict", "prolong", "coarse_mv",
  * "coarse_solve" (one whole coarse BiCGStab), "coarse_build" (one coarse
  * operator construction), "ortho" (one block orthonormalisation).  Classes
  * nest ("coarse_mv" launches inside "coarse_solve" are recorded in both),

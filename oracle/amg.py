@@ -502,3 +502,207 @@ def flexible_bicgstab(apply_D, apply_M, b, tol=1e-10, max_iters=1000):
         p = r + beta * (p - omega * DMp)
     res = b - apply_D(x)
     return x, its, np.sqrt(np.vdot(res, res).real) / bn
+
+
+# ----------------------------------------------------------------------------
+# Multi-level extension (Sec. 3: "a multi-level implementation is
+# straightforward").  The level-1 operator is the 9-point block stencil Dc on
+# the coarse lattice with n = 2 N_v dof per site; its chirality is
+# Gamma = diag(1_{N_v}, -1_{N_v}) (the coarse image of gamma_5), so the two
+# halves of the dof play the role of the spins {0,1} / {2,3}.  Level-1 blocks
+# aggregate coarse sites exactly as level-0 blocks aggregate fine sites.
+# Reading (the paper gives no details): the level-1 smoother is `mr1_iters`
+# global minimal-residual iterations on Dc, the level-1 cycle is a V-cycle, and
+# the coarsest solve is the stabilised BiCGStab.
+# ----------------------------------------------------------------------------
+def coarse_to_blocks(v, cdims, block):
+    """[..., X (cdims), n] -> [..., X2, s, k]: per level-1 block X2 and half s
+    the (n/2)|X2| components, ordered (site in block t,z,y,x; dof in half)."""
+    lead = v.shape[:-2]
+    n = v.shape[-1]
+    nx, ny, nz, nt = coarse_dims(cdims, block)
+    bx, by, bz, bt = block
+    L = len(lead)
+    a = v.reshape(lead + (nt, bt, nz, bz, ny, by, nx, bx, 2, n // 2))
+    perm = list(range(L)) + [L + i for i in (0, 2, 4, 6, 8, 1, 3, 5, 7, 9)]
+    a = a.transpose(perm)
+    return a.reshape(lead + (nt * nz * ny * nx, 2, (n // 2) * bx * by * bz * bt))
+
+
+def coarse_from_blocks(b, cdims, block, n):
+    lead = b.shape[:-3]
+    nx, ny, nz, nt = coarse_dims(cdims, block)
+    bx, by, bz, bt = block
+    L = len(lead)
+    a = b.reshape(lead + (nt, nz, ny, nx, 2, bt, bz, by, bx, n // 2))
+    perm = list(range(L)) + [L + i for i in (0, 5, 1, 6, 2, 7, 3, 8, 4, 9)]
+    a = a.transpose(perm)
+    return a.reshape(lead + (int(np.prod(cdims)), n))
+
+
+class CoarseOp:
+    """The level-1 operator (block stencil Dc on cdims) with a level-1 block
+    decomposition; provides the same interface as FineOp on coarse vectors
+    [..., X, n]."""
+
+    def __init__(self, Dc, cdims, block):
+        self.Dc, self.cdims, self.block = Dc, tuple(cdims), tuple(block)
+        self.n = Dc.shape[-1]
+
+    def D(self, x):
+        return coarse_apply(self.Dc, x, self.cdims)
+
+    def _cross(self, mu, sign):
+        """per-site mask (1 where the hop sign*mu leaves the level-1 block)."""
+        L, b = self.cdims[mu], self.block[mu]
+        c = np.arange(L)
+        if L == b:
+            m = np.zeros(L)
+        elif sign > 0:
+            m = (c % b == b - 1).astype(float)
+        else:
+            m = (c % b == 0).astype(float)
+        shp = [1, 1, 1, 1]
+        shp[3 - mu] = L
+        full = np.broadcast_to(m.reshape(shp), tuple(self.cdims[::-1]))
+        return full.reshape(-1, 1)
+
+    def hop(self, x, mu, sign):
+        d = 1 + mu if sign > 0 else 5 + mu
+        return np.einsum('xnm,...xm->...xn', self.Dc[:, d], coarse_shift(x, self.cdims, mu, sign))
+
+    def Dsap(self, x):
+        y = np.einsum('xnm,...xm->...xn', self.Dc[:, 0], x)
+        for mu in range(4):
+            for sign in (+1, -1):
+                y = y + (1.0 - self._cross(mu, sign)) * self.hop(x, mu, sign)
+        return y
+
+    def hop_cross(self, x, mu, sign):
+        return self._cross(mu, sign) * self.hop(x, mu, sign)
+
+
+def coarse_chiral_project(x, s):
+    n = x.shape[-1]
+    out = np.zeros_like(x)
+    sl = slice(0, n // 2) if s == 0 else slice(n // 2, n)
+    out[..., sl] = x[..., sl]
+    return out
+
+
+def coarse_block_orthonormalize(W, cdims, block, passes=2):
+    """<I|J> = delta_IJ on level 1, per level-1 block and half, order k = 1..N."""
+    n = W.shape[-1]
+    Wb = coarse_to_blocks(W, cdims, block).copy()
+    for _ in range(passes):
+        for i in range(Wb.shape[0]):
+            for k in range(i):
+                c = np.sum(np.conj(Wb[k]) * Wb[i], axis=-1)
+                Wb[i] -= c[..., None] * Wb[k]
+            Wb[i] /= np.sqrt(np.sum(np.abs(Wb[i]) ** 2, axis=-1))[..., None]
+    return coarse_from_blocks(Wb, cdims, block, n)
+
+
+def coarse_restrict(W, x, cdims, block):
+    Wb = coarse_to_blocks(W, cdims, block)
+    xb = coarse_to_blocks(x, cdims, block)
+    xc = np.einsum('ixsk,...xsk->...xsi', np.conj(Wb), xb)
+    return xc.reshape(xc.shape[:-2] + (2 * W.shape[0],))
+
+
+def coarse_prolong(W, xc, cdims, block):
+    nv = W.shape[0]
+    Wb = coarse_to_blocks(W, cdims, block)
+    c = xc.reshape(xc.shape[:-1] + (2, nv))
+    return coarse_from_blocks(np.einsum('ixsk,...xsi->...xsk', Wb, c), cdims, block, W.shape[-1])
+
+
+def coarse_coarse_operator(cop, W):
+    """Dc2[X2, d, (s,k), (s',l)] = <X2,s,k| Dc |X2+e_d, s',l>, by the same
+    9-term construction as the level-0 coarse operator."""
+    nv = W.shape[0]
+    nX = n_blocks(cop.cdims, cop.block)
+    n = 2 * nv
+    Dc2 = np.zeros((nX, NDIR, n, n), np.complex128)
+    for sp in (0, 1):
+        Wp = coarse_chiral_project(W, sp)
+        cols = slice(sp * nv, (sp + 1) * nv)
+        Dc2[:, 0, :, cols] = np.transpose(coarse_restrict(W, cop.Dsap(Wp), cop.cdims, cop.block), (1, 2, 0))
+        for mu in range(4):
+            for sign, d in ((+1, 1 + mu), (-1, 5 + mu)):
+                Y = cop.hop_cross(Wp, mu, sign)
+                Dc2[:, d, :, cols] = np.transpose(coarse_restrict(W, Y, cop.cdims, cop.block), (1, 2, 0))
+    return Dc2
+
+
+def mr_global(apply_A, b, iters):
+    """Minimal-residual iterations on the whole vector from x = 0 (level-1
+    smoother): p = A r; alpha = <p,r>/<p,p>; x += alpha r; r -= alpha p."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    for _ in range(iters):
+        p = apply_A(r)
+        pp = np.vdot(p, p).real
+        if pp == 0:
+            break
+        alpha = np.vdot(p, r) / pp
+        x = x + alpha * r
+        r = r - alpha * p
+    return x
+
+
+class Level1:
+    """Level-1 (coarse) hierarchy: operator Dc on cdims, level-1 test vectors
+    W, level-2 operator Dc2, and the level-1 V-cycle used as the coarse solve
+    of level 0: x = P1 BiCGStab(Dc2, R1 b); x += MR(b - Dc x)."""
+
+    def __init__(self, cop, W, mr1_iters=4, coarse_iters=50, coarse_tol=0.1):
+        self.cop, self.W = cop, W
+        self.mr1_iters, self.coarse_iters, self.coarse_tol = mr1_iters, coarse_iters, coarse_tol
+        self.cdims2 = coarse_dims(cop.cdims, cop.block)
+        self.Dc2 = coarse_coarse_operator(cop, W)
+
+    def vcycle(self, b):
+        shp = b.shape
+        flat = b.reshape((-1,) + shp[-2:])
+        out = np.zeros_like(flat)
+        for k in range(flat.shape[0]):
+            bc2 = coarse_restrict(self.W, flat[k], self.cop.cdims, self.cop.block)
+            xc2, _ = bicgstab(lambda z: coarse_apply(self.Dc2, z, self.cdims2), bc2, self.coarse_iters,
+                              self.coarse_tol)
+            x = coarse_prolong(self.W, xc2, self.cop.cdims, self.cop.block)
+            r = flat[k] - self.cop.D(x)
+            out[k] = x + mr_global(self.cop.D, r, self.mr1_iters)
+        return out.reshape(shp)
+
+
+def setup_level1(cop, W0, n_init=3, n_adapt=3, mr1_iters=4, coarse_iters=50, coarse_tol=0.1, init_mr_iters=8):
+    """Setup of level 1, as (0-a)/(0-b) one level down: MR (init_mr_iters
+    iterations, as the approximate inverse) applied n_init times to the start
+    vectors, orthonormalisation per level-1 block and half, Dc2; then n_adapt
+    passes replacing every vector by the level-1 V-cycle applied to it."""
+    W = W0.copy()
+    for _ in range(n_init):
+        W = np.array([mr_global(cop.D, w, init_mr_iters) for w in W])
+    W = coarse_block_orthonormalize(W, cop.cdims, cop.block)
+    lv = Level1(cop, W, mr1_iters, coarse_iters, coarse_tol)
+    for _ in range(n_adapt):
+        W = lv.vcycle(W)
+        W = coarse_block_orthonormalize(W, cop.cdims, cop.block)
+        lv = Level1(cop, W, mr1_iters, coarse_iters, coarse_tol)
+    return lv
+
+
+class ThreeLevel(TwoLevel):
+    """Level 0 with a level-1 V-cycle as its coarse solve."""
+
+    def __init__(self, op, V, lv1, sap_sweeps=4, mr_iters=6):
+        self.op, self.V = op, V
+        self.sap_sweeps, self.mr_iters = sap_sweeps, mr_iters
+        self.cdims = coarse_dims(op.dims, op.block)
+        self.Dc = coarse_operator(op, V)
+        self.lv1 = lv1
+        self.coarse = 'level1'
+
+    def coarse_solve(self, bc):
+        return self.lv1.vcycle(bc)

@@ -296,13 +296,19 @@ struct wcamg_ctx {
         launch_zero(x, fsz(nrhs, prec), st);
       return;
     }
-    require((size_t)sap_lds_bytes(g, a.mixed) <= lds_max,
+    require((size_t)(a.mixed ? sap_dom_lds_bytes(g) : sap_lds_bytes(g, 0)) <= lds_max,
             "block volume too large for the SAP kernel's LDS at this precision");
+    // per half-sweep: links+clover of the active half of the sites; per rhs
+    // read r (or b), write r, delta and x (plus read x after the first visit)
     double sb = a.mixed ? 8 : 16, fld = a.mixed ? 4 * 9 * 4 + 36 * 4 : 4 * 9 * 16 + 36 * 16;
-    double by = (double)g.V * (sweeps * fld + nrhs * 12.0 * sb * (4.0 * sweeps + (sweeps - 1) + (xinit ? 1 : 0)));
-    double fl = (double)g.V * sweeps * nrhs * (mr * 2200.0 + 400.0);
-    Timed t(this, "sap", by, fl, nrhs);
-    launch_sap(a, st);
+    for (int sw = 0; sw < sweeps; ++sw)
+      for (int col = 0; col < 2; ++col) {
+        double xr = (sw > 0 || xinit) ? 1 : 0;
+        double by = 0.5 * g.V * (fld + nrhs * 12.0 * sb * (4.0 + xr));
+        double fl = 0.5 * g.V * nrhs * (mr * 2200.0 + 400.0);
+        Timed t(this, "sap_half", by, fl, nrhs);
+        launch_sap_half(a, sw, col, st);
+      }
   }
 
   // ---- coarse level
@@ -402,23 +408,13 @@ struct wcamg_ctx {
     require(hb == 0, "orthonormalisation: test vectors linearly dependent on a block", WCAMG_ENUMERIC);
   }
 
-  // coarse operator eq.(7) from the stored vectors
+  // coarse operator eq.(7) from the stored vectors (fused kernel)
   void build_coarse() {
-    int prec = h.prec;
     int nv = h.nv, N = h.N;
     Timed tb(this, "coarse_build", 0, 0, 1, true);
-    void* Y = W("bc_Y", fsz(nv, prec));
     h.Dc.ensure((size_t)h.cg.NC * 9 * N * N * ct_size(crs_t()), capturing);
-    for (int sp = 0; sp < 2; ++sp) {
-      for (int d = 0; d < 9; ++d) {
-        int op = d == 0 ? OP_DSAP : OP_HOP;
-        int hopdir = d == 0 ? 0 : (d <= 4 ? d - 1 : d - 1);
-        dslash(h.V.p, vec_t(), Y, spin_t(prec), nv, op, prec, nullptr, hopdir, sp);
-        char* base = (char*)h.Dc.p + ((size_t)d * N * N + (size_t)sp * nv * N) * ct_size(crs_t());
-        launch_restrict(g, nv, nv, h.V.p, vec_t(), Y, spin_t(prec), frs(), base, crs_t(), N, (size_t)9 * N * N, 0,
-                        st);
-      }
-    }
+    bool mixed = h.prec == WCAMG_PREC_MIXED;
+    launch_coarse_build(g, nv, kappa, h.V.p, mixed ? U16.p : U64.p, mixed ? Cl16.p : Cl64.p, h.Dc.p, mixed, st);
   }
 
   void store_vectors(const void* Vw, int nv) {

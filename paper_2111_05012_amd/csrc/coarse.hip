@@ -9,6 +9,7 @@
 // d = 0 self, 1+mu forward, 5+mu backward neighbour.
 #include <stdexcept>
 
+#include "wc_dirac.h"
 #include "wc_kernels.h"
 
 namespace wc {
@@ -300,6 +301,182 @@ void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void
     coarse_mv_run<float, float2, float2>(cg, N, Dc, x, y, b, nrhs, rs, st);
   else
     coarse_mv_run<double, double2, double2>(cg, N, Dc, x, y, b, nrhs, rs, st);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse operator eq. (7), fused.  One workgroup per (block X, direction d,
+// source chirality sp).  For d = 0 the in-block operator D_SAP is applied to
+// P_sp v_j on every site of X; for d = 1..8 only the sites of X whose hop in
+// direction d leaves the block contribute, through that single hop.  For a
+// tile of sites the results g_j(y) and the vectors v_i(y) are staged in LDS
+// and contracted:
+//   Dc[X][d][(sp, j)][(s, i)] = sum_y sum_{a in s} conj(v_i(y)_a) g_j(y)_a.
+// Thread t owns row n = t % N and the columns of group t / N.
+// ---------------------------------------------------------------------------
+template <class R, class TV, class TL, class TC, class TO, int CPG>
+__global__ __launch_bounds__(256) void k_coarse_build(Geo g, int nv, R kappa, const TV* __restrict__ V,
+                                                      const TL* __restrict__ U, const TC* __restrict__ C,
+                                                      TO* __restrict__ Dc) {
+  extern __shared__ __align__(16) char smem[];
+  const int N = 2 * nv;
+  const int T = 256 / nv;  // sites per tile
+  cplx<R>* sv = (cplx<R>*)smem;     // [T][nv][12]
+  cplx<R>* sgv = sv + T * nv * 12;  // [T][nv][12]
+  const int X = blockIdx.x, d = blockIdx.y, sp = blockIdx.z;
+  const int t = threadIdx.x;
+  const int Vg = g.V;
+  const int mu = (d - 1) & 3;
+  const bool fwd = d <= 4;
+  int nsites;
+  if (d == 0)
+    nsites = g.Vb;
+  else
+    nsites = g.NB[mu] == 1 ? 0 : g.Vb / g.B[mu];
+  const int a0 = sp * 6;  // chirality sp keeps components a0 .. a0+5
+  const int n = t % N, cg = t / N;
+  const int si = n / nv, ii = n - si * nv;
+  cplx<R> acc[CPG];
+#pragma unroll
+  for (int q = 0; q < CPG; ++q) acc[q] = {0, 0};
+
+  for (int tile0 = 0; tile0 < nsites; tile0 += T) {
+    if (t < T * nv) {
+      const int st_ = t / nv, j = t - st_ * nv;
+      const int f = tile0 + st_;
+      cplx<R> vj[12], gj[12];
+      if (f < nsites) {
+        int loc;
+        if (d == 0) {
+          loc = f;
+        } else {
+          int q = f, cc[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            if (m == mu) continue;
+            cc[m] = q % g.B[m];
+            q /= g.B[m];
+          }
+          cc[mu] = fwd ? g.B[mu] - 1 : 0;
+          loc = cc[0] * g.sB[0] + cc[1] * g.sB[1] + cc[2] * g.sB[2] + cc[3] * g.sB[3];
+        }
+        const int sx = X * g.Vb + loc;
+        const TV* vjp = V + (size_t)j * 12 * Vg;
+        load_spinor<R>(vjp, Vg, sx, vj);
+        SiteCoord c = decompose(g, sx);
+        cplx<R> psi[12], u[9];
+#pragma unroll
+        for (int a = 0; a < 12; ++a) gj[a] = {0, 0};
+        if (d == 0) {
+#pragma unroll
+          for (int a = 0; a < 12; ++a) psi[a] = (a >= a0 && a < a0 + 6) ? vj[a] : cplx<R>{0, 0};
+#pragma unroll
+          for (int a = 0; a < 12; ++a) gj[a] = psi[a];
+          clover_accum<R>(C, Vg, sx, psi, gj);
+#pragma unroll 1
+          for (int dir = 0; dir < 8; ++dir) {
+            const int m = dir & 3;
+            int sign;
+            bool inb;
+            int nb = dir < 4 ? neighbour<true>(g, sx, c, m, sign, inb) : neighbour<false>(g, sx, c, m, sign, inb);
+            if (!inb) continue;
+            load_spinor<R>(vjp, Vg, nb, psi);
+#pragma unroll
+            for (int a = 0; a < 12; ++a)
+              if (a < a0 || a >= a0 + 6) psi[a] = {0, 0};
+            if (dir < 4) {
+              load_link<R>(U, Vg, m, sx, u);
+              hop_any<true>(m, psi, u, -kappa * (R)sign, gj);
+            } else {
+              load_link<R>(U, Vg, m, nb, u);
+              hop_any<false>(m, psi, u, -kappa * (R)sign, gj);
+            }
+          }
+        } else {
+          int sign;
+          bool inb;
+          int nb = fwd ? neighbour<true>(g, sx, c, mu, sign, inb) : neighbour<false>(g, sx, c, mu, sign, inb);
+          load_spinor<R>(vjp, Vg, nb, psi);
+#pragma unroll
+          for (int a = 0; a < 12; ++a)
+            if (a < a0 || a >= a0 + 6) psi[a] = {0, 0};
+          if (fwd) {
+            load_link<R>(U, Vg, mu, sx, u);
+            hop_any<true>(mu, psi, u, -kappa * (R)sign, gj);
+          } else {
+            load_link<R>(U, Vg, mu, nb, u);
+            hop_any<false>(mu, psi, u, -kappa * (R)sign, gj);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 12; ++a) vj[a] = gj[a] = {0, 0};
+      }
+#pragma unroll
+      for (int a = 0; a < 12; ++a) {
+        sv[(st_ * nv + j) * 12 + a] = vj[a];
+        sgv[(st_ * nv + j) * 12 + a] = gj[a];
+      }
+    }
+    __syncthreads();
+    if (cg * CPG < nv) {
+      const int tl = min(T, nsites - tile0);
+      for (int st_ = 0; st_ < tl; ++st_) {
+#pragma unroll
+        for (int a6 = 0; a6 < 6; ++a6) {
+          const int a = 6 * si + a6;
+          cplx<R> vv = sv[(st_ * nv + ii) * 12 + a];
+#pragma unroll
+          for (int q = 0; q < CPG; ++q) {
+            const int j = cg * CPG + q;
+            if (j < nv) cjmac(acc[q], vv, sgv[(st_ * nv + j) * 12 + a]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (t < N * (256 / N)) {
+#pragma unroll
+    for (int q = 0; q < CPG; ++q) {
+      const int j = cg * CPG + q;
+      if (cg * CPG < nv && j < nv) st(Dc, ((size_t)(X * 9 + d) * N + (sp * nv + j)) * N + n, acc[q]);
+    }
+  }
+}
+
+template <class R, class TV, class TL, class TC, class TO>
+static void coarse_build_run(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C,
+                             void* Dc, hipStream_t st) {
+  const int N = 2 * nv;
+  if (N > 256 || 256 % nv) throw std::runtime_error("coarse build: nv must divide 256 and 2 nv <= 256");
+  const int ncg = 256 / N;
+  const int cpg = (nv + ncg - 1) / ncg;
+  const size_t lds = 2 * (size_t)(256 / nv) * nv * 12 * sizeof(cplx<R>);
+  dim3 grid(g.nblk, 9, 2);
+  auto go = [&](auto tag) {
+    constexpr int CPG = decltype(tag)::value;
+    auto kern = k_coarse_build<R, TV, TL, TC, TO, CPG>;
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    kern<<<grid, 256, lds, st>>>(g, nv, (R)kappa, (const TV*)V, (const TL*)U, (const TC*)C, (TO*)Dc);
+  };
+  if (cpg <= 1)
+    go(std::integral_constant<int, 1>());
+  else if (cpg <= 2)
+    go(std::integral_constant<int, 2>());
+  else if (cpg <= 4)
+    go(std::integral_constant<int, 4>());
+  else if (cpg <= 8)
+    go(std::integral_constant<int, 8>());
+  else
+    go(std::integral_constant<int, 16>());
+}
+
+void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C, void* Dc,
+                         int mixed, hipStream_t st) {
+  if (mixed)
+    coarse_build_run<float, half2_t, half2_t, half2_t, float2>(g, nv, kappa, V, U, C, Dc, st);
+  else
+    coarse_build_run<double, double2, double2, double2, double2>(g, nv, kappa, V, U, C, Dc, st);
 }
 
 // ---------------------------------------------------------------------------

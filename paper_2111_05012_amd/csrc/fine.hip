@@ -9,128 +9,10 @@
 //   clover  [36 pairs][V]: per chirality b (pairs 18b..18b+17) the Hermitian
 //           6x6 block as 6 real diagonal entries (pairs 0..2) followed by the
 //           15 upper entries (i<j, row-major) as complex numbers.
+#include "wc_dirac.h"
 #include "wc_kernels.h"
 
 namespace wc {
-
-// ---------------------------------------------------------------------------
-// Spin projection in the chiral basis.  For a hop in direction mu the factor
-// (1 -/+ gamma_mu) has rank 2: with u = spins (0,1), l = spins (2,3),
-//   h_k = u_k + tau_k l_{pi(k)},   result = [h ; sigma_k h_{pi(k)}]
-// where pi swaps (mu = x, y) or keeps (mu = z, t) the two spins and tau,
-// sigma are units in {1, i, -1, -i}; the backward sign flips both.  Units are
-// coded 0: 1, 1: i, 2: -1, 3: -i.
-// ---------------------------------------------------------------------------
-template <int MU>
-struct Proj;
-template <>
-struct Proj<0> {
-  static constexpr int pi0 = 1, pi1 = 0, t0 = 1, t1 = 1, s0 = 3, s1 = 3;
-};
-template <>
-struct Proj<1> {
-  static constexpr int pi0 = 1, pi1 = 0, t0 = 0, t1 = 2, s0 = 2, s1 = 0;
-};
-template <>
-struct Proj<2> {
-  static constexpr int pi0 = 0, pi1 = 1, t0 = 1, t1 = 3, s0 = 3, s1 = 1;
-};
-template <>
-struct Proj<3> {
-  static constexpr int pi0 = 0, pi1 = 1, t0 = 0, t1 = 0, s0 = 0, s1 = 0;
-};
-
-// acc += coef * (1 -/+ gamma_mu) W psi with W = U (FWD) or U^dag (backward).
-template <int MU, bool FWD, class R>
-__device__ __forceinline__ void hop_accum(const cplx<R> (&psi)[12], const cplx<R> (&u)[9], R coef,
-                                          cplx<R> (&acc)[12]) {
-  using P = Proj<MU>;
-  constexpr int T0 = FWD ? P::t0 : (P::t0 ^ 2);
-  constexpr int T1 = FWD ? P::t1 : (P::t1 ^ 2);
-  constexpr int S0 = FWD ? P::s0 : (P::s0 ^ 2);
-  constexpr int S1 = FWD ? P::s1 : (P::s1 ^ 2);
-  cplx<R> h0[3], h1[3], g0[3], g1[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    h0[c] = psi[c] + unit<T0>(psi[(2 + P::pi0) * 3 + c]);
-    h1[c] = psi[3 + c] + unit<T1>(psi[(2 + P::pi1) * 3 + c]);
-  }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    cplx<R> a = {0, 0}, b = {0, 0};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (FWD) {
-        cmac(a, u[r * 3 + c], h0[c]);
-        cmac(b, u[r * 3 + c], h1[c]);
-      } else {
-        cjmac(a, u[c * 3 + r], h0[c]);
-        cjmac(b, u[c * 3 + r], h1[c]);
-      }
-    }
-    g0[r] = coef * a;
-    g1[r] = coef * b;
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    acc[c] = acc[c] + g0[c];
-    acc[3 + c] = acc[3 + c] + g1[c];
-    acc[6 + c] = acc[6 + c] + unit<S0>(P::pi0 == 0 ? g0[c] : g1[c]);
-    acc[9 + c] = acc[9 + c] + unit<S1>(P::pi1 == 0 ? g0[c] : g1[c]);
-  }
-}
-
-template <int MU, bool FWD, class R>
-__device__ __forceinline__ void hop_dispatch(int mu, const cplx<R> (&psi)[12], const cplx<R> (&u)[9], R coef,
-                                             cplx<R> (&acc)[12]);
-
-template <bool FWD, class R>
-__device__ __forceinline__ void hop_any(int mu, const cplx<R> (&psi)[12], const cplx<R> (&u)[9], R coef,
-                                        cplx<R> (&acc)[12]) {
-  switch (mu) {
-    case 0: hop_accum<0, FWD>(psi, u, coef, acc); break;
-    case 1: hop_accum<1, FWD>(psi, u, coef, acc); break;
-    case 2: hop_accum<2, FWD>(psi, u, coef, acc); break;
-    default: hop_accum<3, FWD>(psi, u, coef, acc); break;
-  }
-}
-
-template <class R, class TL>
-__device__ __forceinline__ void load_link(const TL* __restrict__ U, int V, int mu, int s, cplx<R> (&u)[9]) {
-#pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = ld<R>(U, (size_t)(mu * 9 + e) * V + s);
-}
-
-template <class R, class TS>
-__device__ __forceinline__ void load_spinor(const TS* __restrict__ p, int V, int s, cplx<R> (&psi)[12]) {
-#pragma unroll
-  for (int a = 0; a < 12; ++a) psi[a] = ld<R>(p, (size_t)a * V + s);
-}
-
-// acc += F(x) psi for the packed clover field.
-template <class R, class TC>
-__device__ __forceinline__ void clover_accum(const TC* __restrict__ C, int V, int s, const cplx<R> (&psi)[12],
-                                             cplx<R> (&acc)[12]) {
-#pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    cplx<R> p[18];
-#pragma unroll
-    for (int k = 0; k < 18; ++k) p[k] = ld<R>(C, (size_t)(18 * b + k) * V + s);
-    R d[6] = {p[0].x, p[0].y, p[1].x, p[1].y, p[2].x, p[2].y};
-#pragma unroll
-    for (int i = 0; i < 6; ++i) acc[6 * b + i] = acc[6 * b + i] + d[i] * psi[6 * b + i];
-    int k = 3;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-#pragma unroll
-      for (int j = i + 1; j < 6; ++j) {
-        cmac(acc[6 * b + i], p[k], psi[6 * b + j]);
-        cjmac(acc[6 * b + j], p[k], psi[6 * b + i]);
-        ++k;
-      }
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Layout conversion
@@ -475,7 +357,7 @@ void launch_dslash(const DslashArgs& a, hipStream_t st) {
 //   2. MR(mr) on D_SAP restricted to the domain from 0 (residual through LDS);
 //   3. x_X += correction, r_X = MR residual, delta_X = correction.
 // ---------------------------------------------------------------------------
-enum { SAP_FIRST = 1, SAP_DELTA = 2 };
+enum { SAP_FIRST = 1, SAP_DELTA = 2, SAP_NO_R = 4, SAP_NO_DELTA = 8 };
 
 template <class R>
 __device__ __forceinline__ R wave_sum(R v) {
@@ -618,6 +500,181 @@ __global__ __launch_bounds__(512) void k_sap_half(Geo g, int colour, int flags, 
   }
 }
 
+// Mixed-precision SAP half-sweep with the domain's operator held in
+// registers: one workgroup per domain of the active colour for ALL right-hand
+// sides.  Each thread keeps its site's 8 links (4 forward, 4 backward, FP16
+// packed) and clover block (FP16) in registers, loaded once, and runs the MR
+// block solves of every right-hand side in turn; only the residual goes
+// through LDS.  Links of hops that leave the domain are not needed by D_SAP;
+// the crossing-hop correction of step 1 reads them from memory.
+__device__ __forceinline__ cplx<float> h2f(half2_t v) { return {(float)v.x, (float)v.y}; }
+
+template <bool FWD>
+__device__ __forceinline__ void hop_h(int mu, const cplx<float> (&psi)[12], const half2_t* u16, float coef,
+                                      cplx<float> (&acc)[12]) {
+  cplx<float> u[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = h2f(u16[e]);
+  hop_any<FWD>(mu, psi, u, coef, acc);
+}
+
+__global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, int mr, float kappa, int nrhs,
+                                                 const float2* __restrict__ b, float2* __restrict__ r,
+                                                 float2* __restrict__ x, float2* __restrict__ delta,
+                                                 const float2* __restrict__ xinit, size_t rs,
+                                                 const half2_t* __restrict__ U, const half2_t* __restrict__ C) {
+  extern __shared__ __align__(16) char smem[];
+  const int Vb = g.Vb;
+  cplx<float>* lds = (cplx<float>*)smem;                   // [12][Vb] residual exchange
+  half2_t* lu = (half2_t*)(smem + 12 * Vb * sizeof(cplx<float>));  // [4][9][Vb] forward links of the domain
+  int* ninfo = (int*)(lu + 36 * Vb);                       // [8][Vb] neighbour info
+  float* red = (float*)(ninfo + 8 * Vb);                   // [nwaves][3]
+  const int half = g.NB[0] >> 1;
+  int k = xcd_remap(blockIdx.x, g.nblk >> 1);
+  if (k >= (g.nblk >> 1)) return;
+  int row = k / half, j = k - row * half;
+  int by = row % g.NB[1];
+  int rz = row / g.NB[1];
+  int bz = rz % g.NB[2];
+  int bt = rz / g.NB[2];
+  int bx = 2 * j + ((colour + by + bz + bt) & 1);
+  int blk = bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
+  const int l = threadIdx.x;
+  const bool act = l < Vb;
+  const int s = blk * Vb + (act ? l : 0);
+  const int V = g.V;
+  const int nw = (blockDim.x + 63) >> 6;
+  SiteCoord c = decompose(g, s);
+
+  // per direction: in-domain neighbour's local index (bits 0..9), in-domain
+  // flag (bit 10), boundary sign -1 (bit 11)
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    int sign;
+    bool inb;
+    int mu = d & 3;
+    int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb) : neighbour<false>(g, s, c, mu, sign, inb);
+    if (act) ninfo[d * Vb + l] = (inb ? ((nb - blk * Vb) | (1 << 10)) : 0) | (sign < 0 ? (1 << 11) : 0);
+  }
+  // the domain's forward links U_mu(x), read by the site (forward hops) and
+  // by its in-domain neighbours (their backward hops)
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < 36; ++q) lu[q * Vb + l] = U[(size_t)q * V + s];
+  }
+  __syncthreads();
+
+  for (int rr = 0; rr < nrhs; ++rr) {
+    const size_t off = rr * rs;
+    cplx<float> rho[12], xm[12], p[12], psi[12];
+    if (act) {
+      load_spinor<float>((flags & SAP_FIRST) ? b + off : r + off, V, s, rho);
+      if (flags & SAP_DELTA) {
+#pragma unroll 1
+        for (int d = 0; d < 8; ++d) {
+          if (ninfo[d * Vb + l] & (1 << 10)) continue;
+          int sign;
+          bool inb;
+          int mu = d & 3;
+          int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb) : neighbour<false>(g, s, c, mu, sign, inb);
+          load_spinor<float>(delta + off, V, nb, psi);
+          half2_t ub[9];
+#pragma unroll
+          for (int e = 0; e < 9; ++e) ub[e] = U[(size_t)(mu * 9 + e) * V + (d < 4 ? s : nb)];
+          if (d < 4)
+            hop_h<true>(mu, psi, ub, kappa * (float)sign, rho);
+          else
+            hop_h<false>(mu, psi, ub, kappa * (float)sign, rho);
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 12; ++a) xm[a] = {0, 0};
+    for (int it = 0; it < mr; ++it) {
+      if (act) {
+#pragma unroll
+        for (int a = 0; a < 12; ++a) lds[a * Vb + l] = rho[a];
+      }
+      __syncthreads();
+      float pr_re = 0, pr_im = 0, pp = 0;
+      if (act) {
+        // p = (1 + F) rho + in-domain hops; the domain's clover blocks stay in L2
+#pragma unroll
+        for (int a = 0; a < 12; ++a) p[a] = rho[a];
+        clover_accum<float>(C, V, s, rho, p);
+#pragma unroll 1
+        for (int d = 0; d < 8; ++d) {
+          const int inf = ninfo[d * Vb + l];
+          if (!(inf & (1 << 10))) continue;
+          int nl = inf & 1023;
+          float coef = (inf & (1 << 11)) ? kappa : -kappa;
+#pragma unroll
+          for (int a = 0; a < 12; ++a) psi[a] = lds[a * Vb + nl];
+          half2_t ub[9];
+          const int ls = d < 4 ? l : nl;  // U_mu(x) or U_mu(x - mu)
+#pragma unroll
+          for (int e = 0; e < 9; ++e) ub[e] = lu[((d & 3) * 9 + e) * Vb + ls];
+          if (d < 4)
+            hop_h<true>(d & 3, psi, ub, coef, p);
+          else
+            hop_h<false>(d & 3, psi, ub, coef, p);
+        }
+#pragma unroll
+        for (int a = 0; a < 12; ++a) {
+          pr_re += p[a].x * rho[a].x + p[a].y * rho[a].y;
+          pr_im += p[a].x * rho[a].y - p[a].y * rho[a].x;
+          pp += p[a].x * p[a].x + p[a].y * p[a].y;
+        }
+      }
+      pr_re = wave_sum(pr_re);
+      pr_im = wave_sum(pr_im);
+      pp = wave_sum(pp);
+      if ((l & 63) == 0) {
+        red[(l >> 6) * 3 + 0] = pr_re;
+        red[(l >> 6) * 3 + 1] = pr_im;
+        red[(l >> 6) * 3 + 2] = pp;
+      }
+      __syncthreads();
+      float sre = 0, sim = 0, spp = 0;
+      for (int w = 0; w < nw; ++w) {
+        sre += red[w * 3 + 0];
+        sim += red[w * 3 + 1];
+        spp += red[w * 3 + 2];
+      }
+      cplx<float> alpha = {0, 0};
+      if (spp > 0) alpha = {sre / spp, sim / spp};
+      if (act) {
+#pragma unroll
+        for (int a = 0; a < 12; ++a) {
+          xm[a] = xm[a] + alpha * rho[a];
+          rho[a] = rho[a] - alpha * p[a];
+        }
+      }
+    }
+    if (act) {
+      float2* xr = x + off;
+      float2* rw = r + off;
+      float2* dw = delta + off;
+#pragma unroll
+      for (int a = 0; a < 12; ++a) {
+        size_t o = (size_t)a * V + s;
+        cplx<float> x0 = {0, 0};
+        if (!(flags & SAP_FIRST)) x0 = ld<float>(xr, o);
+        else if (xinit) x0 = ld<float>(xinit + off, o);
+        st(xr, o, x0 + xm[a]);
+        if (!(flags & SAP_NO_R)) st(rw, o, rho[a]);
+        if (!(flags & SAP_NO_DELTA)) st(dw, o, xm[a]);
+      }
+    }
+    __syncthreads();  // the next right-hand side reuses lds and red
+  }
+}
+
+int sap_dom_lds_bytes(const Geo& g) {
+  int nthr = ((g.Vb + 63) / 64) * 64;
+  return 12 * g.Vb * 8 + 36 * g.Vb * 4 + 8 * g.Vb * 4 + (nthr / 64) * 3 * 4;
+}
+
 int sap_lds_bytes(const Geo& g, int mixed) {
   int rsz = mixed ? 4 : 8;
   int nthr = ((g.Vb + 63) / 64) * 64;
@@ -625,7 +682,7 @@ int sap_lds_bytes(const Geo& g, int mixed) {
 }
 
 template <class R, class TS, class TL, class TC>
-static void sap_run(const SapArgs& a, hipStream_t st) {
+static void sap_half_run(const SapArgs& a, int col, int flags, hipStream_t st) {
   const Geo& g = a.g;
   int nthr = ((g.Vb + 63) / 64) * 64;
   int lds = sap_lds_bytes(g, sizeof(R) == 4);
@@ -633,23 +690,32 @@ static void sap_run(const SapArgs& a, hipStream_t st) {
   auto kern = k_sap_half<R, TS, TL, TC>;
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  for (int sw = 0; sw < a.sweeps; ++sw) {
-    for (int col = 0; col < 2; ++col) {
-      int flags = (sw == 0 ? SAP_FIRST : 0) | ((sw > 0 || col == 1) ? SAP_DELTA : 0);
-      kern<<<grid, nthr, lds, st>>>(g, col, flags, a.mr, (R)a.kappa, (const TS*)a.b, (TS*)a.r, (TS*)a.x,
-                                    (TS*)a.delta, (const TS*)a.xinit, a.rs, (const TL*)a.U, (const TC*)a.C);
-    }
-  }
+  kern<<<grid, nthr, lds, st>>>(g, col, flags, a.mr, (R)a.kappa, (const TS*)a.b, (TS*)a.r, (TS*)a.x,
+                                (TS*)a.delta, (const TS*)a.xinit, a.rs, (const TL*)a.U, (const TC*)a.C);
 }
 
-void launch_sap(const SapArgs& a, hipStream_t st) {
-  if (a.mixed)
-    sap_run<float, float2, half2_t, half2_t>(a, st);
-  else
-    sap_run<double, double2, double2, double2>(a, st);
+void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st) {
+  int flags = (sweep == 0 ? SAP_FIRST : 0) | ((sweep > 0 || col == 1) ? SAP_DELTA : 0);
+  if (!a.mixed) return sap_half_run<double, double2, double2, double2>(a, col, flags, st);
+  // the last visit of a colour: its residual is never read again; the last
+  // half-sweep's correction is never read either
+  if (sweep == a.sweeps - 1) flags |= SAP_NO_R;
+  if (sweep == a.sweeps - 1 && col == 1) flags |= SAP_NO_DELTA;
+  const Geo& g = a.g;
+  int nthr = ((g.Vb + 63) / 64) * 64;
+  int lds = sap_dom_lds_bytes(g);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_sap_dom, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  int ndom = g.nblk / 2;
+  k_sap_dom<<<round8(ndom), nthr, lds, st>>>(g, col, flags, a.mr, (float)a.kappa, a.nrhs, (const float2*)a.b,
+                                              (float2*)a.r, (float2*)a.x, (float2*)a.delta, (const float2*)a.xinit,
+                                              a.rs, (const half2_t*)a.U, (const half2_t*)a.C);
 }
 
 // ---------------------------------------------------------------------------

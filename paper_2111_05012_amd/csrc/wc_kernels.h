@@ -65,8 +65,10 @@ struct SapArgs {
   const void* U = nullptr;
   const void* C = nullptr;
 };
-void launch_sap(const SapArgs& a, hipStream_t st);
-int sap_lds_bytes(const Geo& g, int mixed);
+// one half-sweep (colour col of sweep `sweep`) of the SAP listing
+void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st);
+int sap_lds_bytes(const Geo& g, int mixed);  // FP64 path
+int sap_dom_lds_bytes(const Geo& g);          // mixed path
 
 // ---------------------------------------------------------------- coarse level
 struct CGeo {
@@ -97,6 +99,10 @@ void launch_prolong(const Geo& g, int nv, int nrhs, const void* V, int v_t, cons
 // Dc stored [X][d][m][n] (column-major blocks), vectors [nrhs][NC][N]
 void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
                       size_t rs, int prec32, hipStream_t st);
+// coarse operator eq.(7) from the stored test vectors V [nv][12][V] (mixed: FP16 V,
+// links, clover; FP32 arithmetic; complex64 Dc) into Dc [X][9][m][n]
+void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C, void* Dc,
+                         int mixed, hipStream_t st);
 // Cholesky-based coefficients for block orthonormalisation: given the Gram
 // matrices G[j][X][s*nv+i] = <v_i, v_j>_{X,s} (FP64), write
 // coef[j][X][s*nv+i] = (L^{-H})_{ij} with G = L L^H.  Returns nonzero via

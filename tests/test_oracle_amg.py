@@ -249,3 +249,70 @@ def test_two_level_solve_matches_dense_lu(small):
     assert its < its_plain
     x2, _, res2 = amg.flexible_bicgstab(op.D, mg.vcycle, b, tol=1e-10)
     assert res2 <= 1e-10
+
+
+def test_level1_pieces_are_galerkin(small):
+    """Level 1 of a three-level hierarchy: the coarse chirality Gamma commutes
+    with nothing but is respected by the construction, R1 P1 = 1, and
+    Dc2 = P1^dag Dc P1 by dense brute force, including extent-2 directions."""
+    op, D = small
+    V = amg.block_orthonormalize(syn.gaussian_vectors(DIMS, 3, 31), DIMS, BLOCK)
+    Dc = amg.coarse_operator(op, V)
+    cd = amg.coarse_dims(DIMS, BLOCK)  # 2^4 coarse sites, n = 6
+    cop = amg.CoarseOp(Dc, cd, (1, 1, 2, 2))
+    W = syn.gaussian_coarse(16, 6, 2, 32)
+    W = amg.coarse_block_orthonormalize(W, cd, cop.block)
+    nX2 = amg.n_blocks(cd, cop.block)
+    cols = []
+    for X in range(nX2):
+        for k in range(4):
+            e = np.zeros((nX2, 4), complex)
+            e[X, k] = 1
+            cols.append(amg.coarse_prolong(W, e, cd, cop.block).reshape(-1))
+    P1 = np.array(cols).T
+    assert np.abs(P1.conj().T @ P1 - np.eye(P1.shape[1])).max() < 1e-13
+    M = amg.coarse_dense(Dc, cd)
+    Dc2 = amg.coarse_coarse_operator(cop, W)
+    M2 = amg.coarse_dense(Dc2, amg.coarse_dims(cd, cop.block))
+    assert np.abs(M2 - P1.conj().T @ M @ P1).max() < 1e-13
+    # the in-block part is the block diagonal of the dense coarse matrix
+    x = syn.gaussian_coarse(16, 6, 1, 33)[0]
+    bid = np.array([amg.coarse_to_blocks(np.eye(16 * 6)[i].reshape(16, 6), cd, cop.block).nonzero()[0][0]
+                    for i in range(96)])
+    mask = bid[:, None] == bid[None, :]
+    assert np.abs(cop.Dsap(x).reshape(-1) - (M * mask) @ x.reshape(-1)).max() < 1e-13
+
+
+def test_mr_global_minimises_residual():
+    rng = np.random.default_rng(4)
+    A = np.eye(30) * 3 + 0.4 * (rng.standard_normal((30, 30)) + 1j * rng.standard_normal((30, 30)))
+    b = rng.standard_normal(30) + 0j
+    x1 = amg.mr_global(lambda z: A @ z, b, 1)
+    r1 = b - A @ x1
+    assert abs(np.vdot(A @ b, r1)) < 1e-12 * np.linalg.norm(b) ** 2
+    prev = np.linalg.norm(b)
+    for k in range(1, 8):
+        r = np.linalg.norm(b - A @ amg.mr_global(lambda z: A @ z, b, k))
+        assert r <= prev * (1 + 1e-13)
+        prev = r
+
+
+def test_three_level_solve_matches_dense_lu(small):
+    """Three levels on 4^4: level 0 blocks 2^4 (coarse 2^4, N_v 4), level 1
+    blocks 1x1x2x2 (level-2 lattice 2x2x1x1, N_v 4); FGMRES(16) to 1e-10
+    agrees with dense LU; with an exact level-2 solve and the level-1 cycle,
+    the preconditioner still reduces the iteration count versus M = 1."""
+    op, D = small
+    V0 = syn.gaussian_vectors(DIMS, 4, 41)
+    mg = amg.setup(op, V0, n_init=3, n_adapt=1, coarse_iters=50, coarse_tol=0.1)
+    cop = amg.CoarseOp(mg.Dc, mg.cdims, (1, 1, 2, 2))
+    W0 = syn.gaussian_coarse(16, 8, 4, 42)
+    lv1 = amg.setup_level1(cop, W0, n_init=2, n_adapt=1)
+    three = amg.ThreeLevel(op, mg.V, lv1)
+    b = syn.z2_source(DIMS, 1)[0]
+    x, its, res = amg.fgmres(op.D, three.vcycle, b, tol=1e-10, restart=16)
+    assert res <= 1e-10
+    want = np.linalg.solve(D, b.reshape(-1))
+    assert np.linalg.norm(x.reshape(-1) - want) <= np.linalg.cond(D) * 1e-10 * np.linalg.norm(want)
+    _, its_plain, _ = amg.fgmres(op.D, lambda v: v, b, tol=1e-10, restart=16)
+    assert its < its_plain
