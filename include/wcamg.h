@@ -125,6 +125,19 @@ typedef struct {
   int prec;          /* WCAMG_PREC_FP64 or WCAMG_PREC_MIXED */
   const void* init_vectors; /* nv start vectors (canonical spinor layout), required */
   int init_where;    /* WCAMG_DEVICE or WCAMG_HOST for init_vectors */
+  /* three-level hierarchy (nlevels = 3): level 1 aggregates block1 coarse
+   * sites; its smoother is mr1_iters global minimal-residual iterations on
+   * the level-1 operator, its coarse solve the BiCGStab above on the level-2
+   * operator.  Level-1 setup: (0-a) init_mr1_iters MR iterations applied
+   * n_init times to the start vectors, (0-b) n_adapt level-1 V-cycles. */
+  int nlevels;       /* 2 (default when 0) or 3 */
+  int block1[4];     /* level-1 blocks on the coarse lattice */
+  int nv1;           /* level-1 test vectors */
+  int mr1_iters;
+  int init_mr1_iters;
+  const void* init_vectors1; /* nv1 level-1 start vectors, complex128 [nv1][NC][2nv] (device), or
+                                NULL: drawn by the library's counter-based generator from seed1 */
+  unsigned long long seed1;
 } wcamg_setup_params;
 
 /* Setup stage (0) of Sec. 3: (0-a) SAP applied n_init times to the start
@@ -148,8 +161,17 @@ int wcamg_orthonormalize(wcamg_ctx* ctx, const void* in, void* out, int nv, int 
 int wcamg_restrict(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int where);
 /* eq. (6): out_r = sum_I in[r][I] |I>. */
 int wcamg_prolong(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int where);
-/* Copy the coarse operator out (complex128 [NC][9][2nv][2nv], see above). */
-int wcamg_get_coarse_op(wcamg_ctx* ctx, void* Dc, int where);
+/* Copy a coarse operator out: level 1 = Dc (complex128 [NC][9][2nv][2nv],
+ * see above), level 2 = the level-2 operator of a three-level hierarchy
+ * (complex128 [NC2][9][2nv1][2nv1], same conventions one level down). */
+int wcamg_get_coarse_op(wcamg_ctx* ctx, int level, void* Dc, int where);
+/* Three-level hook: install nv1 level-1 test vectors as given (complex128
+ * [nv1][NC][2nv]; the caller orthonormalises them per level-1 block and
+ * half) on a hierarchy created with nlevels = 3, and build the level-2
+ * operator. */
+int wcamg_set_level1_vectors(wcamg_ctx* ctx, const void* W, int where);
+/* Copy the level-1 test vectors out (complex128 [nv1][NC][2nv]). */
+int wcamg_get_level1_vectors(wcamg_ctx* ctx, void* W, int where);
 /* out = Dc in on coarse vectors (the 9-point block stencil). */
 int wcamg_apply_coarse(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int where);
 /* x = coarse solve of Dc x = b: BiCGStab from x = 0 with the stabilised

@@ -76,6 +76,21 @@ struct Hier {
   double coarse_tol = 0.1;
   DevBuf V;   // stored test vectors [nv][12][V]
   DevBuf Dc;  // [NC][9][N][N]
+  // optional level 1 (three-level hierarchy): blocks of the coarse lattice
+  bool l1 = false;
+  int nw = 0, N2 = 0, b1[4] = {1, 1, 1, 1};
+  int mr1_iters = 4;
+  CGeo cg2{};
+  DevBuf W;    // level-1 test vectors [nw][NC][N]
+  DevBuf Dc2;  // [NC2][9][N2][N2]
+};
+
+// a coarse operator: lattice, dof per site, stencil blocks
+struct COp {
+  CGeo cg;
+  int N;
+  void* Dc;
+  size_t n() const { return (size_t)cg.NC * N; }
 };
 
 struct KStat {
@@ -330,19 +345,24 @@ struct wcamg_ctx {
     launch_prolong(g, h.nv, nrhs, h.V.p, vec_t(), xc, crs_t(), crs_n(), h.N, out, spin_t(h.prec), frs(), 0,
                    h.prec == WCAMG_PREC_MIXED, st);
   }
-  void coarse_mv(const void* x, void* y, const void* b, int nrhs) {
-    double nc = h.cg.NC, N = h.N, cb = ct_size(crs_t());
+  COp op1() { return COp{h.cg, h.N, h.Dc.p}; }
+  COp op2() { return COp{h.cg2, h.N2, h.Dc2.p}; }
+  size_t csz(const COp& o, int nrhs) const { return (size_t)nrhs * o.n() * ct_size(crs_t()); }
+
+  void coarse_mv(const COp& o, const void* x, void* y, const void* b, int nrhs) {
+    double nc = o.cg.NC, N = o.N, cb = ct_size(crs_t());
     double by = nc * 9 * N * N * cb + nrhs * nc * N * cb * (b ? 3 : 2);
     Timed t(this, "coarse_mv", by, 8.0 * 9 * N * N * nc * nrhs, nrhs);
-    launch_coarse_mv(h.cg, h.N, h.Dc.p, x, y, b, nrhs, crs_n(), h.prec == WCAMG_PREC_MIXED, st);
+    launch_coarse_mv(o.cg, o.N, o.Dc, x, y, b, nrhs, o.n(), h.prec == WCAMG_PREC_MIXED, st);
   }
+  void coarse_mv(const void* x, void* y, const void* b, int nrhs) { coarse_mv(op1(), x, y, b, nrhs); }
 
   // BiCGStab with the stabilised omega; early exit checks only outside capture
-  void coarse_solve(const void* b, void* x, int nrhs, int iters, double tol) {
+  void coarse_solve(const COp& o, const void* b, void* x, int nrhs, int iters, double tol) {
     int t = crs_t();
     Timed tc(this, "coarse_solve", 0, 0, nrhs);
-    size_t n = crs_n();
-    size_t bytes = csz(nrhs);
+    size_t n = o.n();
+    size_t bytes = csz(o, nrhs);
     void* r = W("cg_r", bytes);
     void* rt = W("cg_rt", bytes);
     void* p = W("cg_p", bytes);
@@ -355,10 +375,10 @@ struct wcamg_ctx {
     std::vector<BicgScal> hs(nrhs);
     for (int it = 0; it < iters; ++it) {
       launch_bicg_p(p, r, v, t, n, n, nrhs, sc, st);
-      coarse_mv(p, v, nullptr, nrhs);
+      coarse_mv(o, p, v, nullptr, nrhs);
       launch_bicg_alpha(rt, v, t, n, n, nrhs, part, sc, st);
       launch_bicg_s(s, r, v, t, n, n, nrhs, sc, st);
-      coarse_mv(s, tt, nullptr, nrhs);
+      coarse_mv(o, s, tt, nullptr, nrhs);
       launch_bicg_omega(tt, s, t, n, n, nrhs, part, sc, 0.7, st);
       launch_bicg_xr(x, r, p, s, tt, rt, t, n, n, nrhs, part, sc, st);
       if (!capturing && (it % 4 == 3) && it + 1 < iters) {
@@ -371,6 +391,47 @@ struct wcamg_ctx {
     }
   }
 
+  // x += MR(A, r, iters) on coarse vectors (A = the level-1 stencil); r is overwritten
+  void mr_smooth(const COp& o, void* x, void* r, int nrhs, int iters) {
+    int t = crs_t();
+    size_t n = o.n();
+    void* p = W("mr_p", csz(o, nrhs));
+    double2* part = (double2*)W("mr_part", (size_t)nrhs * reduce_nwg(n) * 2 * sizeof(double2));
+    double2* alpha = (double2*)W("mr_alpha", (size_t)nrhs * sizeof(double2));
+    for (int it = 0; it < iters; ++it) {
+      coarse_mv(o, r, p, nullptr, nrhs);
+      launch_mr_alpha(p, r, t, n, n, nrhs, part, alpha, st);
+      launch_mr_update(x, r, p, alpha, t, n, n, nrhs, st);
+    }
+  }
+
+  // level-1 restriction / prolongation
+  void l1_restrict(const void* in, void* out, int nrhs) {
+    launch_l1_restrict(h.cg, h.b1, h.N, h.nw, nrhs, h.W.p, crs_t(), in, crs_t(), op1().n(), out, crs_t(),
+                       op2().n(), h.N2, st);
+  }
+  void l1_prolong(const void* xc, void* out, int nrhs) {
+    launch_l1_prolong(h.cg, h.b1, h.N, h.nw, nrhs, h.W.p, crs_t(), xc, crs_t(), op2().n(), h.N2, out, crs_t(),
+                      op1().n(), st);
+  }
+
+  // level-1 V-cycle as the coarse solve of level 0: x = P1 BiCGStab(Dc2, R1 b); x += MR(b - Dc x)
+  void vcycle1(const void* b, void* x, int nrhs) {
+    COp o1 = op1(), o2 = op2();
+    void* b2 = W("l1_b2", csz(o2, nrhs));
+    void* x2 = W("l1_x2", csz(o2, nrhs));
+    void* r1 = W("l1_r", csz(o1, nrhs));
+    l1_restrict(b, b2, nrhs);
+    coarse_solve(o2, b2, x2, nrhs, h.coarse_iters, h.coarse_tol);
+    l1_prolong(x2, x, nrhs);
+    coarse_mv(o1, x, r1, b, nrhs);
+    mr_smooth(o1, x, r1, nrhs, h.mr1_iters);
+  }
+
+  void coarse_solve(const void* b, void* x, int nrhs, int iters, double tol) {
+    coarse_solve(op1(), b, x, nrhs, iters, tol);
+  }
+
   // M v: restrict, coarse solve, prolong, residual, SAP started from the prolonged vector
   void vcycle(const void* in, void* out, int nrhs) {
     int prec = h.prec;
@@ -379,7 +440,10 @@ struct wcamg_ctx {
     void* x1 = W("vc_x1", fsz(nrhs, prec));
     void* r = W("vc_r", fsz(nrhs, prec));
     restrict_(in, vc, nrhs);
-    coarse_solve(vc, xc, nrhs, h.coarse_iters, h.coarse_tol);
+    if (h.l1)
+      vcycle1(vc, xc, nrhs);
+    else
+      coarse_solve(vc, xc, nrhs, h.coarse_iters, h.coarse_tol);
     prolong_(xc, x1, nrhs);
     dslash(x1, spin_t(prec), r, spin_t(prec), nrhs, OP_D, prec, in);
     sap(r, out, x1, nrhs, h.sap_sweeps, h.mr_iters, prec);
@@ -415,6 +479,81 @@ struct wcamg_ctx {
     h.Dc.ensure((size_t)h.cg.NC * 9 * N * N * ct_size(crs_t()), capturing);
     bool mixed = h.prec == WCAMG_PREC_MIXED;
     launch_coarse_build(g, nv, kappa, h.V.p, mixed ? U16.p : U64.p, mixed ? Cl16.p : Cl64.p, h.Dc.p, mixed, st);
+  }
+
+  // level-1 block orthonormalisation of W in place (CholQR twice, FP64 Gram)
+  void orthonormalize1() {
+    Timed tb(this, "ortho", 0, 0, 1, true);
+    int nw = h.nw, t = crs_t();
+    COp o1 = op1(), o2 = op2();
+    size_t grs = o2.n();  // NC2 * 2 nw
+    double2* G = (double2*)W("or1_G", (size_t)nw * grs * sizeof(double2));
+    void* coef = W("or1_c", (size_t)nw * grs * ct_size(t));
+    void* tmp = W("or1_tmp", csz(o1, nw));
+    int* bad = (int*)W("or_bad", sizeof(int));
+    launch_zero(bad, sizeof(int), st);
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_l1_restrict(h.cg, h.b1, h.N, nw, nw, h.W.p, t, h.W.p, t, o1.n(), G, C128, grs, h.N2, st);
+      launch_cholesky_coef(h.cg2.NC, nw, G, grs, coef, t, grs, bad, st);
+      launch_l1_prolong(h.cg, h.b1, h.N, nw, nw, h.W.p, t, coef, t, grs, h.N2, tmp, t, o1.n(), st);
+      HIPCHK(hipMemcpyAsync(h.W.p, tmp, csz(o1, nw), hipMemcpyDeviceToDevice, st));
+    }
+    int hb = 0;
+    HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    require(hb == 0, "level-1 orthonormalisation: vectors linearly dependent on a block", WCAMG_ENUMERIC);
+  }
+
+  void build_coarse2() {
+    Timed tb(this, "coarse_build", 0, 0, 1, true);
+    h.Dc2.ensure((size_t)h.cg2.NC * 9 * h.N2 * h.N2 * ct_size(crs_t()), capturing);
+    launch_l1_build(h.cg, h.b1, h.N, h.nw, h.Dc.p, h.W.p, h.Dc2.p, h.prec == WCAMG_PREC_MIXED, st);
+  }
+
+  void set_l1_params(const wcamg_setup_params* p) {
+    h.l1 = false;
+    if (p->nlevels <= 2) return;
+    require(p->nlevels == 3, "nlevels must be 2 or 3");
+    require(p->nv1 >= 1 && p->nv1 <= 64 && 2 * p->nv1 * p->nv1 <= 16 * 256, "nv1 must be in [1, 64]");
+    require(p->mr1_iters >= 0 && p->init_mr1_iters >= 0, "negative iteration count");
+    int n2[4];
+    for (int m = 0; m < 4; ++m) {
+      require(p->block1[m] >= 1 && h.cg.N[m] % p->block1[m] == 0, "block1 must divide the coarse lattice");
+      h.b1[m] = p->block1[m];
+      n2[m] = h.cg.N[m] / p->block1[m];
+    }
+    h.nw = p->nv1;
+    h.N2 = 2 * p->nv1;
+    h.cg2 = make_cgeo(n2);
+    h.mr1_iters = p->mr1_iters;
+    h.l1 = true;
+  }
+
+  // level-1 setup on the final level-0 hierarchy (same steps one level down)
+  void setup_level1(const wcamg_setup_params* p, const void* W0) {
+    COp o1 = op1();
+    int nw = h.nw, t = crs_t();
+    h.W.ensure(csz(o1, nw), capturing);
+    if (W0)
+      HIPCHK(hipMemcpyAsync(h.W.p, W0, csz(o1, nw), hipMemcpyDeviceToDevice, st));
+    else
+      launch_gauss(h.W.p, t, (size_t)nw * o1.n(), p->seed1, st);
+    void* Wx = W("su1_x", csz(o1, nw));
+    void* Wr = W("su1_r", csz(o1, nw));
+    for (int k = 0; k < p->n_init; ++k) {
+      launch_zero(Wx, csz(o1, nw), st);
+      HIPCHK(hipMemcpyAsync(Wr, h.W.p, csz(o1, nw), hipMemcpyDeviceToDevice, st));
+      mr_smooth(o1, Wx, Wr, nw, p->init_mr1_iters);
+      HIPCHK(hipMemcpyAsync(h.W.p, Wx, csz(o1, nw), hipMemcpyDeviceToDevice, st));
+    }
+    orthonormalize1();
+    build_coarse2();
+    for (int k = 0; k < p->n_adapt; ++k) {
+      vcycle1(h.W.p, Wx, nw);
+      HIPCHK(hipMemcpyAsync(h.W.p, Wx, csz(o1, nw), hipMemcpyDeviceToDevice, st));
+      orthonormalize1();
+      build_coarse2();
+    }
   }
 
   void store_vectors(const void* Vw, int nv) {
@@ -692,6 +831,7 @@ int wcamg_set_test_vectors(wcamg_ctx* c, const void* V, const wcamg_setup_params
     require(c->have_gauge, "no gauge field", WCAMG_ESTATE);
     c->have_hier = false;
     install_vectors(c, V, where, p);
+    c->set_l1_params(p);
     c->build_coarse();
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
@@ -707,6 +847,7 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
     require(c->have_gauge, "no gauge field", WCAMG_ESTATE);
     c->have_hier = false;
     c->set_params(p);
+    c->set_l1_params(p);
     const Geo& g = c->g;
     int nv = p->nv, prec = p->prec, t = c->spin_t(prec);
     size_t cbytes = (size_t)nv * g.V * 12 * sizeof(double2);
@@ -722,12 +863,26 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
     c->orthonormalize(Vw, nv, prec);
     c->store_vectors(Vw, nv);
     c->build_coarse();
+    // level 0 (0-b) runs with the two-level cycle; level 1 is set up on the final level-0 hierarchy
+    bool l1 = c->h.l1;
+    c->h.l1 = false;
     for (int k = 0; k < p->n_adapt; ++k) {
       c->vcycle(Vw, Vt, nv);
       std::swap(Vw, Vt);
       c->orthonormalize(Vw, nv, prec);
       c->store_vectors(Vw, nv);
       c->build_coarse();
+    }
+    if (l1) {
+      c->h.l1 = true;
+      const void* W0 = nullptr;
+      if (p->init_vectors1) {
+        size_t nel = (size_t)p->nv1 * c->op1().n();
+        void* tmp = c->W("su1_w0", nel * ct_size(c->crs_t()));
+        launch_convert(p->init_vectors1, C128, tmp, c->crs_t(), nel, c->st);
+        W0 = tmp;
+      }
+      c->setup_level1(p, W0);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
@@ -820,25 +975,60 @@ int wcamg_prolong(wcamg_ctx* c, const void* in, void* out, int nrhs, int where) 
   });
 }
 
-int wcamg_get_coarse_op(wcamg_ctx* c, void* Dc, int where) {
+int wcamg_get_coarse_op(wcamg_ctx* c, int level, void* Dc, int where) {
   if (!c) return WCAMG_EINVAL;
   return guard(c, [&] {
     check_where(where);
     require(Dc, "null pointer");
-    require(c->have_hier, "no hierarchy", WCAMG_ESTATE);
-    int N = c->h.N;
-    size_t nel = (size_t)c->h.cg.NC * 9 * N * N;
+    require(level == 1 || level == 2, "level must be 1 or 2");
+    require(c->have_hier || (level == 2 && c->h.l1 && c->h.Dc2.p), "no hierarchy", WCAMG_ESTATE);
+    require(level == 1 || c->h.l1, "no level-2 operator (nlevels < 3)", WCAMG_ESTATE);
+    COp o = level == 1 ? c->op1() : c->op2();
+    int N = o.N;
+    size_t nel = (size_t)o.cg.NC * 9 * N * N;
     void* tmp = c->W("gc_tmp", nel * sizeof(double2));
-    launch_convert(c->h.Dc.p, c->crs_t(), tmp, C128, nel, c->st);
+    launch_convert(o.Dc, c->crs_t(), tmp, C128, nel, c->st);
     std::vector<double2> hst(nel), tr(nel);
     HIPCHK(hipMemcpyAsync(hst.data(), tmp, nel * sizeof(double2), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     // internal [X][d][m][n] -> [X][d][n][m]
-    for (size_t xd = 0; xd < (size_t)c->h.cg.NC * 9; ++xd)
+    for (size_t xd = 0; xd < (size_t)o.cg.NC * 9; ++xd)
       for (int m = 0; m < N; ++m)
         for (int n = 0; n < N; ++n) tr[(xd * N + n) * N + m] = hst[(xd * N + m) * N + n];
     HIPCHK(hipMemcpy(Dc, tr.data(), nel * sizeof(double2),
                      where == WCAMG_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+  });
+}
+
+int wcamg_set_level1_vectors(wcamg_ctx* c, const void* Wv, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(Wv, "null pointer");
+    require(c->have_hier && c->h.l1, "needs a hierarchy set up with nlevels = 3", WCAMG_ESTATE);
+    size_t nel = (size_t)c->h.nw * c->op1().n();
+    HostIO io(c);
+    const void* Wd = io.in(Wv, nel * sizeof(double2), where, "io_in");
+    c->h.W.ensure(nel * ct_size(c->crs_t()), false);
+    launch_convert(Wd, C128, c->h.W.p, c->crs_t(), nel, c->st);
+    c->build_coarse2();
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+  });
+}
+
+int wcamg_get_level1_vectors(wcamg_ctx* c, void* Wv, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(Wv, "null pointer");
+    require(c->have_hier && c->h.l1, "no level-1 vectors", WCAMG_ESTATE);
+    size_t nel = (size_t)c->h.nw * c->op1().n();
+    HostIO io(c);
+    void* Wd = io.out(Wv, nel * sizeof(double2), where, "io_out");
+    launch_convert(c->h.W.p, c->crs_t(), Wd, C128, nel, c->st);
+    HIPCHK(hipGetLastError());
+    io.finish(Wv, Wd, nel * sizeof(double2), where);
   });
 }
 

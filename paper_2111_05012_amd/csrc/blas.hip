@@ -484,4 +484,76 @@ void launch_update_x(double2* x, const void* Z, int z_t, size_t zs, int nk, cons
     k_update_x<float2><<<ew_grid(n, nrhs), 256, 0, st>>>(x, (const float2*)Z, zs, nk, y, n, rs, nrhs);
 }
 
+// ---------------------------------------------------------------- MR smoother (coarse levels)
+// alpha[r] = <p, r> / <p, p> (0 when p = 0), from partials of (<p,r>, <p,p>)
+__global__ void k_mr_fin(const double2* part, int nwg, double2* alpha) {
+  int r = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  cplx<double> pr = sum_parts(part, nwg, 2, r, 0);
+  double pp = sum_parts(part, nwg, 2, r, 1).x;
+  alpha[r] = pp > 0 ? make_double2(pr.x / pp, pr.y / pp) : make_double2(0.0, 0.0);
+}
+
+template <class T, class R>
+__global__ __launch_bounds__(256) void k_mr_update(T* x, T* r, const T* p, const double2* alpha, size_t n,
+                                                   size_t rs) {
+  const int rr = blockIdx.y;
+  const size_t off = rr * rs;
+  cplx<R> al = {(R)alpha[rr].x, (R)alpha[rr].y};
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    cplx<R> ri = ld<R>(r + off, i);
+    st(x + off, i, ld<R>(x + off, i) + al * ri);
+    st(r + off, i, ri - al * ld<R>(p + off, i));
+  }
+}
+
+void launch_mr_alpha(const void* p, const void* r, int t, size_t n, size_t rs, int nrhs, double2* part,
+                     double2* alpha, hipStream_t st) {
+  const void* a[2] = {p, p};
+  const void* b[2] = {r, p};
+  launch_dots_partial(2, a, b, t, n, rs, nrhs, part, st);
+  k_mr_fin<<<nrhs, 64, 0, st>>>(part, reduce_nwg(n), alpha);
+}
+
+void launch_mr_update(void* x, void* r, const void* p, const double2* alpha, int t, size_t n, size_t rs, int nrhs,
+                      hipStream_t st) {
+  if (t == C128)
+    k_mr_update<double2, double><<<ew_grid(n, nrhs), 256, 0, st>>>((double2*)x, (double2*)r, (const double2*)p,
+                                                                   alpha, n, rs);
+  else
+    k_mr_update<float2, float><<<ew_grid(n, nrhs), 256, 0, st>>>((float2*)x, (float2*)r, (const float2*)p, alpha,
+                                                                 n, rs);
+}
+
+// ---------------------------------------------------------------- seeded Gaussian vectors
+// Counter-based: element i of stream `seed` takes two 64-bit words from the
+// SplitMix64 finaliser (Steele, Lea, Flood 2014) of seed*2^32 + 2i and + 2i+1,
+// maps them to uniforms in (0, 1] and applies the Box-Muller transform.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_gauss(T* out, size_t n, unsigned long long seed) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    unsigned long long base = (seed << 32) + 2 * (unsigned long long)i;
+    double u1 = ((splitmix64(base) >> 11) + 1) * (1.0 / 9007199254740992.0);
+    double u2 = (splitmix64(base + 1) >> 11) * (1.0 / 9007199254740992.0);
+    double rad = sqrt(-2.0 * log(u1));
+    double ph = 6.283185307179586 * u2;
+    st(out, i, cplx<double>{rad * cos(ph), rad * sin(ph)});
+  }
+}
+
+void launch_gauss(void* out, int t, size_t n, unsigned long long seed, hipStream_t st) {
+  unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+  if (t == C128)
+    k_gauss<double2><<<nb, 256, 0, st>>>((double2*)out, n, seed);
+  else
+    k_gauss<float2><<<nb, 256, 0, st>>>((float2*)out, n, seed);
+}
+
 }  // namespace wc

@@ -319,7 +319,7 @@ __global__ __launch_bounds__(256) void k_coarse_build(Geo g, int nv, R kappa, co
                                                       TO* __restrict__ Dc) {
   extern __shared__ __align__(16) char smem[];
   const int N = 2 * nv;
-  const int T = 256 / nv;  // sites per tile
+  const int T = 256 / nv;  // sites per tile (threads t < T nv compute the vectors g)
   cplx<R>* sv = (cplx<R>*)smem;     // [T][nv][12]
   cplx<R>* sgv = sv + T * nv * 12;  // [T][nv][12]
   const int X = blockIdx.x, d = blockIdx.y, sp = blockIdx.z;
@@ -448,7 +448,7 @@ template <class R, class TV, class TL, class TC, class TO>
 static void coarse_build_run(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C,
                              void* Dc, hipStream_t st) {
   const int N = 2 * nv;
-  if (N > 256 || 256 % nv) throw std::runtime_error("coarse build: nv must divide 256 and 2 nv <= 256");
+  if (N > 256) throw std::runtime_error("coarse build: 2 nv must be <= 256");
   const int ncg = 256 / N;
   const int cpg = (nv + ncg - 1) / ncg;
   const size_t lds = 2 * (size_t)(256 / nv) * nv * 12 * sizeof(cplx<R>);
@@ -477,6 +477,266 @@ void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, cons
     coarse_build_run<float, half2_t, half2_t, half2_t, float2>(g, nv, kappa, V, U, C, Dc, st);
   else
     coarse_build_run<double, double2, double2, double2, double2>(g, nv, kappa, V, U, C, Dc, st);
+}
+
+// ---------------------------------------------------------------------------
+// Level-1 (coarse-lattice) aggregation for multi-level hierarchies.  Vectors
+// on the coarse lattice are [rhs][X1][n1] (X1 lexicographic over cg.N); a
+// level-1 block X2 collects b1[0] x .. x b1[3] coarse sites; the two halves
+// of the n1 = 2 nv dof are the coarse chiralities.  Level-1 test vectors W
+// are [nw][X1][n1]; level-2 vectors are [rhs][X2][2 nw].
+// ---------------------------------------------------------------------------
+struct L1Geo {
+  CGeo c1;      // level-1 lattice
+  CGeo c2;      // level-2 lattice
+  int b1[4];    // block extents
+  int vb1;      // sites per block
+};
+
+__device__ __forceinline__ int l1_site(const L1Geo& q, int X2, int loc) {
+  int c2[4], cl[4];
+  int r = X2, l = loc;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    c2[m] = r % q.c2.N[m];
+    r /= q.c2.N[m];
+    cl[m] = l % q.b1[m];
+    l /= q.b1[m];
+  }
+  int X1 = 0;
+#pragma unroll
+  for (int m = 3; m >= 0; --m) X1 = X1 * q.c1.N[m] + c2[m] * q.b1[m] + cl[m];
+  return X1;
+}
+
+__device__ __forceinline__ int l1_block(const L1Geo& q, int X1) {
+  int r = X1, X2 = 0, mul = 1;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    int c = r % q.c1.N[m];
+    r /= q.c1.N[m];
+    X2 += (c / q.b1[m]) * mul;
+    mul *= q.c2.N[m];
+  }
+  return X2;
+}
+
+// out[r][X2][s*nw + k] = sum_{X1 in X2} sum_{a in half s} conj(W_k(X1)_a) x_r(X1)_a
+template <class RA, class TW, class TI, class TO>
+__global__ __launch_bounds__(256) void k_l1_restrict(L1Geo q, int n1, int nw, int nrhs, const TW* __restrict__ W,
+                                                     const TI* __restrict__ x, size_t x_rs, TO* __restrict__ out,
+                                                     size_t out_rs, size_t out_xs) {
+  size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+  size_t total = (size_t)nrhs * q.c2.NC * 2 * nw;
+  if (t >= total) return;
+  int k = t % nw;
+  size_t u = t / nw;
+  int s = u % 2;
+  u /= 2;
+  int X2 = u % q.c2.NC;
+  int r = u / q.c2.NC;
+  int h = n1 / 2;
+  cplx<RA> acc = {0, 0};
+  for (int loc = 0; loc < q.vb1; ++loc) {
+    int X1 = l1_site(q, X2, loc);
+    const TW* w = W + ((size_t)k * q.c1.NC + X1) * n1 + s * h;
+    const TI* xv = x + r * x_rs + (size_t)X1 * n1 + s * h;
+    for (int a = 0; a < h; ++a) cjmac(acc, ld<RA>(w, a), ld<RA>(xv, a));
+  }
+  st(out, r * out_rs + X2 * out_xs + s * nw + k, acc);
+}
+
+// out_r(X1)_a = sum_k W_k(X1)_a xc[r][X2(X1)][s(a) nw + k]
+template <class R, class TW, class TC, class TO>
+__global__ __launch_bounds__(256) void k_l1_prolong(L1Geo q, int n1, int nw, int nrhs, const TW* __restrict__ W,
+                                                    const TC* __restrict__ xc, size_t xc_rs, size_t xc_xs,
+                                                    TO* __restrict__ out, size_t out_rs) {
+  size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+  size_t total = (size_t)nrhs * q.c1.NC * n1;
+  if (t >= total) return;
+  int a = t % n1;
+  size_t u = t / n1;
+  int X1 = u % q.c1.NC;
+  int r = u / q.c1.NC;
+  int X2 = l1_block(q, X1);
+  int s = a >= n1 / 2;
+  cplx<R> acc = {0, 0};
+  const TC* c = xc + r * xc_rs + X2 * xc_xs + s * nw;
+  for (int k = 0; k < nw; ++k) cmac(acc, ld<R>(W, ((size_t)k * q.c1.NC + X1) * n1 + a), ld<R>(c, k));
+  st(out, r * out_rs + (size_t)X1 * n1 + a, acc);
+}
+
+void launch_l1_restrict(const CGeo& c1, const int* b1, int n1, int nw, int nrhs, const void* W, int w_t,
+                        const void* x, int x_t, size_t x_rs, void* out, int out_t, size_t out_rs, size_t out_xs,
+                        hipStream_t st) {
+  L1Geo q;
+  q.c1 = c1;
+  int n2[4];
+  for (int m = 0; m < 4; ++m) {
+    q.b1[m] = b1[m];
+    n2[m] = c1.N[m] / b1[m];
+  }
+  q.c2 = make_cgeo(n2);
+  q.vb1 = b1[0] * b1[1] * b1[2] * b1[3];
+  size_t total = (size_t)nrhs * q.c2.NC * 2 * nw;
+  unsigned nb = (unsigned)((total + 255) / 256);
+  if (w_t == C128 && x_t == C128 && out_t == C128)
+    k_l1_restrict<double, double2, double2, double2><<<nb, 256, 0, st>>>(q, n1, nw, nrhs, (const double2*)W,
+                                                                         (const double2*)x, x_rs, (double2*)out,
+                                                                         out_rs, out_xs);
+  else if (w_t == C64 && x_t == C64 && out_t == C64)
+    k_l1_restrict<float, float2, float2, float2><<<nb, 256, 0, st>>>(q, n1, nw, nrhs, (const float2*)W,
+                                                                     (const float2*)x, x_rs, (float2*)out, out_rs,
+                                                                     out_xs);
+  else if (w_t == C64 && x_t == C64 && out_t == C128)
+    k_l1_restrict<double, float2, float2, double2><<<nb, 256, 0, st>>>(q, n1, nw, nrhs, (const float2*)W,
+                                                                       (const float2*)x, x_rs, (double2*)out,
+                                                                       out_rs, out_xs);
+  else
+    throw std::runtime_error("launch_l1_restrict: unsupported type combination");
+}
+
+void launch_l1_prolong(const CGeo& c1, const int* b1, int n1, int nw, int nrhs, const void* W, int w_t,
+                       const void* xc, int xc_t, size_t xc_rs, size_t xc_xs, void* out, int out_t, size_t out_rs,
+                       hipStream_t st) {
+  L1Geo q;
+  q.c1 = c1;
+  int n2[4];
+  for (int m = 0; m < 4; ++m) {
+    q.b1[m] = b1[m];
+    n2[m] = c1.N[m] / b1[m];
+  }
+  q.c2 = make_cgeo(n2);
+  q.vb1 = b1[0] * b1[1] * b1[2] * b1[3];
+  size_t total = (size_t)nrhs * c1.NC * n1;
+  unsigned nb = (unsigned)((total + 255) / 256);
+  if (w_t == C128 && xc_t == C128 && out_t == C128)
+    k_l1_prolong<double, double2, double2, double2><<<nb, 256, 0, st>>>(q, n1, nw, nrhs, (const double2*)W,
+                                                                        (const double2*)xc, xc_rs, xc_xs,
+                                                                        (double2*)out, out_rs);
+  else if (w_t == C64 && xc_t == C64 && out_t == C64)
+    k_l1_prolong<float, float2, float2, float2><<<nb, 256, 0, st>>>(q, n1, nw, nrhs, (const float2*)W,
+                                                                    (const float2*)xc, xc_rs, xc_xs, (float2*)out,
+                                                                    out_rs);
+  else
+    throw std::runtime_error("launch_l1_prolong: unsupported type combination");
+}
+
+// Level-2 operator from the level-1 stencil Dc1 ([X1][9][m][n], n1 x n1) and
+// the level-1 test vectors W: one workgroup per (X2, d, source half sp).  For
+// every site X1 of the block (or of its face in direction d) the vectors
+//   g_l(X1) = sum_{d1} Dc1[X1][d1] (P_sp W_l)(X1 + e_d1)
+// (d1 over the in-block hops and the self term for d = 0, the single
+// crossing hop d for d > 0) are formed in LDS and contracted with conj(W_k).
+template <class R, class TC, class TW, class TO>
+__global__ __launch_bounds__(256) void k_l1_build(L1Geo q, int n1, int nw, const TC* __restrict__ Dc1,
+                                                  const TW* __restrict__ W, TO* __restrict__ Dc2) {
+  extern __shared__ __align__(16) char smem[];
+  cplx<R>* gl = (cplx<R>*)smem;  // [nw][n1]
+  const int X2 = blockIdx.x, d = blockIdx.y, sp = blockIdx.z;
+  const int t = threadIdx.x;
+  const int h = n1 / 2, N2 = 2 * nw;
+  const int mu = (d - 1) & 3;
+  const bool fwd = d <= 4;
+  // outputs: (row n = (s,k), column l), looped by the workgroup
+  const int nout = N2 * nw;
+  constexpr int MAXO = 16;
+  cplx<R> acc[MAXO];
+#pragma unroll
+  for (int o = 0; o < MAXO; ++o) acc[o] = {0, 0};
+  for (int loc = 0; loc < q.vb1; ++loc) {
+    // site of the block; for d > 0 only sites on the face of direction d
+    int cl[4], r = loc;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      cl[m] = r % q.b1[m];
+      r /= q.b1[m];
+    }
+    if (d > 0) {
+      if (q.c2.N[mu] == 1) break;  // a single block in this direction: no crossing hop
+      if (cl[mu] != (fwd ? q.b1[mu] - 1 : 0)) continue;
+    }
+    const int X1 = l1_site(q, X2, loc);
+    int c1[4];
+    {
+      int rr = X1;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        c1[m] = rr % q.c1.N[m];
+        rr /= q.c1.N[m];
+      }
+    }
+    // g_l(X1)_a for (l, a) pairs
+    for (int e = t; e < nw * n1; e += 256) {
+      const int l = e / n1, a = e - l * n1;
+      cplx<R> g = {0, 0};
+      for (int d1 = 0; d1 < 9; ++d1) {
+        int m1 = (d1 - 1) & 3;
+        int Y = X1;
+        if (d1 > 0) {
+          int step = d1 <= 4 ? 1 : -1;
+          int cc = c1[m1] + step;
+          if (cc == q.c1.N[m1]) cc = 0;
+          if (cc < 0) cc = q.c1.N[m1] - 1;
+          Y = X1 + (cc - c1[m1]) * q.c1.sN[m1];
+          // in-block?  (same level-1 block iff the block coordinate is unchanged)
+          bool inb = (cc / q.b1[m1]) == (c1[m1] / q.b1[m1]);
+          if (d == 0 && !inb) continue;
+          if (d > 0 && (d1 != d || inb)) continue;
+        } else if (d > 0) {
+          continue;
+        }
+        const TC* B = Dc1 + ((size_t)(X1 * 9 + d1) * n1) * n1;  // column-major: (row a, col b) at b*n1 + a
+        const TW* w = W + ((size_t)l * q.c1.NC + Y) * n1 + sp * h;
+        for (int b = 0; b < h; ++b) cmac(g, ld<R>(B, (size_t)(sp * h + b) * n1 + a), ld<R>(w, b));
+      }
+      gl[l * n1 + a] = g;
+    }
+    __syncthreads();
+    for (int o = 0; o < MAXO; ++o) {
+      int idx = t + o * 256;
+      if (idx >= nout) break;
+      int n = idx % N2, l = idx / N2;
+      int s = n / nw, k = n - s * nw;
+      const TW* w = W + ((size_t)k * q.c1.NC + X1) * n1 + s * h;
+      for (int b = 0; b < h; ++b) cjmac(acc[o], ld<R>(w, b), gl[l * n1 + s * h + b]);
+    }
+    __syncthreads();
+  }
+  for (int o = 0; o < MAXO; ++o) {
+    int idx = t + o * 256;
+    if (idx >= nout) break;
+    int n = idx % N2, l = idx / N2;
+    st(Dc2, ((size_t)(X2 * 9 + d) * N2 + (sp * nw + l)) * N2 + n, acc[o]);
+  }
+}
+
+void launch_l1_build(const CGeo& c1, const int* b1, int n1, int nw, const void* Dc1, const void* W, void* Dc2,
+                     int prec32, hipStream_t st) {
+  L1Geo q;
+  q.c1 = c1;
+  int n2[4];
+  for (int m = 0; m < 4; ++m) {
+    q.b1[m] = b1[m];
+    n2[m] = c1.N[m] / b1[m];
+  }
+  q.c2 = make_cgeo(n2);
+  q.vb1 = b1[0] * b1[1] * b1[2] * b1[3];
+  if (2 * nw * nw > 16 * 256) throw std::runtime_error("l1 build: too many outputs");
+  dim3 grid(q.c2.NC, 9, 2);
+  if (prec32) {
+    size_t lds = (size_t)nw * n1 * sizeof(cplx<float>);
+    (void)hipFuncSetAttribute((const void*)k_l1_build<float, float2, float2, float2>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    k_l1_build<float, float2, float2, float2><<<grid, 256, lds, st>>>(q, n1, nw, (const float2*)Dc1,
+                                                                      (const float2*)W, (float2*)Dc2);
+  } else {
+    size_t lds = (size_t)nw * n1 * sizeof(cplx<double>);
+    (void)hipFuncSetAttribute((const void*)k_l1_build<double, double2, double2, double2>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    k_l1_build<double, double2, double2, double2><<<grid, 256, lds, st>>>(q, n1, nw, (const double2*)Dc1,
+                                                                          (const double2*)W, (double2*)Dc2);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -103,6 +103,16 @@ void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void
 // links, clover; FP32 arithmetic; complex64 Dc) into Dc [X][9][m][n]
 void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C, void* Dc,
                          int mixed, hipStream_t st);
+// level-1 aggregation (multi-level): coarse vectors [rhs][X1][n1], level-1
+// test vectors W [nw][X1][n1], level-1 blocks b1, level-2 vectors [rhs][X2][2nw]
+void launch_l1_restrict(const CGeo& c1, const int* b1, int n1, int nw, int nrhs, const void* W, int w_t,
+                        const void* x, int x_t, size_t x_rs, void* out, int out_t, size_t out_rs, size_t out_xs,
+                        hipStream_t st);
+void launch_l1_prolong(const CGeo& c1, const int* b1, int n1, int nw, int nrhs, const void* W, int w_t,
+                       const void* xc, int xc_t, size_t xc_rs, size_t xc_xs, void* out, int out_t, size_t out_rs,
+                       hipStream_t st);
+void launch_l1_build(const CGeo& c1, const int* b1, int n1, int nw, const void* Dc1, const void* W, void* Dc2,
+                     int prec32, hipStream_t st);
 // Cholesky-based coefficients for block orthonormalisation: given the Gram
 // matrices G[j][X][s*nv+i] = <v_i, v_j>_{X,s} (FP64), write
 // coef[j][X][s*nv+i] = (L^{-H})_{ij} with G = L L^H.  Returns nonzero via
@@ -156,5 +166,13 @@ void launch_update_x(double2* x, const void* Z, int z_t, size_t zs, int nk, cons
 // norm2[r] = ||v[r]||^2
 void launch_norm2(const void* v, int t, size_t n, size_t rs, int nrhs, double2* part, double* norm2,
                   hipStream_t st);
+
+// global MR steps on coarse vectors: alpha[r] = <p,r>/<p,p>; x += alpha r, r -= alpha p
+void launch_mr_alpha(const void* p, const void* r, int t, size_t n, size_t rs, int nrhs, double2* part,
+                     double2* alpha, hipStream_t st);
+void launch_mr_update(void* x, void* r, const void* p, const double2* alpha, int t, size_t n, size_t rs, int nrhs,
+                      hipStream_t st);
+// n complex Gaussian numbers (re, im each N(0,1)) from a counter-based generator
+void launch_gauss(void* out, int t, size_t n, unsigned long long seed, hipStream_t st);
 
 }  // namespace wc

@@ -30,7 +30,9 @@ class SetupParams(ctypes.Structure):
     _fields_ = [('nv', ctypes.c_int), ('n_init', ctypes.c_int), ('n_adapt', ctypes.c_int),
                 ('sap_sweeps', ctypes.c_int), ('mr_iters', ctypes.c_int), ('coarse_iters', ctypes.c_int),
                 ('coarse_tol', ctypes.c_double), ('prec', ctypes.c_int), ('init_vectors', ctypes.c_void_p),
-                ('init_where', ctypes.c_int)]
+                ('init_where', ctypes.c_int), ('nlevels', ctypes.c_int), ('block1', _c_int4), ('nv1', ctypes.c_int),
+                ('mr1_iters', ctypes.c_int), ('init_mr1_iters', ctypes.c_int), ('init_vectors1', ctypes.c_void_p),
+                ('seed1', ctypes.c_ulonglong)]
 
 
 class SolveParams(ctypes.Structure):
@@ -69,7 +71,9 @@ SIGNATURES = {
     'wcamg_orthonormalize': (_I, [_P, _P, _P, _I, _I, _I]),
     'wcamg_restrict': (_I, [_P, _P, _P, _I, _I]),
     'wcamg_prolong': (_I, [_P, _P, _P, _I, _I]),
-    'wcamg_get_coarse_op': (_I, [_P, _P, _I]),
+    'wcamg_get_coarse_op': (_I, [_P, _I, _P, _I]),
+    'wcamg_set_level1_vectors': (_I, [_P, _P, _I]),
+    'wcamg_get_level1_vectors': (_I, [_P, _P, _I]),
     'wcamg_apply_coarse': (_I, [_P, _P, _P, _I, _I]),
     'wcamg_coarse_solve': (_I, [_P, _P, _P, _I, _I, _D, _I]),
     'wcamg_vcycle': (_I, [_P, _P, _P, _I, _I]),
@@ -185,12 +189,19 @@ class Context:
 
     @staticmethod
     def setup_params(nv, prec=PREC_FP64, n_init=3, n_adapt=3, sap_sweeps=4, mr_iters=6, coarse_iters=50,
-                     coarse_tol=0.1, init_vectors=None):
-        p = SetupParams(nv, n_init, n_adapt, sap_sweeps, mr_iters, coarse_iters, coarse_tol, prec, None, DEVICE)
+                     coarse_tol=0.1, init_vectors=None, nlevels=2, block1=(1, 1, 1, 1), nv1=0, mr1_iters=4,
+                     init_mr1_iters=8, init_vectors1=None, seed1=1):
+        p = SetupParams(nv, n_init, n_adapt, sap_sweeps, mr_iters, coarse_iters, coarse_tol, prec, None, DEVICE,
+                        nlevels, _c_int4(*block1), nv1, mr1_iters, init_mr1_iters, None, seed1)
         if init_vectors is not None:
             ptr, w = _ptr(init_vectors)
             p.init_vectors = ptr
             p.init_where = w
+        if init_vectors1 is not None:
+            ptr, w = _ptr(init_vectors1)
+            if w != DEVICE:
+                raise ValueError('init_vectors1 must be a device tensor')
+            p.init_vectors1 = ptr
         return p
 
     def setup(self, params):
@@ -216,9 +227,17 @@ class Context:
         w = _same_where(xc, out)
         self._done(self.lib.wcamg_prolong(self.h, _ptr(xc)[0], _ptr(out)[0], nrhs, w), out)
 
-    def get_coarse_op(self, Dc):
+    def get_coarse_op(self, Dc, level=1):
         p, w = _ptr(Dc)
-        self._done(self.lib.wcamg_get_coarse_op(self.h, p, w), Dc)
+        self._done(self.lib.wcamg_get_coarse_op(self.h, level, p, w), Dc)
+
+    def set_level1_vectors(self, W):
+        p, w = _ptr(W)
+        self._chk(self.lib.wcamg_set_level1_vectors(self.h, p, w))
+
+    def get_level1_vectors(self, W):
+        p, w = _ptr(W)
+        self._done(self.lib.wcamg_get_level1_vectors(self.h, p, w), W)
 
     def apply_coarse(self, x, out, nrhs):
         w = _same_where(x, out)

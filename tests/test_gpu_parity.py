@@ -113,7 +113,7 @@ def test_coarse_operator_fp64(prob):
     V = _hier(prob)
     nX = amg.n_blocks(prob.dims, prob.block)
     Dc = prob.zeros((nX, 9, 8, 8))
-    prob.ctx.get_coarse_op(Dc)
+    prob.ctx.get_coarse_op(Dc, level=1)
     want = amg.coarse_operator(prob.op, V)
     assert rel(prob.N(Dc), want) < 1e-13
     x = syn.gaussian_coarse(nX, 8, 3, 20)
@@ -185,6 +185,61 @@ def test_setup_and_solve_mixed_c1():
     p = prob.ctx.setup_params(c['nv'], PREC_MIXED, init_vectors=prob.T(V0))
     prob.ctx.setup(p)
     b = syn.z2_source(prob.dims, c['seed'], nrhs=2)
+    x = prob.zeros(b.shape)
+    rc, info = prob.ctx.solve(prob.T(b), x, 2, restart=16, tol=1e-10)
+    assert rc == 0
+    xg = prob.N(x)
+    for k in range(2):
+        assert np.linalg.norm(b[k] - prob.op.D(xg[k])) / np.linalg.norm(b[k]) <= 1e-10
+
+
+# ---------------------------------------------------------------- three levels
+def _three_level_problem(prec=0, nv=4, nv1=4):
+    """8^4 with 2^4 blocks (coarse 4^4), level-1 blocks 2^4 (level-2 2^4)."""
+    prob = Problem((8, 8, 8, 8), (2, 2, 2, 2), eps=0.5, seed=1, kappa=0.124, csw=1.0)
+    V = amg.block_orthonormalize(syn.gaussian_vectors(prob.dims, nv, 51), prob.dims, prob.block)
+    p = prob.ctx.setup_params(nv, prec, coarse_iters=8, coarse_tol=0.0, nlevels=3, block1=(2, 2, 2, 2),
+                              nv1=nv1, mr1_iters=3)
+    prob.ctx.set_test_vectors(prob.T(V), p)
+    Dc = amg.coarse_operator(prob.op, V)
+    cd = amg.coarse_dims(prob.dims, prob.block)
+    cop = amg.CoarseOp(Dc, cd, (2, 2, 2, 2))
+    W = amg.coarse_block_orthonormalize(syn.gaussian_coarse(cop.Dc.shape[0], 2 * nv, nv1, 52), cd, cop.block)
+    prob.ctx.set_level1_vectors(prob.T(W))
+    return prob, V, cop, W
+
+
+def test_level2_operator_fp64():
+    prob, V, cop, W = _three_level_problem()
+    want = amg.coarse_coarse_operator(cop, W)
+    got = prob.zeros(want.shape)
+    prob.ctx.get_coarse_op(got, level=2)
+    assert rel(prob.N(got), want) < 1e-12
+    Wg = prob.zeros(W.shape)
+    prob.ctx.get_level1_vectors(Wg)
+    assert rel(prob.N(Wg), W) == 0.0
+
+
+def test_three_level_vcycle_fp64():
+    prob, V, cop, W = _three_level_problem()
+    lv1 = amg.Level1(cop, W, mr1_iters=3, coarse_iters=8, coarse_tol=0.0)
+    mg = amg.ThreeLevel(prob.op, V, lv1, 4, 6)
+    v = syn.gaussian_vectors(prob.dims, 2, 53)
+    out = prob.zeros(v.shape)
+    prob.ctx.vcycle(prob.T(v), out, 2)
+    assert rel(prob.N(out), mg.vcycle(v)) < 1e-10
+
+
+@pytest.mark.parametrize('prec', [0, 1])
+def test_three_level_setup_and_solve(prec):
+    """Full three-level setup (level-1 start vectors from the library's
+    seeded generator) and FGMRES solve; residual recomputed by the oracle."""
+    prob = Problem((8, 8, 8, 8), (2, 2, 2, 2), eps=0.5, seed=1, kappa=0.124, csw=1.0)
+    V0 = syn.gaussian_vectors(prob.dims, 6, 54)
+    p = prob.ctx.setup_params(6, prec, init_vectors=prob.T(V0), nlevels=3, block1=(2, 2, 2, 2), nv1=6,
+                              mr1_iters=4, seed1=7)
+    prob.ctx.setup(p)
+    b = syn.z2_source(prob.dims, 2, nrhs=2)
     x = prob.zeros(b.shape)
     rc, info = prob.ctx.solve(prob.T(b), x, 2, restart=16, tol=1e-10)
     assert rc == 0
