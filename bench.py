@@ -299,6 +299,7 @@ def main():
         outer_iters=iters, relres_max=relres, converged=converged,
         roofline=roof, dslash_fp64=dsl, kernels=kernels, plain_fp64=plain,
         speedup_vs_plain=round(plain['tts_s'] / tts, 2) if plain else None,
+        autotune=ctx.autotune_info(),
         cpu_baseline=cpu)
     print(json.dumps(res), flush=True)
 

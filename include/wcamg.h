@@ -207,6 +207,19 @@ typedef struct {
 int wcamg_solve(wcamg_ctx* ctx, const void* b, void* x, int nrhs, const wcamg_solve_params* p,
                 wcamg_solve_info* info);
 
+/* Launch-variant autotuner (on by default): the first time a kernel is
+ * launched for a new key (kernel, shapes, precision, GPU architecture) each
+ * candidate variant (Dslash workgroup size, coarse-matvec right-hand sides per
+ * thread, restriction tile) is timed with HIP events on the real operands and
+ * the fastest is kept; variants never change results.  cache_path (or the
+ * environment variable WCAMG_AUTOTUNE_CACHE at create time) names a flat
+ * JSON file {"key": variant} that is read now and rewritten after each newly
+ * tuned key; NULL keeps the current file. */
+int wcamg_autotune(wcamg_ctx* ctx, int enable, const char* cache_path);
+/* Time spent tuning (ms, not part of any solve), keys tuned by this context
+ * and keys known (tuned or loaded). Pointers may be NULL. */
+int wcamg_autotune_info(wcamg_ctx* ctx, double* tune_ms, int* keys_tuned, int* keys_known);
+
 /* Per-kernel-class timing with HIP events on the context stream, for
  * roofline measurements: enable (1) / disable (0, also clears nothing).
  * When enabled, the work of each class is bracketed by events: "dslash64",

@@ -10,6 +10,8 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <functional>
 #include <map>
 #include <memory>
@@ -142,6 +144,51 @@ std::vector<double> sigma_table() {
   return t;
 }
 
+// Launch-variant autotuner.  The first time a key (kernel, shapes,
+// precision, architecture) is seen, every candidate variant is timed with HIP
+// events on the real operands (all variants compute identical results: they
+// change workgroup shapes or staging only, never the order of a sum) and the
+// fastest is kept; choices persist in a flat JSON file {"key": variant, ...}.
+struct Tuner {
+  bool enabled = true;
+  std::string path;
+  std::map<std::string, int> best;
+  double tune_ms = 0;
+  int tuned = 0;
+
+  void load(const std::string& p) {
+    path = p;
+    std::ifstream f(p);
+    if (!f) return;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    std::string txt = ss.str();
+    size_t i = 0;
+    while ((i = txt.find('"', i)) != std::string::npos) {
+      size_t j = txt.find('"', i + 1);
+      if (j == std::string::npos) break;
+      std::string key = txt.substr(i + 1, j - i - 1);
+      size_t c = txt.find(':', j);
+      if (c == std::string::npos) break;
+      best[key] = std::atoi(txt.c_str() + c + 1);
+      i = txt.find_first_of(",}", c);
+      if (i == std::string::npos) break;
+    }
+  }
+  void save() const {
+    if (path.empty()) return;
+    std::ofstream f(path);
+    if (!f) return;
+    f << "{";
+    bool first = true;
+    for (auto& kv : best) {
+      f << (first ? "\n  " : ",\n  ") << '"' << kv.first << "\": " << kv.second;
+      first = false;
+    }
+    f << "\n}\n";
+  }
+};
+
 }  // namespace
 
 struct wcamg_ctx {
@@ -172,6 +219,47 @@ struct wcamg_ctx {
   int graph_prec = -1;
   hipStream_t cap_st = nullptr;  // library-owned stream used for graph capture
   size_t lds_max = 0;            // LDS bytes available to one workgroup
+  Tuner tuner;
+  std::string arch;
+
+  // pick the fastest of `cands` for `key` (runs each on the real operands
+  // when the key is new and no graph is being captured)
+  int tune(const std::string& key0, const std::vector<int>& cands, const std::function<void(int)>& run) {
+    if (cands.size() == 1) return cands[0];
+    std::string key = arch + "|" + key0;
+    auto it = tuner.best.find(key);
+    if (it != tuner.best.end()) return it->second;
+    if (!tuner.enabled || capturing) return cands[0];
+    bool tm = timing;
+    timing = false;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto t0 = std::chrono::steady_clock::now();
+    int bestv = cands[0];
+    float bestt = 1e30f;
+    for (int v : cands) {
+      run(v);  // warm-up (and allocation of any workspace)
+      HIPCHK(hipEventRecord(e0, st));
+      for (int k = 0; k < 3; ++k) run(v);
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < bestt) {
+        bestt = ms;
+        bestv = v;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    timing = tm;
+    tuner.best[key] = bestv;
+    tuner.tuned += 1;
+    tuner.tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    tuner.save();
+    return bestv;
+  }
 
   ~wcamg_ctx() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -283,6 +371,14 @@ struct wcamg_ctx {
     double site = (double)g.V;
     double fld = 4.0 * 9 * (a.fields16 ? 4 : 16) + 36.0 * (a.fields16 ? 4 : 16);
     double by = site * (fld + nrhs * 12.0 * (ct_size(in_t) + ct_size(out_t) * (b ? 2 : 1)));
+    char key[160];
+    snprintf(key, sizeof(key), "dslash|op%d|in%d|out%d|f%d|c%d|res%d|V%d|Vb%d|n%d", op, in_t, out_t, a.fields16,
+             a.compute32, b ? 1 : 0, g.V, g.Vb, nrhs);
+    a.block_size = tune(key, {64, 128, 256, 512}, [&](int v) {
+      DslashArgs q = a;
+      q.block_size = v;
+      launch_dslash(q, st);
+    });
     Timed t(this, a.compute32 ? "dslash32" : "dslash64", by, 1920.0 * site * nrhs, nrhs);
     launch_dslash(a, st);
   }
@@ -335,8 +431,19 @@ struct wcamg_ctx {
   void restrict_(const void* in, void* out, int nrhs) {
     double by = (double)g.V * 12 * (h.nv * ct_size(vec_t()) + nrhs * ct_size(spin_t(h.prec))) +
                 (double)nrhs * crs_n() * ct_size(crs_t());
+    char key[160];
+    snprintf(key, sizeof(key), "restrict|nv%d|n%d|Vb%d|V%d|p%d", h.nv, nrhs, g.Vb, g.V, h.prec);
+    std::vector<int> cands;
+    for (int v : {32, 16, 8, 4})
+      if (g.Vb % v == 0) cands.push_back(v);
+    if (cands.empty()) cands.push_back(0);
+    int tile = tune(key, cands, [&](int v) {
+      launch_restrict(g, h.nv, nrhs, h.V.p, vec_t(), in, spin_t(h.prec), frs(), out, crs_t(), crs_n(), h.N, 0, st,
+                      v);
+    });
     Timed t(this, "restrict", by, 96.0 * g.V * h.nv * nrhs, nrhs);
-    launch_restrict(g, h.nv, nrhs, h.V.p, vec_t(), in, spin_t(h.prec), frs(), out, crs_t(), crs_n(), h.N, 0, st);
+    launch_restrict(g, h.nv, nrhs, h.V.p, vec_t(), in, spin_t(h.prec), frs(), out, crs_t(), crs_n(), h.N, 0, st,
+                    tile);
   }
   void prolong_(const void* xc, void* out, int nrhs) {
     double by = (double)g.V * 12 * (h.nv * ct_size(vec_t()) + nrhs * ct_size(spin_t(h.prec))) +
@@ -352,8 +459,16 @@ struct wcamg_ctx {
   void coarse_mv(const COp& o, const void* x, void* y, const void* b, int nrhs) {
     double nc = o.cg.NC, N = o.N, cb = ct_size(crs_t());
     double by = nc * 9 * N * N * cb + nrhs * nc * N * cb * (b ? 3 : 2);
+    std::vector<int> cands;
+    for (int v : {1, 4, 8, 12, 16})
+      if (v == 1 || v <= nrhs + 3) cands.push_back(v);
+    char key[160];
+    snprintf(key, sizeof(key), "coarse_mv|N%d|NC%d|n%d|p%d|res%d", o.N, o.cg.NC, nrhs, h.prec, b ? 1 : 0);
+    int var = tune(key, cands, [&](int v) {
+      launch_coarse_mv(o.cg, o.N, o.Dc, x, y, b, nrhs, o.n(), h.prec == WCAMG_PREC_MIXED, st, v);
+    });
     Timed t(this, "coarse_mv", by, 8.0 * 9 * N * N * nc * nrhs, nrhs);
-    launch_coarse_mv(o.cg, o.N, o.Dc, x, y, b, nrhs, o.n(), h.prec == WCAMG_PREC_MIXED, st);
+    launch_coarse_mv(o.cg, o.N, o.Dc, x, y, b, nrhs, o.n(), h.prec == WCAMG_PREC_MIXED, st, var);
   }
   void coarse_mv(const void* x, void* y, const void* b, int nrhs) { coarse_mv(op1(), x, y, b, nrhs); }
 
@@ -675,6 +790,10 @@ int wcamg_create(wcamg_ctx** out, const wcamg_lattice* lat, void* hip_stream) {
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, dev));
     c->lds_max = prop.sharedMemPerBlock;
+    c->arch = prop.gcnArchName;
+    c->arch = c->arch.substr(0, c->arch.find(':'));
+    const char* cache = std::getenv("WCAMG_AUTOTUNE_CACHE");
+    if (cache && *cache) c->tuner.load(cache);
   });
   if (rc != WCAMG_OK) {
     delete c;
@@ -1337,6 +1456,23 @@ int wcamg_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, const wcamg_solv
     if (info) *info = inf;
   });
   return rc != WCAMG_OK ? rc : status;
+}
+
+int wcamg_autotune(wcamg_ctx* c, int enable, const char* cache_path) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    c->tuner.enabled = enable != 0;
+    if (cache_path) c->tuner.load(cache_path);
+  });
+}
+
+int wcamg_autotune_info(wcamg_ctx* c, double* tune_ms, int* keys_tuned, int* keys_known) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    if (tune_ms) *tune_ms = c->tuner.tune_ms;
+    if (keys_tuned) *keys_tuned = c->tuner.tuned;
+    if (keys_known) *keys_known = (int)c->tuner.best.size();
+  });
 }
 
 int wcamg_kernel_timing(wcamg_ctx* c, int enable) {

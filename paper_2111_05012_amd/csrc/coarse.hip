@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_restrict(Geo g, int nv, int nrhs, int T
 
 template <class RA, class TV, class TI, class TO, int RB>
 static void restrict_run(const Geo& g, int nv, int nrhs, const void* V, const void* in, size_t in_rs, void* out,
-                         size_t out_rs, size_t out_xs, hipStream_t st) {
+                         size_t out_rs, size_t out_xs, hipStream_t st, int tile) {
   int nrg = (nrhs + RB - 1) / RB;
   if (2 * nv * nrg > 256) throw std::runtime_error("restrict: too many outputs per block");
   // largest power-of-two tile (dividing Vb) with LDS <= 48 KiB
@@ -90,38 +90,39 @@ static void restrict_run(const Geo& g, int nv, int nrhs, const void* V, const vo
     return (((size_t)ts * nv * 12 * sizeof(TV) + 15) & ~(size_t)15) + (size_t)ts * nrhs * 12 * sizeof(cplx<RA>);
   };
   while (TS * 2 <= 32 && g.Vb % (TS * 2) == 0 && bytes(TS * 2) <= 48 * 1024) TS *= 2;
+  if (tile > 0 && tile < TS && g.Vb % tile == 0) TS = tile;
   k_restrict<RA, TV, TI, TO, RB><<<g.nblk, 256, bytes(TS), st>>>(g, nv, nrhs, TS, (const TV*)V, (const TI*)in,
                                                                 in_rs, (TO*)out, out_rs, out_xs);
 }
 
 template <class RA, class TV, class TI, class TO>
 static void restrict_rb(const Geo& g, int nv, int nrhs, const void* V, const void* in, size_t in_rs, void* out,
-                        size_t out_rs, size_t out_xs, hipStream_t st) {
+                        size_t out_rs, size_t out_xs, hipStream_t st, int tile) {
   // choose the rhs group so that 2 nv ceil(nrhs/RB) <= 256
   int need = (2 * nv * nrhs + 255) / 256;
   if (need <= 1)
-    restrict_run<RA, TV, TI, TO, 1>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+    restrict_run<RA, TV, TI, TO, 1>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st, tile);
   else if (need <= 2)
-    restrict_run<RA, TV, TI, TO, 2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+    restrict_run<RA, TV, TI, TO, 2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st, tile);
   else if (need <= 4)
-    restrict_run<RA, TV, TI, TO, 4>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+    restrict_run<RA, TV, TI, TO, 4>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st, tile);
   else if (need <= 8)
-    restrict_run<RA, TV, TI, TO, 8>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+    restrict_run<RA, TV, TI, TO, 8>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st, tile);
   else
-    restrict_run<RA, TV, TI, TO, 16>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+    restrict_run<RA, TV, TI, TO, 16>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st, tile);
 }
 
 void launch_restrict(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* in, int in_t,
                      size_t in_rs, void* out, int out_t, size_t out_rs, size_t out_xs, int acc64,
-                     hipStream_t st) {
+                     hipStream_t st, int tile) {
   if (v_t == C128 && in_t == C128 && out_t == C128)
-    return restrict_rb<double, double2, double2, double2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+    return restrict_rb<double, double2, double2, double2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st, tile);
   if (v_t == C32H && in_t == C64 && out_t == C64 && !acc64)
-    return restrict_rb<float, half2_t, float2, float2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+    return restrict_rb<float, half2_t, float2, float2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st, tile);
   if (v_t == C32H && in_t == C32H && out_t == C64 && !acc64)
-    return restrict_rb<float, half2_t, half2_t, float2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+    return restrict_rb<float, half2_t, half2_t, float2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st, tile);
   if (v_t == C64 && in_t == C64 && out_t == C128 && acc64)
-    return restrict_rb<double, float2, float2, double2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st);
+    return restrict_rb<double, float2, float2, double2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st, tile);
   throw std::runtime_error("launch_restrict: unsupported type combination");
 }
 
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(256) void k_coarse_mv(CGeo cg, int N, const TC* __r
 
 template <class R, class TC, class TX>
 static void coarse_mv_run(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
-                          size_t rs, hipStream_t st) {
+                          size_t rs, hipStream_t st, int variant) {
   int nb = (cg.NC * N + 255) / 256;
   auto go = [&](auto tag) {
     constexpr int NR = decltype(tag)::value;
@@ -283,24 +284,25 @@ static void coarse_mv_run(const CGeo& cg, int N, const void* Dc, const void* x, 
     k_coarse_mv<R, TC, TX, NR><<<grid, 256, 0, st>>>(cg, N, (const TC*)Dc, (const TX*)x, (TX*)y, (const TX*)b, rs,
                                                      nrhs);
   };
-  if (nrhs == 1)
+  int nr = variant > 0 ? variant : (nrhs == 1 ? 1 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : nrhs <= 12 ? 12 : 16);
+  if (nr == 1)
     go(std::integral_constant<int, 1>());
-  else if (nrhs <= 4)
+  else if (nr <= 4)
     go(std::integral_constant<int, 4>());
-  else if (nrhs <= 8)
+  else if (nr <= 8)
     go(std::integral_constant<int, 8>());
-  else if (nrhs <= 12)
+  else if (nr <= 12)
     go(std::integral_constant<int, 12>());
   else
     go(std::integral_constant<int, 16>());
 }
 
 void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
-                      size_t rs, int prec32, hipStream_t st) {
+                      size_t rs, int prec32, hipStream_t st, int variant) {
   if (prec32)
-    coarse_mv_run<float, float2, float2>(cg, N, Dc, x, y, b, nrhs, rs, st);
+    coarse_mv_run<float, float2, float2>(cg, N, Dc, x, y, b, nrhs, rs, st, variant);
   else
-    coarse_mv_run<double, double2, double2>(cg, N, Dc, x, y, b, nrhs, rs, st);
+    coarse_mv_run<double, double2, double2>(cg, N, Dc, x, y, b, nrhs, rs, st, variant);
 }
 
 // ---------------------------------------------------------------------------

@@ -244,13 +244,14 @@ __global__ __launch_bounds__(128) void k_clover_build(Geo g, const double2* __re
 // Dslash family
 // ---------------------------------------------------------------------------
 template <class R, class TI, class TO, class TL, class TC, int OP>
-__global__ __launch_bounds__(256) void k_dslash(Geo g, const TI* __restrict__ in, size_t in_rs, TO* __restrict__ out,
+__global__ __launch_bounds__(512) void k_dslash(Geo g, const TI* __restrict__ in, size_t in_rs, TO* __restrict__ out,
                                                 size_t out_rs, const TO* __restrict__ b, const TL* __restrict__ U,
                                                 const TC* __restrict__ C, R kappa, int hopdir, int chir) {
-  int ntile = (g.V + 255) >> 8;
+  const int bs = blockDim.x;
+  int ntile = (g.V + bs - 1) / bs;
   int tile = xcd_remap(blockIdx.x, ntile);
   if (tile >= ntile) return;
-  int s = tile * 256 + threadIdx.x;
+  int s = tile * bs + threadIdx.x;
   if (s >= g.V) return;
   int r = blockIdx.y;
   const TI* inr = in + r * in_rs;
@@ -309,7 +310,8 @@ __global__ __launch_bounds__(256) void k_dslash(Geo g, const TI* __restrict__ in
 
 template <class R, class TI, class TO, class TL, class TC>
 static void dslash_dispatch(const DslashArgs& a, hipStream_t st) {
-  int ntile = (a.g.V + 255) / 256;
+  const int bs = a.block_size > 0 ? a.block_size : 256;
+  int ntile = (a.g.V + bs - 1) / bs;
   dim3 grid(round8(ntile), a.nrhs);
   const TI* in = (const TI*)a.in;
   TO* out = (TO*)a.out;
@@ -319,15 +321,15 @@ static void dslash_dispatch(const DslashArgs& a, hipStream_t st) {
   R kappa = (R)a.kappa;
   switch (a.op) {
     case OP_D:
-      k_dslash<R, TI, TO, TL, TC, OP_D><<<grid, 256, 0, st>>>(a.g, in, a.in_rs, out, a.out_rs, b, U, C, kappa, 0,
+      k_dslash<R, TI, TO, TL, TC, OP_D><<<grid, bs, 0, st>>>(a.g, in, a.in_rs, out, a.out_rs, b, U, C, kappa, 0,
                                                               a.chir);
       break;
     case OP_DSAP:
-      k_dslash<R, TI, TO, TL, TC, OP_DSAP><<<grid, 256, 0, st>>>(a.g, in, a.in_rs, out, a.out_rs, b, U, C, kappa,
+      k_dslash<R, TI, TO, TL, TC, OP_DSAP><<<grid, bs, 0, st>>>(a.g, in, a.in_rs, out, a.out_rs, b, U, C, kappa,
                                                                  0, a.chir);
       break;
     default:
-      k_dslash<R, TI, TO, TL, TC, OP_HOP><<<grid, 256, 0, st>>>(a.g, in, a.in_rs, out, a.out_rs, b, U, C, kappa,
+      k_dslash<R, TI, TO, TL, TC, OP_HOP><<<grid, bs, 0, st>>>(a.g, in, a.in_rs, out, a.out_rs, b, U, C, kappa,
                                                                 a.hopdir, a.chir);
       break;
   }

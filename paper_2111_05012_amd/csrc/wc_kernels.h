@@ -47,6 +47,7 @@ struct DslashArgs {
   int fields16 = 0;  // 0: FP64 links/clover, 1: FP16
   int compute32 = 0; // 0: FP64 arithmetic, 1: FP32
   double kappa = 0;
+  int block_size = 256;  // threads per workgroup (64 .. 512, autotuned)
 };
 void launch_dslash(const DslashArgs& a, hipStream_t st);
 
@@ -88,17 +89,19 @@ inline CGeo make_cgeo(const int* n) {
 // restriction eq.(5): out[r][X][s*nv+i] = sum_{y in X, a in s} conj(V_i(y,a)) in_r(y,a)
 // V: [nv][12][V] of type v_t; in: [nrhs][12][V] (in_rs); out element (r, X, n) at
 // r*out_rs + X*out_xs + n.  acc64: accumulate in FP64.
+// tile: sites per LDS tile (0: largest that fits 48 KiB; else a power of two dividing Vb)
 void launch_restrict(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* in, int in_t,
                      size_t in_rs, void* out, int out_t, size_t out_rs, size_t out_xs, int acc64,
-                     hipStream_t st);
+                     hipStream_t st, int tile = 0);
 // prolongation eq.(6): out_r(y,a) (+)= sum_i V_i(y,a) xc[r][X(y)][s(a)*nv+i]
 void launch_prolong(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* xc, int xc_t,
                     size_t xc_rs, size_t xc_xs, void* out, int out_t, size_t out_rs, int accumulate,
                     int compute32, hipStream_t st);
 // coarse 9-point stencil: y[r][X] = sum_d Dc[X][d] x[r][X+e_d]   (or y = b - Dc x)
 // Dc stored [X][d][m][n] (column-major blocks), vectors [nrhs][NC][N]
+// variant: right-hand sides per thread (0: automatic; else 1, 4, 8, 12 or 16)
 void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
-                      size_t rs, int prec32, hipStream_t st);
+                      size_t rs, int prec32, hipStream_t st, int variant = 0);
 // coarse operator eq.(7) from the stored test vectors V [nv][12][V] (mixed: FP16 V,
 // links, clover; FP32 arithmetic; complex64 Dc) into Dc [X][9][m][n]
 void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C, void* Dc,

@@ -78,6 +78,8 @@ SIGNATURES = {
     'wcamg_coarse_solve': (_I, [_P, _P, _P, _I, _I, _D, _I]),
     'wcamg_vcycle': (_I, [_P, _P, _P, _I, _I]),
     'wcamg_solve': (_I, [_P, _P, _P, _I, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo)]),
+    'wcamg_autotune': (_I, [_P, _I, ctypes.c_char_p]),
+    'wcamg_autotune_info': (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     'wcamg_kernel_timing': (_I, [_P, _I]),
     'wcamg_kernel_stats': (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_D),
                                 ctypes.POINTER(_D), ctypes.POINTER(_D)]),
@@ -262,6 +264,14 @@ class Context:
         rc = self._chk(self.lib.wcamg_solve(self.h, pb, px, nrhs, ctypes.byref(prm), ctypes.byref(info)),
                        allow=(OK, NOT_CONVERGED))
         return rc, info
+
+    def autotune(self, enable=True, cache_path=None):
+        self._chk(self.lib.wcamg_autotune(self.h, int(enable), cache_path.encode() if cache_path else None))
+
+    def autotune_info(self):
+        ms, a, b = ctypes.c_double(), ctypes.c_int(), ctypes.c_int()
+        self._chk(self.lib.wcamg_autotune_info(self.h, ctypes.byref(ms), ctypes.byref(a), ctypes.byref(b)))
+        return dict(tune_ms=ms.value, keys_tuned=a.value, keys_known=b.value)
 
     def kernel_timing(self, enable):
         self._chk(self.lib.wcamg_kernel_timing(self.h, int(enable)))

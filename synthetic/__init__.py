@@ -138,6 +138,20 @@ def gaussian_clover(dims, seed, stream=STREAM_PROBE):
     return 0.05 * (a + np.conj(np.swapaxes(a, -1, -2)))
 
 
+def net_weights(C, L, seed, scale=None):
+    """Start weights of the equivariant network, [L][9, C, C, 4, 4] complex:
+    small Gaussian entries (re, im each N(0, scale^2)) plus, on the identity
+    path d = 0, a spin-diagonal N(0, 1/C) channel mixing (stream 3)."""
+    g = rng(seed, STREAM_NET)
+    s = scale if scale is not None else 0.1 / np.sqrt(9 * C * 4)
+    Ws = []
+    for _ in range(L):
+        W = s * (g.standard_normal((9, C, C, 4, 4)) + 1j * g.standard_normal((9, C, C, 4, 4)))
+        W[0] += np.eye(4)[None, None] * (g.standard_normal((C, C))[..., None, None] / np.sqrt(C))
+        Ws.append(W)
+    return Ws
+
+
 # Workload recipes (lattice, generator parameters, hierarchy) used by tests and bench.
 CONFIGS = {
     'c1': dict(dims=(4, 4, 4, 4), eps=0.5, seed=1, kappa=0.124, csw=1.0, block=(2, 2, 2, 2),
