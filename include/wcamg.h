@@ -138,6 +138,9 @@ typedef struct {
   const void* init_vectors1; /* nv1 level-1 start vectors, complex128 [nv1][NC][2nv] (device), or
                                 NULL: drawn by the library's counter-based generator from seed1 */
   unsigned long long seed1;
+  /* learned start: when nonzero, step (0-a) is replaced by the network of
+   * wcamg_net_init applied to init_vectors (nv must equal its channels). */
+  int init_net;
 } wcamg_setup_params;
 
 /* Setup stage (0) of Sec. 3: (0-a) SAP applied n_init times to the start
@@ -206,6 +209,27 @@ typedef struct {
  * tol within max_iters (info filled either way). */
 int wcamg_solve(wcamg_ctx* ctx, const void* b, void* x, int nrhs, const wcamg_solve_params* p,
                 wcamg_solve_info* info);
+
+/* Gauge-equivariant network proposing initial test vectors (replaces setup
+ * step (0-a) when wcamg_setup_params.init_net is set).  Layers
+ *   psi'_o(x) = sum_i sum_{d=0..8} W[d][o][i] (T_d psi_i)(x),
+ * T_0 = 1, T_{+mu} psi(x) = U_mu(x) psi(x+mu), T_{-mu} psi(x) =
+ * U_mu(x-mu)^dag psi(x-mu) (boundary hops carry bc), W[d][o][i] a complex
+ * 4x4 spin matrix; no bias or nonlinearity (gauge covariant).  Weights:
+ * complex64 [layers][9][C][C][4][4]; C = 16.  Inputs r and outputs: C
+ * spinor fields (canonical layout, complex128).  The loss against a teacher
+ * basis Q (C fields, orthonormal per block and chirality) is the mean over
+ * blocks and chiralities of 1 - tr(Q^dag P_A Q)/C, P_A the projector on the
+ * span of the output A there. */
+int wcamg_net_init(wcamg_ctx* ctx, int layers, int channels, const void* weights, int where);
+int wcamg_net_get_weights(wcamg_ctx* ctx, void* weights, int where);
+int wcamg_net_forward(wcamg_ctx* ctx, const void* r, void* out, int where);
+/* Loss and its gradient dL/d conj(W) (complex64, weight layout; grad may be
+ * NULL) for inputs r and teacher basis Q on the loaded gauge field. */
+int wcamg_net_gradient(wcamg_ctx* ctx, const void* r, const void* teacher, double* loss, void* grad, int where);
+/* One training step: loss, gradient, then Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8) with learning rate lr on the real and imaginary parts. */
+int wcamg_net_train_step(wcamg_ctx* ctx, const void* r, const void* teacher, double lr, double* loss, int where);
 
 /* Launch-variant autotuner (on by default): the first time a kernel is
  * launched for a new key (kernel, shapes, precision, GPU architecture) each

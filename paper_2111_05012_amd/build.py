@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, 'csrc')
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, 'libwcamg.so')
-SOURCES = ['fine.hip', 'coarse.hip', 'blas.hip', 'api.cpp']
+SOURCES = ['fine.hip', 'coarse.hip', 'blas.hip', 'net.hip', 'api.cpp']
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 FLAGS = ['-O3', '-std=c++17', '-fPIC', '--offload-arch=gfx950', '-munsafe-fp-atomics',
          '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',

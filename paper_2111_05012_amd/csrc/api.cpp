@@ -221,6 +221,67 @@ struct wcamg_ctx {
   size_t lds_max = 0;            // LDS bytes available to one workgroup
   Tuner tuner;
   std::string arch;
+  // equivariant network for initial test vectors
+  struct Net {
+    int L = 0, C = 0, t = 0;
+    DevBuf W, m, v, grad, part;
+    std::vector<void*> acts;  // L+1 activation fields [C][12][V] (FP32)
+  } net;
+  std::vector<std::unique_ptr<DevBuf>> net_act_bufs;
+  size_t net_wsize() const { return (size_t)net.L * 9 * net.C * net.C * 16; }
+
+  // forward pass from C input fields (FP32 [C][12][V]); activations kept for backward
+  void net_forward(const void* r) {
+    size_t fb = (size_t)net.C * 12 * g.V * sizeof(float2);
+    while ((int)net_act_bufs.size() < net.L + 1) net_act_bufs.emplace_back(new DevBuf());
+    net.acts.resize(net.L + 1);
+    for (int l = 0; l <= net.L; ++l) net.acts[l] = net_act_bufs[l]->ensure(fb, capturing);
+    HIPCHK(hipMemcpyAsync(net.acts[0], r, fb, hipMemcpyDeviceToDevice, st));
+    size_t ws = (size_t)9 * net.C * net.C * 16;
+    for (int l = 0; l < net.L; ++l)
+      launch_ptc(g, (const float2*)net.W.p + l * ws, (const float2*)net.acts[l], (float2*)net.acts[l + 1],
+                 (const double2*)U64.p, 0, st);
+  }
+
+  // subspace loss of the last activation against the teacher Q (FP32 [C][12][V])
+  // and its gradient into net.grad; returns the loss (synchronises)
+  double net_loss_backward(const void* Q) {
+    int C = net.C;
+    size_t fb = (size_t)C * 12 * g.V * sizeof(float2);
+    size_t rs = (size_t)g.nblk * 2 * C;
+    double2* G = (double2*)W("nt_G", (size_t)C * rs * sizeof(double2));
+    double2* B = (double2*)W("nt_B", (size_t)C * rs * sizeof(double2));
+    float2* cq = (float2*)W("nt_cq", (size_t)C * rs * sizeof(float2));
+    float2* ca = (float2*)W("nt_ca", (size_t)C * rs * sizeof(float2));
+    double* lp = (double*)W("nt_lp", (size_t)2 * g.nblk * sizeof(double));
+    float2* ga = (float2*)W("nt_ga", fb);
+    float2* gb = (float2*)W("nt_gb", fb);
+    const void* A = net.acts[net.L];
+    launch_restrict(g, C, C, A, C64, A, C64, frs(), G, C128, rs, 2 * C, 1, st);
+    launch_restrict(g, C, C, A, C64, Q, C64, frs(), B, C128, rs, 2 * C, 1, st);
+    launch_net_loss_coef(g.nblk, G, B, rs, 1.0 / (C * 2.0 * g.nblk), cq, ca, lp, st);
+    launch_prolong(g, C, C, Q, C64, cq, C64, rs, 2 * C, ga, C64, frs(), 0, 1, st);
+    launch_prolong(g, C, C, A, C64, ca, C64, rs, 2 * C, ga, C64, frs(), 1, 1, st);
+    size_t ws = (size_t)9 * C * C * 16;
+    int nwg = ptc_wgrad_nwg(g);
+    net.part.ensure((size_t)nwg * ws * sizeof(float2), capturing);
+    float2* gcur = ga;
+    float2* gnext = gb;
+    for (int l = net.L - 1; l >= 0; --l) {
+      launch_ptc_wgrad(g, gcur, (const float2*)net.acts[l], (const double2*)U64.p, (float2*)net.part.p,
+                       (float2*)net.grad.p + l * ws, st);
+      if (l > 0) {
+        launch_ptc(g, (const float2*)net.W.p + l * ws, gcur, gnext, (const double2*)U64.p, 1, st);
+        std::swap(gcur, gnext);
+      }
+    }
+    std::vector<double> hl(2 * g.nblk);
+    HIPCHK(hipMemcpyAsync(hl.data(), lp, hl.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double loss = 0;
+    for (double v : hl) loss += v;
+    return loss / hl.size();
+  }
 
   // pick the fastest of `cands` for `key` (runs each on the real operands
   // when the key is new and no graph is being captured)
@@ -962,6 +1023,7 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
   if (!c) return WCAMG_EINVAL;
   return guard(c, [&] {
     require(p && p->init_vectors, "setup needs init_vectors");
+    require(!p->init_net || p->prec == WCAMG_PREC_MIXED || p->prec == WCAMG_PREC_FP64, "invalid prec");
     check_where(p->init_where);
     require(c->have_gauge, "no gauge field", WCAMG_ESTATE);
     c->have_hier = false;
@@ -974,10 +1036,19 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
     const double2* Vd = (const double2*)io.in(p->init_vectors, cbytes, p->init_where, "io_in");
     void* Vw = c->W("su_w", c->fsz(nv, prec));
     void* Vt = c->W("su_t", c->fsz(nv, prec));
-    launch_pack_spinor(g, Vd, Vw, t, c->frs(), nv, c->st);
-    for (int k = 0; k < p->n_init; ++k) {
-      c->sap(Vw, Vt, nullptr, nv, p->sap_sweeps, p->mr_iters, prec);
-      std::swap(Vw, Vt);
+    if (p->init_net) {
+      // (0-a) replaced by the network: its output from the nv start vectors
+      require(c->net.L > 0 && c->net.C == nv, "init_net needs a network with nv channels (wcamg_net_init)");
+      void* r32 = c->W("su_r32", (size_t)nv * 12 * g.V * sizeof(float2));
+      launch_pack_spinor(g, Vd, r32, C64, c->frs(), nv, c->st);
+      c->net_forward(r32);
+      launch_convert(c->net.acts[c->net.L], C64, Vw, t, (size_t)nv * 12 * g.V, c->st);
+    } else {
+      launch_pack_spinor(g, Vd, Vw, t, c->frs(), nv, c->st);
+      for (int k = 0; k < p->n_init; ++k) {
+        c->sap(Vw, Vt, nullptr, nv, p->sap_sweeps, p->mr_iters, prec);
+        std::swap(Vw, Vt);
+      }
     }
     c->orthonormalize(Vw, nv, prec);
     c->store_vectors(Vw, nv);
@@ -1472,6 +1543,109 @@ int wcamg_autotune_info(wcamg_ctx* c, double* tune_ms, int* keys_tuned, int* key
     if (tune_ms) *tune_ms = c->tuner.tune_ms;
     if (keys_tuned) *keys_tuned = c->tuner.tuned;
     if (keys_known) *keys_known = (int)c->tuner.best.size();
+  });
+}
+
+int wcamg_net_init(wcamg_ctx* c, int layers, int channels, const void* weights, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(weights, "null pointer");
+    require(channels == net_channels(), "the network kernels are built for " + std::to_string(net_channels()) +
+                                            " channels");
+    require(layers >= 1 && layers <= 16, "layers must be in [1, 16]");
+    c->net.L = layers;
+    c->net.C = channels;
+    c->net.t = 0;
+    size_t n = c->net_wsize();
+    c->net.W.ensure(n * sizeof(float2), false);
+    c->net.grad.ensure(n * sizeof(float2), false);
+    c->net.m.ensure(n * sizeof(float2), false);
+    c->net.v.ensure(n * sizeof(float2), false);
+    HostIO io(c);
+    const void* wd = io.in(weights, n * sizeof(float2), where, "io_in");
+    HIPCHK(hipMemcpyAsync(c->net.W.p, wd, n * sizeof(float2), hipMemcpyDeviceToDevice, c->st));
+    launch_zero(c->net.m.p, n * sizeof(float2), c->st);
+    launch_zero(c->net.v.p, n * sizeof(float2), c->st);
+    HIPCHK(hipStreamSynchronize(c->st));
+  });
+}
+
+int wcamg_net_get_weights(wcamg_ctx* c, void* weights, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(weights, "null pointer");
+    require(c->net.L > 0, "no network", WCAMG_ESTATE);
+    size_t n = c->net_wsize() * sizeof(float2);
+    HostIO io(c);
+    void* wd = io.out(weights, n, where, "io_out");
+    HIPCHK(hipMemcpyAsync(wd, c->net.W.p, n, hipMemcpyDeviceToDevice, c->st));
+    io.finish(weights, wd, n, where);
+  });
+}
+
+int wcamg_net_forward(wcamg_ctx* c, const void* r, void* out, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(r && out, "null pointer");
+    require(c->have_gauge && c->net.L > 0, "needs a gauge field and a network", WCAMG_ESTATE);
+    const Geo& g = c->g;
+    int C = c->net.C;
+    size_t cb = (size_t)C * g.V * 12 * sizeof(double2);
+    HostIO io(c);
+    const double2* rd = (const double2*)io.in(r, cb, where, "io_in");
+    double2* od = (double2*)io.out(out, cb, where, "io_out");
+    void* r32 = c->W("nt_r", (size_t)C * 12 * g.V * sizeof(float2));
+    launch_pack_spinor(g, rd, r32, C64, c->frs(), C, c->st);
+    c->net_forward(r32);
+    launch_unpack_spinor(g, c->net.acts[c->net.L], C64, c->frs(), od, C, c->st);
+    HIPCHK(hipGetLastError());
+    io.finish(out, od, cb, where);
+  });
+}
+
+int wcamg_net_gradient(wcamg_ctx* c, const void* r, const void* teacher, double* loss, void* grad, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(r && teacher && loss, "null pointer");
+    require(c->have_gauge && c->net.L > 0, "needs a gauge field and a network", WCAMG_ESTATE);
+    const Geo& g = c->g;
+    int C = c->net.C;
+    size_t cb = (size_t)C * g.V * 12 * sizeof(double2);
+    HostIO io(c);
+    const double2* rd = (const double2*)io.in(r, cb, where, "io_in");
+    void* r32 = c->W("nt_r", (size_t)C * 12 * g.V * sizeof(float2));
+    launch_pack_spinor(g, rd, r32, C64, c->frs(), C, c->st);
+    const double2* qd = (const double2*)io.in(teacher, cb, where, "io_in2");
+    void* q32 = c->W("nt_q", (size_t)C * 12 * g.V * sizeof(float2));
+    launch_pack_spinor(g, qd, q32, C64, c->frs(), C, c->st);
+    c->net_forward(r32);
+    *loss = c->net_loss_backward(q32);
+    if (grad) {
+      size_t n = c->net_wsize() * sizeof(float2);
+      void* gd = io.out(grad, n, where, "io_out");
+      HIPCHK(hipMemcpyAsync(gd, c->net.grad.p, n, hipMemcpyDeviceToDevice, c->st));
+      io.finish(grad, gd, n, where);
+    }
+  });
+}
+
+int wcamg_net_train_step(wcamg_ctx* c, const void* r, const void* teacher, double lr, double* loss, int where) {
+  if (!c) return WCAMG_EINVAL;
+  int rc = wcamg_net_gradient(c, r, teacher, loss, nullptr, where);
+  if (rc != WCAMG_OK) return rc;
+  return guard(c, [&] {
+    require(std::isfinite(*loss), "non-finite network loss", WCAMG_ENUMERIC);
+    c->net.t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    float c1 = 1.f - std::pow(b1, (float)c->net.t), c2 = 1.f - std::pow(b2, (float)c->net.t);
+    launch_adam((float2*)c->net.W.p, (const float2*)c->net.grad.p, (float2*)c->net.m.p, (float2*)c->net.v.p,
+                c->net_wsize(), (float)lr, b1, b2, 1e-8f, c1, c2, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
   });
 }
 

@@ -178,4 +178,16 @@ void launch_mr_update(void* x, void* r, const void* p, const double2* alpha, int
 // n complex Gaussian numbers (re, im each N(0,1)) from a counter-based generator
 void launch_gauss(void* out, int t, size_t n, unsigned long long seed, hipStream_t st);
 
+// equivariant network (net.hip): C = net_channels() channels, fields [C][12][V] FP32
+int net_channels();
+void launch_ptc(const Geo& g, const float2* W, const float2* in, float2* out, const double2* U, int adjoint,
+                hipStream_t st);
+int ptc_wgrad_nwg(const Geo& g);
+void launch_ptc_wgrad(const Geo& g, const float2* gout, const float2* in, const double2* U, float2* part,
+                      float2* grad, hipStream_t st);
+void launch_net_loss_coef(int nblk, const double2* G, const double2* B, size_t rs, double scale, float2* coefQ,
+                          float2* coefA, double* lpart, hipStream_t st);
+void launch_adam(float2* w, const float2* grad, float2* m, float2* v, size_t n, float lr, float b1, float b2,
+                 float eps, float c1, float c2, hipStream_t st);
+
 }  // namespace wc

@@ -1,0 +1,158 @@
+"""Train the gauge-equivariant network that proposes initial test vectors,
+and evaluate what it gains over the setup without it.
+
+Workload (defaults): 16^4 lattices, eps uniform in [0.3, 0.5] per seed
+(stream 4), kappa 0.1355, c_sw 1.0, blocks 4^4, N_v = 16, mixed precision.
+Teachers are the test vectors of the plain adaptive setup ((0-a) 3 SAP
+applications + 3 (0-b) passes) on each training seed; the network (4 layers,
+16 channels) maps 16 seeded random fields to 16 vectors and is trained with
+the subspace loss and Adam, entirely by the library's GPU kernels.
+
+Evaluation on held-out seeds, at tolerance 1e-10 on one Z2 source:
+  plain   -- (0-a) SAP x3, then n_adapt_plain (0-b) passes  (the reference setup)
+  ablate  -- no (0-a) (random vectors orthonormalised), then k (0-b) passes
+  net     -- (0-a) replaced by the trained network, then k (0-b) passes
+reporting setup time and outer iterations; the plain setup stays the fallback
+whenever the network setup needs more outer iterations.
+
+    python -m paper_2111_05012_amd.train_net --epochs 4 --out weights.npy --report report.json
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def eps_of(seed):
+    import synthetic as syn
+    return float(syn.rng(seed, syn.STREAM_EPS).uniform(0.3, 0.5))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--dims', type=int, nargs=4, default=[16, 16, 16, 16])
+    ap.add_argument('--block', type=int, nargs=4, default=[4, 4, 4, 4])
+    ap.add_argument('--kappa', type=float, default=0.1355)
+    ap.add_argument('--csw', type=float, default=1.0)
+    ap.add_argument('--train', type=int, nargs=2, default=[100, 299])
+    ap.add_argument('--eval', type=int, nargs=2, default=[300, 319])
+    ap.add_argument('--layers', type=int, default=4)
+    ap.add_argument('--epochs', type=int, default=4)
+    ap.add_argument('--lr', type=float, default=2e-3)
+    ap.add_argument('--k', type=int, default=1, help='(0-b) passes after the network / ablation start')
+    ap.add_argument('--n-adapt-plain', type=int, default=3)
+    ap.add_argument('--out', default=None)
+    ap.add_argument('--report', default=None)
+    args = ap.parse_args(argv)
+
+    import torch
+    import synthetic as syn
+    from paper_2111_05012_amd import Context, PREC_MIXED
+
+    dev = torch.device('cuda:0')
+    dims, block = tuple(args.dims), tuple(args.block)
+    C = 16
+    bc = (1, 1, 1, -1)
+    ctx = Context(dims, block, bc, args.kappa, args.csw)
+
+    def log(*a):
+        print('[train_net]', *a, file=sys.stderr, flush=True)
+
+    def plain_setup(seed, n_init=3, n_adapt=3, init_net=0, r=None):
+        V0 = r if r is not None else syn.gaussian_vectors_torch(dims, C, seed, dev)
+        p = ctx.setup_params(C, PREC_MIXED, init_vectors=V0, n_init=n_init, n_adapt=n_adapt, init_net=init_net)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.setup(p)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    def net_input(seed):
+        return syn.gaussian_vectors_torch(dims, C, seed + 100000, dev)
+
+    # teachers
+    train = list(range(args.train[0], args.train[1] + 1))
+    gauges, teachers = {}, {}
+    t0 = time.perf_counter()
+    for s in train:
+        U = syn.gauge_field_torch(dims, eps_of(s), s, dev)
+        ctx.load_gauge(U)
+        plain_setup(s)
+        Q = torch.zeros((C,) + syn.shape_of(dims) + (4, 3), dtype=torch.complex128, device=dev)
+        ctx.get_test_vectors(Q)
+        gauges[s] = U
+        teachers[s] = Q.to(torch.complex64)
+    t_teach = time.perf_counter() - t0
+    log('teachers: %d configs in %.1f s' % (len(train), t_teach))
+
+    # training
+    W = np.ascontiguousarray(np.stack(syn.net_weights(C, args.layers, 1)).astype(np.complex64))
+    ctx.net_init(torch.from_numpy(W).to(dev), args.layers, C)
+    order = np.random.default_rng(7).permutation(len(train))
+    hist = []
+    t0 = time.perf_counter()
+    for ep in range(args.epochs):
+        tot = 0.0
+        for k in order:
+            s = train[k]
+            ctx.load_gauge(gauges[s])
+            tot += ctx.net_train_step(net_input(s), teachers[s].to(torch.complex128), args.lr)
+        hist.append(tot / len(train))
+        log('epoch %d: mean loss %.4f' % (ep, hist[-1]))
+        order = np.random.default_rng(8 + ep).permutation(len(train))
+    t_train = time.perf_counter() - t0
+    Wt = torch.zeros(W.shape, dtype=torch.complex64, device=dev)
+    ctx.net_get_weights(Wt)
+    if args.out:
+        np.save(args.out, Wt.cpu().numpy())
+
+    # evaluation
+    rows = []
+    for s in range(args.eval[0], args.eval[1] + 1):
+        U = syn.gauge_field_torch(dims, eps_of(s), s, dev)
+        ctx.load_gauge(U)
+        b = torch.from_numpy(syn.z2_source(dims, s)).to(dev)
+        x = torch.zeros_like(b)
+        row = dict(seed=s, eps=eps_of(s))
+        for name, kw in (('plain', dict(n_init=3, n_adapt=args.n_adapt_plain)),
+                         ('ablate', dict(n_init=0, n_adapt=args.k)),
+                         ('net', dict(n_init=0, n_adapt=args.k, init_net=1, r=net_input(s)))):
+            ts = plain_setup(s, **kw)
+            rc, info = ctx.solve(b, x, 1, tol=1e-10)
+            row[name] = dict(setup_s=round(ts, 4), iters=int(info.iters[0]), relres=float(info.relres[0]),
+                             converged=bool(rc == 0), solve_s=round(info.t_solve, 4))
+        # the network's loss against this seed's plain-setup vectors
+        rows.append(row)
+        log('seed %d: plain %s | ablate %s | net %s' % (s, row['plain'], row['ablate'], row['net']))
+
+    def mean(key, f):
+        return float(np.mean([r[key][f] for r in rows]))
+
+    summary = {name: dict(setup_s=mean(name, 'setup_s'), iters=mean(name, 'iters'),
+                          tts_s=mean(name, 'setup_s') + mean(name, 'solve_s'))
+               for name in ('plain', 'ablate', 'net')}
+    use_net = summary['net']['iters'] <= summary['plain']['iters'] and all(r['net']['converged'] for r in rows)
+    report = dict(config=dict(dims=dims, block=block, kappa=args.kappa, csw=args.csw, layers=args.layers,
+                              channels=C, epochs=args.epochs, lr=args.lr, k=args.k, train_seeds=args.train,
+                              eval_seeds=args.eval),
+                  teacher_s=round(t_teach, 2), train_s=round(t_train, 2), loss_history=hist,
+                  eval=rows, summary=summary,
+                  net_gain_vs_ablation_iters=summary['ablate']['iters'] - summary['net']['iters'],
+                  decision='net' if use_net else 'plain (fallback)')
+    print(json.dumps(report['summary']), flush=True)
+    log('decision:', report['decision'])
+    if args.report:
+        with open(args.report, 'w') as f:
+            json.dump(report, f, indent=1)
+    return report
+
+
+if __name__ == '__main__':
+    main()

@@ -32,7 +32,7 @@ class SetupParams(ctypes.Structure):
                 ('coarse_tol', ctypes.c_double), ('prec', ctypes.c_int), ('init_vectors', ctypes.c_void_p),
                 ('init_where', ctypes.c_int), ('nlevels', ctypes.c_int), ('block1', _c_int4), ('nv1', ctypes.c_int),
                 ('mr1_iters', ctypes.c_int), ('init_mr1_iters', ctypes.c_int), ('init_vectors1', ctypes.c_void_p),
-                ('seed1', ctypes.c_ulonglong)]
+                ('seed1', ctypes.c_ulonglong), ('init_net', ctypes.c_int)]
 
 
 class SolveParams(ctypes.Structure):
@@ -78,6 +78,11 @@ SIGNATURES = {
     'wcamg_coarse_solve': (_I, [_P, _P, _P, _I, _I, _D, _I]),
     'wcamg_vcycle': (_I, [_P, _P, _P, _I, _I]),
     'wcamg_solve': (_I, [_P, _P, _P, _I, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo)]),
+    'wcamg_net_init': (_I, [_P, _I, _I, _P, _I]),
+    'wcamg_net_get_weights': (_I, [_P, _P, _I]),
+    'wcamg_net_forward': (_I, [_P, _P, _P, _I]),
+    'wcamg_net_gradient': (_I, [_P, _P, _P, ctypes.POINTER(_D), _P, _I]),
+    'wcamg_net_train_step': (_I, [_P, _P, _P, _D, ctypes.POINTER(_D), _I]),
     'wcamg_autotune': (_I, [_P, _I, ctypes.c_char_p]),
     'wcamg_autotune_info': (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     'wcamg_kernel_timing': (_I, [_P, _I]),
@@ -192,9 +197,9 @@ class Context:
     @staticmethod
     def setup_params(nv, prec=PREC_FP64, n_init=3, n_adapt=3, sap_sweeps=4, mr_iters=6, coarse_iters=50,
                      coarse_tol=0.1, init_vectors=None, nlevels=2, block1=(1, 1, 1, 1), nv1=0, mr1_iters=4,
-                     init_mr1_iters=8, init_vectors1=None, seed1=1):
+                     init_mr1_iters=8, init_vectors1=None, seed1=1, init_net=0):
         p = SetupParams(nv, n_init, n_adapt, sap_sweeps, mr_iters, coarse_iters, coarse_tol, prec, None, DEVICE,
-                        nlevels, _c_int4(*block1), nv1, mr1_iters, init_mr1_iters, None, seed1)
+                        nlevels, _c_int4(*block1), nv1, mr1_iters, init_mr1_iters, None, seed1, init_net)
         if init_vectors is not None:
             ptr, w = _ptr(init_vectors)
             p.init_vectors = ptr
@@ -264,6 +269,32 @@ class Context:
         rc = self._chk(self.lib.wcamg_solve(self.h, pb, px, nrhs, ctypes.byref(prm), ctypes.byref(info)),
                        allow=(OK, NOT_CONVERGED))
         return rc, info
+
+    def net_init(self, weights, layers, channels=16):
+        p, w = _ptr(weights)
+        self._chk(self.lib.wcamg_net_init(self.h, layers, channels, p, w))
+
+    def net_get_weights(self, out):
+        p, w = _ptr(out)
+        self._done(self.lib.wcamg_net_get_weights(self.h, p, w), out)
+
+    def net_forward(self, r, out):
+        w = _same_where(r, out)
+        self._done(self.lib.wcamg_net_forward(self.h, _ptr(r)[0], _ptr(out)[0], w), out)
+
+    def net_gradient(self, r, teacher, grad=None):
+        w = _same_where(r, teacher)
+        loss = ctypes.c_double()
+        gp = _ptr(grad)[0] if grad is not None else None
+        self._done(self.lib.wcamg_net_gradient(self.h, _ptr(r)[0], _ptr(teacher)[0], ctypes.byref(loss), gp, w),
+                   *([grad] if grad is not None else []))
+        return loss.value
+
+    def net_train_step(self, r, teacher, lr):
+        w = _same_where(r, teacher)
+        loss = ctypes.c_double()
+        self._chk(self.lib.wcamg_net_train_step(self.h, _ptr(r)[0], _ptr(teacher)[0], lr, ctypes.byref(loss), w))
+        return loss.value
 
     def autotune(self, enable=True, cache_path=None):
         self._chk(self.lib.wcamg_autotune(self.h, int(enable), cache_path.encode() if cache_path else None))
