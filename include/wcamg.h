@@ -123,7 +123,8 @@ typedef struct {
   int coarse_iters;  /* coarse BiCGStab: maximum iterations */
   double coarse_tol; /* coarse BiCGStab: relative residual tolerance */
   int prec;          /* WCAMG_PREC_FP64 or WCAMG_PREC_MIXED */
-  const void* init_vectors; /* nv start vectors (canonical spinor layout), required */
+  const void* init_vectors; /* nv start vectors (canonical spinor layout), or NULL: complex
+                               Gaussian vectors from the library's counter-based generator (seed) */
   int init_where;    /* WCAMG_DEVICE or WCAMG_HOST for init_vectors */
   /* three-level hierarchy (nlevels = 3): level 1 aggregates block1 coarse
    * sites; its smoother is mr1_iters global minimal-residual iterations on
@@ -141,6 +142,7 @@ typedef struct {
   /* learned start: when nonzero, step (0-a) is replaced by the network of
    * wcamg_net_init applied to init_vectors (nv must equal its channels). */
   int init_net;
+  unsigned long long seed; /* start vectors when init_vectors is NULL */
 } wcamg_setup_params;
 
 /* Setup stage (0) of Sec. 3: (0-a) SAP applied n_init times to the start

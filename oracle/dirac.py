@@ -267,3 +267,53 @@ def allowed_momenta(dims, bc):
         n = np.arange(L)
         out.append(2 * np.pi * n / L if bc[mu] == 1 else (2 * n + 1) * np.pi / L)
     return out
+
+
+# ----------------------------------------------------------------------------
+# Single-site evaluation (for sampled checks on lattices too large for the
+# whole-field oracle): eq. (1) and the clover term at one site, by explicit
+# coordinate arithmetic on the canonical arrays.
+# ----------------------------------------------------------------------------
+def _at(field, c):
+    """field[..., t, z, y, x, a, b] at coordinates c = (x, y, z, t)."""
+    return field[..., c[3], c[2], c[1], c[0], :, :]
+
+
+def _step(c, dims, mu, s):
+    cc = list(c)
+    cc[mu] = (c[mu] + s) % dims[mu]
+    return tuple(cc)
+
+
+def clover_site(U, c, kappa, csw):
+    """F(x) at coordinates c as a 12x12 matrix (same reading as clover_full)."""
+    dims = (U.shape[4], U.shape[3], U.shape[2], U.shape[1])
+    F = np.zeros((12, 12), np.complex128)
+    lk = lambda mu, x: _at(U[mu], x)  # noqa: E731
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            xm = _step(c, dims, mu, -1)
+            xn = _step(c, dims, nu, -1)
+            xmn = _step(xm, dims, nu, -1)
+            q = (lk(mu, c) @ lk(nu, _step(c, dims, mu, 1)) @ dagger(lk(mu, _step(c, dims, nu, 1))) @ dagger(lk(nu, c))
+                 + lk(nu, c) @ dagger(lk(mu, _step(xm, dims, nu, 1))) @ dagger(lk(nu, xm)) @ lk(mu, xm)
+                 + dagger(lk(mu, xm)) @ dagger(lk(nu, xmn)) @ lk(mu, xmn) @ lk(nu, xn)
+                 + dagger(lk(nu, xn)) @ lk(mu, xn) @ lk(nu, _step(xn, dims, mu, 1)) @ dagger(lk(mu, c)))
+            fh = (q - dagger(q)) / 8.0
+            F += 1j * csw * kappa * np.kron(SIGMA[mu, nu], fh)
+    return F
+
+
+def apply_D_site(U, psi, c, kappa, csw, bc):
+    """(D psi)(x) at coordinates c, eq. (1); psi [Lt,Lz,Ly,Lx,4,3]."""
+    dims = (U.shape[4], U.shape[3], U.shape[2], U.shape[1])
+    p0 = _at(psi, c).reshape(12)
+    out = p0 + clover_site(U, c, kappa, csw) @ p0
+    for mu in range(4):
+        xf = _step(c, dims, mu, 1)
+        sf = bc[mu] if c[mu] == dims[mu] - 1 else 1.0
+        out -= kappa * sf * np.kron(ONE4 - GAMMA[mu], _at(U[mu], c)) @ _at(psi, xf).reshape(12)
+        xb = _step(c, dims, mu, -1)
+        sb = bc[mu] if c[mu] == 0 else 1.0
+        out -= kappa * sb * np.kron(ONE4 + GAMMA[mu], dagger(_at(U[mu], xb))) @ _at(psi, xb).reshape(12)
+    return out.reshape(4, 3)

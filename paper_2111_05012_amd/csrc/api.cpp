@@ -1022,7 +1022,7 @@ int wcamg_set_test_vectors(wcamg_ctx* c, const void* V, const wcamg_setup_params
 int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
   if (!c) return WCAMG_EINVAL;
   return guard(c, [&] {
-    require(p && p->init_vectors, "setup needs init_vectors");
+    require(p != nullptr, "null parameters");
     require(!p->init_net || p->prec == WCAMG_PREC_MIXED || p->prec == WCAMG_PREC_FP64, "invalid prec");
     check_where(p->init_where);
     require(c->have_gauge, "no gauge field", WCAMG_ESTATE);
@@ -1033,18 +1033,28 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
     int nv = p->nv, prec = p->prec, t = c->spin_t(prec);
     size_t cbytes = (size_t)nv * g.V * 12 * sizeof(double2);
     HostIO io(c);
-    const double2* Vd = (const double2*)io.in(p->init_vectors, cbytes, p->init_where, "io_in");
+    const double2* Vd = nullptr;
+    if (p->init_vectors) Vd = (const double2*)io.in(p->init_vectors, cbytes, p->init_where, "io_in");
     void* Vw = c->W("su_w", c->fsz(nv, prec));
     void* Vt = c->W("su_t", c->fsz(nv, prec));
+    // start vectors: given (canonical layout) or drawn by the counter-based
+    // generator (in the internal layout: the generator's element order is the
+    // internal one)
+    auto start = [&](void* dst, int dt) {
+      if (Vd)
+        launch_pack_spinor(g, Vd, dst, dt, c->frs(), nv, c->st);
+      else
+        launch_gauss(dst, dt, (size_t)nv * 12 * g.V, p->seed, c->st);
+    };
     if (p->init_net) {
       // (0-a) replaced by the network: its output from the nv start vectors
       require(c->net.L > 0 && c->net.C == nv, "init_net needs a network with nv channels (wcamg_net_init)");
       void* r32 = c->W("su_r32", (size_t)nv * 12 * g.V * sizeof(float2));
-      launch_pack_spinor(g, Vd, r32, C64, c->frs(), nv, c->st);
+      start(r32, C64);
       c->net_forward(r32);
       launch_convert(c->net.acts[c->net.L], C64, Vw, t, (size_t)nv * 12 * g.V, c->st);
     } else {
-      launch_pack_spinor(g, Vd, Vw, t, c->frs(), nv, c->st);
+      start(Vw, t);
       for (int k = 0; k < p->n_init; ++k) {
         c->sap(Vw, Vt, nullptr, nv, p->sap_sweeps, p->mr_iters, prec);
         std::swap(Vw, Vt);
@@ -1076,6 +1086,9 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
+    // setup workspaces (sized for nv right-hand sides) are released: the
+    // solve allocates its own, and the memory is needed for the Krylov basis
+    c->ws.clear();
     c->have_hier = true;
   });
 }

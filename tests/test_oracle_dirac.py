@@ -176,3 +176,19 @@ def test_clover_constant_abelian_field():
     F = od.clover_full(U, kappa, csw)
     want = -csw * kappa * np.sin(B) * np.kron(od.SIGMA[0, 1], np.diag([1.0, -1.0, 0.0]))
     assert np.abs(F - want).max() < 1e-14
+
+
+def test_single_site_evaluation_matches_field_oracle():
+    dims = (4, 6, 2, 4)
+    U = syn.gauge_field(dims, 0.5, 8)
+    kappa, csw = 0.13, 1.2
+    Fb = od.clover_blocks(U, kappa, csw)
+    psi = _rand_psi(dims, 1, 9)[0]
+    full = od.apply_D(U, Fb, psi, kappa, BC_AP)
+    Ff = od.clover_full(U, kappa, csw)
+    rng = np.random.default_rng(1)
+    for _ in range(12):
+        c = tuple(int(rng.integers(L)) for L in dims)
+        assert np.abs(od.clover_site(U, c, kappa, csw) - Ff[c[3], c[2], c[1], c[0]]).max() < 1e-14
+        got = od.apply_D_site(U, psi, c, kappa, csw, BC_AP)
+        assert np.abs(got - full[c[3], c[2], c[1], c[0]]).max() < 1e-13
