@@ -435,7 +435,9 @@ struct wcamg_ctx {
     char key[160];
     snprintf(key, sizeof(key), "dslash|op%d|in%d|out%d|f%d|c%d|res%d|V%d|Vb%d|n%d", op, in_t, out_t, a.fields16,
              a.compute32, b ? 1 : 0, g.V, g.Vb, nrhs);
-    a.block_size = tune(key, {64, 128, 256, 512}, [&](int v) {
+    std::vector<int> dcands = {64, 128, 256, 512};
+    if (op == OP_D) dcands.push_back(-1);  // colour-split variant
+    a.block_size = tune(key, dcands, [&](int v) {
       DslashArgs q = a;
       q.block_size = v;
       launch_dslash(q, st);

@@ -308,8 +308,133 @@ __global__ __launch_bounds__(512) void k_dslash(Geo g, const TI* __restrict__ in
   }
 }
 
+// One hop for a single colour row: with w the link row (forward: U[r][.],
+// backward: conj(U[.][r]) = row r of U^dag), acc[spin] += coef * row r of
+// (1 -/+ gamma_mu) W psi.
+template <int MU, bool FWD, class R>
+__device__ __forceinline__ void hop_row_acc(const cplx<R> (&psi)[12], const cplx<R> (&w)[3], R coef,
+                                            cplx<R> (&acc)[4]) {
+  using P = Proj<MU>;
+  constexpr int T0 = FWD ? P::t0 : (P::t0 ^ 2);
+  constexpr int T1 = FWD ? P::t1 : (P::t1 ^ 2);
+  constexpr int S0 = FWD ? P::s0 : (P::s0 ^ 2);
+  constexpr int S1 = FWD ? P::s1 : (P::s1 ^ 2);
+  cplx<R> g0 = {0, 0}, g1 = {0, 0};
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    cplx<R> h0 = psi[cc] + unit<T0>(psi[(2 + P::pi0) * 3 + cc]);
+    cplx<R> h1 = psi[3 + cc] + unit<T1>(psi[(2 + P::pi1) * 3 + cc]);
+    if (FWD) {
+      cmac(g0, w[cc], h0);
+      cmac(g1, w[cc], h1);
+    } else {
+      cjmac(g0, w[cc], h0);
+      cjmac(g1, w[cc], h1);
+    }
+  }
+  g0 = coef * g0;
+  g1 = coef * g1;
+  acc[0] = acc[0] + g0;
+  acc[1] = acc[1] + g1;
+  acc[2] = acc[2] + unit<S0>(P::pi0 == 0 ? g0 : g1);
+  acc[3] = acc[3] + unit<S1>(P::pi1 == 0 ? g0 : g1);
+}
+
+// Colour-split variant of the full operator: three wavefronts share a tile
+// of 64 sites, wavefront r computing the colour-r row of the result for all 4
+// spins.  Each thread reads the whole neighbour spinor (shared through the
+// caches with the other two rows) but only row r of each link, and holds a
+// quarter of the accumulators, for higher occupancy.
+template <class R, class TI, class TO, class TL, class TC>
+__global__ __launch_bounds__(192) void k_dslash_cs(Geo g, const TI* __restrict__ in, size_t in_rs,
+                                                   TO* __restrict__ out, size_t out_rs, const TO* __restrict__ b,
+                                                   const TL* __restrict__ U, const TC* __restrict__ C, R kappa) {
+  const int ntile = (g.V + 63) >> 6;
+  const int tile = xcd_remap(blockIdx.x, ntile);
+  if (tile >= ntile) return;
+  const int r = threadIdx.x >> 6;  // colour row of this wavefront
+  const int s = tile * 64 + (threadIdx.x & 63);
+  if (s >= g.V) return;
+  const int rh = blockIdx.y;
+  const TI* inr = in + rh * in_rs;
+  const int V = g.V;
+  SiteCoord c = decompose(g, s);
+  cplx<R> psi[12];
+  cplx<R> acc[4];
+  load_spinor<R>(inr, V, s, psi);
+  // (1 + F) psi, row r of each spin: F row (b, sl*3 + r) of chiral block b
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp) acc[sp] = psi[sp * 3 + r];
+#pragma unroll
+  for (int bq = 0; bq < 2; ++bq) {
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int i = sl * 3 + r;  // row inside the 6x6 block
+      cplx<R> a = {0, 0};
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        cplx<R> f;
+        if (i == j) {
+          cplx<R> dp = ld<R>(C, (size_t)(18 * bq + i / 2) * V + s);
+          f = {(i & 1) ? dp.y : dp.x, (R)0};
+        } else {
+          int lo = i < j ? i : j, hi = i < j ? j : i;
+          int k = 3 + lo * 5 - lo * (lo - 1) / 2 + (hi - lo - 1);  // index of (lo, hi) among the 15 upper entries
+          cplx<R> u = ld<R>(C, (size_t)(18 * bq + k) * V + s);
+          f = i < j ? u : cj(u);
+        }
+        cmac(a, f, psi[6 * bq + j]);
+      }
+      acc[2 * bq + sl] = acc[2 * bq + sl] + a;
+    }
+  }
+#pragma unroll 1
+  for (int dir = 0; dir < 8; ++dir) {
+    const int mu = dir & 3;
+    const bool fw = dir < 4;
+    int sign;
+    bool inb;
+    int nb = fw ? neighbour<true>(g, s, c, mu, sign, inb) : neighbour<false>(g, s, c, mu, sign, inb);
+    load_spinor<R>(inr, V, nb, psi);
+    cplx<R> u[3];  // row r of U_mu(x) (forward) or column r of U_mu(x-mu) (backward: row r of U^dag, conjugated)
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+      u[e] = fw ? ld<R>(U, (size_t)(mu * 9 + r * 3 + e) * V + s) : ld<R>(U, (size_t)(mu * 9 + e * 3 + r) * V + nb);
+    const R coef = -kappa * (R)sign;
+    switch (dir) {
+      case 0: hop_row_acc<0, true>(psi, u, coef, acc); break;
+      case 1: hop_row_acc<1, true>(psi, u, coef, acc); break;
+      case 2: hop_row_acc<2, true>(psi, u, coef, acc); break;
+      case 3: hop_row_acc<3, true>(psi, u, coef, acc); break;
+      case 4: hop_row_acc<0, false>(psi, u, coef, acc); break;
+      case 5: hop_row_acc<1, false>(psi, u, coef, acc); break;
+      case 6: hop_row_acc<2, false>(psi, u, coef, acc); break;
+      default: hop_row_acc<3, false>(psi, u, coef, acc); break;
+    }
+  }
+  TO* outr = out + rh * out_rs;
+  if (b) {
+    const TO* br = b + rh * out_rs;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+      size_t o = (size_t)(sp * 3 + r) * V + s;
+      st(outr, o, ld<R>(br, o) - acc[sp]);
+    }
+  } else {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) st(outr, (size_t)(sp * 3 + r) * V + s, acc[sp]);
+  }
+}
+
 template <class R, class TI, class TO, class TL, class TC>
 static void dslash_dispatch(const DslashArgs& a, hipStream_t st) {
+  if (a.block_size < 0 && a.op == OP_D) {
+    int nt = (a.g.V + 63) / 64;
+    k_dslash_cs<R, TI, TO, TL, TC><<<dim3(round8(nt), a.nrhs), 192, 0, st>>>(
+        a.g, (const TI*)a.in, a.in_rs, (TO*)a.out, a.out_rs, (const TO*)a.b, (const TL*)a.U, (const TC*)a.C,
+        (R)a.kappa);
+    return;
+  }
   const int bs = a.block_size > 0 ? a.block_size : 256;
   int ntile = (a.g.V + bs - 1) / bs;
   dim3 grid(round8(ntile), a.nrhs);

@@ -47,7 +47,7 @@ struct DslashArgs {
   int fields16 = 0;  // 0: FP64 links/clover, 1: FP16
   int compute32 = 0; // 0: FP64 arithmetic, 1: FP32
   double kappa = 0;
-  int block_size = 256;  // threads per workgroup (64 .. 512, autotuned)
+  int block_size = 256;  // threads per workgroup (64 .. 512, autotuned); -1: colour-split variant (OP_D)
 };
 void launch_dslash(const DslashArgs& a, hipStream_t st);
 

@@ -246,3 +246,28 @@ def test_three_level_setup_and_solve(prec):
     xg = prob.N(x)
     for k in range(2):
         assert np.linalg.norm(b[k] - prob.op.D(xg[k])) / np.linalg.norm(b[k]) <= 1e-10
+
+
+def test_dslash_every_launch_variant(tmp_path):
+    """All autotuner variants of the fine operator (workgroup sizes and the
+    colour-split kernel) give the oracle's result: force each one through the
+    tuner's cache file."""
+    import json
+    from paper_2111_05012_amd import PREC_FP64, PREC_MIXED
+    prob = Problem((6, 4, 4, 6), (2, 2, 2, 2), eps=0.5, seed=3, kappa=0.124, csw=1.1)
+    cache = str(tmp_path / 'tune.json')
+    prob.ctx.autotune(True, cache)
+    psi = syn.gaussian_vectors(prob.dims, 2, 61)
+    want = prob.op.D(psi)
+    for prec, tol in ((PREC_FP64, 1e-13), (PREC_MIXED, 2e-3)):
+        out = prob.zeros(psi.shape)
+        prob.ctx.apply_D(prob.T(psi), out, 2, prec)  # tunes and writes the cache
+        keys = json.load(open(cache))
+        for v in (64, 128, 256, 512, -1):
+            forced = {k: (v if k.split('|')[1] == 'dslash' else val) for k, val in keys.items()}
+            with open(cache, 'w') as f:
+                json.dump(forced, f)
+            prob.ctx.autotune(True, cache)
+            out = prob.zeros(psi.shape)
+            prob.ctx.apply_D(prob.T(psi), out, 2, prec)
+            assert rel(prob.N(out), want) < tol, (prec, v)
