@@ -519,7 +519,7 @@ struct wcamg_ctx {
   COp op2() { return COp{h.cg2, h.N2, h.Dc2.p}; }
   size_t csz(const COp& o, int nrhs) const { return (size_t)nrhs * o.n() * ct_size(crs_t()); }
 
-  void coarse_mv(const COp& o, const void* x, void* y, const void* b, int nrhs) {
+  void coarse_mv(const COp& o, const void* x, void* y, const void* b, int nrhs, const BicgScal* live = nullptr) {
     double nc = o.cg.NC, N = o.N, cb = ct_size(crs_t());
     double by = nc * 9 * N * N * cb + nrhs * nc * N * cb * (b ? 3 : 2);
     std::vector<int> cands;
@@ -531,7 +531,8 @@ struct wcamg_ctx {
       launch_coarse_mv(o.cg, o.N, o.Dc, x, y, b, nrhs, o.n(), h.prec == WCAMG_PREC_MIXED, st, v);
     });
     Timed t(this, "coarse_mv", by, 8.0 * 9 * N * N * nc * nrhs, nrhs);
-    launch_coarse_mv(o.cg, o.N, o.Dc, x, y, b, nrhs, o.n(), h.prec == WCAMG_PREC_MIXED, st, var);
+    launch_coarse_mv(o.cg, o.N, o.Dc, x, y, b, nrhs, o.n(), h.prec == WCAMG_PREC_MIXED, st, var,
+                     live ? &live->active : nullptr, (int)(sizeof(BicgScal) / sizeof(int)));
   }
   void coarse_mv(const void* x, void* y, const void* b, int nrhs) { coarse_mv(op1(), x, y, b, nrhs); }
 
@@ -553,10 +554,10 @@ struct wcamg_ctx {
     std::vector<BicgScal> hs(nrhs);
     for (int it = 0; it < iters; ++it) {
       launch_bicg_p(p, r, v, t, n, n, nrhs, sc, st);
-      coarse_mv(o, p, v, nullptr, nrhs);
+      coarse_mv(o, p, v, nullptr, nrhs, sc);
       launch_bicg_alpha(rt, v, t, n, n, nrhs, part, sc, st);
       launch_bicg_s(s, r, v, t, n, n, nrhs, sc, st);
-      coarse_mv(o, s, tt, nullptr, nrhs);
+      coarse_mv(o, s, tt, nullptr, nrhs, sc);
       launch_bicg_omega(tt, s, t, n, n, nrhs, part, sc, 0.7, st);
       launch_bicg_xr(x, r, p, s, tt, rt, t, n, n, nrhs, part, sc, st);
       if (!capturing && (it % 4 == 3) && it + 1 < iters) {

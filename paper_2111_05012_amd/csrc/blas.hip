@@ -93,9 +93,15 @@ void launch_zero(void* p, size_t bytes, hipStream_t st) {
 template <class T, int ND>
 __global__ __launch_bounds__(RED_THREADS) void k_dots_partial(const T* a0, const T* b0, const T* a1, const T* b1,
                                                               const T* a2, const T* b2, size_t n, size_t rs,
-                                                              double2* part) {
+                                                              double2* part, const int* active, int astride) {
   const int r = blockIdx.y;
   const size_t off = r * rs;
+  if (active && !active[(size_t)r * astride]) {
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int k = 0; k < ND; ++k) part[((size_t)r * gridDim.x + blockIdx.x) * ND + k] = make_double2(0.0, 0.0);
+    return;
+  }
   const T* A[3] = {a0, a1, a2};
   const T* B[3] = {b0, b1, b2};
   double v[2 * ND];
@@ -118,19 +124,25 @@ __global__ __launch_bounds__(RED_THREADS) void k_dots_partial(const T* a0, const
 
 template <class T>
 static void dots_partial_t(int nd, const void* const* a, const void* const* b, size_t n, size_t rs, int nrhs,
-                           double2* part, hipStream_t st) {
+                           double2* part, hipStream_t st, const int* active, int astride) {
   dim3 grid(reduce_nwg(n), nrhs);
   const T* A[3] = {(const T*)a[0], nd > 1 ? (const T*)a[1] : nullptr, nd > 2 ? (const T*)a[2] : nullptr};
   const T* B[3] = {(const T*)b[0], nd > 1 ? (const T*)b[1] : nullptr, nd > 2 ? (const T*)b[2] : nullptr};
-  if (nd == 1) k_dots_partial<T, 1><<<grid, RED_THREADS, 0, st>>>(A[0], B[0], A[1], B[1], A[2], B[2], n, rs, part);
-  else if (nd == 2) k_dots_partial<T, 2><<<grid, RED_THREADS, 0, st>>>(A[0], B[0], A[1], B[1], A[2], B[2], n, rs, part);
-  else k_dots_partial<T, 3><<<grid, RED_THREADS, 0, st>>>(A[0], B[0], A[1], B[1], A[2], B[2], n, rs, part);
+  if (nd == 1)
+    k_dots_partial<T, 1><<<grid, RED_THREADS, 0, st>>>(A[0], B[0], A[1], B[1], A[2], B[2], n, rs, part, active,
+                                                       astride);
+  else if (nd == 2)
+    k_dots_partial<T, 2><<<grid, RED_THREADS, 0, st>>>(A[0], B[0], A[1], B[1], A[2], B[2], n, rs, part, active,
+                                                       astride);
+  else
+    k_dots_partial<T, 3><<<grid, RED_THREADS, 0, st>>>(A[0], B[0], A[1], B[1], A[2], B[2], n, rs, part, active,
+                                                       astride);
 }
 
 void launch_dots_partial(int nd, const void* const* a, const void* const* b, int t, size_t n, size_t rs, int nrhs,
-                         double2* part, hipStream_t st) {
-  if (t == C128) dots_partial_t<double2>(nd, a, b, n, rs, nrhs, part, st);
-  else if (t == C64) dots_partial_t<float2>(nd, a, b, n, rs, nrhs, part, st);
+                         double2* part, hipStream_t st, const int* active, int astride) {
+  if (t == C128) dots_partial_t<double2>(nd, a, b, n, rs, nrhs, part, st, active, astride);
+  else if (t == C64) dots_partial_t<float2>(nd, a, b, n, rs, nrhs, part, st, active, astride);
   else throw std::runtime_error("dots: unsupported type");
 }
 
@@ -258,7 +270,7 @@ void launch_bicg_alpha(const void* rt, const void* v, int t, size_t n, size_t rs
                        BicgScal* sc, hipStream_t st) {
   const void* a[1] = {rt};
   const void* b[1] = {v};
-  launch_dots_partial(1, a, b, t, n, rs, nrhs, part, st);
+  launch_dots_partial(1, a, b, t, n, rs, nrhs, part, st, &sc->active, sizeof(BicgScal) / sizeof(int));
   k_bicg_alpha_fin<<<nrhs, 64, 0, st>>>(part, reduce_nwg(n), sc);
 }
 
@@ -306,7 +318,7 @@ void launch_bicg_omega(const void* tt, const void* s, int t, size_t n, size_t rs
                        BicgScal* sc, double stab, hipStream_t st) {
   const void* a[3] = {tt, tt, s};
   const void* b[3] = {s, tt, s};
-  launch_dots_partial(3, a, b, t, n, rs, nrhs, part, st);
+  launch_dots_partial(3, a, b, t, n, rs, nrhs, part, st, &sc->active, sizeof(BicgScal) / sizeof(int));
   k_bicg_omega_fin<<<nrhs, 64, 0, st>>>(part, reduce_nwg(n), sc, stab);
 }
 

@@ -225,11 +225,18 @@ void launch_prolong(const Geo& g, int nv, int nrhs, const void* V, int v_t, cons
 template <class R, class TC, class TX, int NR>
 __global__ __launch_bounds__(256) void k_coarse_mv(CGeo cg, int N, const TC* __restrict__ Dc,
                                                    const TX* __restrict__ x, TX* __restrict__ y,
-                                                   const TX* __restrict__ b, size_t rs, int nrhs) {
+                                                   const TX* __restrict__ b, size_t rs, int nrhs,
+                                                   const int* __restrict__ active, int astride) {
   int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= cg.NC * N) return;
   int X = t / N, n = t - X * N;
   int r0 = blockIdx.y * NR;
+  // right-hand sides whose Krylov solve has stopped are skipped (their y is not used)
+  unsigned live = 0;
+#pragma unroll
+  for (int q = 0; q < NR; ++q)
+    if (r0 + q < nrhs && (!active || active[(size_t)(r0 + q) * astride])) live |= 1u << q;
+  if (!live) return;
   int c[4];
   {
     int q = X;
@@ -258,13 +265,13 @@ __global__ __launch_bounds__(256) void k_coarse_mv(CGeo cg, int N, const TC* __r
       cplx<R> bb = ld<R>(B, (size_t)m * N);
 #pragma unroll
       for (int q = 0; q < NR; ++q)
-        if (r0 + q < nrhs) cmac(acc[q], bb, ld<R>(xy, (r0 + q) * rs + m));
+        if (live & (1u << q)) cmac(acc[q], bb, ld<R>(xy, (r0 + q) * rs + m));
     }
   }
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     int r = r0 + q;
-    if (r < nrhs) {
+    if (live & (1u << q)) {
       size_t o = r * rs + (size_t)X * N + n;
       if (b)
         st(y, o, ld<R>(b, o) - acc[q]);
@@ -276,13 +283,13 @@ __global__ __launch_bounds__(256) void k_coarse_mv(CGeo cg, int N, const TC* __r
 
 template <class R, class TC, class TX>
 static void coarse_mv_run(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
-                          size_t rs, hipStream_t st, int variant) {
+                          size_t rs, hipStream_t st, int variant, const int* active, int astride) {
   int nb = (cg.NC * N + 255) / 256;
   auto go = [&](auto tag) {
     constexpr int NR = decltype(tag)::value;
     dim3 grid(nb, (nrhs + NR - 1) / NR);
     k_coarse_mv<R, TC, TX, NR><<<grid, 256, 0, st>>>(cg, N, (const TC*)Dc, (const TX*)x, (TX*)y, (const TX*)b, rs,
-                                                     nrhs);
+                                                     nrhs, active, astride);
   };
   int nr = variant > 0 ? variant : (nrhs == 1 ? 1 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : nrhs <= 12 ? 12 : 16);
   if (nr == 1)
@@ -298,11 +305,11 @@ static void coarse_mv_run(const CGeo& cg, int N, const void* Dc, const void* x, 
 }
 
 void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
-                      size_t rs, int prec32, hipStream_t st, int variant) {
+                      size_t rs, int prec32, hipStream_t st, int variant, const int* active, int astride) {
   if (prec32)
-    coarse_mv_run<float, float2, float2>(cg, N, Dc, x, y, b, nrhs, rs, st, variant);
+    coarse_mv_run<float, float2, float2>(cg, N, Dc, x, y, b, nrhs, rs, st, variant, active, astride);
   else
-    coarse_mv_run<double, double2, double2>(cg, N, Dc, x, y, b, nrhs, rs, st, variant);
+    coarse_mv_run<double, double2, double2>(cg, N, Dc, x, y, b, nrhs, rs, st, variant, active, astride);
 }
 
 // ---------------------------------------------------------------------------

@@ -99,9 +99,11 @@ void launch_prolong(const Geo& g, int nv, int nrhs, const void* V, int v_t, cons
                     int compute32, hipStream_t st);
 // coarse 9-point stencil: y[r][X] = sum_d Dc[X][d] x[r][X+e_d]   (or y = b - Dc x)
 // Dc stored [X][d][m][n] (column-major blocks), vectors [nrhs][NC][N]
-// variant: right-hand sides per thread (0: automatic; else 1, 4, 8, 12 or 16)
+// variant: right-hand sides per thread (0: automatic; else 1, 4, 8, 12 or 16).
+// active (optional): per-rhs flags at active[r * astride]; rhs with a zero flag are skipped.
 void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
-                      size_t rs, int prec32, hipStream_t st, int variant = 0);
+                      size_t rs, int prec32, hipStream_t st, int variant = 0, const int* active = nullptr,
+                      int astride = 0);
 // coarse operator eq.(7) from the stored test vectors V [nv][12][V] (mixed: FP16 V,
 // links, clover; FP32 arithmetic; complex64 Dc) into Dc [X][9][m][n]
 void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C, void* Dc,
@@ -131,8 +133,9 @@ void launch_zero(void* p, size_t bytes, hipStream_t st);
 // result[r*nd + k] for k < nd dots (a_k, b_k) -- see blas.hip for the sets
 int reduce_nwg(size_t n);
 // partial sums of up to 3 inner products <a_k, b_k> per rhs: part[r][wg][k] (complex)
+// active (optional): per-rhs flags at active[r * astride]; inactive rhs write zero partials
 void launch_dots_partial(int nd, const void* const* a, const void* const* b, int t, size_t n, size_t rs,
-                         int nrhs, double2* part, hipStream_t st);
+                         int nrhs, double2* part, hipStream_t st, const int* active = nullptr, int astride = 0);
 
 // BiCGStab on device-resident per-rhs scalars (coarse solve)
 struct BicgScal {
