@@ -202,6 +202,8 @@ def main():
     ap.add_argument('--warmup', type=int, default=1)
     ap.add_argument('--workload', default='c3', choices=sorted(WORKLOADS))
     ap.add_argument('--plain-rhs', type=int, default=1, help='RHS solved by the plain FP64 comparison (0: skip)')
+    ap.add_argument('--plain-batched', type=int, default=1,
+                    help='also time the FP64 AMG with all RHS batched (separates the batching and precision gains)')
     ap.add_argument('--no-cpu', action='store_true')
     ap.add_argument('--profile-kernels', action='store_true',
                     help='short kernel-only run for hardware counters: a 1 GiB copy, then D, SAP, V-cycle')
@@ -277,6 +279,14 @@ def main():
                               % w['nrhs'], iters=list(infop.iters[:nr]),
                      relres_max=max(infop.relres[:nr]))
         log('plain fp64: setup %.3f s, solve/rhs %.3f s' % (sp, per))
+    plain_b = None
+    if args.plain_batched and w['nrhs'] > 1:
+        xb = torch.zeros_like(b)
+        sb, vb, infob, rcb = run_step(ctx, U, b, xb, V0, w, PREC_FP64)
+        plain_b = dict(setup_s=round(sb, 3), solve_s=round(vb, 3), tts_s=round(sb + vb, 3),
+                       iters=list(infob.iters[:w['nrhs']]), relres_max=max(infob.relres[:w['nrhs']]),
+                       converged=rcb == 0, note='FP64 everywhere, all %d RHS batched' % w['nrhs'])
+        log('plain fp64 batched: setup %.3f s, solve %.3f s' % (sb, vb))
 
     cpu = None
     if not args.no_cpu:
@@ -297,8 +307,9 @@ def main():
         setup_s=round(sum(t[0] for t in times) / len(times), 4),
         solve_s=round(sum(t[1] for t in times) / len(times), 4),
         outer_iters=iters, relres_max=relres, converged=converged,
-        roofline=roof, dslash_fp64=dsl, kernels=kernels, plain_fp64=plain,
+        roofline=roof, dslash_fp64=dsl, kernels=kernels, plain_fp64=plain, plain_fp64_batched=plain_b,
         speedup_vs_plain=round(plain['tts_s'] / tts, 2) if plain else None,
+        speedup_vs_plain_batched=round(plain_b['tts_s'] / tts, 2) if plain_b else None,
         autotune=ctx.autotune_info(),
         cpu_baseline=cpu)
     print(json.dumps(res), flush=True)

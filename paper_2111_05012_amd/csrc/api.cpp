@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -35,14 +36,23 @@ struct WcError : std::runtime_error {
 #define HIPCHK(x)                                                                                \
   do {                                                                                           \
     hipError_t e_ = (x);                                                                         \
-    if (e_ != hipSuccess)                                                                        \
+    if (e_ != hipSuccess) {                                                                      \
+      /* reset the thread's last-error state so that a failed allocation is */                   \
+      /* not reported again by the next launch check                         */                  \
+      (void)hipGetLastError();                                                                   \
       throw WcError(e_ == hipErrorOutOfMemory ? WCAMG_ENOMEM : WCAMG_EHIP,                       \
                     std::string(#x) + ": " + hipGetErrorString(e_));                              \
+    }                                                                                            \
   } while (0)
 
 void require(bool c, const std::string& m, int code = WCAMG_EINVAL) {
   if (!c) throw WcError(code, m);
 }
+
+// Incremented whenever any device buffer of the library is allocated,
+// reallocated or freed: captured graphs hold raw addresses and are replayed
+// only while this count is unchanged since their capture.
+static std::atomic<unsigned long long> g_alloc_epoch{0};
 
 struct DevBuf {
   void* p = nullptr;
@@ -56,6 +66,7 @@ struct DevBuf {
   void* ensure(size_t bytes, bool frozen) {
     if (bytes <= n) return p;
     require(!frozen, "internal: workspace growth during graph capture", WCAMG_ESTATE);
+    ++g_alloc_epoch;
     if (p) HIPCHK(hipFree(p));
     p = nullptr;
     n = 0;
@@ -64,6 +75,7 @@ struct DevBuf {
     return p;
   }
   void release() {
+    ++g_alloc_epoch;
     if (p) (void)hipFree(p);
     p = nullptr;
     n = 0;
@@ -217,6 +229,8 @@ struct wcamg_ctx {
   // graphs: key (slot, nrhs) -> exec
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   int graph_prec = -1;
+  unsigned long long graph_epoch = 0;  // g_alloc_epoch when the graphs were captured
+  std::vector<double> graph_sig;        // hierarchy parameters the graphs were captured with
   hipStream_t cap_st = nullptr;  // library-owned stream used for graph capture
   size_t lds_max = 0;            // LDS bytes available to one workgroup
   Tuner tuner;
@@ -341,6 +355,31 @@ struct wcamg_ctx {
   void drop_graphs() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
+  }
+  // every scalar of the hierarchy that a captured V-cycle depends on
+  std::vector<double> hier_sig() const {
+    std::vector<double> s = {(double)h.prec, (double)h.nv, (double)h.sap_sweeps, (double)h.mr_iters,
+                             (double)h.coarse_iters, h.coarse_tol, (double)h.l1, (double)h.nw,
+                             (double)h.mr1_iters};
+    for (int m = 0; m < 4; ++m) s.push_back(h.b1[m]);
+    return s;
+  }
+  // drops the graphs when a buffer was (re)allocated or freed since their
+  // capture, or when the hierarchy's parameters changed
+  void validate_graphs() {
+    if (graphs.empty()) return;
+    if (graph_epoch != g_alloc_epoch.load() || graph_sig != hier_sig()) drop_graphs();
+  }
+  // Releases every workspace (and the graphs that refer to them) when less
+  // than `need` bytes (plus 2 GiB of headroom) of device memory are free.
+  // Called only on entry to a top-level operation, where no workspace
+  // pointer is live; workspaces are otherwise kept between calls.
+  void trim(size_t need) {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    if (fr >= need + ((size_t)2 << 30)) return;
+    drop_graphs();
+    ws.clear();
   }
 
   // ---- kernel timing
@@ -756,7 +795,6 @@ struct wcamg_ctx {
     h.mr_iters = p->mr_iters;
     h.coarse_iters = p->coarse_iters;
     h.coarse_tol = p->coarse_tol;
-    drop_graphs();
   }
 };
 
@@ -901,7 +939,6 @@ int wcamg_load_gauge(wcamg_ctx* c, const void* U, int where) {
     HIPCHK(hipStreamSynchronize(c->st));
     c->have_gauge = true;
     c->have_hier = false;
-    c->drop_graphs();
   });
 }
 
@@ -918,7 +955,6 @@ int wcamg_load_clover(wcamg_ctx* c, const void* F, int where) {
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
     c->have_hier = false;
-    c->drop_graphs();
   });
 }
 
@@ -1035,6 +1071,8 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
     const Geo& g = c->g;
     int nv = p->nv, prec = p->prec, t = c->spin_t(prec);
     size_t cbytes = (size_t)nv * g.V * 12 * sizeof(double2);
+    // at most eight fine fields of nv vectors are live during the setup
+    c->trim(8 * c->fsz(nv, prec));
     HostIO io(c);
     const double2* Vd = nullptr;
     if (p->init_vectors) Vd = (const double2*)io.in(p->init_vectors, cbytes, p->init_where, "io_in");
@@ -1089,9 +1127,6 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
-    // setup workspaces (sized for nv right-hand sides) are released: the
-    // solve allocates its own, and the memory is needed for the Krylov basis
-    c->ws.clear();
     c->have_hier = true;
   });
 }
@@ -1348,6 +1383,7 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
       c->vcycle(in, zj, nrhs);
       return;
     }
+    c->validate_graphs();
     auto key = std::make_pair(j, nrhs);
     auto it = c->graphs.find(key);
     if (it == c->graphs.end() || c->graph_prec != prec) {
@@ -1378,6 +1414,15 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
       hipGraphExec_t ex;
       HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
       HIPCHK(hipGraphDestroy(gr));
+      if (c->graphs.empty()) {
+        c->graph_epoch = g_alloc_epoch.load();
+        c->graph_sig = c->hier_sig();
+      } else if (c->graph_epoch != g_alloc_epoch.load()) {
+        // a buffer moved while this graph was captured: the others are stale
+        c->drop_graphs();
+        c->graph_epoch = g_alloc_epoch.load();
+        c->graph_sig = c->hier_sig();
+      }
       c->graphs[key] = ex;
       c->graph_prec = prec;
       it = c->graphs.find(key);
@@ -1525,6 +1570,15 @@ int wcamg_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, const wcamg_solv
     const Geo& g = c->g;
     size_t n = (size_t)12 * g.V;
     int chunk = p->rhs_chunk > 0 ? std::min(p->rhs_chunk, nrhs) : nrhs;
+    {
+      // packed b and x, the FP64 Krylov basis, the preconditioned vectors,
+      // the V-cycle's input and about four fine fields inside the V-cycle
+      const int prec = c->h.prec;
+      size_t per = 2 * sizeof(double2) + (size_t)(p->restart + 1) * sizeof(double2) +
+                   (size_t)p->restart * ct_size(c->spin_t(prec)) +
+                   (prec == WCAMG_PREC_MIXED ? sizeof(float2) : 0);
+      c->trim((size_t)chunk * n * per + 4 * c->fsz(chunk, prec));
+    }
     wcamg_solve_info inf;
     std::memset(&inf, 0, sizeof(inf));
     for (int r0 = 0; r0 < nrhs; r0 += chunk) {

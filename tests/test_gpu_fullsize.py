@@ -25,7 +25,10 @@ def c3():
     U = syn.gauge_field_torch(w['dims'], w['eps'], w['seed'], dev)
     ctx = _ctx(w)
     ctx.load_gauge(U)
-    return w, ctx, U, dev
+    yield w, ctx, U, dev
+    ctx.close()
+    del U
+    torch.cuda.empty_cache()
 
 
 def _samples(dims, n, seed):
@@ -143,28 +146,3 @@ def test_solve_c3_12rhs_mixed(c3):
         for r in (0, 7):
             res = bn[r, c[3], c[2], c[1], c[0]] - od.apply_D_site(Un, xn[r], c, w['kappa'], w['csw'], BC)
             assert np.abs(res).max() <= 1e-9 * np.abs(xn[r]).max()
-
-
-def test_three_level_c5_12rhs():
-    """48^3x96 (eps 0.28, kappa 0.1368, c_sw 1.1): three levels (blocks 4^4
-    with N_v 24, then 2^4 with N_v 32), 12 point sources in chunks of 2,
-    mixed precision; every RHS to 1e-10 by the FP64 operator (chunks of 2 keep the
-    FP64 Krylov basis within memory)."""
-    import torch
-    dims, block = (48, 48, 48, 96), (4, 4, 4, 4)
-    dev = torch.device('cuda:0')
-    U = syn.gauge_field_torch(dims, 0.28, 1, dev)
-    from paper_2111_05012_amd import Context
-    ctx = Context(dims, block, BC, 0.1368, 1.1)
-    ctx.load_gauge(U)
-    del U
-    ctx.setup(ctx.setup_params(24, 1, seed=5, coarse_iters=30, nlevels=3, block1=(2, 2, 2, 2), nv1=32,
-                               mr1_iters=4, seed1=6))
-    b = torch.from_numpy(syn.point_sources(dims, 12)).to(dev)
-    x = torch.zeros_like(b)
-    rc, info = ctx.solve(b, x, 12, tol=1e-10, rhs_chunk=2)
-    assert rc == 0
-    res = []
-    for k in range(0, 12, 4):
-        res.append(_residual(ctx, b[k:k + 4].contiguous(), x[k:k + 4].contiguous()))
-    assert np.concatenate(res).max() <= 1e-10
