@@ -2,8 +2,9 @@
 // coarse 9-point block stencil of eq. (7) and the per-block Cholesky factor
 // used to orthonormalise the test vectors (<I|J> = delta_IJ, Sec. 3).
 //
-// Test vectors are stored like spinor fields, [nv][12][V] (blocked site order),
-// so that block X's part of one (vector, component) row is contiguous.
+// Test vectors are stored like spinor fields, [nv][blk][12][Vb] (blocked site
+// order, block-major planes), so that block X's part of one vector is one
+// contiguous range of 12 Vb elements.
 // Coarse vectors are [rhs][X][N] with N = 2 nv and n = s*nv + i.  The coarse
 // operator is stored [X][d][m][n] (each 2nv x 2nv block column-major) with
 // d = 0 self, 1+mu forward, 5+mu backward neighbour.
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(256) void k_restrict(Geo g, int nv, int nrhs, int T
   const int i = rem / nrg;
   const int rg = rem - i * nrg;
   const int V_ = g.V;
-  const size_t base = (size_t)X * g.Vb;
+  const size_t base = (size_t)X * 12 * g.Vb;  // plane 0 of block X
   cplx<RA> acc[RB];
 #pragma unroll
   for (int q = 0; q < RB; ++q) acc[q] = {0, 0};
@@ -45,13 +46,13 @@ __global__ __launch_bounds__(256) void k_restrict(Geo g, int nv, int nrhs, int T
       int st_ = e % TS;
       int row = e / TS;  // i*12 + a
       int ii = row / 12, a = row - ii * 12;
-      sv[(st_ * nv + ii) * 12 + a] = V[(size_t)row * V_ + base + s0 + st_];
+      sv[(st_ * nv + ii) * 12 + a] = V[(size_t)ii * 12 * V_ + base + (size_t)a * g.Vb + s0 + st_];
     }
     for (int e = t; e < TS * nrhs * 12; e += 256) {
       int st_ = e % TS;
       int row = e / TS;  // r*12 + a
       int r = row / 12, a = row - r * 12;
-      si[(st_ * nrhs + r) * 12 + a] = ld<RA>(in, r * in_rs + (size_t)a * V_ + base + s0 + st_);
+      si[(st_ * nrhs + r) * 12 + a] = ld<RA>(in, r * in_rs + (size_t)a * g.Vb + base + s0 + st_);
     }
     __syncthreads();
     if (t < nout) {
@@ -140,6 +141,7 @@ __global__ __launch_bounds__(256) void k_prolong(Geo g, int nv, int nrhs, const 
   int col = t / V_;
   int s = t - col * V_;
   int X = s / g.Vb;
+  const size_t fb = fbase_b(g, 12, s, X);
   for (int r0 = 0; r0 < nrhs; r0 += RB) {
     cplx<R> acc[4][RB];
 #pragma unroll
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(256) void k_prolong(Geo g, int nv, int nrhs, const 
     for (int i = 0; i < nv; ++i) {
       cplx<R> v[4];
 #pragma unroll
-      for (int sp = 0; sp < 4; ++sp) v[sp] = ld<R>(V, (size_t)(i * 12 + sp * 3 + col) * V_ + s);
+      for (int sp = 0; sp < 4; ++sp) v[sp] = ld<R>(V, (size_t)i * 12 * V_ + (size_t)(sp * 3 + col) * g.Vb + fb);
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
         int r = r0 + q;
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(256) void k_prolong(Geo g, int nv, int nrhs, const 
       if (r < nrhs) {
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp) {
-          size_t o = r * out_rs + (size_t)(sp * 3 + col) * V_ + s;
+          size_t o = r * out_rs + (size_t)(sp * 3 + col) * g.Vb + fb;
           cplx<R> val = acc[sp][q];
           if (accumulate) val = val + ld<R>(out, o);
           st(out, o, val);
@@ -369,8 +371,10 @@ __global__ __launch_bounds__(256) void k_coarse_build(Geo g, int nv, R kappa, co
           loc = cc[0] * g.sB[0] + cc[1] * g.sB[1] + cc[2] * g.sB[2] + cc[3] * g.sB[3];
         }
         const int sx = X * g.Vb + loc;
+        const int ps = g.Vb;
+        const size_t fb12 = fbase_b(g, 12, sx, X), fb36 = fbase_b(g, 36, sx, X);
         const TV* vjp = V + (size_t)j * 12 * Vg;
-        load_spinor<R>(vjp, Vg, sx, vj);
+        ld_spinor<R>(vjp, ps, fb12, vj);
         SiteCoord c = decompose(g, sx);
         cplx<R> psi[12], u[9];
 #pragma unroll
@@ -380,7 +384,7 @@ __global__ __launch_bounds__(256) void k_coarse_build(Geo g, int nv, R kappa, co
           for (int a = 0; a < 12; ++a) psi[a] = (a >= a0 && a < a0 + 6) ? vj[a] : cplx<R>{0, 0};
 #pragma unroll
           for (int a = 0; a < 12; ++a) gj[a] = psi[a];
-          clover_accum<R>(C, Vg, sx, psi, gj);
+          clover_acc<R>(C, ps, fb36, psi, gj);
 #pragma unroll 1
           for (int dir = 0; dir < 8; ++dir) {
             const int m = dir & 3;
@@ -388,31 +392,32 @@ __global__ __launch_bounds__(256) void k_coarse_build(Geo g, int nv, R kappa, co
             bool inb;
             int nb = dir < 4 ? neighbour<true>(g, sx, c, m, sign, inb) : neighbour<false>(g, sx, c, m, sign, inb);
             if (!inb) continue;
-            load_spinor<R>(vjp, Vg, nb, psi);
+            ld_spinor<R>(vjp, ps, fbase_b(g, 12, nb, X), psi);
 #pragma unroll
             for (int a = 0; a < 12; ++a)
               if (a < a0 || a >= a0 + 6) psi[a] = {0, 0};
             if (dir < 4) {
-              load_link<R>(U, Vg, m, sx, u);
+              ld_link<R>(U, ps, m, fb36, u);
               hop_any<true>(m, psi, u, -kappa * (R)sign, gj);
             } else {
-              load_link<R>(U, Vg, m, nb, u);
+              ld_link<R>(U, ps, m, fbase_b(g, 36, nb, X), u);
               hop_any<false>(m, psi, u, -kappa * (R)sign, gj);
             }
           }
         } else {
-          int sign;
+          int sign, nblk;
           bool inb;
-          int nb = fwd ? neighbour<true>(g, sx, c, mu, sign, inb) : neighbour<false>(g, sx, c, mu, sign, inb);
-          load_spinor<R>(vjp, Vg, nb, psi);
+          int nb = fwd ? neighbour<true>(g, sx, c, mu, sign, inb, nblk)
+                       : neighbour<false>(g, sx, c, mu, sign, inb, nblk);
+          ld_spinor<R>(vjp, ps, fbase_b(g, 12, nb, nblk), psi);
 #pragma unroll
           for (int a = 0; a < 12; ++a)
             if (a < a0 || a >= a0 + 6) psi[a] = {0, 0};
           if (fwd) {
-            load_link<R>(U, Vg, mu, sx, u);
+            ld_link<R>(U, ps, mu, fb36, u);
             hop_any<true>(mu, psi, u, -kappa * (R)sign, gj);
           } else {
-            load_link<R>(U, Vg, mu, nb, u);
+            ld_link<R>(U, ps, mu, fbase_b(g, 36, nb, nblk), u);
             hop_any<false>(mu, psi, u, -kappa * (R)sign, gj);
           }
         }

@@ -3,12 +3,13 @@
 // domain-crossing hops) and the SAP smoother (Sec. 3) with minimal-residual
 // block solves.
 //
-// Internal layouts (blocked site order, see wc_common.h):
-//   spinor  [rhs][12 = spin*3 + colour][V]         complex (double2 / float2)
-//   links   [4 mu][9 = row*3 + col][V]            complex (double2 / half2)
-//   clover  [36 pairs][V]: per chirality b (pairs 18b..18b+17) the Hermitian
-//           6x6 block as 6 real diagonal entries (pairs 0..2) followed by the
-//           15 upper entries (i<j, row-major) as complex numbers.
+// Internal layouts (blocked site order, block-major planes, see wc_common.h):
+//   spinor  [rhs][blk][12 = spin*3 + colour][Vb]          complex (double2 / float2)
+//   links   [blk][36 = mu*9 + row*3 + col][Vb]           complex (double2 / half2)
+//   clover  [blk][36 pairs][Vb]: per chirality b (pairs 18b..18b+17) the
+//           Hermitian 6x6 block as 6 real diagonal entries (pairs 0..2)
+//           followed by the 15 upper entries (i<j, row-major) as complex
+//           numbers.
 #include "wc_dirac.h"
 #include "wc_kernels.h"
 
@@ -43,8 +44,9 @@ __global__ __launch_bounds__(256) void k_pack_spinor(Geo g, const double2* __res
   int s = blocked_index(g, cs);
   const double2* src = canon + ((size_t)r * g.V + cs) * 12;
   TO* dst = out + r * out_rs;
+  const size_t fb = fbase(g, 12, s);
 #pragma unroll
-  for (int a = 0; a < 12; ++a) st(dst, (size_t)a * g.V + s, ld<double>(src, a));
+  for (int a = 0; a < 12; ++a) st(dst, (size_t)a * g.Vb + fb, ld<double>(src, a));
 }
 
 template <class TI>
@@ -56,8 +58,9 @@ __global__ __launch_bounds__(256) void k_unpack_spinor(Geo g, const TI* __restri
   int s = blocked_index(g, cs);
   double2* dst = canon + ((size_t)r * g.V + cs) * 12;
   const TI* src = in + r * in_rs;
+  const size_t fb = fbase(g, 12, s);
 #pragma unroll
-  for (int a = 0; a < 12; ++a) st(dst, a, ld<double>(src, (size_t)a * g.V + s));
+  for (int a = 0; a < 12; ++a) st(dst, a, ld<double>(src, (size_t)a * g.Vb + fb));
 }
 
 __global__ __launch_bounds__(256) void k_pack_gauge(Geo g, const double2* __restrict__ canon,
@@ -70,14 +73,14 @@ __global__ __launch_bounds__(256) void k_pack_gauge(Geo g, const double2* __rest
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
     double2 v = src[e];
-    size_t o = (size_t)(mu * 9 + e) * g.V + s;
+    size_t o = (size_t)(mu * 9 + e) * g.Vb + fbase(g, 36, s);
     U64[o] = v;
     st(U16, o, cplx<double>{v.x, v.y});
   }
 }
 
 // pack a full Hermitian 6x6 chiral block pair (canonical [2][6][6]) into 36 pairs
-__device__ __forceinline__ void clover_pack_site(const double2 (&f)[2][6][6], int V, int s, double2* C64,
+__device__ __forceinline__ void clover_pack_site(const double2 (&f)[2][6][6], int ps, size_t base, double2* C64,
                                                  half2_t* C16) {
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
@@ -95,7 +98,7 @@ __device__ __forceinline__ void clover_pack_site(const double2 (&f)[2][6][6], in
       for (int j = i + 1; j < 6; ++j) pr[k++] = f[b][i][j];
 #pragma unroll
     for (int q = 0; q < 18; ++q) {
-      size_t o = (size_t)(18 * b + q) * V + s;
+      size_t o = (size_t)(18 * b + q) * ps + base;
       C64[o] = pr[q];
       if (C16) st(C16, o, cplx<double>{pr[q].x, pr[q].y});
     }
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(256) void k_pack_clover(Geo g, const double2* __res
   for (int b = 0; b < 2; ++b)
     for (int i = 0; i < 6; ++i)
       for (int j = 0; j < 6; ++j) f[b][i][j] = src[(b * 6 + i) * 6 + j];
-  clover_pack_site(f, g.V, s, C64, C16);
+  clover_pack_site(f, g.Vb, fbase(g, 36, s), C64, C16);
 }
 
 __global__ __launch_bounds__(256) void k_unpack_clover(Geo g, const double2* __restrict__ C64,
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(256) void k_unpack_clover(Geo g, const double2* __r
   double2* dst = canon + (size_t)cs * 72;
   for (int b = 0; b < 2; ++b) {
     double2 pr[18];
-    for (int q = 0; q < 18; ++q) pr[q] = C64[(size_t)(18 * b + q) * g.V + s];
+    for (int q = 0; q < 18; ++q) pr[q] = C64[(size_t)(18 * b + q) * g.Vb + fbase(g, 36, s)];
     double d[6] = {pr[0].x, pr[0].y, pr[1].x, pr[1].y, pr[2].x, pr[2].y};
     int k = 3;
     for (int i = 0; i < 6; ++i) {
@@ -145,9 +148,10 @@ __global__ __launch_bounds__(256) void k_unpack_clover(Geo g, const double2* __r
 struct Su3 {
   cplx<double> a[9];
 };
-__device__ __forceinline__ Su3 su3_load(const double2* U, int V, int mu, int s) {
+__device__ __forceinline__ Su3 su3_load(const Geo& g, const double2* U, int mu, int s) {
   Su3 m;
-  for (int e = 0; e < 9; ++e) m.a[e] = ld<double>(U, (size_t)(mu * 9 + e) * V + s);
+  const size_t fb = fbase(g, 36, s);
+  for (int e = 0; e < 9; ++e) m.a[e] = ld<double>(U, (size_t)(mu * 9 + e) * g.Vb + fb);
   return m;
 }
 __device__ __forceinline__ Su3 su3_mul(const Su3& x, const Su3& y) {
@@ -199,21 +203,21 @@ __global__ __launch_bounds__(128) void k_clover_build(Geo g, const double2* __re
   for (int mu = 0; mu < 4; ++mu) {
     for (int nu = mu + 1; nu < 4; ++nu, ++plane) {
       // leaf 1: U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
-      Su3 l1 = su3_mul(su3_mul(su3_load(U, g.V, mu, s), su3_load(U, g.V, nu, shifted(g, s, mu, 1, nu, 0))),
-                       su3_mul(su3_dag(su3_load(U, g.V, mu, shifted(g, s, nu, 1, mu, 0))),
-                               su3_dag(su3_load(U, g.V, nu, s))));
+      Su3 l1 = su3_mul(su3_mul(su3_load(g, U, mu, s), su3_load(g, U, nu, shifted(g, s, mu, 1, nu, 0))),
+                       su3_mul(su3_dag(su3_load(g, U, mu, shifted(g, s, nu, 1, mu, 0))),
+                               su3_dag(su3_load(g, U, nu, s))));
       // leaf 2: U_nu(x) U_mu(x-mu+nu)^dag U_nu(x-mu)^dag U_mu(x-mu)
       int xm = shifted(g, s, mu, -1, nu, 0);
-      Su3 l2 = su3_mul(su3_mul(su3_load(U, g.V, nu, s), su3_dag(su3_load(U, g.V, mu, shifted(g, s, mu, -1, nu, 1)))),
-                       su3_mul(su3_dag(su3_load(U, g.V, nu, xm)), su3_load(U, g.V, mu, xm)));
+      Su3 l2 = su3_mul(su3_mul(su3_load(g, U, nu, s), su3_dag(su3_load(g, U, mu, shifted(g, s, mu, -1, nu, 1)))),
+                       su3_mul(su3_dag(su3_load(g, U, nu, xm)), su3_load(g, U, mu, xm)));
       // leaf 3: U_mu(x-mu)^dag U_nu(x-mu-nu)^dag U_mu(x-mu-nu) U_nu(x-nu)
       int xmn = shifted(g, s, mu, -1, nu, -1);
       int xn = shifted(g, s, nu, -1, mu, 0);
-      Su3 l3 = su3_mul(su3_mul(su3_dag(su3_load(U, g.V, mu, xm)), su3_dag(su3_load(U, g.V, nu, xmn))),
-                       su3_mul(su3_load(U, g.V, mu, xmn), su3_load(U, g.V, nu, xn)));
+      Su3 l3 = su3_mul(su3_mul(su3_dag(su3_load(g, U, mu, xm)), su3_dag(su3_load(g, U, nu, xmn))),
+                       su3_mul(su3_load(g, U, mu, xmn), su3_load(g, U, nu, xn)));
       // leaf 4: U_nu(x-nu)^dag U_mu(x-nu) U_nu(x+mu-nu) U_mu(x)^dag
-      Su3 l4 = su3_mul(su3_mul(su3_dag(su3_load(U, g.V, nu, xn)), su3_load(U, g.V, mu, xn)),
-                       su3_mul(su3_load(U, g.V, nu, shifted(g, s, mu, 1, nu, -1)), su3_dag(su3_load(U, g.V, mu, s))));
+      Su3 l4 = su3_mul(su3_mul(su3_dag(su3_load(g, U, nu, xn)), su3_load(g, U, mu, xn)),
+                       su3_mul(su3_load(g, U, nu, shifted(g, s, mu, 1, nu, -1)), su3_dag(su3_load(g, U, mu, s))));
       Su3 fh;
       for (int e = 0; e < 9; ++e) {
         int i = e / 3, j = e % 3;
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(128) void k_clover_build(Geo g, const double2* __re
           }
     }
   }
-  clover_pack_site(f, g.V, s, C64, C16);
+  clover_pack_site(f, g.Vb, fbase(g, 36, s), C64, C16);
 }
 
 // ---------------------------------------------------------------------------
@@ -255,20 +259,21 @@ __global__ __launch_bounds__(512) void k_dslash(Geo g, const TI* __restrict__ in
   if (s >= g.V) return;
   int r = blockIdx.y;
   const TI* inr = in + r * in_rs;
-  const int V = g.V;
   SiteCoord c = decompose(g, s);
+  const int ps = g.Vb;
+  const size_t fb12 = fbase_b(g, 12, s, c.blk), fb36 = fbase_b(g, 36, s, c.blk);
   cplx<R> acc[12];
   cplx<R> psi[12];
   cplx<R> u[9];
   const int a0 = chir == 1 ? 6 : 0, a1 = chir == 0 ? 6 : 12;  // components kept by the chirality projection
   if (OP != OP_HOP) {
-    load_spinor<R>(inr, V, s, psi);
+    ld_spinor<R>(inr, ps, fb12, psi);
 #pragma unroll
     for (int a = 0; a < 12; ++a)
       if (a < a0 || a >= a1) psi[a] = {0, 0};
 #pragma unroll
     for (int a = 0; a < 12; ++a) acc[a] = psi[a];
-    clover_accum<R>(C, V, s, psi, acc);
+    clover_acc<R>(C, ps, fb36, psi, acc);
   } else {
 #pragma unroll
     for (int a = 0; a < 12; ++a) acc[a] = {0, 0};
@@ -279,21 +284,21 @@ __global__ __launch_bounds__(512) void k_dslash(Geo g, const TI* __restrict__ in
     const int mu = dir & 3;
     const bool fw = dir < 4;
     if (OP == OP_HOP && dir != hopdir) continue;
-    int sign;
+    int sign, nblk;
     bool inb;
-    int nb = fw ? neighbour<true>(g, s, c, mu, sign, inb) : neighbour<false>(g, s, c, mu, sign, inb);
+    int nb = fw ? neighbour<true>(g, s, c, mu, sign, inb, nblk) : neighbour<false>(g, s, c, mu, sign, inb, nblk);
     if (OP == OP_DSAP && !inb) continue;
     if (OP == OP_HOP && inb) continue;
-    load_spinor<R>(inr, V, nb, psi);
+    ld_spinor<R>(inr, ps, fbase_b(g, 12, nb, nblk), psi);
 #pragma unroll
     for (int a = 0; a < 12; ++a)
       if (a < a0 || a >= a1) psi[a] = {0, 0};
     R coef = -kappa * (R)sign;
     if (fw) {
-      load_link<R>(U, V, mu, s, u);
+      ld_link<R>(U, ps, mu, fb36, u);
       hop_any<true>(mu, psi, u, coef, acc);
     } else {
-      load_link<R>(U, V, mu, nb, u);
+      ld_link<R>(U, ps, mu, fbase_b(g, 36, nb, nblk), u);
       hop_any<false>(mu, psi, u, coef, acc);
     }
   }
@@ -301,10 +306,10 @@ __global__ __launch_bounds__(512) void k_dslash(Geo g, const TI* __restrict__ in
   if (b) {
     const TO* br = b + r * out_rs;
 #pragma unroll
-    for (int a = 0; a < 12; ++a) st(outr, (size_t)a * V + s, ld<R>(br, (size_t)a * V + s) - acc[a]);
+    for (int a = 0; a < 12; ++a) st(outr, (size_t)a * ps + fb12, ld<R>(br, (size_t)a * ps + fb12) - acc[a]);
   } else {
 #pragma unroll
-    for (int a = 0; a < 12; ++a) st(outr, (size_t)a * V + s, acc[a]);
+    for (int a = 0; a < 12; ++a) st(outr, (size_t)a * ps + fb12, acc[a]);
   }
 }
 
@@ -357,11 +362,12 @@ __global__ __launch_bounds__(192) void k_dslash_cs(Geo g, const TI* __restrict__
   if (s >= g.V) return;
   const int rh = blockIdx.y;
   const TI* inr = in + rh * in_rs;
-  const int V = g.V;
   SiteCoord c = decompose(g, s);
+  const int ps = g.Vb;
+  const size_t fb12 = fbase_b(g, 12, s, c.blk), fb36 = fbase_b(g, 36, s, c.blk);
   cplx<R> psi[12];
   cplx<R> acc[4];
-  load_spinor<R>(inr, V, s, psi);
+  ld_spinor<R>(inr, ps, fb12, psi);
   // (1 + F) psi, row r of each spin: F row (b, sl*3 + r) of chiral block b
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp) acc[sp] = psi[sp * 3 + r];
@@ -375,12 +381,12 @@ __global__ __launch_bounds__(192) void k_dslash_cs(Geo g, const TI* __restrict__
       for (int j = 0; j < 6; ++j) {
         cplx<R> f;
         if (i == j) {
-          cplx<R> dp = ld<R>(C, (size_t)(18 * bq + i / 2) * V + s);
+          cplx<R> dp = ld<R>(C, (size_t)(18 * bq + i / 2) * ps + fb36);
           f = {(i & 1) ? dp.y : dp.x, (R)0};
         } else {
           int lo = i < j ? i : j, hi = i < j ? j : i;
           int k = 3 + lo * 5 - lo * (lo - 1) / 2 + (hi - lo - 1);  // index of (lo, hi) among the 15 upper entries
-          cplx<R> u = ld<R>(C, (size_t)(18 * bq + k) * V + s);
+          cplx<R> u = ld<R>(C, (size_t)(18 * bq + k) * ps + fb36);
           f = i < j ? u : cj(u);
         }
         cmac(a, f, psi[6 * bq + j]);
@@ -392,14 +398,15 @@ __global__ __launch_bounds__(192) void k_dslash_cs(Geo g, const TI* __restrict__
   for (int dir = 0; dir < 8; ++dir) {
     const int mu = dir & 3;
     const bool fw = dir < 4;
-    int sign;
+    int sign, nblk;
     bool inb;
-    int nb = fw ? neighbour<true>(g, s, c, mu, sign, inb) : neighbour<false>(g, s, c, mu, sign, inb);
-    load_spinor<R>(inr, V, nb, psi);
+    int nb = fw ? neighbour<true>(g, s, c, mu, sign, inb, nblk) : neighbour<false>(g, s, c, mu, sign, inb, nblk);
+    ld_spinor<R>(inr, ps, fbase_b(g, 12, nb, nblk), psi);
+    const size_t nb36 = fbase_b(g, 36, nb, nblk);
     cplx<R> u[3];  // row r of U_mu(x) (forward) or column r of U_mu(x-mu) (backward: row r of U^dag, conjugated)
 #pragma unroll
     for (int e = 0; e < 3; ++e)
-      u[e] = fw ? ld<R>(U, (size_t)(mu * 9 + r * 3 + e) * V + s) : ld<R>(U, (size_t)(mu * 9 + e * 3 + r) * V + nb);
+      u[e] = fw ? ld<R>(U, (size_t)(mu * 9 + r * 3 + e) * ps + fb36) : ld<R>(U, (size_t)(mu * 9 + e * 3 + r) * ps + nb36);
     const R coef = -kappa * (R)sign;
     switch (dir) {
       case 0: hop_row_acc<0, true>(psi, u, coef, acc); break;
@@ -417,12 +424,12 @@ __global__ __launch_bounds__(192) void k_dslash_cs(Geo g, const TI* __restrict__
     const TO* br = b + rh * out_rs;
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp) {
-      size_t o = (size_t)(sp * 3 + r) * V + s;
+      size_t o = (size_t)(sp * 3 + r) * ps + fb12;
       st(outr, o, ld<R>(br, o) - acc[sp]);
     }
   } else {
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp) st(outr, (size_t)(sp * 3 + r) * V + s, acc[sp]);
+    for (int sp = 0; sp < 4; ++sp) st(outr, (size_t)(sp * 3 + r) * ps + fb12, acc[sp]);
   }
 }
 
@@ -516,28 +523,28 @@ __global__ __launch_bounds__(512) void k_sap_half(Geo g, int colour, int flags, 
   const bool act = l < Vb;
   const int s = blk * Vb + (act ? l : 0);
   const size_t off = blockIdx.y * rs;
-  const int V = g.V;
   const int nw = (blockDim.x + 63) >> 6;
   SiteCoord c = decompose(g, s);
+  const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
 
   cplx<R> rho[12], xm[12], p[12], psi[12], u[9];
   if (act) {
-    load_spinor<R>((flags & SAP_FIRST) ? b + off : r + off, V, s, rho);
+    ld_spinor<R>((flags & SAP_FIRST) ? b + off : r + off, Vb, fb12, rho);
     if (flags & SAP_DELTA) {
 #pragma unroll 1
       for (int mu = 0; mu < 4; ++mu) {
-        int sign;
+        int sign, nblk;
         bool inb;
-        int nb = neighbour<true>(g, s, c, mu, sign, inb);
+        int nb = neighbour<true>(g, s, c, mu, sign, inb, nblk);
         if (!inb) {
-          load_spinor<R>(delta + off, V, nb, psi);
-          load_link<R>(U, V, mu, s, u);
+          ld_spinor<R>(delta + off, Vb, fbase_b(g, 12, nb, nblk), psi);
+          ld_link<R>(U, Vb, mu, fb36, u);
           hop_any<true>(mu, psi, u, kappa * (R)sign, rho);
         }
-        nb = neighbour<false>(g, s, c, mu, sign, inb);
+        nb = neighbour<false>(g, s, c, mu, sign, inb, nblk);
         if (!inb) {
-          load_spinor<R>(delta + off, V, nb, psi);
-          load_link<R>(U, V, mu, nb, u);
+          ld_spinor<R>(delta + off, Vb, fbase_b(g, 12, nb, nblk), psi);
+          ld_link<R>(U, Vb, mu, fbase_b(g, 36, nb, nblk), u);
           hop_any<false>(mu, psi, u, kappa * (R)sign, rho);
         }
       }
@@ -556,7 +563,7 @@ __global__ __launch_bounds__(512) void k_sap_half(Geo g, int colour, int flags, 
     if (act) {
 #pragma unroll
       for (int a = 0; a < 12; ++a) p[a] = rho[a];
-      clover_accum<R>(C, V, s, rho, p);
+      clover_acc<R>(C, Vb, fb36, rho, p);
 #pragma unroll 1
       for (int mu = 0; mu < 4; ++mu) {
         int sign;
@@ -566,7 +573,7 @@ __global__ __launch_bounds__(512) void k_sap_half(Geo g, int colour, int flags, 
           int nl = nb - blk * Vb;
 #pragma unroll
           for (int a = 0; a < 12; ++a) psi[a] = lds[a * Vb + nl];
-          load_link<R>(U, V, mu, s, u);
+          ld_link<R>(U, Vb, mu, fb36, u);
           hop_any<true>(mu, psi, u, -kappa * (R)sign, p);
         }
         nb = neighbour<false>(g, s, c, mu, sign, inb);
@@ -574,7 +581,7 @@ __global__ __launch_bounds__(512) void k_sap_half(Geo g, int colour, int flags, 
           int nl = nb - blk * Vb;
 #pragma unroll
           for (int a = 0; a < 12; ++a) psi[a] = lds[a * Vb + nl];
-          load_link<R>(U, V, mu, nb, u);
+          ld_link<R>(U, Vb, mu, fb36 + (nl - l), u);  // same block: the neighbour's planes are nl - l further
           hop_any<false>(mu, psi, u, -kappa * (R)sign, p);
         }
       }
@@ -616,7 +623,7 @@ __global__ __launch_bounds__(512) void k_sap_half(Geo g, int colour, int flags, 
     TS* dr = delta + off;
 #pragma unroll
     for (int a = 0; a < 12; ++a) {
-      size_t o = (size_t)a * V + s;
+      size_t o = (size_t)a * Vb + fb12;
       cplx<R> x0 = {0, 0};
       if (!(flags & SAP_FIRST)) x0 = ld<R>(xr, o);
       else if (xinit) x0 = ld<R>(xinit + off, o);
@@ -627,13 +634,13 @@ __global__ __launch_bounds__(512) void k_sap_half(Geo g, int colour, int flags, 
   }
 }
 
-// Mixed-precision SAP half-sweep with the domain's operator held in
-// registers: one workgroup per domain of the active colour for ALL right-hand
-// sides.  Each thread keeps its site's 8 links (4 forward, 4 backward, FP16
-// packed) and clover block (FP16) in registers, loaded once, and runs the MR
-// block solves of every right-hand side in turn; only the residual goes
-// through LDS.  Links of hops that leave the domain are not needed by D_SAP;
-// the crossing-hop correction of step 1 reads them from memory.
+// Mixed-precision SAP half-sweep: one workgroup per domain of the active
+// colour for ALL right-hand sides.  The domain's forward links (FP16) and a
+// table of in-domain neighbours are staged in LDS once; the MR block solves of
+// the right-hand sides then run in turn with the residual exchanged through
+// LDS and the clover (FP16, one contiguous range per domain) read through the
+// caches.  Links of hops that leave the domain are not needed by D_SAP; the
+// crossing-hop correction of step 1 reads them from memory.
 __device__ __forceinline__ cplx<float> h2f(half2_t v) { return {(float)v.x, (float)v.y}; }
 
 template <bool FWD>
@@ -669,9 +676,9 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   const int l = threadIdx.x;
   const bool act = l < Vb;
   const int s = blk * Vb + (act ? l : 0);
-  const int V = g.V;
   const int nw = (blockDim.x + 63) >> 6;
   SiteCoord c = decompose(g, s);
+  const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
 
   // per direction: in-domain neighbour's local index (bits 0..9), in-domain
   // flag (bit 10), boundary sign -1 (bit 11)
@@ -687,7 +694,7 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   // by its in-domain neighbours (their backward hops)
   if (act) {
 #pragma unroll
-    for (int q = 0; q < 36; ++q) lu[q * Vb + l] = U[(size_t)q * V + s];
+    for (int q = 0; q < 36; ++q) lu[q * Vb + l] = U[(size_t)q * Vb + fb36];
   }
   __syncthreads();
 
@@ -695,19 +702,21 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
     const size_t off = rr * rs;
     cplx<float> rho[12], xm[12], p[12], psi[12];
     if (act) {
-      load_spinor<float>((flags & SAP_FIRST) ? b + off : r + off, V, s, rho);
+      ld_spinor<float>((flags & SAP_FIRST) ? b + off : r + off, Vb, fb12, rho);
       if (flags & SAP_DELTA) {
 #pragma unroll 1
         for (int d = 0; d < 8; ++d) {
           if (ninfo[d * Vb + l] & (1 << 10)) continue;
-          int sign;
+          int sign, nblk;
           bool inb;
           int mu = d & 3;
-          int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb) : neighbour<false>(g, s, c, mu, sign, inb);
-          load_spinor<float>(delta + off, V, nb, psi);
+          int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb, nblk)
+                         : neighbour<false>(g, s, c, mu, sign, inb, nblk);
+          ld_spinor<float>(delta + off, Vb, fbase_b(g, 12, nb, nblk), psi);
+          const size_t lb = d < 4 ? fb36 : fbase_b(g, 36, nb, nblk);
           half2_t ub[9];
 #pragma unroll
-          for (int e = 0; e < 9; ++e) ub[e] = U[(size_t)(mu * 9 + e) * V + (d < 4 ? s : nb)];
+          for (int e = 0; e < 9; ++e) ub[e] = U[(size_t)(mu * 9 + e) * Vb + lb];
           if (d < 4)
             hop_h<true>(mu, psi, ub, kappa * (float)sign, rho);
           else
@@ -728,7 +737,7 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
         // p = (1 + F) rho + in-domain hops; the domain's clover blocks stay in L2
 #pragma unroll
         for (int a = 0; a < 12; ++a) p[a] = rho[a];
-        clover_accum<float>(C, V, s, rho, p);
+        clover_acc<float>(C, Vb, fb36, rho, p);
 #pragma unroll 1
         for (int d = 0; d < 8; ++d) {
           const int inf = ninfo[d * Vb + l];
@@ -784,7 +793,7 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
       float2* dw = delta + off;
 #pragma unroll
       for (int a = 0; a < 12; ++a) {
-        size_t o = (size_t)a * V + s;
+        size_t o = (size_t)a * Vb + fb12;
         cplx<float> x0 = {0, 0};
         if (!(flags & SAP_FIRST)) x0 = ld<float>(xr, o);
         else if (xinit) x0 = ld<float>(xinit + off, o);

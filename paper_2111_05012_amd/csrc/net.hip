@@ -4,7 +4,8 @@
 // T_0 = 1, T_{+mu} psi(x) = U_mu(x) psi(x+mu), T_{-mu} psi(x) =
 // U_mu(x-mu)^dag psi(x-mu), their adjoint (input gradient), the weight
 // gradient, the per-block coefficients of the subspace loss, and Adam.
-// Channels are fields [C][12][V] (FP32), weights [9][C][C][4][4] complex64.
+// Channels are fields [C][blk][12][Vb] (FP32, block-major planes like every
+// site field), weights [9][C][C][4][4] complex64.
 #include <stdexcept>
 
 #include "wc_dirac.h"
@@ -17,28 +18,28 @@ constexpr int NTS = 256 / NETC;   // sites per workgroup tile
 
 __device__ __forceinline__ int opp_dir(int d) { return d == 0 ? 0 : (d <= 4 ? d + 4 : d - 4); }
 
-// (T_d f)(x) for one field f ([12][V]) at site s, FP64 links, FP32 result
+// (T_d f)(x) for one field f ([blk][12][Vb]) at site s, FP64 links, FP32 result
 __device__ __forceinline__ void transport_site(const Geo& g, const double2* __restrict__ U,
                                                const float2* __restrict__ f, int s, const SiteCoord& c, int d,
                                                cplx<float> (&out)[12]) {
-  const int V = g.V;
+  const int ps = g.Vb;
   if (d == 0) {
-    load_spinor<float>(f, V, s, out);
+    ld_spinor<float>(f, ps, fbase_b(g, 12, s, c.blk), out);
     return;
   }
   const int mu = (d - 1) & 3;
-  int sign;
+  int sign, nblk;
   bool inb;
   cplx<float> psi[12], u[9];
   int nb;
   if (d <= 4) {
-    nb = neighbour<true>(g, s, c, mu, sign, inb);
-    load_spinor<float>(f, V, nb, psi);
-    load_link<float>(U, V, mu, s, u);
+    nb = neighbour<true>(g, s, c, mu, sign, inb, nblk);
+    ld_spinor<float>(f, ps, fbase_b(g, 12, nb, nblk), psi);
+    ld_link<float>(U, ps, mu, fbase_b(g, 36, s, c.blk), u);
   } else {
-    nb = neighbour<false>(g, s, c, mu, sign, inb);
-    load_spinor<float>(f, V, nb, psi);
-    load_link<float>(U, V, mu, nb, u);
+    nb = neighbour<false>(g, s, c, mu, sign, inb, nblk);
+    ld_spinor<float>(f, ps, fbase_b(g, 12, nb, nblk), psi);
+    ld_link<float>(U, ps, mu, fbase_b(g, 36, nb, nblk), u);
   }
   const float sg = (float)sign;
 #pragma unroll
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(256) void k_ptc(Geo g, const float2* __restrict__ W
   }
   if (act) {
 #pragma unroll
-    for (int a = 0; a < 12; ++a) st(out + ch * fs, (size_t)a * V + s, acc[a]);
+    for (int a = 0; a < 12; ++a) st(out + ch * fs, (size_t)a * g.Vb + fbase_b(g, 12, s, c.blk), acc[a]);
   }
 }
 
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(256) void k_ptc_wgrad(Geo g, const float2* __restri
     if (s < V) {
       SiteCoord c = decompose(g, s);
       transport_site(g, U, in + ch * fs, s, c, d, tv);
-      load_spinor<float>(gout + ch * fs, V, s, gv);
+      ld_spinor<float>(gout + ch * fs, g.Vb, fbase_b(g, 12, s, c.blk), gv);
     } else {
 #pragma unroll
       for (int a = 0; a < 12; ++a) tv[a] = gv[a] = {0, 0};

@@ -143,13 +143,29 @@ __host__ __device__ __forceinline__ SiteCoord decompose(const Geo& g, int s) {
   return c;
 }
 
+// Field storage.  A site field of K planes (K = 12 spin-colour components
+// for spinors and test vectors, 36 for the links [mu][row][col] and for the
+// packed clover) is stored block-major, [blk][K][Vb]: the K planes of one
+// block are contiguous.  Everything a block (an SAP domain, a multigrid
+// aggregate) touches is then one contiguous range, and the planes of a site
+// are Vb elements apart instead of V (at lattice volumes that are large powers
+// of two, planes V apart all fall into the same cache set).  Plane q of site s
+// = blk * Vb + loc lies at fbase(g, K, s) + q * Vb.
+__host__ __device__ __forceinline__ size_t fbase_b(const Geo& g, int K, int s, int blk) {
+  return (size_t)s + (size_t)blk * (K - 1) * g.Vb;
+}
+__host__ __device__ __forceinline__ size_t fbase(const Geo& g, int K, int s) {
+  return fbase_b(g, K, s, s / g.Vb);
+}
+
 // Neighbour of site s (coordinates c) in direction +mu (FWD) or -mu.  Sets
-// sign to bc[mu] when the hop crosses the lattice boundary and inblk to
-// whether the neighbour lies in the same block.
+// sign to bc[mu] when the hop crosses the lattice boundary, inblk to whether
+// the neighbour lies in the same block and nblk to the neighbour's block.
 template <bool FWD>
 __host__ __device__ __forceinline__ int neighbour(const Geo& g, int s, const SiteCoord& c, int mu, int& sign,
-                                                  bool& inblk) {
+                                                  bool& inblk, int& nblk_out) {
   sign = 1;
+  nblk_out = c.blk;
   if (FWD) {
     if (c.lc[mu] < g.B[mu] - 1) {
       inblk = true;
@@ -164,6 +180,7 @@ __host__ __device__ __forceinline__ int neighbour(const Geo& g, int s, const Sit
       sign = g.bc[mu];
     }
     inblk = (nblk == c.blk);
+    nblk_out = nblk;
     return nblk * g.Vb + nloc;
   } else {
     if (c.lc[mu] > 0) {
@@ -179,8 +196,15 @@ __host__ __device__ __forceinline__ int neighbour(const Geo& g, int s, const Sit
       sign = g.bc[mu];
     }
     inblk = (nblk == c.blk);
+    nblk_out = nblk;
     return nblk * g.Vb + nloc;
   }
+}
+template <bool FWD>
+__host__ __device__ __forceinline__ int neighbour(const Geo& g, int s, const SiteCoord& c, int mu, int& sign,
+                                                  bool& inblk) {
+  int nblk;
+  return neighbour<FWD>(g, s, c, mu, sign, inblk, nblk);
 }
 
 // Map a launch's workgroup index so that consecutive logical tiles land on

@@ -84,27 +84,29 @@ __device__ __forceinline__ void hop_any(int mu, const cplx<R> (&psi)[12], const 
   }
 }
 
+// Site-field loads: `base` is the offset of the site's plane 0 (fbase) and
+// `ps` the plane stride (Vb) of the block-major layout.
 template <class R, class TL>
-__device__ __forceinline__ void load_link(const TL* __restrict__ U, int V, int mu, int s, cplx<R> (&u)[9]) {
+__device__ __forceinline__ void ld_link(const TL* __restrict__ U, int ps, int mu, size_t base, cplx<R> (&u)[9]) {
 #pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = ld<R>(U, (size_t)(mu * 9 + e) * V + s);
+  for (int e = 0; e < 9; ++e) u[e] = ld<R>(U, (size_t)(mu * 9 + e) * ps + base);
 }
 
 template <class R, class TS>
-__device__ __forceinline__ void load_spinor(const TS* __restrict__ p, int V, int s, cplx<R> (&psi)[12]) {
+__device__ __forceinline__ void ld_spinor(const TS* __restrict__ p, int ps, size_t base, cplx<R> (&psi)[12]) {
 #pragma unroll
-  for (int a = 0; a < 12; ++a) psi[a] = ld<R>(p, (size_t)a * V + s);
+  for (int a = 0; a < 12; ++a) psi[a] = ld<R>(p, (size_t)a * ps + base);
 }
 
-// acc += F(x) psi for the packed clover field.
+// acc += F(x) psi for the packed clover field (plane stride ps, site base).
 template <class R, class TC>
-__device__ __forceinline__ void clover_accum(const TC* __restrict__ C, int V, int s, const cplx<R> (&psi)[12],
-                                             cplx<R> (&acc)[12]) {
+__device__ __forceinline__ void clover_acc(const TC* __restrict__ C, int ps, size_t base, const cplx<R> (&psi)[12],
+                                           cplx<R> (&acc)[12]) {
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     cplx<R> p[18];
 #pragma unroll
-    for (int k = 0; k < 18; ++k) p[k] = ld<R>(C, (size_t)(18 * b + k) * V + s);
+    for (int k = 0; k < 18; ++k) p[k] = ld<R>(C, (size_t)(18 * b + k) * ps + base);
     R d[6] = {p[0].x, p[0].y, p[1].x, p[1].y, p[2].x, p[2].y};
 #pragma unroll
     for (int i = 0; i < 6; ++i) acc[6 * b + i] = acc[6 * b + i] + d[i] * psi[6 * b + i];
