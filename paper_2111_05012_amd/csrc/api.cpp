@@ -61,7 +61,10 @@ struct DevBuf {
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      ++g_alloc_epoch;
+      (void)hipFree(p);
+    }
   }
   void* ensure(size_t bytes, bool frozen) {
     if (bytes <= n) return p;
@@ -370,15 +373,36 @@ struct wcamg_ctx {
     if (graphs.empty()) return;
     if (graph_epoch != g_alloc_epoch.load() || graph_sig != hier_sig()) drop_graphs();
   }
-  // Releases every workspace (and the graphs that refer to them) when less
-  // than `need` bytes (plus 2 GiB of headroom) of device memory are free.
-  // Called only on entry to a top-level operation, where no workspace
-  // pointer is live; workspaces are otherwise kept between calls.
-  void trim(size_t need) {
-    size_t fr = 0, tot = 0;
-    HIPCHK(hipMemGetInfo(&fr, &tot));
-    if (fr >= need + ((size_t)2 << 30)) return;
+  // Workspaces are kept between calls.  reserve() is called on entry to a
+  // top-level operation (where no workspace pointer is live) with the large
+  // workspaces the operation will use (name, bytes): when their growth does
+  // not fit into the free device memory (with 2 GiB of headroom), first the
+  // workspaces outside this list and then all workspaces are released,
+  // together with the graphs that refer to them.
+  size_t ws_grow(const std::string& name, size_t bytes) const {
+    auto it = ws.find(name);
+    size_t have = (it == ws.end() || !it->second) ? 0 : it->second->n;
+    return bytes > have ? bytes - have : 0;
+  }
+  void reserve(const std::vector<std::pair<std::string, size_t>>& plan) {
+    auto fits = [&] {
+      size_t need = (size_t)2 << 30;
+      for (auto& q : plan) need += ws_grow(q.first, q.second);
+      size_t fr = 0, tot = 0;
+      HIPCHK(hipMemGetInfo(&fr, &tot));
+      return fr >= need;
+    };
+    if (fits()) return;
     drop_graphs();
+    for (auto it = ws.begin(); it != ws.end();) {
+      bool used = false;
+      for (auto& q : plan) used = used || q.first == it->first;
+      if (used)
+        ++it;
+      else
+        it = ws.erase(it);
+    }
+    if (fits()) return;
     ws.clear();
   }
 
@@ -693,10 +717,17 @@ struct wcamg_ctx {
   // coarse operator eq.(7) from the stored vectors (fused kernel)
   void build_coarse() {
     int nv = h.nv, N = h.N;
-    Timed tb(this, "coarse_build", 0, 0, 1, true);
     h.Dc.ensure((size_t)h.cg.NC * 9 * N * N * ct_size(crs_t()), capturing);
     bool mixed = h.prec == WCAMG_PREC_MIXED;
-    launch_coarse_build(g, nv, kappa, h.V.p, mixed ? U16.p : U64.p, mixed ? Cl16.p : Cl64.p, h.Dc.p, mixed, st);
+    const void* Uf = mixed ? U16.p : U64.p;
+    const void* Cf = mixed ? Cl16.p : Cl64.p;
+    std::vector<int> cands = {0};
+    if (mixed && nv <= 32) cands = {1, 0};  // matrix-core contraction first
+    char key[96];
+    snprintf(key, sizeof(key), "coarse_build|nv%d|Vb%d|V%d", nv, g.Vb, g.V);
+    int var = tune(key, cands, [&](int v) { launch_coarse_build(g, nv, kappa, h.V.p, Uf, Cf, h.Dc.p, mixed, st, v); });
+    Timed tb(this, "coarse_build", 0, 0, 1, true);
+    launch_coarse_build(g, nv, kappa, h.V.p, Uf, Cf, h.Dc.p, mixed, st, var);
   }
 
   // level-1 block orthonormalisation of W in place (CholQR twice, FP64 Gram)
@@ -1071,8 +1102,10 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
     const Geo& g = c->g;
     int nv = p->nv, prec = p->prec, t = c->spin_t(prec);
     size_t cbytes = (size_t)nv * g.V * 12 * sizeof(double2);
-    // at most eight fine fields of nv vectors are live during the setup
-    c->trim(8 * c->fsz(nv, prec));
+    {
+      const size_t f = c->fsz(nv, prec);
+      c->reserve({{"su_w", f}, {"su_t", f}, {"sap_r", f}, {"sap_d", f}, {"or_tmp", f}, {"vc_r", f}, {"vc_x1", f}});
+    }
     HostIO io(c);
     const double2* Vd = nullptr;
     if (p->init_vectors) Vd = (const double2*)io.in(p->init_vectors, cbytes, p->init_where, "io_in");
@@ -1572,12 +1605,20 @@ int wcamg_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, const wcamg_solv
     int chunk = p->rhs_chunk > 0 ? std::min(p->rhs_chunk, nrhs) : nrhs;
     {
       // packed b and x, the FP64 Krylov basis, the preconditioned vectors,
-      // the V-cycle's input and about four fine fields inside the V-cycle
+      // the V-cycle's input and the fine fields inside the V-cycle
       const int prec = c->h.prec;
-      size_t per = 2 * sizeof(double2) + (size_t)(p->restart + 1) * sizeof(double2) +
-                   (size_t)p->restart * ct_size(c->spin_t(prec)) +
-                   (prec == WCAMG_PREC_MIXED ? sizeof(float2) : 0);
-      c->trim((size_t)chunk * n * per + 4 * c->fsz(chunk, prec));
+      const size_t cn = (size_t)chunk * n, f = c->fsz(chunk, prec);
+      std::vector<std::pair<std::string, size_t>> plan = {
+          {"sv_b", cn * sizeof(double2)},
+          {"sv_x", cn * sizeof(double2)},
+          {"fg_V", (size_t)(p->restart + 1) * cn * sizeof(double2)},
+          {"fg_Z", (size_t)p->restart * cn * ct_size(c->spin_t(prec))},
+          {"vc_r", f},
+          {"vc_x1", f},
+          {"sap_r", f},
+          {"sap_d", f}};
+      if (prec == WCAMG_PREC_MIXED) plan.push_back({"fg_vin", cn * sizeof(float2)});
+      c->reserve(plan);
     }
     wcamg_solve_info inf;
     std::memset(&inf, 0, sizeof(inf));

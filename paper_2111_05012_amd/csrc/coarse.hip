@@ -458,6 +458,162 @@ __global__ __launch_bounds__(256) void k_coarse_build(Geo g, int nv, R kappa, co
   }
 }
 
+// Matrix-core variant of the fused build (FP16 vectors and fields, FP32
+// arithmetic, nv <= 32).  The vectors g_j of a tile are formed as above; the
+// contraction then runs on MFMA.  For target chirality s the block
+//   C_s[i][j] = sum_k conj(v_i(k)) g_j(k),
+// k over the tile's sites and the 6 components of chirality s, is a real
+// 32x32 product pair: Re C = vr^T gr + vi^T gi and Im C = vr^T gi - vi^T gr.
+// Wave w computes (s = w / 2, real part for even w, imaginary for odd w)
+// with v_mfma_f32_32x32x2f32 (A: lane l holds row l % 32 of k-slice l / 32;
+// B: column l % 32 of k-slice l / 32; accumulator v of lane l is element
+// (8 (v / 4) + 4 (l / 32) + v % 4, l % 32)).  Indices i, j >= nv are padding
+// held at zero in LDS.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+template <int T>
+__global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float kappa, const half2_t* __restrict__ V,
+                                                         const half2_t* __restrict__ U,
+                                                         const half2_t* __restrict__ C, float2* __restrict__ Dc) {
+  constexpr int K = T * 6;  // k per tile and chirality
+  __shared__ float svr[2][K][32], svi[2][K][32], sgr[2][K][32], sgi[2][K][32];
+  const int N = 2 * nv;
+  const int X = blockIdx.x, d = blockIdx.y, sp = blockIdx.z;
+  const int t = threadIdx.x;
+  const int Vg = g.V;
+  const int mu = (d - 1) & 3;
+  const bool fwd = d <= 4;
+  int nsites;
+  if (d == 0)
+    nsites = g.Vb;
+  else
+    nsites = g.NB[mu] == 1 ? 0 : g.Vb / g.B[mu];
+  const int a0 = sp * 6;
+  for (int e = t; e < 2 * K * 32; e += 256) {
+    (&svr[0][0][0])[e] = 0.f;
+    (&svi[0][0][0])[e] = 0.f;
+    (&sgr[0][0][0])[e] = 0.f;
+    (&sgi[0][0][0])[e] = 0.f;
+  }
+  const int w = t >> 6, lane = t & 63;
+  const int ws = w >> 1, part = w & 1;
+  f32x16 acc;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+  __syncthreads();
+
+  for (int tile0 = 0; tile0 < nsites; tile0 += T) {
+    if (t < T * nv) {
+      const int st_ = t / nv, j = t - st_ * nv;
+      const int f = tile0 + st_;
+      cplx<float> vj[12], gj[12];
+      if (f < nsites) {
+        int loc;
+        if (d == 0) {
+          loc = f;
+        } else {
+          int q = f, cc[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            if (m == mu) continue;
+            cc[m] = q % g.B[m];
+            q /= g.B[m];
+          }
+          cc[mu] = fwd ? g.B[mu] - 1 : 0;
+          loc = cc[0] * g.sB[0] + cc[1] * g.sB[1] + cc[2] * g.sB[2] + cc[3] * g.sB[3];
+        }
+        const int sx = X * g.Vb + loc;
+        const int ps = g.Vb;
+        const size_t fb12 = fbase_b(g, 12, sx, X), fb36 = fbase_b(g, 36, sx, X);
+        const half2_t* vjp = V + (size_t)j * 12 * Vg;
+        ld_spinor<float>(vjp, ps, fb12, vj);
+        SiteCoord c = decompose(g, sx);
+        cplx<float> psi[12], u[9];
+#pragma unroll
+        for (int a = 0; a < 12; ++a) gj[a] = {0, 0};
+        if (d == 0) {
+#pragma unroll
+          for (int a = 0; a < 12; ++a) psi[a] = (a >= a0 && a < a0 + 6) ? vj[a] : cplx<float>{0, 0};
+#pragma unroll
+          for (int a = 0; a < 12; ++a) gj[a] = psi[a];
+          clover_acc<float>(C, ps, fb36, psi, gj);
+#pragma unroll 1
+          for (int dir = 0; dir < 8; ++dir) {
+            const int m = dir & 3;
+            int sign;
+            bool inb;
+            int nb = dir < 4 ? neighbour<true>(g, sx, c, m, sign, inb) : neighbour<false>(g, sx, c, m, sign, inb);
+            if (!inb) continue;
+            ld_spinor<float>(vjp, ps, fbase_b(g, 12, nb, X), psi);
+#pragma unroll
+            for (int a = 0; a < 12; ++a)
+              if (a < a0 || a >= a0 + 6) psi[a] = {0, 0};
+            if (dir < 4) {
+              ld_link<float>(U, ps, m, fb36, u);
+              hop_any<true>(m, psi, u, -kappa * (float)sign, gj);
+            } else {
+              ld_link<float>(U, ps, m, fbase_b(g, 36, nb, X), u);
+              hop_any<false>(m, psi, u, -kappa * (float)sign, gj);
+            }
+          }
+        } else {
+          int sign, nblk;
+          bool inb;
+          int nb = fwd ? neighbour<true>(g, sx, c, mu, sign, inb, nblk)
+                       : neighbour<false>(g, sx, c, mu, sign, inb, nblk);
+          ld_spinor<float>(vjp, ps, fbase_b(g, 12, nb, nblk), psi);
+#pragma unroll
+          for (int a = 0; a < 12; ++a)
+            if (a < a0 || a >= a0 + 6) psi[a] = {0, 0};
+          if (fwd) {
+            ld_link<float>(U, ps, mu, fb36, u);
+            hop_any<true>(mu, psi, u, -kappa * (float)sign, gj);
+          } else {
+            ld_link<float>(U, ps, mu, fbase_b(g, 36, nb, nblk), u);
+            hop_any<false>(mu, psi, u, -kappa * (float)sign, gj);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 12; ++a) vj[a] = gj[a] = {0, 0};
+      }
+#pragma unroll
+      for (int a = 0; a < 12; ++a) {
+        const int s = a / 6, k = st_ * 6 + (a % 6);
+        svr[s][k][j] = vj[a].x;
+        svi[s][k][j] = vj[a].y;
+        sgr[s][k][j] = gj[a].x;
+        sgi[s][k][j] = gj[a].y;
+      }
+    }
+    __syncthreads();
+    // tiles past nsites hold zeros (written above), so every k-slice is summed
+    const int r = lane & 31, kh = lane >> 5;
+#pragma unroll 2
+    for (int kk = 0; kk < K; kk += 2) {
+      const int k = kk + kh;
+      const float ar = svr[ws][k][r], ai = svi[ws][k][r];
+      const float br = sgr[ws][k][r], bi = sgi[ws][k][r];
+      if (part == 0) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, acc, 0, 0, 0);
+      } else {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, br, acc, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // D element (i, j): column (sp, j), row (s, i) of the column-major block
+  float* out = (float*)Dc;
+  const int j = lane & 31;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int i = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+    if (i < nv && j < nv) out[2 * ((((size_t)X * 9 + d) * N + (sp * nv + j)) * N + (ws * nv + i)) + part] = acc[q];
+  }
+}
+
 template <class R, class TV, class TL, class TC, class TO>
 static void coarse_build_run(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C,
                              void* Dc, hipStream_t st) {
@@ -486,7 +642,14 @@ static void coarse_build_run(const Geo& g, int nv, double kappa, const void* V, 
 }
 
 void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C, void* Dc,
-                         int mixed, hipStream_t st) {
+                         int mixed, hipStream_t st, int variant) {
+  if (mixed && variant == 1) {
+    if (nv > 32) throw std::runtime_error("coarse build: the matrix-core variant needs nv <= 32");
+    constexpr int T = 8;  // 256 threads cover T * nv <= 256 (site, vector) pairs
+    k_coarse_build_mf<T><<<dim3(g.nblk, 9, 2), 256, 0, st>>>(g, nv, (float)kappa, (const half2_t*)V,
+                                                               (const half2_t*)U, (const half2_t*)C, (float2*)Dc);
+    return;
+  }
   if (mixed)
     coarse_build_run<float, half2_t, half2_t, half2_t, float2>(g, nv, kappa, V, U, C, Dc, st);
   else

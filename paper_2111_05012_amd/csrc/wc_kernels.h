@@ -105,9 +105,10 @@ void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void
                       size_t rs, int prec32, hipStream_t st, int variant = 0, const int* active = nullptr,
                       int astride = 0);
 // coarse operator eq.(7) from the stored test vectors V [nv][12][V] (mixed: FP16 V,
-// links, clover; FP32 arithmetic; complex64 Dc) into Dc [X][9][m][n]
+// links, clover; FP32 arithmetic; complex64 Dc) into Dc [X][9][m][n].
+// variant (mixed only): 0 vector-ALU contraction, 1 matrix-core contraction (nv <= 32)
 void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C, void* Dc,
-                         int mixed, hipStream_t st);
+                         int mixed, hipStream_t st, int variant = 0);
 // level-1 aggregation (multi-level): coarse vectors [rhs][X1][n1], level-1
 // test vectors W [nw][X1][n1], level-1 blocks b1, level-2 vectors [rhs][X2][2nw]
 void launch_l1_restrict(const CGeo& c1, const int* b1, int n1, int nw, int nrhs, const void* W, int w_t,

@@ -52,11 +52,17 @@ def test_net_adam_step(setup):
     W1 = net.Adam(lr=1e-3).step(Ws, gWs)
     got = torch.zeros((2, 9, C, C, 4, 4), dtype=torch.complex64, device=prob.dev)
     prob.ctx.net_get_weights(got)
-    # one Adam step moves every entry by ~lr * sign(g); compare the update
+    # the first Adam step moves each real and imaginary part by
+    # lr * g / (|g| + eps) ~ lr * sign(g); compare it where the gradient part is
+    # well above eps and above the FP32 gradient's rounding (elsewhere the step
+    # depends on the sign of a rounding error)
     upd_g = got.cpu().numpy() - np.stack(Ws)
     upd_o = np.stack(W1) - np.stack(Ws)
-    big = np.abs(upd_o) > 5e-4  # entries whose gradient is not ~0 relative to eps
-    assert np.abs(upd_g - upd_o)[big].max() < 1e-5
+    go = np.stack(gWs)
+    for part in (np.real, np.imag):
+        m = np.abs(part(go)) > 1e-3 * np.abs(go).max()
+        assert m.sum() > 0.1 * m.size
+        assert np.abs(part(upd_g) - part(upd_o))[m].max() < 1e-5
     assert np.isfinite(loss)
     # restore the weights for the other tests
     prob.ctx.net_init(prob.T(np.ascontiguousarray(np.stack(Ws).astype(np.complex64))), 2, C)

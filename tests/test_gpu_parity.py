@@ -123,6 +123,34 @@ def test_coarse_operator_fp64(prob):
     assert rel(prob.N(y), amg.coarse_apply(want, x, cd)) < 1e-13
 
 
+@pytest.mark.parametrize('nv', [4, 12])
+def test_coarse_operator_mixed_every_variant(prob, nv, tmp_path):
+    """Mixed-precision coarse operator (FP16 vectors, links and clover, FP32
+    arithmetic) from both contraction kernels (vector ALU and matrix cores),
+    each forced through the tuner's cache file, against the oracle's Galerkin
+    product of the same FP16-rounded vectors."""
+    import json
+    from paper_2111_05012_amd import PREC_MIXED
+    cache = str(tmp_path / 'tune.json')
+    prob.ctx.autotune(True, cache)
+    V = _hier(prob, nv=nv, prec=PREC_MIXED)
+    V16 = V.real.astype(np.float16).astype(np.float64) + 1j * V.imag.astype(np.float16).astype(np.float64)
+    want = amg.coarse_operator(prob.op, V16)
+    nX = amg.n_blocks(prob.dims, prob.block)
+    keys = json.load(open(cache))
+    assert any(k.split('|')[1] == 'coarse_build' for k in keys)
+    for v in (0, 1):
+        forced = {k: (v if k.split('|')[1] == 'coarse_build' else val) for k, val in keys.items()}
+        with open(cache, 'w') as f:
+            json.dump(forced, f)
+        prob.ctx.autotune(True, cache)
+        _hier(prob, nv=nv, prec=PREC_MIXED)  # rebuilds the coarse operator with the forced kernel
+        Dc = prob.zeros((nX, 9, 2 * nv, 2 * nv))
+        prob.ctx.get_coarse_op(Dc, level=1)
+        assert rel(prob.N(Dc), want) < 3e-3, v
+    prob.ctx.autotune(False, None)
+
+
 def test_coarse_solve_fp64(prob):
     V = _hier(prob)
     nX = amg.n_blocks(prob.dims, prob.block)
