@@ -652,15 +652,18 @@ __device__ __forceinline__ void hop_h(int mu, const cplx<float> (&psi)[12], cons
   hop_any<FWD>(mu, psi, u, coef, acc);
 }
 
+// VB: the domain volume when known at compile time (LDS offsets become
+// immediates), 0 for any volume.
+template <int VB>
 __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, int mr, float kappa, int nrhs,
                                                  const float2* __restrict__ b, float2* __restrict__ r,
                                                  float2* __restrict__ x, float2* __restrict__ delta,
                                                  const float2* __restrict__ xinit, size_t rs,
                                                  const half2_t* __restrict__ U, const half2_t* __restrict__ C) {
   extern __shared__ __align__(16) char smem[];
-  const int Vb = g.Vb;
+  const int Vb = VB ? VB : g.Vb;
   cplx<float>* lds = (cplx<float>*)smem;                   // [12][Vb] residual exchange
-  half2_t* lu = (half2_t*)(smem + 12 * Vb * sizeof(cplx<float>));  // [4][9][Vb] forward links of the domain
+  half2_t* lu = (half2_t*)(smem + 12 * Vb * sizeof(cplx<float>));  // [4][9][Vb] -kappa sign U_mu(x) of the domain
   int* ninfo = (int*)(lu + 36 * Vb);                       // [8][Vb] neighbour info
   float* red = (float*)(ninfo + 8 * Vb);                   // [nwaves][3]
   const int half = g.NB[0] >> 1;
@@ -682,19 +685,26 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
 
   // per direction: in-domain neighbour's local index (bits 0..9), in-domain
   // flag (bit 10), boundary sign -1 (bit 11)
+  float fsign[4];
 #pragma unroll
   for (int d = 0; d < 8; ++d) {
     int sign;
     bool inb;
     int mu = d & 3;
     int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb) : neighbour<false>(g, s, c, mu, sign, inb);
+    if (d < 4) fsign[mu] = (float)sign;
     if (act) ninfo[d * Vb + l] = (inb ? ((nb - blk * Vb) | (1 << 10)) : 0) | (sign < 0 ? (1 << 11) : 0);
   }
-  // the domain's forward links U_mu(x), read by the site (forward hops) and
-  // by its in-domain neighbours (their backward hops)
+  // the domain's forward links scaled by the hop coefficient, -kappa sign
+  // U_mu(x) (sign: bc of a hop x -> x + mu that crosses the lattice boundary,
+  // which is also the sign of the backward hop x + mu -> x), read by the site
+  // (forward hops) and by its in-domain neighbours (their backward hops)
   if (act) {
 #pragma unroll
-    for (int q = 0; q < 36; ++q) lu[q * Vb + l] = U[(size_t)q * Vb + fb36];
+    for (int q = 0; q < 36; ++q) {
+      const float f = -kappa * fsign[q / 9];
+      st(lu, (size_t)q * Vb + l, f * ld<float>(U, (size_t)q * Vb + fb36));
+    }
   }
   __syncthreads();
 
@@ -738,22 +748,23 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
 #pragma unroll
         for (int a = 0; a < 12; ++a) p[a] = rho[a];
         clover_acc<float>(C, Vb, fb36, rho, p);
-#pragma unroll 1
+        // unrolled: direction and projection are compile-time constants
+#pragma unroll
         for (int d = 0; d < 8; ++d) {
           const int inf = ninfo[d * Vb + l];
-          if (!(inf & (1 << 10))) continue;
-          int nl = inf & 1023;
-          float coef = (inf & (1 << 11)) ? kappa : -kappa;
+          if (inf & (1 << 10)) {
+            int nl = inf & 1023;
 #pragma unroll
-          for (int a = 0; a < 12; ++a) psi[a] = lds[a * Vb + nl];
-          half2_t ub[9];
-          const int ls = d < 4 ? l : nl;  // U_mu(x) or U_mu(x - mu)
+            for (int a = 0; a < 12; ++a) psi[a] = lds[a * Vb + nl];
+            half2_t ub[9];
+            const int ls = d < 4 ? l : nl;  // U_mu(x) or U_mu(x - mu), scaled
 #pragma unroll
-          for (int e = 0; e < 9; ++e) ub[e] = lu[((d & 3) * 9 + e) * Vb + ls];
-          if (d < 4)
-            hop_h<true>(d & 3, psi, ub, coef, p);
-          else
-            hop_h<false>(d & 3, psi, ub, coef, p);
+            for (int e = 0; e < 9; ++e) ub[e] = lu[((d & 3) * 9 + e) * Vb + ls];
+            if (d < 4)
+              hop_h<true>(d & 3, psi, ub, 1.0f, p);
+            else
+              hop_h<false>(d & 3, psi, ub, 1.0f, p);
+          }
         }
 #pragma unroll
         for (int a = 0; a < 12; ++a) {
@@ -843,15 +854,23 @@ void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st) {
   const Geo& g = a.g;
   int nthr = ((g.Vb + 63) / 64) * 64;
   int lds = sap_dom_lds_bytes(g);
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_sap_dom, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
   int ndom = g.nblk / 2;
-  k_sap_dom<<<round8(ndom), nthr, lds, st>>>(g, col, flags, a.mr, (float)a.kappa, a.nrhs, (const float2*)a.b,
-                                              (float2*)a.r, (float2*)a.x, (float2*)a.delta, (const float2*)a.xinit,
-                                              a.rs, (const half2_t*)a.U, (const half2_t*)a.C);
+  static bool attr_set[3] = {false, false, false};
+  auto go = [&](auto kern, int id) {
+    if (!attr_set[id]) {
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      attr_set[id] = true;
+    }
+    kern<<<round8(ndom), nthr, lds, st>>>(g, col, flags, a.mr, (float)a.kappa, a.nrhs, (const float2*)a.b,
+                                          (float2*)a.r, (float2*)a.x, (float2*)a.delta, (const float2*)a.xinit, a.rs,
+                                          (const half2_t*)a.U, (const half2_t*)a.C);
+  };
+  if (g.Vb == 512)
+    go(k_sap_dom<512>, 0);
+  else if (g.Vb == 256)
+    go(k_sap_dom<256>, 1);
+  else
+    go(k_sap_dom<0>, 2);
 }
 
 // ---------------------------------------------------------------------------
