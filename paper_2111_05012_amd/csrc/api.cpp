@@ -374,10 +374,11 @@ struct wcamg_ctx {
     if (graph_epoch != g_alloc_epoch.load() || graph_sig != hier_sig()) drop_graphs();
   }
   // Workspaces are kept between calls.  reserve() is called on entry to a
-  // top-level operation (where no workspace pointer is live) with the large
-  // workspaces the operation will use (name, bytes): when their growth does
-  // not fit into the free device memory (with 2 GiB of headroom), first the
-  // workspaces outside this list and then all workspaces are released,
+  // top-level operation (where no workspace pointer other than the host
+  // staging buffers "io_*" is live) with the large workspaces the operation
+  // will use (name, bytes): when their growth does not fit into the free
+  // device memory (with 2 GiB of headroom), first the workspaces outside this
+  // list and then all workspaces except the staging buffers are released,
   // together with the graphs that refer to them.
   size_t ws_grow(const std::string& name, size_t bytes) const {
     auto it = ws.find(name);
@@ -394,16 +395,21 @@ struct wcamg_ctx {
     };
     if (fits()) return;
     drop_graphs();
-    for (auto it = ws.begin(); it != ws.end();) {
-      bool used = false;
-      for (auto& q : plan) used = used || q.first == it->first;
-      if (used)
-        ++it;
-      else
-        it = ws.erase(it);
-    }
+    // host-transfer staging buffers ("io_*") may already be live in this call
+    auto release = [&](bool keep_plan) {
+      for (auto it = ws.begin(); it != ws.end();) {
+        bool keep = it->first.compare(0, 3, "io_") == 0;
+        if (keep_plan)
+          for (auto& q : plan) keep = keep || q.first == it->first;
+        if (keep)
+          ++it;
+        else
+          it = ws.erase(it);
+      }
+    };
+    release(true);
     if (fits()) return;
-    ws.clear();
+    release(false);
   }
 
   // ---- kernel timing
@@ -1019,6 +1025,7 @@ static int apply_op(wcamg_ctx* c, const void* in, void* out, int nrhs, int prec,
     const double2* ind = (const double2*)io.in(in, cbytes, where, "io_in");
     double2* outd = (double2*)io.out(out, cbytes, where, "io_out");
     int t = c->spin_t(prec);
+    c->reserve({{"ap_a", c->fsz(nrhs, prec)}, {"ap_b", c->fsz(nrhs, prec)}});
     void* a = c->W("ap_a", c->fsz(nrhs, prec));
     void* b = c->W("ap_b", c->fsz(nrhs, prec));
     launch_pack_spinor(g, ind, a, t, c->frs(), nrhs, c->st);
@@ -1053,6 +1060,8 @@ int wcamg_sap(wcamg_ctx* c, const void* b, void* x, int nrhs, int sweeps, int mr
     const double2* bd = (const double2*)io.in(b, cbytes, where, "io_in");
     double2* xd = (double2*)io.out(x, cbytes, where, "io_out");
     int t = c->spin_t(prec);
+    c->reserve({{"ap_a", c->fsz(nrhs, prec)}, {"ap_b", c->fsz(nrhs, prec)}, {"sap_r", c->fsz(nrhs, prec)},
+                {"sap_d", c->fsz(nrhs, prec)}});
     void* bi = c->W("ap_a", c->fsz(nrhs, prec));
     void* xi = c->W("ap_b", c->fsz(nrhs, prec));
     launch_pack_spinor(g, bd, bi, t, c->frs(), nrhs, c->st);
@@ -1192,6 +1201,7 @@ int wcamg_orthonormalize(wcamg_ctx* c, const void* in, void* out, int nv, int pr
     const double2* ind = (const double2*)io.in(in, cbytes, where, "io_in");
     double2* outd = (double2*)io.out(out, cbytes, where, "io_out");
     int t = c->spin_t(prec);
+    c->reserve({{"ap_a", c->fsz(nv, prec)}, {"or_tmp", c->fsz(nv, prec)}});
     void* Vw = c->W("ap_a", c->fsz(nv, prec));
     launch_pack_spinor(g, ind, Vw, t, c->frs(), nv, c->st);
     c->orthonormalize(Vw, nv, prec);
@@ -1215,6 +1225,7 @@ int wcamg_restrict(wcamg_ctx* c, const void* in, void* out, int nrhs, int where)
     const double2* ind = (const double2*)io.in(in, fb, where, "io_in");
     double2* outd = (double2*)io.out(out, cb, where, "io_out");
     int t = c->spin_t(c->h.prec);
+    c->reserve({{"ap_a", c->fsz(nrhs, c->h.prec)}});
     void* a = c->W("ap_a", c->fsz(nrhs, c->h.prec));
     void* xc = c->W("ap_c", c->csz(nrhs));
     launch_pack_spinor(g, ind, a, t, c->frs(), nrhs, c->st);
@@ -1239,6 +1250,7 @@ int wcamg_prolong(wcamg_ctx* c, const void* in, void* out, int nrhs, int where) 
     const double2* ind = (const double2*)io.in(in, cb, where, "io_in");
     double2* outd = (double2*)io.out(out, fb, where, "io_out");
     int t = c->spin_t(c->h.prec);
+    c->reserve({{"ap_a", c->fsz(nrhs, c->h.prec)}});
     void* xc = c->W("ap_c", c->csz(nrhs));
     void* a = c->W("ap_a", c->fsz(nrhs, c->h.prec));
     launch_convert(ind, C128, xc, c->crs_t(), (size_t)nrhs * c->crs_n(), c->st);
@@ -1362,6 +1374,8 @@ int wcamg_vcycle(wcamg_ctx* c, const void* in, void* out, int nrhs, int where) {
     const double2* ind = (const double2*)io.in(in, fb, where, "io_in");
     double2* outd = (double2*)io.out(out, fb, where, "io_out");
     int prec = c->h.prec, t = c->spin_t(prec);
+    c->reserve({{"ap_a", c->fsz(nrhs, prec)}, {"ap_b", c->fsz(nrhs, prec)}, {"vc_r", c->fsz(nrhs, prec)},
+                {"vc_x1", c->fsz(nrhs, prec)}, {"sap_r", c->fsz(nrhs, prec)}, {"sap_d", c->fsz(nrhs, prec)}});
     void* a = c->W("ap_a", c->fsz(nrhs, prec));
     void* b = c->W("ap_b", c->fsz(nrhs, prec));
     launch_pack_spinor(g, ind, a, t, c->frs(), nrhs, c->st);
@@ -1708,6 +1722,7 @@ int wcamg_net_forward(wcamg_ctx* c, const void* r, void* out, int where) {
     HostIO io(c);
     const double2* rd = (const double2*)io.in(r, cb, where, "io_in");
     double2* od = (double2*)io.out(out, cb, where, "io_out");
+    c->reserve({{"nt_r", (size_t)C * 12 * g.V * sizeof(float2)}});
     void* r32 = c->W("nt_r", (size_t)C * 12 * g.V * sizeof(float2));
     launch_pack_spinor(g, rd, r32, C64, c->frs(), C, c->st);
     c->net_forward(r32);
@@ -1728,6 +1743,7 @@ int wcamg_net_gradient(wcamg_ctx* c, const void* r, const void* teacher, double*
     size_t cb = (size_t)C * g.V * 12 * sizeof(double2);
     HostIO io(c);
     const double2* rd = (const double2*)io.in(r, cb, where, "io_in");
+    c->reserve({{"nt_r", (size_t)C * 12 * g.V * sizeof(float2)}, {"nt_q", (size_t)C * 12 * g.V * sizeof(float2)}});
     void* r32 = c->W("nt_r", (size_t)C * 12 * g.V * sizeof(float2));
     launch_pack_spinor(g, rd, r32, C64, c->frs(), C, c->st);
     const double2* qd = (const double2*)io.in(teacher, cb, where, "io_in2");
