@@ -505,7 +505,8 @@ struct wcamg_ctx {
     snprintf(key, sizeof(key), "dslash|op%d|in%d|out%d|f%d|c%d|res%d|V%d|Vb%d|n%d", op, in_t, out_t, a.fields16,
              a.compute32, b ? 1 : 0, g.V, g.Vb, nrhs);
     std::vector<int> dcands = {64, 128, 256, 512};
-    if (op == OP_D) dcands.push_back(-1);  // colour-split variant
+    if (op == OP_D) dcands.push_back(-1);                                // colour-split variant
+    if (op == OP_D && dslash_lds_slices(g) > 0) dcands.push_back(-2);  // LDS-staged tiles
     a.block_size = tune(key, dcands, [&](int v) {
       DslashArgs q = a;
       q.block_size = v;

@@ -333,7 +333,12 @@ __global__ __launch_bounds__(256) void k_coarse_build(Geo g, int nv, R kappa, co
   const int T = 256 / nv;  // sites per tile (threads t < T nv compute the vectors g)
   cplx<R>* sv = (cplx<R>*)smem;     // [T][nv][12]
   cplx<R>* sgv = sv + T * nv * 12;  // [T][nv][12]
-  const int X = blockIdx.x, d = blockIdx.y, sp = blockIdx.z;
+  // one workgroup per (X, d, sp), X slowest; consecutive logical indices run on
+  // one XCD, so the 18 workgroups of a block share that XCD's L2
+  const int nlog = g.nblk * 18;
+  const int lg = xcd_remap(blockIdx.x, nlog);
+  if (lg >= nlog) return;
+  const int X = lg / 18, d = (lg % 18) >> 1, sp = lg & 1;
   const int t = threadIdx.x;
   const int Vg = g.V;
   const int mu = (d - 1) & 3;
@@ -478,7 +483,12 @@ __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float ka
   constexpr int K = T * 6;  // k per tile and chirality
   __shared__ float svr[2][K][32], svi[2][K][32], sgr[2][K][32], sgi[2][K][32];
   const int N = 2 * nv;
-  const int X = blockIdx.x, d = blockIdx.y, sp = blockIdx.z;
+  // one workgroup per (X, d, sp), X slowest; consecutive logical indices run on
+  // one XCD, so the 18 workgroups of a block share that XCD's L2
+  const int nlog = g.nblk * 18;
+  const int lg = xcd_remap(blockIdx.x, nlog);
+  if (lg >= nlog) return;
+  const int X = lg / 18, d = (lg % 18) >> 1, sp = lg & 1;
   const int t = threadIdx.x;
   const int Vg = g.V;
   const int mu = (d - 1) & 3;
@@ -622,7 +632,7 @@ static void coarse_build_run(const Geo& g, int nv, double kappa, const void* V, 
   const int ncg = 256 / N;
   const int cpg = (nv + ncg - 1) / ncg;
   const size_t lds = 2 * (size_t)(256 / nv) * nv * 12 * sizeof(cplx<R>);
-  dim3 grid(g.nblk, 9, 2);
+  dim3 grid(round8(g.nblk * 18));
   auto go = [&](auto tag) {
     constexpr int CPG = decltype(tag)::value;
     auto kern = k_coarse_build<R, TV, TL, TC, TO, CPG>;
@@ -646,7 +656,7 @@ void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, cons
   if (mixed && variant == 1) {
     if (nv > 32) throw std::runtime_error("coarse build: the matrix-core variant needs nv <= 32");
     constexpr int T = 8;  // 256 threads cover T * nv <= 256 (site, vector) pairs
-    k_coarse_build_mf<T><<<dim3(g.nblk, 9, 2), 256, 0, st>>>(g, nv, (float)kappa, (const half2_t*)V,
+    k_coarse_build_mf<T><<<dim3(round8(g.nblk * 18)), 256, 0, st>>>(g, nv, (float)kappa, (const half2_t*)V,
                                                                (const half2_t*)U, (const half2_t*)C, (float2*)Dc);
     return;
   }

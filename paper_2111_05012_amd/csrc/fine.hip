@@ -433,8 +433,102 @@ __global__ __launch_bounds__(192) void k_dslash_cs(Geo g, const TI* __restrict__
   }
 }
 
+// LDS-staged variant of the full operator.  A workgroup takes one tile: a
+// slab of tt consecutive t-slices of one block (TS = B0 B1 B2 tt sites, one
+// thread per site).  The tile's input spinors are staged in LDS once, so every
+// hop to a neighbour inside the tile reads LDS; hops leaving the tile read
+// memory.  The forward and backward hop of each direction are taken back to
+// back, so that the backward link U_mu(x - mu), the forward link of another
+// site of the tile, is read while that line is still in the caches.
+template <class R, class TI, class TO, class TL, class TC>
+__global__ __launch_bounds__(256) void k_dslash_lds(Geo g, int tt, const TI* __restrict__ in, size_t in_rs,
+                                                    TO* __restrict__ out, size_t out_rs, const TO* __restrict__ b,
+                                                    const TL* __restrict__ U, const TC* __restrict__ C, R kappa) {
+  extern __shared__ __align__(16) char smem[];
+  cplx<R>* sp = (cplx<R>*)smem;  // [12][TS]
+  const int TS = blockDim.x;
+  const int per_blk = g.B[3] / tt;
+  const int ntile = g.nblk * per_blk;
+  const int tile = xcd_remap(blockIdx.x, ntile);
+  if (tile >= ntile) return;  // whole workgroup: no barrier is left waiting
+  const int blk = tile / per_blk, tb = tile - blk * per_blk;
+  const int loc0 = tb * TS;
+  const int l = threadIdx.x;
+  const int s = blk * g.Vb + loc0 + l;
+  const int rh = blockIdx.y;
+  const TI* inr = in + rh * in_rs;
+  const SiteCoord c = decompose(g, s);
+  const int ps = g.Vb;
+  const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
+  const int t_lo = tb * tt, t_hi = t_lo + tt;
+  cplx<R> acc[12], psi[12], u[9];
+  ld_spinor<R>(inr, ps, fb12, psi);
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    sp[a * TS + l] = psi[a];
+    acc[a] = psi[a];
+  }
+  clover_acc<R>(C, ps, fb36, psi, acc);
+  __syncthreads();
+#pragma unroll 1
+  for (int k = 0; k < 8; ++k) {
+    const int mu = k >> 1;
+    const bool fw = (k & 1) == 0;
+    int sign, nblk;
+    bool inb;
+    const int nb = fw ? neighbour<true>(g, s, c, mu, sign, inb, nblk) : neighbour<false>(g, s, c, mu, sign, inb, nblk);
+    bool intile = inb;
+    if (mu == 3) intile = inb && (fw ? c.lc[3] + 1 < t_hi : c.lc[3] - 1 >= t_lo);
+    if (intile) {
+      const int nl = nb - blk * g.Vb - loc0;
+#pragma unroll
+      for (int a = 0; a < 12; ++a) psi[a] = sp[a * TS + nl];
+    } else {
+      ld_spinor<R>(inr, ps, fbase_b(g, 12, nb, nblk), psi);
+    }
+    const R coef = -kappa * (R)sign;
+    if (fw) {
+      ld_link<R>(U, ps, mu, fb36, u);
+      hop_any<true>(mu, psi, u, coef, acc);
+    } else {
+      ld_link<R>(U, ps, mu, fbase_b(g, 36, nb, nblk), u);
+      hop_any<false>(mu, psi, u, coef, acc);
+    }
+  }
+  TO* outr = out + rh * out_rs;
+  if (b) {
+    const TO* br = b + rh * out_rs;
+#pragma unroll
+    for (int a = 0; a < 12; ++a) st(outr, (size_t)a * ps + fb12, ld<R>(br, (size_t)a * ps + fb12) - acc[a]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 12; ++a) st(outr, (size_t)a * ps + fb12, acc[a]);
+  }
+}
+
+// t-slices per tile of the LDS-staged operator (tile <= 256 sites), 0 if the
+// block's x-y-z cross-section alone exceeds 256 sites
+int dslash_lds_slices(const Geo& g) {
+  const int bxyz = g.B[0] * g.B[1] * g.B[2];
+  if (bxyz > 256) return 0;
+  int tt = 1;
+  for (int d = 1; d <= g.B[3]; ++d)
+    if (g.B[3] % d == 0 && bxyz * d <= 256) tt = d;
+  return tt;
+}
+
 template <class R, class TI, class TO, class TL, class TC>
 static void dslash_dispatch(const DslashArgs& a, hipStream_t st) {
+  if (a.block_size == -2 && a.op == OP_D) {
+    const int tt = dslash_lds_slices(a.g);
+    if (tt < 1) throw std::runtime_error("launch_dslash: no LDS tile for this block shape");
+    const int TS = a.g.B[0] * a.g.B[1] * a.g.B[2] * tt;
+    const int ntile = a.g.nblk * (a.g.B[3] / tt);
+    k_dslash_lds<R, TI, TO, TL, TC><<<dim3(round8(ntile), a.nrhs), TS, (size_t)12 * TS * sizeof(cplx<R>), st>>>(
+        a.g, tt, (const TI*)a.in, a.in_rs, (TO*)a.out, a.out_rs, (const TO*)a.b, (const TL*)a.U, (const TC*)a.C,
+        (R)a.kappa);
+    return;
+  }
   if (a.block_size < 0 && a.op == OP_D) {
     int nt = (a.g.V + 63) / 64;
     k_dslash_cs<R, TI, TO, TL, TC><<<dim3(round8(nt), a.nrhs), 192, 0, st>>>(

@@ -47,9 +47,12 @@ struct DslashArgs {
   int fields16 = 0;  // 0: FP64 links/clover, 1: FP16
   int compute32 = 0; // 0: FP64 arithmetic, 1: FP32
   double kappa = 0;
-  int block_size = 256;  // threads per workgroup (64 .. 512, autotuned); -1: colour-split variant (OP_D)
+  int block_size = 256;  // threads per workgroup (64 .. 512, autotuned); -1: colour-split variant,
+                         // -2: LDS-staged tiles (both OP_D only)
 };
 void launch_dslash(const DslashArgs& a, hipStream_t st);
+// t-slices per tile of the LDS-staged operator, 0 when it does not apply
+int dslash_lds_slices(const Geo& g);
 
 // ---------------------------------------------------------------- SAP smoother
 struct SapArgs {

@@ -89,6 +89,8 @@ def main(argv=None):
         ctx.get_test_vectors(Q)
         gauges[s] = U
         teachers[s] = Q.to(torch.complex64)
+        if (s - train[0]) % 25 == 24:
+            log('teachers: %d of %d (%.1f s)' % (s - train[0] + 1, len(train), time.perf_counter() - t0))
     t_teach = time.perf_counter() - t0
     log('teachers: %d configs in %.1f s' % (len(train), t_teach))
 
