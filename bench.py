@@ -25,6 +25,13 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
+# roofline of each kernel class: what bounds it, and its work unit for the
+# counter-based traffic (profiles/pmc_traffic.json, per unit of work)
+CLASS_BOUND = {'sap_half': 'alu32', 'coarse_mv': 'alu32', 'dslash64': 'hbm', 'dslash32': 'hbm', 'restrict': 'hbm',
+               'prolong': 'hbm', 'coarse_build': 'alu32', 'ortho': 'hbm'}
+CLASS_SOURCES = {'sap_half': ['fine.hip', 'wc_dirac.h', 'wc_common.h'],
+                 'dslash64': ['fine.hip', 'wc_dirac.h', 'wc_common.h']}
+
 WORKLOADS = {
     'c3': dict(dims=(32, 32, 32, 64), eps=0.3, seed=1, kappa=0.1365, csw=1.1, block=(4, 4, 4, 8), nv=32,
                nrhs=12, source='point'),
@@ -70,6 +77,31 @@ def run_step(ctx, U, b, x, V0, w, prec, rhs_chunk=0, nrhs=None):
 CLASSES = ['dslash64', 'dslash32', 'sap_half', 'restrict', 'prolong', 'coarse_solve', 'coarse_mv', 'coarse_build',
            'ortho']
 LEAVES = ['dslash64', 'dslash32', 'sap_half', 'restrict', 'prolong', 'coarse_mv', 'coarse_build', 'ortho']
+
+
+def source_sha(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, 'paper_2111_05012_amd', 'csrc', f), 'rb') as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(cls, units_per_launch):
+    """HBM bytes per launch of a kernel class from the committed counter runs
+    (FETCH_SIZE + WRITE_SIZE, calibrated by a 1 GiB copy), or None when there
+    are none or the kernel's sources changed since they were taken."""
+    try:
+        with open(os.path.join(ROOT, 'profiles', 'pmc_traffic.json')) as f:
+            t = json.load(f)['kernels'][cls]
+    except (OSError, KeyError, ValueError):
+        return None
+    if cls not in CLASS_SOURCES or t.get('source_sha') != source_sha(CLASS_SOURCES[cls]):
+        return None
+    if 'fetch_per_unit' not in t:
+        return None
+    return (t['fetch_per_unit'] + t['write_per_unit']) * units_per_launch
 
 
 def kernel_profile(ctx, U, b, x, V0, w, prec):
@@ -246,7 +278,7 @@ def main():
 
     # kernel-class profile of one more (untimed) step
     prof, prof_s = kernel_profile(ctx, U, b, x, V0, w, PREC_MIXED)
-    leaf_ms = {k: prof[k]['ms'] for k in LEAVES}
+    leaf_ms = {k: prof[k]['ms'] for k in LEAVES if prof[k]['bytes'] or prof[k]['flops']}
     dom = max(leaf_ms, key=leaf_ms.get)
     d = prof[dom]
     kernels = {}
@@ -258,11 +290,25 @@ def main():
                           gbs=round(p['bytes'] / (p['ms'] * 1e-3) / 1e9, 1) if p['bytes'] else None,
                           tflops=round(p['flops'] / (p['ms'] * 1e-3) / 1e12, 2) if p['flops'] else None,
                           share=round(p['ms'] / (prof_s * 1e3), 3))
-    achieved = d['bytes'] / (d['ms'] * 1e-3) / 1e9 if d['bytes'] else None
-    roof = dict(kernel=dom, bound='hbm', achieved=round(achieved, 1) if achieved else None, peak=HBM_PEAK_GBS,
-                unit='GB/s', frac=round(achieved / HBM_PEAK_GBS, 4) if achieved else None, traffic=None,
-                ms_per_launch=round(d['ms'] / max(d['count'], 1), 4),
-                bytes_per_launch=d['bytes'] / max(d['count'], 1))
+    nl = max(d['count'], 1)
+    V = 1
+    for L in w['dims']:
+        V *= L
+    # units of the class per launch: RHS x sites (half the lattice for a SAP half-sweep)
+    units = d['units'] / nl * (V / 2 if dom == 'sap_half' else V)
+    traffic = counter_traffic(dom, units)
+    if CLASS_BOUND.get(dom, 'hbm') == 'hbm':
+        achieved = d['bytes'] / (d['ms'] * 1e-3) / 1e9
+        roof = dict(kernel=dom, bound='hbm', achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit='GB/s',
+                    frac=round(achieved / HBM_PEAK_GBS, 4))
+    else:
+        achieved = d['flops'] / (d['ms'] * 1e-3) / 1e12
+        roof = dict(kernel=dom, bound='alu', achieved=round(achieved, 2), peak=FP32_PEAK_TFLOPS, unit='TFLOP/s',
+                    frac=round(achieved / FP32_PEAK_TFLOPS, 4))
+    roof.update(traffic=round(traffic) if traffic else None, ms_per_launch=round(d['ms'] / nl, 4),
+                bytes_per_launch=d['bytes'] / nl, flops_per_launch=d['flops'] / nl,
+                traffic_note='HBM bytes per launch from FETCH_SIZE + WRITE_SIZE (profiles/pmc_traffic.json, '
+                             'scaled by a 1 GiB copy); null when the kernel changed since the counters were taken')
     dsl = dslash_bandwidth(ctx, w, dev)
     log('dslash fp64: %.3f ms, %.0f GB/s' % (dsl['ms_per_launch'], dsl['gbs']))
 

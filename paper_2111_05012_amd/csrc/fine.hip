@@ -433,6 +433,70 @@ __global__ __launch_bounds__(192) void k_dslash_cs(Geo g, const TI* __restrict__
   }
 }
 
+// Multi-RHS variant of the full operator: a thread applies D at one site to
+// NR right-hand sides, so that the site's clover block and each link are
+// loaded once and used NR times (grid.y = right-hand-side groups).
+template <class R, class TI, class TO, class TL, class TC, int NR>
+__global__ __launch_bounds__(256) void k_dslash_nr(Geo g, int nrhs, const TI* __restrict__ in, size_t in_rs,
+                                                   TO* __restrict__ out, size_t out_rs, const TO* __restrict__ b,
+                                                   const TL* __restrict__ U, const TC* __restrict__ C, R kappa) {
+  const int ntile = (g.V + 255) >> 8;
+  const int tile = xcd_remap(blockIdx.x, ntile);
+  if (tile >= ntile) return;
+  const int s = tile * 256 + threadIdx.x;
+  if (s >= g.V) return;
+  const int r0 = blockIdx.y * NR;
+  const SiteCoord c = decompose(g, s);
+  const int ps = g.Vb;
+  const size_t fb12 = fbase_b(g, 12, s, c.blk), fb36 = fbase_b(g, 36, s, c.blk);
+  cplx<R> acc[NR][12], psi[12], u[9];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    if (r0 + q < nrhs) {
+      ld_spinor<R>(in + (size_t)(r0 + q) * in_rs, ps, fb12, psi);
+#pragma unroll
+      for (int a = 0; a < 12; ++a) acc[q][a] = psi[a];
+      clover_acc<R>(C, ps, fb36, psi, acc[q]);
+    }
+  }
+#pragma unroll 1
+  for (int k = 0; k < 8; ++k) {
+    const int mu = k >> 1;
+    const bool fw = (k & 1) == 0;
+    int sign, nblk;
+    bool inb;
+    const int nb = fw ? neighbour<true>(g, s, c, mu, sign, inb, nblk) : neighbour<false>(g, s, c, mu, sign, inb, nblk);
+    const size_t nb12 = fbase_b(g, 12, nb, nblk);
+    ld_link<R>(U, ps, mu, fw ? fb36 : fbase_b(g, 36, nb, nblk), u);
+    const R coef = -kappa * (R)sign;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      if (r0 + q < nrhs) {
+        ld_spinor<R>(in + (size_t)(r0 + q) * in_rs, ps, nb12, psi);
+        if (fw)
+          hop_any<true>(mu, psi, u, coef, acc[q]);
+        else
+          hop_any<false>(mu, psi, u, coef, acc[q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    if (r0 + q < nrhs) {
+      TO* outr = out + (size_t)(r0 + q) * out_rs;
+      if (b) {
+        const TO* br = b + (size_t)(r0 + q) * out_rs;
+#pragma unroll
+        for (int a = 0; a < 12; ++a)
+          st(outr, (size_t)a * ps + fb12, ld<R>(br, (size_t)a * ps + fb12) - acc[q][a]);
+      } else {
+#pragma unroll
+        for (int a = 0; a < 12; ++a) st(outr, (size_t)a * ps + fb12, acc[q][a]);
+      }
+    }
+  }
+}
+
 // LDS-staged variant of the full operator.  A workgroup takes one tile: a
 // slab of tt consecutive t-slices of one block (TS = B0 B1 B2 tt sites, one
 // thread per site).  The tile's input spinors are staged in LDS once, so every
@@ -519,6 +583,22 @@ int dslash_lds_slices(const Geo& g) {
 
 template <class R, class TI, class TO, class TL, class TC>
 static void dslash_dispatch(const DslashArgs& a, hipStream_t st) {
+  if (a.block_size <= -12 && a.op == OP_D) {
+    const int NR = -a.block_size - 10;
+    const int nt = (a.g.V + 255) / 256;
+    dim3 grid(round8(nt), (a.nrhs + NR - 1) / NR);
+    auto go = [&](auto kern) {
+      kern<<<grid, 256, 0, st>>>(a.g, a.nrhs, (const TI*)a.in, a.in_rs, (TO*)a.out, a.out_rs, (const TO*)a.b,
+                                 (const TL*)a.U, (const TC*)a.C, (R)a.kappa);
+    };
+    if (NR == 2)
+      go(k_dslash_nr<R, TI, TO, TL, TC, 2>);
+    else if (NR == 4)
+      go(k_dslash_nr<R, TI, TO, TL, TC, 4>);
+    else
+      throw std::runtime_error("launch_dslash: unsupported right-hand sides per thread");
+    return;
+  }
   if (a.block_size == -2 && a.op == OP_D) {
     const int tt = dslash_lds_slices(a.g);
     if (tt < 1) throw std::runtime_error("launch_dslash: no LDS tile for this block shape");
