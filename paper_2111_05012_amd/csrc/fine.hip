@@ -882,6 +882,12 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   }
   __syncthreads();
 
+  // the site's clover (FP16): reloaded at the end of every MR iteration for the
+  // next one, so that the load is in flight during the reduction and barrier
+  // instead of stalling the start of the iteration
+  half2_t cl[36];
+#pragma unroll
+  for (int q = 0; q < 36; ++q) cl[q] = C[(size_t)q * Vb + fb36];
   for (int rr = 0; rr < nrhs; ++rr) {
     const size_t off = rr * rs;
     cplx<float> rho[12], xm[12], p[12], psi[12];
@@ -918,10 +924,10 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
       __syncthreads();
       float pr_re = 0, pr_im = 0, pp = 0;
       if (act) {
-        // p = (1 + F) rho + in-domain hops; the domain's clover blocks stay in L2
+        // p = (1 + F) rho + in-domain hops
 #pragma unroll
         for (int a = 0; a < 12; ++a) p[a] = rho[a];
-        clover_acc<float>(C, Vb, fb36, rho, p);
+        clover_acc<float>(cl, 1, 0, rho, p);
         // unrolled: direction and projection are compile-time constants
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
