@@ -572,6 +572,7 @@ struct wcamg_ctx {
     for (int v : {32, 16, 8, 4})
       if (g.Vb % v == 0) cands.push_back(v);
     if (cands.empty()) cands.push_back(0);
+    if (h.prec == WCAMG_PREC_FP64 && h.nv <= 32 && nrhs <= 32) cands.push_back(RESTRICT_MFMA64);
     int tile = tune(key, cands, [&](int v) {
       launch_restrict(g, h.nv, nrhs, h.V.p, vec_t(), in, spin_t(h.prec), frs(), out, crs_t(), crs_n(), h.N, 0, st,
                       v);
@@ -712,7 +713,7 @@ struct wcamg_ctx {
     launch_zero(bad, sizeof(int), st);
     size_t grs = (size_t)g.nblk * 2 * nv;
     for (int pass = 0; pass < 2; ++pass) {
-      launch_restrict(g, nv, nv, Vw, t, Vw, t, frs(), G, C128, grs, 2 * nv, 1, st);
+      launch_restrict(g, nv, nv, Vw, t, Vw, t, frs(), G, C128, grs, 2 * nv, 1, st, nv <= 32 ? RESTRICT_MFMA64 : 0);
       launch_cholesky_coef(g.nblk, nv, G, grs, coef, t, grs, bad, st);
       launch_prolong(g, nv, nv, Vw, t, coef, t, grs, 2 * nv, tmp, t, frs(), 0, prec == WCAMG_PREC_MIXED, st);
       HIPCHK(hipMemcpyAsync(Vw, tmp, fsz(nv, prec), hipMemcpyDeviceToDevice, st));
@@ -734,9 +735,13 @@ struct wcamg_ctx {
     if (mixed && nv <= 32) cands = {1, 0};  // matrix-core contraction first
     char key[96];
     snprintf(key, sizeof(key), "coarse_build|nv%d|Vb%d|V%d", nv, g.Vb, g.V);
-    int var = tune(key, cands, [&](int v) { launch_coarse_build(g, nv, kappa, h.V.p, Uf, Cf, h.Dc.p, mixed, st, v); });
+    void* part = nullptr;
+    if (mixed && nv <= 32)
+      part = W("cb_part", (size_t)coarse_build_chunks(g) * g.nblk * N * N * sizeof(float2));
+    int var = tune(key, cands,
+                   [&](int v) { launch_coarse_build(g, nv, kappa, h.V.p, Uf, Cf, h.Dc.p, mixed, st, v, part); });
     Timed tb(this, "coarse_build", 0, 0, 1, true);
-    launch_coarse_build(g, nv, kappa, h.V.p, Uf, Cf, h.Dc.p, mixed, st, var);
+    launch_coarse_build(g, nv, kappa, h.V.p, Uf, Cf, h.Dc.p, mixed, st, var, part);
   }
 
   // level-1 block orthonormalisation of W in place (CholQR twice, FP64 Gram)

@@ -15,6 +15,11 @@
 
 namespace wc {
 
+// matrix-core accumulator types
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+
 // ---------------------------------------------------------------------------
 // Restriction.  One workgroup per block X.  Thread t owns the outputs
 // (s, i, rhs group of RB); tiles of TS sites of V and of the input are staged
@@ -113,9 +118,84 @@ static void restrict_rb(const Geo& g, int nv, int nrhs, const void* V, const voi
     restrict_run<RA, TV, TI, TO, 16>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st, tile);
 }
 
+// Matrix-core restriction with FP64 products and sums (the Gram matrices of
+// the orthonormalisation, and the FP64 restriction), nv <= 32, nrhs <= 32:
+//   out[r][X][s nv + i] = sum_{y in X, a in s} conj(v_i(y)_a) x_r(y)_a.
+// One workgroup per (block, chirality); wave w owns the 16x16 output tile
+// (rows i in 16 (w & 1) .., columns r in 16 (w >> 1) ..) as real and
+// imaginary accumulators of v_mfma_f64_16x16x4f64 (A: lane l holds row
+// l % 16 of k-slice l / 16; B: column l % 16 of k-slice l / 16; accumulator q
+// of lane l is element (4 (l / 16) + q, l % 16)).  k runs over (component of
+// the chirality, site) in stages of 32 sites staged in LDS.
+
+template <class TI>
+__global__ __launch_bounds__(256) void k_restrict_mf64(Geo g, int nv, int nrhs, const TI* __restrict__ V,
+                                                       const TI* __restrict__ in, size_t in_rs,
+                                                       double2* __restrict__ out, size_t out_rs, size_t out_xs) {
+  constexpr int KC = 32;
+  __shared__ double2 sv[KC][33], sx[KC][33];
+  const int nlog = g.nblk * 2;
+  const int lg = xcd_remap(blockIdx.x, nlog);
+  if (lg >= nlog) return;
+  const int X = lg >> 1, s = lg & 1;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int it = w & 1, rt = w >> 1;
+  f64x4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+  const size_t base = (size_t)X * 12 * g.Vb;  // plane 0 of block X
+  for (int a6 = 0; a6 < 6; ++a6) {
+    const size_t pl = base + (size_t)(6 * s + a6) * g.Vb;
+    for (int l0 = 0; l0 < g.Vb; l0 += KC) {
+      // stage KC sites of component a for every vector and right-hand side:
+      // a wavefront reads KC consecutive sites of one plane
+      for (int e = t; e < 32 * KC; e += 256) {
+        const int c = e / KC, kk = e - c * KC;
+        const int loc = l0 + kk;
+        cplx<double> v = {0, 0}, x = {0, 0};
+        if (loc < g.Vb) {
+          if (c < nv) v = ld<double>(V, (size_t)c * 12 * g.V + pl + loc);
+          if (c < nrhs) x = ld<double>(in, (size_t)c * in_rs + pl + loc);
+        }
+        sv[kk][c] = make_double2(v.x, v.y);
+        sx[kk][c] = make_double2(x.x, x.y);
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < KC; kk += 4) {
+        const int k = kk + (lane >> 4);
+        const double2 va = sv[k][16 * it + (lane & 15)];
+        const double2 xb = sx[k][16 * rt + (lane & 15)];
+        re = __builtin_amdgcn_mfma_f64_16x16x4f64(va.x, xb.x, re, 0, 0, 0);
+        re = __builtin_amdgcn_mfma_f64_16x16x4f64(va.y, xb.y, re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f64_16x16x4f64(va.x, xb.y, im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f64_16x16x4f64(-va.y, xb.x, im, 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  const int r = 16 * rt + (lane & 15);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = 16 * it + 4 * (lane >> 4) + q;
+    if (i < nv && r < nrhs) out[(size_t)r * out_rs + (size_t)X * out_xs + s * nv + i] = make_double2(re[q], im[q]);
+  }
+}
+
 void launch_restrict(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* in, int in_t,
                      size_t in_rs, void* out, int out_t, size_t out_rs, size_t out_xs, int acc64,
                      hipStream_t st, int tile) {
+  if (tile == RESTRICT_MFMA64) {
+    if (nv > 32 || nrhs > 32 || out_t != C128 || v_t != in_t || (v_t != C128 && v_t != C64))
+      throw std::runtime_error("launch_restrict: the FP64 matrix-core path needs FP64 output, equal FP64 or FP32 "
+                               "operand types and nv, nrhs <= 32");
+    const dim3 grid(round8(g.nblk * 2));
+    if (v_t == C128)
+      k_restrict_mf64<double2><<<grid, 256, 0, st>>>(g, nv, nrhs, (const double2*)V, (const double2*)in, in_rs,
+                                                     (double2*)out, out_rs, out_xs);
+    else
+      k_restrict_mf64<float2><<<grid, 256, 0, st>>>(g, nv, nrhs, (const float2*)V, (const float2*)in, in_rs,
+                                                    (double2*)out, out_rs, out_xs);
+    return;
+  }
   if (v_t == C128 && in_t == C128 && out_t == C128)
     return restrict_rb<double, double2, double2, double2>(g, nv, nrhs, V, in, in_rs, out, out_rs, out_xs, st, tile);
   if (v_t == C32H && in_t == C64 && out_t == C64 && !acc64)
@@ -202,6 +282,70 @@ static void prolong_run(const Geo& g, int nv, int nrhs, const void* V, const voi
     go(std::integral_constant<int, 16>());
 }
 
+// Matrix-core prolongation for FP32 vectors and coefficients (the update
+// V' = V coef of the orthonormalisation), nv <= 32, nrhs <= 32:
+//   out_r(y, a) (+)= sum_i V_i(y, a) xc[r][X(y)][s(a) nv + i].
+// Computed transposed, out^T[r][k] = sum_i xc[i][r] V_i[k], so that a
+// wavefront's results for one right-hand side are 32 consecutive sites.  One
+// workgroup per (block, chirality); each wavefront takes tiles of 32 sites of
+// one component plane; v_mfma_f32_32x32x2f32 with A = coefficients (lane l:
+// row r = l % 32, i-slice l / 32) and B = vectors (lane l: i-slice l / 32,
+// site l % 32); accumulator q of lane l is (r = 8 (q / 4) + 4 (l / 32) + q % 4,
+// site l % 32).
+__global__ __launch_bounds__(256) void k_prolong_mf(Geo g, int nv, int nrhs, const float2* __restrict__ V,
+                                                    const float2* __restrict__ xc, size_t xc_rs, size_t xc_xs,
+                                                    float2* __restrict__ out, size_t out_rs, int accumulate) {
+  const int nlog = g.nblk * 2;
+  const int lg = xcd_remap(blockIdx.x, nlog);
+  if (lg >= nlog) return;
+  const int X = lg >> 1, s = lg & 1;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int lr = lane & 31, lh = lane >> 5;
+  // coefficients of this lane for the 16 i-steps: xc[r = lr][X][s nv + i], i = 2 step + lh
+  float cr[16], ci[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int i = 2 * q + lh;
+    cplx<float> c = {0, 0};
+    if (i < nv && lr < nrhs) c = ld<float>(xc, (size_t)lr * xc_rs + (size_t)X * xc_xs + s * nv + i);
+    cr[q] = c.x;
+    ci[q] = c.y;
+  }
+  const int nst = (g.Vb + 31) / 32;  // site tiles per component plane
+  const size_t base = (size_t)X * 12 * g.Vb;
+  for (int tl = w; tl < 6 * nst; tl += 4) {
+    const int a = 6 * s + tl / nst;
+    const int loc = (tl % nst) * 32 + lr;
+    const bool in = loc < g.Vb;
+    const size_t o = base + (size_t)a * g.Vb + (in ? loc : 0);
+    f32x16 re, im;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) re[q] = im[q] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int i = 2 * q + lh;
+      cplx<float> v = {0, 0};
+      if (in && i < nv) v = ld<float>(V, (size_t)i * 12 * g.V + o);
+      re = __builtin_amdgcn_mfma_f32_32x32x2f32(cr[q], v.x, re, 0, 0, 0);
+      re = __builtin_amdgcn_mfma_f32_32x32x2f32(-ci[q], v.y, re, 0, 0, 0);
+      im = __builtin_amdgcn_mfma_f32_32x32x2f32(cr[q], v.y, im, 0, 0, 0);
+      im = __builtin_amdgcn_mfma_f32_32x32x2f32(ci[q], v.x, im, 0, 0, 0);
+    }
+    if (in) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int r = 8 * (q >> 2) + 4 * lh + (q & 3);
+        if (r < nrhs) {
+          const size_t oo = (size_t)r * out_rs + o;
+          cplx<float> val = {re[q], im[q]};
+          if (accumulate) val = val + ld<float>(out, oo);
+          st(out, oo, val);
+        }
+      }
+    }
+  }
+}
+
 void launch_prolong(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* xc, int xc_t, size_t xc_rs,
                     size_t xc_xs, void* out, int out_t, size_t out_rs, int accumulate, int compute32,
                     hipStream_t st) {
@@ -211,9 +355,15 @@ void launch_prolong(const Geo& g, int nv, int nrhs, const void* V, int v_t, cons
   if (compute32 && v_t == C32H && xc_t == C64 && out_t == C64)
     return prolong_run<float, half2_t, float2, float2>(g, nv, nrhs, V, xc, xc_rs, xc_xs, out, out_rs, accumulate,
                                                        st);
-  if (compute32 && v_t == C64 && xc_t == C64 && out_t == C64)
+  if (compute32 && v_t == C64 && xc_t == C64 && out_t == C64) {
+    if (nv <= 32 && nrhs <= 32) {
+      k_prolong_mf<<<round8(g.nblk * 2), 256, 0, st>>>(g, nv, nrhs, (const float2*)V, (const float2*)xc, xc_rs,
+                                                       xc_xs, (float2*)out, out_rs, accumulate);
+      return;
+    }
     return prolong_run<float, float2, float2, float2>(g, nv, nrhs, V, xc, xc_rs, xc_xs, out, out_rs, accumulate,
                                                       st);
+  }
   if (!compute32 && v_t == C64 && xc_t == C128 && out_t == C64)
     return prolong_run<double, float2, double2, float2>(g, nv, nrhs, V, xc, xc_rs, xc_xs, out, out_rs, accumulate,
                                                         st);
@@ -474,21 +624,36 @@ __global__ __launch_bounds__(256) void k_coarse_build(Geo g, int nv, R kappa, co
 // B: column l % 32 of k-slice l / 32; accumulator v of lane l is element
 // (8 (v / 4) + 4 (l / 32) + v % 4, l % 32)).  Indices i, j >= nv are padding
 // held at zero in LDS.
-typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+//
+// Work units per block X: the in-block part (d = 0) split into nch chunks of
+// site tiles for each sp, then (d, sp) for the 8 crossing directions.  All
+// units of a block are consecutive logical indices on one XCD, so that few
+// blocks are in flight per XCD and their vectors stay in its L2.  A d = 0
+// chunk writes its partial block to part[X][chunk][(sp, j)][(s, i)]; the
+// partials are summed in chunk order by k_coarse_build_sum (deterministic).
 template <int T>
 __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float kappa, const half2_t* __restrict__ V,
                                                          const half2_t* __restrict__ U,
-                                                         const half2_t* __restrict__ C, float2* __restrict__ Dc) {
+                                                         const half2_t* __restrict__ C, float2* __restrict__ Dc,
+                                                         int nch, int tpc, float2* __restrict__ part) {
   constexpr int K = T * 6;  // k per tile and chirality
   __shared__ float svr[2][K][32], svi[2][K][32], sgr[2][K][32], sgi[2][K][32];
   const int N = 2 * nv;
-  // one workgroup per (X, d, sp), X slowest; consecutive logical indices run on
-  // one XCD, so the 18 workgroups of a block share that XCD's L2
-  const int nlog = g.nblk * 18;
+  const int nu = 2 * nch + 16;
+  const int nlog = g.nblk * nu;
   const int lg = xcd_remap(blockIdx.x, nlog);
   if (lg >= nlog) return;
-  const int X = lg / 18, d = (lg % 18) >> 1, sp = lg & 1;
+  const int X = lg / nu, u = lg - X * nu;
+  int d, sp, chunk = 0;
+  if (u < 2 * nch) {
+    d = 0;
+    sp = u & 1;
+    chunk = u >> 1;
+  } else {
+    d = 1 + ((u - 2 * nch) >> 1);
+    sp = u & 1;
+  }
   const int t = threadIdx.x;
   const int Vg = g.V;
   const int mu = (d - 1) & 3;
@@ -506,18 +671,20 @@ __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float ka
     (&sgi[0][0][0])[e] = 0.f;
   }
   const int w = t >> 6, lane = t & 63;
-  const int ws = w >> 1, part = w & 1;
+  const int ws = w >> 1, part_ = w & 1;
   f32x16 acc;
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.f;
   __syncthreads();
 
-  for (int tile0 = 0; tile0 < nsites; tile0 += T) {
+  const int tbeg = d == 0 ? chunk * tpc * T : 0;
+  const int tend = d == 0 ? min(nsites, (chunk + 1) * tpc * T) : nsites;
+  for (int tile0 = tbeg; tile0 < tend; tile0 += T) {
     if (t < T * nv) {
       const int st_ = t / nv, j = t - st_ * nv;
       const int f = tile0 + st_;
       cplx<float> vj[12], gj[12];
-      if (f < nsites) {
+      if (f < tend) {
         int loc;
         if (d == 0) {
           loc = f;
@@ -604,7 +771,7 @@ __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float ka
       const int k = kk + kh;
       const float ar = svr[ws][k][r], ai = svi[ws][k][r];
       const float br = sgr[ws][k][r], bi = sgi[ws][k][r];
-      if (part == 0) {
+      if (part_ == 0) {
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, acc, 0, 0, 0);
       } else {
@@ -615,13 +782,31 @@ __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float ka
     __syncthreads();
   }
   // D element (i, j): column (sp, j), row (s, i) of the column-major block
-  float* out = (float*)Dc;
+  // (d = 0: of this chunk's partial block)
+  float* out = d == 0 ? (float*)part : (float*)Dc;
+  const size_t blk0 = d == 0 ? (size_t)X * nch + chunk : (size_t)X * 9 + d;
   const int j = lane & 31;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int i = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-    if (i < nv && j < nv) out[2 * ((((size_t)X * 9 + d) * N + (sp * nv + j)) * N + (ws * nv + i)) + part] = acc[q];
+    if (i < nv && j < nv) out[2 * ((blk0 * N + (sp * nv + j)) * N + (ws * nv + i)) + part_] = acc[q];
   }
+}
+
+// Dc[X][0] = sum over chunks of the partial in-block blocks, in chunk order
+__global__ __launch_bounds__(256) void k_coarse_build_sum(int nblk, int N, int nch, const float2* __restrict__ part,
+                                                          float2* __restrict__ Dc) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t nn = (size_t)N * N;
+  if (e >= (size_t)nblk * nn) return;
+  const size_t X = e / nn, r = e - X * nn;
+  float2 s = make_float2(0.f, 0.f);
+  for (int c = 0; c < nch; ++c) {
+    const float2 v = part[(X * nch + c) * nn + r];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  Dc[X * 9 * nn + r] = s;
 }
 
 template <class R, class TV, class TL, class TC, class TO>
@@ -651,13 +836,26 @@ static void coarse_build_run(const Geo& g, int nv, double kappa, const void* V, 
     go(std::integral_constant<int, 16>());
 }
 
+int coarse_build_chunks(const Geo& g) {
+  const int ntile = (g.Vb + 7) / 8;  // 8-site tiles
+  return (ntile + 7) / 8;            // 8 tiles per chunk
+}
+
 void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C, void* Dc,
-                         int mixed, hipStream_t st, int variant) {
+                         int mixed, hipStream_t st, int variant, void* part) {
   if (mixed && variant == 1) {
     if (nv > 32) throw std::runtime_error("coarse build: the matrix-core variant needs nv <= 32");
+    if (!part) throw std::runtime_error("coarse build: the matrix-core variant needs its partial-sum workspace");
     constexpr int T = 8;  // 256 threads cover T * nv <= 256 (site, vector) pairs
-    k_coarse_build_mf<T><<<dim3(round8(g.nblk * 18)), 256, 0, st>>>(g, nv, (float)kappa, (const half2_t*)V,
-                                                               (const half2_t*)U, (const half2_t*)C, (float2*)Dc);
+    const int tpc = 8;    // tiles per in-block chunk (64 sites)
+    const int nch = coarse_build_chunks(g);
+    const int N = 2 * nv;
+    k_coarse_build_mf<T><<<dim3(round8(g.nblk * (2 * nch + 16))), 256, 0, st>>>(
+        g, nv, (float)kappa, (const half2_t*)V, (const half2_t*)U, (const half2_t*)C, (float2*)Dc, nch, tpc,
+        (float2*)part);
+    const size_t ne = (size_t)g.nblk * N * N;
+    k_coarse_build_sum<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(g.nblk, N, nch, (const float2*)part,
+                                                                     (float2*)Dc);
     return;
   }
   if (mixed)

@@ -93,7 +93,10 @@ inline CGeo make_cgeo(const int* n) {
 // restriction eq.(5): out[r][X][s*nv+i] = sum_{y in X, a in s} conj(V_i(y,a)) in_r(y,a)
 // V: [nv][12][V] of type v_t; in: [nrhs][12][V] (in_rs); out element (r, X, n) at
 // r*out_rs + X*out_xs + n.  acc64: accumulate in FP64.
-// tile: sites per LDS tile (0: largest that fits 48 KiB; else a power of two dividing Vb)
+// tile: sites per LDS tile (0: largest that fits 48 KiB; else a power of two dividing Vb);
+// RESTRICT_MFMA64: FP64 matrix-core path (FP64 output, equal FP64 or FP32 operands,
+// nv, nrhs <= 32)
+constexpr int RESTRICT_MFMA64 = -64;
 void launch_restrict(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* in, int in_t,
                      size_t in_rs, void* out, int out_t, size_t out_rs, size_t out_xs, int acc64,
                      hipStream_t st, int tile = 0);
@@ -110,9 +113,11 @@ void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void
                       int astride = 0);
 // coarse operator eq.(7) from the stored test vectors V [nv][12][V] (mixed: FP16 V,
 // links, clover; FP32 arithmetic; complex64 Dc) into Dc [X][9][m][n].
-// variant (mixed only): 0 vector-ALU contraction, 1 matrix-core contraction (nv <= 32)
+// variant (mixed only): 0 vector-ALU contraction, 1 matrix-core contraction (nv <= 32),
+// which needs a workspace `part` of coarse_build_chunks(g) * nblk * (2 nv)^2 complex64
 void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C, void* Dc,
-                         int mixed, hipStream_t st, int variant = 0);
+                         int mixed, hipStream_t st, int variant = 0, void* part = nullptr);
+int coarse_build_chunks(const Geo& g);
 // level-1 aggregation (multi-level): coarse vectors [rhs][X1][n1], level-1
 // test vectors W [nw][X1][n1], level-1 blocks b1, level-2 vectors [rhs][X2][2nw]
 void launch_l1_restrict(const CGeo& c1, const int* b1, int n1, int nw, int nrhs, const void* W, int w_t,

@@ -78,13 +78,29 @@ def test_sap_mixed(prob):
     assert rel(prob.N(x), want) < 1e-2
 
 
-def test_orthonormalize_fp64(prob):
+@pytest.mark.parametrize('nv', [6, 20])
+def test_orthonormalize_fp64(prob, nv):
+    """FP64 block orthonormalisation (Gram matrices on the FP64 matrix cores;
+    nv = 20 spans two 16-row output tiles)."""
     from paper_2111_05012_amd import PREC_FP64
-    V = syn.gaussian_vectors(prob.dims, 6, 16)
+    V = syn.gaussian_vectors(prob.dims, nv, 16)
     out = prob.zeros(V.shape)
-    prob.ctx.orthonormalize(prob.T(V), out, 6, PREC_FP64)
+    prob.ctx.orthonormalize(prob.T(V), out, nv, PREC_FP64)
     want = amg.block_orthonormalize(V, prob.dims, prob.block)
     assert rel(prob.N(out), want) < 1e-12
+
+
+@pytest.mark.parametrize('nv', [6, 20])
+def test_orthonormalize_mixed(prob, nv):
+    """Mixed precision (FP32 vectors, FP64 Gram on the matrix cores, FP32
+    matrix-core update): the result of Cholesky-QR twice agrees with the
+    oracle to FP32 rounding amplified by the blocks' condition numbers."""
+    from paper_2111_05012_amd import PREC_MIXED
+    V = syn.gaussian_vectors(prob.dims, nv, 16)
+    out = prob.zeros(V.shape)
+    prob.ctx.orthonormalize(prob.T(V), out, nv, PREC_MIXED)
+    want = amg.block_orthonormalize(V, prob.dims, prob.block)
+    assert rel(prob.N(out), want) < 2e-5
 
 
 def _hier(prob, nv=4, prec=0, coarse_iters=20, coarse_tol=0.0, seed=17):
