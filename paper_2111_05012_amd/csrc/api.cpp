@@ -598,6 +598,7 @@ struct wcamg_ctx {
     std::vector<int> cands;
     for (int v : {1, 4, 8, 12, 16})
       if (v == 1 || v <= nrhs + 3) cands.push_back(v);
+    if (h.prec == WCAMG_PREC_MIXED && o.N <= 64 && nrhs <= 32) cands.push_back(COARSE_MV_MFMA);
     char key[160];
     snprintf(key, sizeof(key), "coarse_mv|N%d|NC%d|n%d|p%d|res%d", o.N, o.cg.NC, nrhs, h.prec, b ? 1 : 0);
     int var = tune(key, cands, [&](int v) {
@@ -1525,15 +1526,30 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
       void* zj = (char*)Z + (size_t)j * vs * ct_size(zt);
       double2* w = V + (size_t)(j + 1) * vs;
       c->dslash(zj, zt, w, C128, nrhs, OP_D, WCAMG_PREC_FP64);
+      // classical Gram-Schmidt, repeated when the projection removed more than
+      // half of |w|^2 for some right-hand side (|w'|^2 < sum_i |h_i|^2, the
+      // criterion of Daniel, Gragg, Kaufman and Stewart with 1/sqrt(2))
       launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h1, c->st);
-      launch_multiaxpy(V, vs, j + 1, h1, w, n, rs, nrhs, part, nullptr, c->st);
-      launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h2, c->st);
-      launch_multiaxpy(V, vs, j + 1, h2, w, n, rs, nrhs, part, nrm, c->st);
+      launch_multiaxpy(V, vs, j + 1, h1, w, n, rs, nrhs, part, nrm, c->st);
       HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
                             c->st));
-      HIPCHK(hipMemcpyAsync(hh2.data(), h2, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
-                            c->st));
       sync_get(hn.data(), nrm, nrhs * sizeof(double));
+      bool again = false;
+      for (int r = 0; r < nrhs; ++r) {
+        if (!ext[r]) continue;
+        double hsum = 0;
+        for (int i = 0; i <= j; ++i) hsum += hh1[(size_t)i * nrhs + r].x * hh1[(size_t)i * nrhs + r].x +
+                                             hh1[(size_t)i * nrhs + r].y * hh1[(size_t)i * nrhs + r].y;
+        again = again || !(hn[r] >= hsum);
+      }
+      std::fill(hh2.begin(), hh2.end(), make_double2(0.0, 0.0));
+      if (again) {
+        launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h2, c->st);
+        launch_multiaxpy(V, vs, j + 1, h2, w, n, rs, nrhs, part, nrm, c->st);
+        HIPCHK(hipMemcpyAsync(hh2.data(), h2, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
+                              c->st));
+        sync_get(hn.data(), nrm, nrhs * sizeof(double));
+      }
       bool any = false;
       for (int r = 0; r < nrhs; ++r) {
         hs[r] = 0.0;

@@ -125,7 +125,7 @@ static void restrict_rb(const Geo& g, int nv, int nrhs, const void* V, const voi
 // (rows i in 16 (w & 1) .., columns r in 16 (w >> 1) ..) as real and
 // imaginary accumulators of v_mfma_f64_16x16x4f64 (A: lane l holds row
 // l % 16 of k-slice l / 16; B: column l % 16 of k-slice l / 16; accumulator q
-// of lane l is element (4 (l / 16) + q, l % 16)).  k runs over (component of
+// of lane l is element (l / 16 + 4 q, l % 16)).  k runs over (component of
 // the chirality, site) in stages of 32 sites staged in LDS.
 
 template <class TI>
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_restrict_mf64(Geo g, int nv, int nrhs, 
   const int r = 16 * rt + (lane & 15);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int i = 16 * it + 4 * (lane >> 4) + q;
+    const int i = 16 * it + (lane >> 4) + 4 * q;
     if (i < nv && r < nrhs) out[(size_t)r * out_rs + (size_t)X * out_xs + s * nv + i] = make_double2(re[q], im[q]);
   }
 }
@@ -433,6 +433,87 @@ __global__ __launch_bounds__(256) void k_coarse_mv(CGeo cg, int N, const TC* __r
   }
 }
 
+// Matrix-core coarse stencil (complex64, 2 nv <= 64, nrhs <= 32).  One
+// workgroup per coarse site X; wave w computes the rows 32 (w & 1) .. of the
+// real (w < 2) or imaginary (w >= 2) part of y[.][X] for all right-hand sides
+// with v_mfma_f32_32x32x2f32: A = the stencil block (lane l: row l % 32 of
+// column-slice l / 32), B = the neighbour's vectors staged in LDS (lane l:
+// slice l / 32, right-hand side l % 32).  The results pass through LDS so that
+// each right-hand side's 2 nv entries are written contiguously.
+__global__ __launch_bounds__(256) void k_coarse_mv_mf(CGeo cg, int N, const float2* __restrict__ Dc,
+                                                      const float2* __restrict__ x, float2* __restrict__ y,
+                                                      const float2* __restrict__ b, size_t rs, int nrhs,
+                                                      const int* __restrict__ active, int astride) {
+  __shared__ float2 sx[64][33];    // [m][r]
+  __shared__ float sy[2][32][65];  // [re, im][r][n]
+  const int X = xcd_remap(blockIdx.x, cg.NC);
+  if (X >= cg.NC) return;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  // nothing to do once every right-hand side has stopped (same decision in all threads)
+  bool any = active == nullptr;
+  for (int r = 0; r < nrhs && !any; ++r) any = active[(size_t)r * astride] != 0;
+  if (!any) return;
+  int c[4];
+  {
+    int q = X;
+    for (int m = 0; m < 3; ++m) {
+      c[m] = q % cg.N[m];
+      q /= cg.N[m];
+    }
+    c[3] = q;
+  }
+  const int nt = w & 1, part = w >> 1;
+  const int n = 32 * nt + (lane & 31);
+  f32x16 acc;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+  for (int d = 0; d < 9; ++d) {
+    int Y = X;
+    if (d > 0) {
+      const int mu = (d - 1) & 3;
+      int cc = c[mu] + (d <= 4 ? 1 : -1);
+      if (cc == cg.N[mu]) cc = 0;
+      if (cc < 0) cc = cg.N[mu] - 1;
+      Y = X + (cc - c[mu]) * cg.sN[mu];
+    }
+    for (int e = t; e < 64 * 32; e += 256) {
+      const int r = e >> 6, m = e & 63;
+      float2 v = make_float2(0.f, 0.f);
+      if (r < nrhs && m < N) v = x[(size_t)r * rs + (size_t)Y * N + m];
+      sx[m][r] = v;
+    }
+    __syncthreads();
+    const float2* B = Dc + (size_t)(X * 9 + d) * N * N;
+#pragma unroll 4
+    for (int kk = 0; kk < 64; kk += 2) {
+      const int m = kk + (lane >> 5);
+      float2 av = make_float2(0.f, 0.f);
+      if (m < N && n < N) av = B[(size_t)m * N + n];
+      const float2 xb = sx[m][lane & 31];
+      if (part == 0) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, xb.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y, xb.y, acc, 0, 0, 0);
+      } else {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, xb.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, xb.x, acc, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) sy[part][lane & 31][32 * nt + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3)] = acc[q];
+  __syncthreads();
+  for (int e = t; e < 32 * 64; e += 256) {
+    const int r = e >> 6, nn = e & 63;
+    if (r < nrhs && nn < N && (!active || active[(size_t)r * astride])) {
+      const size_t o = (size_t)r * rs + (size_t)X * N + nn;
+      float2 v = make_float2(sy[0][r][nn], sy[1][r][nn]);
+      if (b) v = make_float2(b[o].x - v.x, b[o].y - v.y);
+      y[o] = v;
+    }
+  }
+}
+
 template <class R, class TC, class TX>
 static void coarse_mv_run(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
                           size_t rs, hipStream_t st, int variant, const int* active, int astride) {
@@ -458,6 +539,13 @@ static void coarse_mv_run(const CGeo& cg, int N, const void* Dc, const void* x, 
 
 void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
                       size_t rs, int prec32, hipStream_t st, int variant, const int* active, int astride) {
+  if (variant == COARSE_MV_MFMA) {
+    if (!prec32 || N > 64 || nrhs > 32)
+      throw std::runtime_error("coarse matvec: the matrix-core path needs complex64, 2 nv <= 64 and nrhs <= 32");
+    k_coarse_mv_mf<<<round8(cg.NC), 256, 0, st>>>(cg, N, (const float2*)Dc, (const float2*)x, (float2*)y,
+                                                 (const float2*)b, rs, nrhs, active, astride);
+    return;
+  }
   if (prec32)
     coarse_mv_run<float, float2, float2>(cg, N, Dc, x, y, b, nrhs, rs, st, variant, active, astride);
   else
