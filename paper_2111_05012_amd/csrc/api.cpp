@@ -506,7 +506,10 @@ struct wcamg_ctx {
              a.compute32, b ? 1 : 0, g.V, g.Vb, nrhs);
     std::vector<int> dcands = {64, 128, 256, 512};
     if (op == OP_D) dcands.push_back(-1);                                // colour-split variant
-    if (op == OP_D && dslash_lds_slices(g) > 0) dcands.push_back(-2);  // LDS-staged tiles
+    if (op == OP_D && dslash_lds_slices(g) > 0) {
+      dcands.push_back(-2);  // LDS-staged tiles
+      dcands.push_back(-3);  // LDS-staged tiles, backward hops exchanged as half-spinors
+    }
     if (op == OP_D && nrhs >= 2) dcands.push_back(-12);                 // 2 RHS per thread
     if (op == OP_D && nrhs >= 4 && a.compute32) dcands.push_back(-14);  // 4 RHS per thread
     a.block_size = tune(key, dcands, [&](int v) {

@@ -769,7 +769,7 @@ __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float ka
   const int tend = d == 0 ? min(nsites, (chunk + 1) * tpc * T) : nsites;
   for (int tile0 = tbeg; tile0 < tend; tile0 += T) {
     if (t < T * nv) {
-      const int st_ = t / nv, j = t - st_ * nv;
+      const int j = t / T, st_ = t - j * T;  // lanes run over sites: coalesced vector loads
       const int f = tile0 + st_;
       cplx<float> vj[12], gj[12];
       if (f < tend) {

@@ -570,6 +570,104 @@ __global__ __launch_bounds__(256) void k_dslash_lds(Geo g, int tt, const TI* __r
   }
 }
 
+// Half-spinor exchange variant of the full operator.  Tiles as in
+// k_dslash_lds (a t-slab of one block, one thread per site, the tile's input
+// spinors in LDS).  For each direction mu a thread loads only its own link
+// U_mu(x): it takes its forward hop, and it computes the projected backward
+// hop -kappa sign (1 + gamma_mu) U_mu(x)^dag psi(x) that the site x + mu
+// receives, handing it over through LDS as a half-spinor (6 complex).  A site
+// whose x - mu lies outside the tile takes that hop itself from memory.  Every
+// link of the tile is read once.
+template <class R, class TI, class TO, class TL, class TC>
+__global__ __launch_bounds__(256) void k_dslash_hx(Geo g, int tt, const TI* __restrict__ in, size_t in_rs,
+                                                   TO* __restrict__ out, size_t out_rs, const TO* __restrict__ b,
+                                                   const TL* __restrict__ U, const TC* __restrict__ C, R kappa) {
+  extern __shared__ __align__(16) char smem[];
+  const int TS = blockDim.x;
+  cplx<R>* sp = (cplx<R>*)smem;  // [12][TS] input spinors of the tile
+  cplx<R>* hx = sp + 12 * TS;     // [6][TS] backward half-spinors by receiving site
+  const int per_blk = g.B[3] / tt;
+  const int ntile = g.nblk * per_blk;
+  const int tile = xcd_remap(blockIdx.x, ntile);
+  if (tile >= ntile) return;  // whole workgroup: no barrier is left waiting
+  const int blk = tile / per_blk, tb = tile - blk * per_blk;
+  const int loc0 = tb * TS;
+  const int l = threadIdx.x;
+  const int s = blk * g.Vb + loc0 + l;
+  const int rh = blockIdx.y;
+  const TI* inr = in + rh * in_rs;
+  const SiteCoord c = decompose(g, s);
+  const int ps = g.Vb;
+  const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
+  const int t_lo = tb * tt, t_hi = t_lo + tt;
+  cplx<R> acc[12];
+  {
+    cplx<R> psi[12];
+    ld_spinor<R>(inr, ps, fb12, psi);
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      sp[a * TS + l] = psi[a];
+      acc[a] = psi[a];
+    }
+    clover_acc<R>(C, ps, fb36, psi, acc);
+  }
+  __syncthreads();
+  cplx<R> psi[12], u[9], g0[3], g1[3];
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    int sign, nblk;
+    bool inb;
+    const int nbf = neighbour<true>(g, s, c, mu, sign, inb, nblk);
+    const bool fin = inb && (mu != 3 || c.lc[3] + 1 < t_hi);
+    const R coef = -kappa * (R)sign;
+    ld_link<R>(U, ps, mu, fb36, u);
+    // the backward hop that x + mu receives from x, handed over through LDS
+    if (fin) {
+#pragma unroll
+      for (int a = 0; a < 12; ++a) psi[a] = sp[a * TS + l];
+      hop_half_any<false>(mu, psi, u, coef, g0, g1);
+      const int nl = nbf - blk * g.Vb - loc0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        hx[q * TS + nl] = g0[q];
+        hx[(3 + q) * TS + nl] = g1[q];
+      }
+#pragma unroll
+      for (int a = 0; a < 12; ++a) psi[a] = sp[a * TS + nl];
+    } else {
+      ld_spinor<R>(inr, ps, fbase_b(g, 12, nbf, nblk), psi);
+    }
+    // the forward hop x -> x + mu
+    hop_any<true>(mu, psi, u, coef, acc);
+    __syncthreads();
+    // the backward hop x - mu -> x
+    const int nbb = neighbour<false>(g, s, c, mu, sign, inb, nblk);
+    const bool bin = inb && (mu != 3 || c.lc[3] - 1 >= t_lo);
+    if (bin) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        g0[q] = hx[q * TS + l];
+        g1[q] = hx[(3 + q) * TS + l];
+      }
+      hop_recon_any<false>(mu, g0, g1, acc);
+    } else {
+      ld_spinor<R>(inr, ps, fbase_b(g, 12, nbb, nblk), psi);
+      ld_link<R>(U, ps, mu, fbase_b(g, 36, nbb, nblk), u);
+      hop_any<false>(mu, psi, u, -kappa * (R)sign, acc);
+    }
+    __syncthreads();  // hx is rewritten by the next direction
+  }
+  TO* outr = out + rh * out_rs;
+  if (b) {
+    const TO* br = b + rh * out_rs;
+#pragma unroll
+    for (int a = 0; a < 12; ++a) st(outr, (size_t)a * ps + fb12, ld<R>(br, (size_t)a * ps + fb12) - acc[a]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 12; ++a) st(outr, (size_t)a * ps + fb12, acc[a]);
+  }
+}
+
 // t-slices per tile of the LDS-staged operator (tile <= 256 sites), 0 if the
 // block's x-y-z cross-section alone exceeds 256 sites
 int dslash_lds_slices(const Geo& g) {
@@ -599,14 +697,20 @@ static void dslash_dispatch(const DslashArgs& a, hipStream_t st) {
       throw std::runtime_error("launch_dslash: unsupported right-hand sides per thread");
     return;
   }
-  if (a.block_size == -2 && a.op == OP_D) {
+  if ((a.block_size == -2 || a.block_size == -3) && a.op == OP_D) {
     const int tt = dslash_lds_slices(a.g);
     if (tt < 1) throw std::runtime_error("launch_dslash: no LDS tile for this block shape");
     const int TS = a.g.B[0] * a.g.B[1] * a.g.B[2] * tt;
     const int ntile = a.g.nblk * (a.g.B[3] / tt);
-    k_dslash_lds<R, TI, TO, TL, TC><<<dim3(round8(ntile), a.nrhs), TS, (size_t)12 * TS * sizeof(cplx<R>), st>>>(
-        a.g, tt, (const TI*)a.in, a.in_rs, (TO*)a.out, a.out_rs, (const TO*)a.b, (const TL*)a.U, (const TC*)a.C,
-        (R)a.kappa);
+    const dim3 grid(round8(ntile), a.nrhs);
+    if (a.block_size == -2)
+      k_dslash_lds<R, TI, TO, TL, TC><<<grid, TS, (size_t)12 * TS * sizeof(cplx<R>), st>>>(
+          a.g, tt, (const TI*)a.in, a.in_rs, (TO*)a.out, a.out_rs, (const TO*)a.b, (const TL*)a.U, (const TC*)a.C,
+          (R)a.kappa);
+    else
+      k_dslash_hx<R, TI, TO, TL, TC><<<grid, TS, (size_t)18 * TS * sizeof(cplx<R>), st>>>(
+          a.g, tt, (const TI*)a.in, a.in_rs, (TO*)a.out, a.out_rs, (const TO*)a.b, (const TL*)a.U, (const TC*)a.C,
+          (R)a.kappa);
     return;
   }
   if (a.block_size < 0 && a.op == OP_D) {

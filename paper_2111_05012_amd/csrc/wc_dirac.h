@@ -73,6 +73,75 @@ __device__ __forceinline__ void hop_accum(const cplx<R> (&psi)[12], const cplx<R
   }
 }
 
+// The two halves of hop_accum, for kernels that hand the projected result of
+// a hop to the site that receives it: g = coef * W h (h the spin projection
+// of psi), and acc += the spin reconstruction of g.
+template <int MU, bool FWD, class R>
+__device__ __forceinline__ void hop_half(const cplx<R> (&psi)[12], const cplx<R> (&u)[9], R coef, cplx<R> (&g0)[3],
+                                         cplx<R> (&g1)[3]) {
+  using P = Proj<MU>;
+  constexpr int T0 = FWD ? P::t0 : (P::t0 ^ 2);
+  constexpr int T1 = FWD ? P::t1 : (P::t1 ^ 2);
+  cplx<R> h0[3], h1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    h0[c] = psi[c] + unit<T0>(psi[(2 + P::pi0) * 3 + c]);
+    h1[c] = psi[3 + c] + unit<T1>(psi[(2 + P::pi1) * 3 + c]);
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    cplx<R> a = {0, 0}, b = {0, 0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (FWD) {
+        cmac(a, u[r * 3 + c], h0[c]);
+        cmac(b, u[r * 3 + c], h1[c]);
+      } else {
+        cjmac(a, u[c * 3 + r], h0[c]);
+        cjmac(b, u[c * 3 + r], h1[c]);
+      }
+    }
+    g0[r] = coef * a;
+    g1[r] = coef * b;
+  }
+}
+
+template <int MU, bool FWD, class R>
+__device__ __forceinline__ void hop_recon(const cplx<R> (&g0)[3], const cplx<R> (&g1)[3], cplx<R> (&acc)[12]) {
+  using P = Proj<MU>;
+  constexpr int S0 = FWD ? P::s0 : (P::s0 ^ 2);
+  constexpr int S1 = FWD ? P::s1 : (P::s1 ^ 2);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    acc[c] = acc[c] + g0[c];
+    acc[3 + c] = acc[3 + c] + g1[c];
+    acc[6 + c] = acc[6 + c] + unit<S0>(P::pi0 == 0 ? g0[c] : g1[c]);
+    acc[9 + c] = acc[9 + c] + unit<S1>(P::pi1 == 0 ? g0[c] : g1[c]);
+  }
+}
+
+template <bool FWD, class R>
+__device__ __forceinline__ void hop_half_any(int mu, const cplx<R> (&psi)[12], const cplx<R> (&u)[9], R coef,
+                                             cplx<R> (&g0)[3], cplx<R> (&g1)[3]) {
+  switch (mu) {
+    case 0: hop_half<0, FWD>(psi, u, coef, g0, g1); break;
+    case 1: hop_half<1, FWD>(psi, u, coef, g0, g1); break;
+    case 2: hop_half<2, FWD>(psi, u, coef, g0, g1); break;
+    default: hop_half<3, FWD>(psi, u, coef, g0, g1); break;
+  }
+}
+
+template <bool FWD, class R>
+__device__ __forceinline__ void hop_recon_any(int mu, const cplx<R> (&g0)[3], const cplx<R> (&g1)[3],
+                                              cplx<R> (&acc)[12]) {
+  switch (mu) {
+    case 0: hop_recon<0, FWD>(g0, g1, acc); break;
+    case 1: hop_recon<1, FWD>(g0, g1, acc); break;
+    case 2: hop_recon<2, FWD>(g0, g1, acc); break;
+    default: hop_recon<3, FWD>(g0, g1, acc); break;
+  }
+}
+
 template <bool FWD, class R>
 __device__ __forceinline__ void hop_any(int mu, const cplx<R> (&psi)[12], const cplx<R> (&u)[9], R coef,
                                         cplx<R> (&acc)[12]) {

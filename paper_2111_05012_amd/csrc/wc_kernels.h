@@ -48,7 +48,8 @@ struct DslashArgs {
   int compute32 = 0; // 0: FP64 arithmetic, 1: FP32
   double kappa = 0;
   int block_size = 256;  // threads per workgroup (64 .. 512, autotuned); -1: colour-split variant,
-                         // -2: LDS-staged tiles, -10 - NR: NR right-hand sides per thread
+                         // -2: LDS-staged tiles, -3: LDS-staged tiles with the backward hops
+                         // handed over as half-spinors, -10 - NR: NR right-hand sides per thread
                          // (NR = 2, 4; all OP_D only)
 };
 void launch_dslash(const DslashArgs& a, hipStream_t st);

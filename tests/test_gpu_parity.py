@@ -341,7 +341,7 @@ def test_dslash_every_launch_variant(tmp_path):
         out = prob.zeros(psi.shape)
         prob.ctx.apply_D(prob.T(psi), out, 2, prec)  # tunes and writes the cache
         keys = json.load(open(cache))
-        for v in (64, 128, 256, 512, -1, -2, -12, -14):
+        for v in (64, 128, 256, 512, -1, -2, -3, -12, -14):
             forced = {k: (v if k.split('|')[1] == 'dslash' else val) for k, val in keys.items()}
             with open(cache, 'w') as f:
                 json.dump(forced, f)
