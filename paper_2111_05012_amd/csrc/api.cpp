@@ -1413,7 +1413,7 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
   double2* V = (double2*)c->W("fg_V", (size_t)(m + 1) * vs * sizeof(double2));
   void* Z = c->W("fg_Z", (size_t)m * vs * ct_size(zt));
   void* vin = prec == WCAMG_PREC_MIXED ? c->W("fg_vin", vs * sizeof(float2)) : nullptr;
-  double2* part = (double2*)c->W("fg_part", (size_t)nrhs * reduce_nwg(n) * 8 * sizeof(double2));
+  double2* part = (double2*)c->W("fg_part", (size_t)nrhs * reduce_nwg(n) * 16 * sizeof(double2));
   double2* h1 = (double2*)c->W("fg_h1", (size_t)(m + 1) * nrhs * sizeof(double2));
   double2* h2 = (double2*)c->W("fg_h2", (size_t)(m + 1) * nrhs * sizeof(double2));
   double* nrm = (double*)c->W("fg_nrm", (size_t)nrhs * sizeof(double));
@@ -1529,30 +1529,21 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
       void* zj = (char*)Z + (size_t)j * vs * ct_size(zt);
       double2* w = V + (size_t)(j + 1) * vs;
       c->dslash(zj, zt, w, C128, nrhs, OP_D, WCAMG_PREC_FP64);
-      // classical Gram-Schmidt, repeated when the projection removed more than
-      // half of |w|^2 for some right-hand side (|w'|^2 < sum_i |h_i|^2, the
-      // criterion of Daniel, Gragg, Kaufman and Stewart with 1/sqrt(2))
+      // classical Gram-Schmidt twice; the update of the first pass and the
+      // projections of the second share one sweep over the basis
       launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h1, c->st);
-      launch_multiaxpy(V, vs, j + 1, h1, w, n, rs, nrhs, part, nrm, c->st);
+      if (j + 1 <= 16) {
+        launch_multiaxpy_dot(V, vs, j + 1, h1, w, n, rs, nrhs, part, h2, c->st);
+      } else {
+        launch_multiaxpy(V, vs, j + 1, h1, w, n, rs, nrhs, part, nullptr, c->st);
+        launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h2, c->st);
+      }
+      launch_multiaxpy(V, vs, j + 1, h2, w, n, rs, nrhs, part, nrm, c->st);
       HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
                             c->st));
+      HIPCHK(hipMemcpyAsync(hh2.data(), h2, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
+                            c->st));
       sync_get(hn.data(), nrm, nrhs * sizeof(double));
-      bool again = false;
-      for (int r = 0; r < nrhs; ++r) {
-        if (!ext[r]) continue;
-        double hsum = 0;
-        for (int i = 0; i <= j; ++i) hsum += hh1[(size_t)i * nrhs + r].x * hh1[(size_t)i * nrhs + r].x +
-                                             hh1[(size_t)i * nrhs + r].y * hh1[(size_t)i * nrhs + r].y;
-        again = again || !(hn[r] >= hsum);
-      }
-      std::fill(hh2.begin(), hh2.end(), make_double2(0.0, 0.0));
-      if (again) {
-        launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h2, c->st);
-        launch_multiaxpy(V, vs, j + 1, h2, w, n, rs, nrhs, part, nrm, c->st);
-        HIPCHK(hipMemcpyAsync(hh2.data(), h2, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
-                              c->st));
-        sync_get(hn.data(), nrm, nrhs * sizeof(double));
-      }
       bool any = false;
       for (int r = 0; r < nrhs; ++r) {
         hs[r] = 0.0;

@@ -458,6 +458,57 @@ void launch_multiaxpy(const double2* V, size_t vs, int nk, const double2* h, dou
   if (norm2) k_norm2_fin<<<nrhs, 64, 0, st>>>(part, nwg, norm2);
 }
 
+// Classical Gram-Schmidt, the update of the first pass fused with the
+// projections of the second: w -= sum_k h[k] V_k, and in the same sweep over
+// the basis the partial sums of conj(V_k) w (k < nk <= 16) for the second pass.
+constexpr int KM = 16;
+__global__ __launch_bounds__(RED_THREADS) void k_multiaxpy_dot(const double2* V, size_t vs, int nk, const double2* h,
+                                                               double2* w, size_t n, size_t rs, int nrhs,
+                                                               double2* part) {
+  const int r = blockIdx.y;
+  const size_t off = r * rs;
+  cplx<double> hk[KM];
+#pragma unroll
+  for (int k = 0; k < KM; ++k) hk[k] = k < nk ? C(h[(size_t)k * nrhs + r]) : cplx<double>{0, 0};
+  double v[2 * KM];
+#pragma unroll
+  for (int k = 0; k < 2 * KM; ++k) v[k] = 0;
+  for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (size_t)gridDim.x * RED_THREADS) {
+    cplx<double> acc = ld<double>(w + off, i);
+    cplx<double> a[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+      if (k < nk) {
+        a[k] = ld<double>(V + (size_t)k * vs + off, i);
+        acc = acc - hk[k] * a[k];
+      }
+    st(w + off, i, acc);
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+      if (k < nk) {
+        v[2 * k] += a[k].x * acc.x + a[k].y * acc.y;
+        v[2 * k + 1] += a[k].x * acc.y - a[k].y * acc.x;
+      }
+  }
+  block_sum<2 * KM>(v);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < nk; ++k) part[((size_t)r * gridDim.x + blockIdx.x) * KM + k] = make_double2(v[2 * k], v[2 * k + 1]);
+}
+
+__global__ void k_multidot16_fin(const double2* part, int nwg, int nk, int nrhs, double2* h2) {
+  const int r = blockIdx.x, k = threadIdx.x;
+  if (k >= nk) return;
+  h2[(size_t)k * nrhs + r] = D2(sum_parts(part, nwg, KM, r, k));
+}
+
+void launch_multiaxpy_dot(const double2* V, size_t vs, int nk, const double2* h, double2* w, size_t n, size_t rs,
+                          int nrhs, double2* part, double2* h2, hipStream_t st) {
+  if (nk > KM) throw std::runtime_error("multiaxpy_dot: at most 16 basis vectors");
+  const int nwg = reduce_nwg(n);
+  k_multiaxpy_dot<<<dim3(nwg, nrhs), RED_THREADS, 0, st>>>(V, vs, nk, h, w, n, rs, nrhs, part);
+  k_multidot16_fin<<<nrhs, 64, 0, st>>>(part, nwg, nk, nrhs, h2);
+}
+
 __global__ __launch_bounds__(256) void k_scale(const double2* w, const double* scale, double2* out, float2* out32,
                                                size_t n, size_t rs) {
   const int r = blockIdx.y;

@@ -176,6 +176,10 @@ void launch_multidot(const double2* V, size_t vs, int nk, const double2* w, size
 // w[r] -= sum_k h[k][r] V_k[r]; then norm2[r] = ||w[r]||^2 (if norm2 != null)
 void launch_multiaxpy(const double2* V, size_t vs, int nk, const double2* h, double2* w, size_t n, size_t rs,
                       int nrhs, double2* part, double* norm2, hipStream_t st);
+// w[r] -= sum_k h[k][r] V_k[r], and h2[k][r] = V_k[r]^H w[r] of the updated w in the
+// same sweep (nk <= 16; part holds nrhs * reduce_nwg(n) * 16 partial sums)
+void launch_multiaxpy_dot(const double2* V, size_t vs, int nk, const double2* h, double2* w, size_t n, size_t rs,
+                          int nrhs, double2* part, double2* h2, hipStream_t st);
 // out[r] = w[r] * scale[r]; optional FP32 copy out32
 void launch_scale(const double2* w, const double* scale, double2* out, float2* out32, size_t n, size_t rs, int nrhs,
                   hipStream_t st);
