@@ -1101,6 +1101,315 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   }
 }
 
+// Split variant of the mixed-precision SAP half-sweep: two threads per site,
+// for twice the resident wavefronts of k_sap_dom.  Threads [0, Vb) take the
+// hops in the x and y directions and own spin-colour components 0..5 of the
+// residual, correction and MR direction; threads [Vb, 2 Vb) take z and t and
+// own components 6..11 (Vb is a multiple of 64, so the split is uniform per
+// wavefront).  After its hops a thread holds a partial D_SAP result for all
+// 12 components; the halves are exchanged through the residual's LDS buffer
+// (free at that point), and the clover block and the MR updates act on the
+// thread's own 6 components (the clover is block diagonal in chirality).
+// LDS as in k_sap_dom: residual [12][Vb], scaled forward links [36][Vb],
+// neighbour table [8][Vb].
+__device__ __forceinline__ void clover_block(const half2_t* __restrict__ C, int ps, size_t base, int bq,
+                                             const cplx<float> (&v)[6], cplx<float> (&acc)[6]) {
+  cplx<float> pr[18];
+#pragma unroll
+  for (int k = 0; k < 18; ++k) pr[k] = ld<float>(C, (size_t)(18 * bq + k) * ps + base);
+  const float d[6] = {pr[0].x, pr[0].y, pr[1].x, pr[1].y, pr[2].x, pr[2].y};
+#pragma unroll
+  for (int i = 0; i < 6; ++i) acc[i] = acc[i] + d[i] * v[i];
+  int k = 3;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+#pragma unroll
+    for (int j = i + 1; j < 6; ++j) {
+      cmac(acc[i], pr[k], v[j]);
+      cjmac(acc[j], pr[k], v[i]);
+      ++k;
+    }
+  }
+}
+
+// lo += upper and hi += lower two spins of coef (1 -/+ gamma_MU) W psi, for
+// W the FP16 link u16 (FWD) or its adjoint.  The spinor psi (planes of stride
+// ps from site offset base, in LDS or global memory) is read straight into its
+// spin projection: the full spinor is never held.
+template <int MU, bool FWD, class SP>
+__device__ __forceinline__ void hop_proj(const SP* src, int ps, size_t base, const half2_t* u16, float coef,
+                                         cplx<float> (&lo)[6], cplx<float> (&hi)[6]) {
+  using P = Proj<MU>;
+  constexpr int T0 = FWD ? P::t0 : (P::t0 ^ 2);
+  constexpr int T1 = FWD ? P::t1 : (P::t1 ^ 2);
+  constexpr int S0 = FWD ? P::s0 : (P::s0 ^ 2);
+  constexpr int S1 = FWD ? P::s1 : (P::s1 ^ 2);
+  auto rd = [&](int a) -> cplx<float> {
+    const SP v = src[(size_t)a * ps + base];
+    return {v.x, v.y};
+  };
+  cplx<float> h0[3], h1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    h0[c] = rd(c) + unit<T0>(rd((2 + P::pi0) * 3 + c));
+    h1[c] = rd(3 + c) + unit<T1>(rd((2 + P::pi1) * 3 + c));
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    cplx<float> x = {0, 0}, y = {0, 0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (FWD) {
+        const cplx<float> u = h2f(u16[r * 3 + c]);
+        cmac(x, u, h0[c]);
+        cmac(y, u, h1[c]);
+      } else {
+        const cplx<float> u = h2f(u16[c * 3 + r]);
+        cjmac(x, u, h0[c]);
+        cjmac(y, u, h1[c]);
+      }
+    }
+    x = coef * x;
+    y = coef * y;
+    lo[r] = lo[r] + x;
+    lo[3 + r] = lo[3 + r] + y;
+    hi[r] = hi[r] + unit<S0>(P::pi0 == 0 ? x : y);
+    hi[3 + r] = hi[3 + r] + unit<S1>(P::pi1 == 0 ? x : y);
+  }
+}
+
+// the in-domain hops of direction MU (forward and backward), links from LDS
+template <int MU>
+__device__ __forceinline__ void pair_hops(const cplx<float>* lds, const half2_t* lu, const int* ninfo, int Vb, int l,
+                                          cplx<float> (&lo)[6], cplx<float> (&hi)[6]) {
+  half2_t ub[9];
+  int inf = ninfo[MU * Vb + l];
+  if (inf & (1 << 10)) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) ub[e] = lu[(MU * 9 + e) * Vb + l];
+    hop_proj<MU, true>(lds, Vb, (size_t)(inf & 1023), ub, 1.0f, lo, hi);
+  }
+  asm volatile("" ::: "memory");  // one hop after the other (register use)
+  inf = ninfo[(MU + 4) * Vb + l];
+  if (inf & (1 << 10)) {
+    const int nl = inf & 1023;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) ub[e] = lu[(MU * 9 + e) * Vb + nl];
+    hop_proj<MU, false>(lds, Vb, (size_t)nl, ub, 1.0f, lo, hi);
+  }
+}
+
+// neighbour table entries and scaled forward links of direction MU
+template <int MU>
+__device__ __forceinline__ void pair_stage(const Geo& g, int s, const SiteCoord& c, int blk, int l, int Vb,
+                                           float kappa, const half2_t* __restrict__ U, size_t fb36, half2_t* lu,
+                                           int* ninfo) {
+  int sign;
+  bool inb;
+  int nb = neighbour<true>(g, s, c, MU, sign, inb);
+  ninfo[MU * Vb + l] = (inb ? ((nb - blk * Vb) | (1 << 10)) : 0) | (sign < 0 ? (1 << 11) : 0);
+  const float f = -kappa * (float)sign;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) st(lu, (size_t)(MU * 9 + e) * Vb + l, f * ld<float>(U, (size_t)(MU * 9 + e) * Vb + fb36));
+  nb = neighbour<false>(g, s, c, MU, sign, inb);
+  ninfo[(MU + 4) * Vb + l] = (inb ? ((nb - blk * Vb) | (1 << 10)) : 0) | (sign < 0 ? (1 << 11) : 0);
+}
+
+// the hop of direction MU (FWD or backward) from the correction delta of the
+// neighbouring domain when it leaves this one: lo/hi += kappa sign W delta
+template <int MU, bool FWD>
+__device__ __forceinline__ void pair_cross(const Geo& g, int s, const SiteCoord& c, int Vb, const int* ninfo, int l,
+                                           float kappa, const float2* __restrict__ dlt, const half2_t* __restrict__ U,
+                                           size_t fb36, cplx<float> (&lo)[6], cplx<float> (&hi)[6]) {
+  if (ninfo[(MU + (FWD ? 0 : 4)) * Vb + l] & (1 << 10)) return;
+  int sign, nblk;
+  bool inb;
+  const int nb = neighbour<FWD>(g, s, c, MU, sign, inb, nblk);
+  const size_t lb = FWD ? fb36 : fbase_b(g, 36, nb, nblk);
+  half2_t ub[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) ub[e] = U[(size_t)(MU * 9 + e) * Vb + lb];
+  hop_proj<MU, FWD>(dlt, Vb, fbase_b(g, 12, nb, nblk), ub, kappa * (float)sign, lo, hi);
+}
+
+// Split variant of the mixed-precision SAP half-sweep: two threads per site,
+// for twice the resident wavefronts of k_sap_dom.  Threads [0, Vb) take the
+// hops in the x and y directions and own spin-colour components 0..5 (the
+// upper two spins) of the residual, correction and MR direction; threads
+// [Vb, 2 Vb) take z and t and own components 6..11 (Vb is a multiple of 64,
+// so the split is uniform per wavefront).  After its hops a thread holds a
+// partial D_SAP result for all 12 components (own: its half, oth: the
+// partner's); the halves are exchanged through the residual's LDS buffer
+// (free at that point), and the clover block and the MR updates act on the
+// thread's own 6 components (the clover is block diagonal in chirality).
+// Arrays are only ever indexed with constants, so that they stay in
+// registers.  LDS as in k_sap_dom: residual [12][Vb], scaled forward links
+// [36][Vb], neighbour table [8][Vb].
+template <int VB>
+__global__ __launch_bounds__(1024) void k_sap_pair(Geo g, int colour, int flags, int mr, float kappa, int nrhs,
+                                                   const float2* __restrict__ b, float2* __restrict__ r,
+                                                   float2* __restrict__ x, float2* __restrict__ delta,
+                                                   const float2* __restrict__ xinit, size_t rs,
+                                                   const half2_t* __restrict__ U, const half2_t* __restrict__ C) {
+  extern __shared__ __align__(16) char smem[];
+  const int Vb = VB ? VB : g.Vb;
+  cplx<float>* lds = (cplx<float>*)smem;                           // [12][Vb]
+  half2_t* lu = (half2_t*)(smem + 12 * Vb * sizeof(cplx<float>));  // [36][Vb]
+  int* ninfo = (int*)(lu + 36 * Vb);                               // [8][Vb]
+  float* red = (float*)(ninfo + 8 * Vb);                           // [nwaves][3]
+  const int half = g.NB[0] >> 1;
+  int k = xcd_remap(blockIdx.x, g.nblk >> 1);
+  if (k >= (g.nblk >> 1)) return;
+  int row = k / half, j = k - row * half;
+  int by = row % g.NB[1];
+  int rz = row / g.NB[1];
+  int bz = rz % g.NB[2];
+  int bt = rz / g.NB[2];
+  int bx = 2 * j + ((colour + by + bz + bt) & 1);
+  int blk = bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
+  const int t = threadIdx.x;
+  const int hh = t >= Vb ? 1 : 0;  // uniform per wavefront (Vb % 64 == 0)
+  const int l = t - hh * Vb;
+  const int a0 = 6 * hh;
+  const int s = blk * Vb + l;
+  const int nw = blockDim.x >> 6;
+  const SiteCoord c = decompose(g, s);
+  const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
+
+  if (hh == 0) {
+    pair_stage<0>(g, s, c, blk, l, Vb, kappa, U, fb36, lu, ninfo);
+    pair_stage<1>(g, s, c, blk, l, Vb, kappa, U, fb36, lu, ninfo);
+  } else {
+    pair_stage<2>(g, s, c, blk, l, Vb, kappa, U, fb36, lu, ninfo);
+    pair_stage<3>(g, s, c, blk, l, Vb, kappa, U, fb36, lu, ninfo);
+  }
+  __syncthreads();
+
+  for (int rr = 0; rr < nrhs; ++rr) {
+    const size_t off = rr * rs;
+    cplx<float> rho[6], xm[6], pw[6], own[6], oth[6];
+    const float2* src = (flags & SAP_FIRST) ? b + off : r + off;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) rho[q] = ld<float>(src, (size_t)(a0 + q) * Vb + fb12);
+    if (flags & SAP_DELTA) {
+      // r -= D delta over the hops of this thread's directions that leave the domain
+#pragma unroll
+      for (int q = 0; q < 6; ++q) own[q] = oth[q] = {0, 0};
+      const float2* dl = delta + off;
+      // an opaque copy of the site index: the neighbours' addresses are
+      // recomputed here, not hoisted out of the loop over right-hand sides
+      // and held in registers through the MR iterations
+      int sq = s;
+      asm volatile("" : "+v"(sq));
+      const SiteCoord cq = decompose(g, sq);
+      if (hh == 0) {
+        pair_cross<0, true>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, own, oth);
+        asm volatile("" ::: "memory");
+        pair_cross<0, false>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, own, oth);
+        asm volatile("" ::: "memory");
+        pair_cross<1, true>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, own, oth);
+        asm volatile("" ::: "memory");
+        pair_cross<1, false>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, own, oth);
+      } else {
+        pair_cross<2, true>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, oth, own);
+        asm volatile("" ::: "memory");
+        pair_cross<2, false>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, oth, own);
+        asm volatile("" ::: "memory");
+        pair_cross<3, true>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, oth, own);
+        asm volatile("" ::: "memory");
+        pair_cross<3, false>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, oth, own);
+      }
+      // exchange the halves: write the partner's components, read this thread's
+#pragma unroll
+      for (int q = 0; q < 6; ++q) lds[(6 - a0 + q) * Vb + l] = oth[q];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 6; ++q) rho[q] = rho[q] + own[q] + lds[(a0 + q) * Vb + l];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) xm[q] = {0, 0};
+    for (int it = 0; it < mr; ++it) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) lds[(a0 + q) * Vb + l] = rho[q];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 6; ++q) own[q] = oth[q] = {0, 0};
+      // opaque copy of the site index: the neighbour table and forward links
+      // are re-read from LDS each iteration rather than held in registers
+      int lq = l;
+      asm volatile("" : "+v"(lq));
+      if (hh == 0) {
+        pair_hops<0>(lds, lu, ninfo, Vb, lq, own, oth);
+        asm volatile("" ::: "memory");
+        pair_hops<1>(lds, lu, ninfo, Vb, lq, own, oth);
+      } else {
+        pair_hops<2>(lds, lu, ninfo, Vb, lq, oth, own);
+        asm volatile("" ::: "memory");
+        pair_hops<3>(lds, lu, ninfo, Vb, lq, oth, own);
+      }
+      __syncthreads();  // every hop has read the residual
+#pragma unroll
+      for (int q = 0; q < 6; ++q) lds[(6 - a0 + q) * Vb + l] = oth[q];
+      __syncthreads();
+      // p = (1 + F) rho + in-domain hops, this thread's components
+#pragma unroll
+      for (int q = 0; q < 6; ++q) pw[q] = rho[q] + own[q] + lds[(a0 + q) * Vb + l];
+      // the clover is the same in every iteration: an opaque copy of the
+      // chirality index keeps its loads here instead of hoisted out of the
+      // loops (36 more live registers all the time)
+      int hq = hh;
+      asm volatile("" : "+v"(hq));
+      clover_block(C, Vb, fb36, hq, rho, pw);
+      float pr_re = 0, pr_im = 0, pp = 0;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        pr_re += pw[q].x * rho[q].x + pw[q].y * rho[q].y;
+        pr_im += pw[q].x * rho[q].y - pw[q].y * rho[q].x;
+        pp += pw[q].x * pw[q].x + pw[q].y * pw[q].y;
+      }
+      pr_re = wave_sum(pr_re);
+      pr_im = wave_sum(pr_im);
+      pp = wave_sum(pp);
+      if ((t & 63) == 0) {
+        red[(t >> 6) * 3 + 0] = pr_re;
+        red[(t >> 6) * 3 + 1] = pr_im;
+        red[(t >> 6) * 3 + 2] = pp;
+      }
+      __syncthreads();
+      float sre = 0, sim = 0, spp = 0;
+      for (int w = 0; w < nw; ++w) {
+        sre += red[w * 3 + 0];
+        sim += red[w * 3 + 1];
+        spp += red[w * 3 + 2];
+      }
+      cplx<float> alpha = {0, 0};
+      if (spp > 0) alpha = {sre / spp, sim / spp};
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        xm[q] = xm[q] + alpha * rho[q];
+        rho[q] = rho[q] - alpha * pw[q];
+      }
+    }
+    float2* xr = x + off;
+    float2* rw = r + off;
+    float2* dw = delta + off;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const size_t o = (size_t)(a0 + q) * Vb + fb12;
+      cplx<float> x0 = {0, 0};
+      if (!(flags & SAP_FIRST)) x0 = ld<float>(xr, o);
+      else if (xinit) x0 = ld<float>(xinit + off, o);
+      st(xr, o, x0 + xm[q]);
+      if (!(flags & SAP_NO_R)) st(rw, o, rho[q]);
+      if (!(flags & SAP_NO_DELTA)) st(dw, o, xm[q]);
+    }
+    __syncthreads();  // the next right-hand side reuses lds and red
+  }
+}
+
+bool sap_pair_ok(const Geo& g) { return g.Vb % 64 == 0 && g.Vb <= 512; }
+int sap_pair_lds_bytes(const Geo& g) { return 12 * g.Vb * 8 + 36 * g.Vb * 4 + 8 * g.Vb * 4 + (2 * g.Vb / 64) * 3 * 4; }
 int sap_dom_lds_bytes(const Geo& g) {
   int nthr = ((g.Vb + 63) / 64) * 64;
   return 12 * g.Vb * 8 + 36 * g.Vb * 4 + 8 * g.Vb * 4 + (nthr / 64) * 3 * 4;
@@ -1149,6 +1458,26 @@ void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st) {
                                           (float2*)a.r, (float2*)a.x, (float2*)a.delta, (const float2*)a.xinit, a.rs,
                                           (const half2_t*)a.U, (const half2_t*)a.C);
   };
+  if (a.variant == SAP_PAIR) {
+    static bool pair_attr[3] = {false, false, false};
+    if (!sap_pair_ok(g)) throw std::runtime_error("SAP split kernel: block volume must be a multiple of 64, at most 512");
+    auto gp = [&](auto kern, int id) {
+      if (!pair_attr[id]) {
+        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        pair_attr[id] = true;
+      }
+      kern<<<round8(ndom), 2 * g.Vb, sap_pair_lds_bytes(g), st>>>(
+          g, col, flags, a.mr, (float)a.kappa, a.nrhs, (const float2*)a.b, (float2*)a.r, (float2*)a.x,
+          (float2*)a.delta, (const float2*)a.xinit, a.rs, (const half2_t*)a.U, (const half2_t*)a.C);
+    };
+    if (g.Vb == 512)
+      gp(k_sap_pair<512>, 0);
+    else if (g.Vb == 256)
+      gp(k_sap_pair<256>, 1);
+    else
+      gp(k_sap_pair<0>, 2);
+    return;
+  }
   if (g.Vb == 512)
     go(k_sap_dom<512>, 0);
   else if (g.Vb == 256)
