@@ -554,6 +554,7 @@ struct wcamg_ctx {
       snprintf(key, sizeof(key), "sap|Vb%d|n%d|V%d|mr%d|sw%d", g.Vb, nrhs, g.V, mr, sweeps);
       std::vector<int> cands = {SAP_DOM};
       if (sap_pair_ok(g) && (size_t)sap_pair_lds_bytes(g) <= lds_max) cands.push_back(SAP_PAIR);
+      if ((size_t)sap_h16_lds_bytes(g) <= lds_max) cands.push_back(SAP_H16);
       a.variant = tune(key, cands, [&](int v) {
         SapArgs t = a;
         t.variant = v;

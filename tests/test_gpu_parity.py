@@ -80,9 +80,11 @@ def test_sap_mixed(prob):
 
 @pytest.mark.parametrize('block', [(4, 4, 2, 2), (4, 4, 4, 4)])
 def test_sap_mixed_every_kernel(tmp_path, block):
-    """Both mixed-precision SAP kernels (one thread per site; two threads per
-    site with the hop directions split between them) on 3 right-hand sides,
-    domains of 64 and 256 sites, forced in turn through the tuner's cache."""
+    """Every mixed-precision SAP kernel (one thread per site; two threads per
+    site with the hop directions split between them; one thread per site with
+    the residual exchanged in FP16 and the products on the FP16 dot-product
+    instructions) on 3 right-hand sides, domains of 64 and 256 sites, forced
+    in turn through the tuner's cache."""
     import json
     from paper_2111_05012_amd import PREC_MIXED
     prob = Problem((8, 8, 8, 8), block, eps=0.5, seed=5, kappa=0.124, csw=1.1)
@@ -94,7 +96,7 @@ def test_sap_mixed_every_kernel(tmp_path, block):
     prob.ctx.sap(prob.T(b), x, 3, 3, 5, PREC_MIXED)  # tunes and writes the cache
     keys = json.load(open(cache))
     assert any(k.split('|')[1] == 'sap' for k in keys)
-    for v in (0, 1):
+    for v in (0, 1, 2):
         forced = {k: (v if k.split('|')[1] == 'sap' else val) for k, val in keys.items()}
         with open(cache, 'w') as f:
             json.dump(forced, f)
