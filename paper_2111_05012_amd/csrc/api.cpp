@@ -547,20 +547,6 @@ struct wcamg_ctx {
     }
     require((size_t)(a.mixed ? sap_dom_lds_bytes(g) : sap_lds_bytes(g, 0)) <= lds_max,
             "block volume too large for the SAP kernel's LDS at this precision");
-    if (a.mixed) {
-      // kernel choice, timed on the first half-sweep: it reads only b (and
-      // xinit) and overwrites x, r and delta, so repeating it is harmless
-      char key[160];
-      snprintf(key, sizeof(key), "sap|Vb%d|n%d|V%d|mr%d|sw%d", g.Vb, nrhs, g.V, mr, sweeps);
-      std::vector<int> cands = {SAP_DOM};
-      if (sap_pair_ok(g) && (size_t)sap_pair_lds_bytes(g) <= lds_max) cands.push_back(SAP_PAIR);
-      if ((size_t)sap_h16_lds_bytes(g) <= lds_max) cands.push_back(SAP_H16);
-      a.variant = tune(key, cands, [&](int v) {
-        SapArgs t = a;
-        t.variant = v;
-        launch_sap_half(t, 0, 0, st);
-      });
-    }
     // per half-sweep: links+clover of the active half of the sites; per rhs
     // read r (or b), write r, delta and x (plus read x after the first visit)
     double sb = a.mixed ? 8 : 16, fld = a.mixed ? 4 * 9 * 4 + 36 * 4 : 4 * 9 * 16 + 36 * 16;

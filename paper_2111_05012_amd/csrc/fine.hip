@@ -1101,621 +1101,6 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   }
 }
 
-// Split variant of the mixed-precision SAP half-sweep: two threads per site,
-// for twice the resident wavefronts of k_sap_dom.  Threads [0, Vb) take the
-// hops in the x and y directions and own spin-colour components 0..5 of the
-// residual, correction and MR direction; threads [Vb, 2 Vb) take z and t and
-// own components 6..11 (Vb is a multiple of 64, so the split is uniform per
-// wavefront).  After its hops a thread holds a partial D_SAP result for all
-// 12 components; the halves are exchanged through the residual's LDS buffer
-// (free at that point), and the clover block and the MR updates act on the
-// thread's own 6 components (the clover is block diagonal in chirality).
-// LDS as in k_sap_dom: residual [12][Vb], scaled forward links [36][Vb],
-// neighbour table [8][Vb].
-__device__ __forceinline__ void clover_block(const half2_t* __restrict__ C, int ps, size_t base, int bq,
-                                             const cplx<float> (&v)[6], cplx<float> (&acc)[6]) {
-  cplx<float> pr[18];
-#pragma unroll
-  for (int k = 0; k < 18; ++k) pr[k] = ld<float>(C, (size_t)(18 * bq + k) * ps + base);
-  const float d[6] = {pr[0].x, pr[0].y, pr[1].x, pr[1].y, pr[2].x, pr[2].y};
-#pragma unroll
-  for (int i = 0; i < 6; ++i) acc[i] = acc[i] + d[i] * v[i];
-  int k = 3;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-#pragma unroll
-    for (int j = i + 1; j < 6; ++j) {
-      cmac(acc[i], pr[k], v[j]);
-      cjmac(acc[j], pr[k], v[i]);
-      ++k;
-    }
-  }
-}
-
-// lo += upper and hi += lower two spins of coef (1 -/+ gamma_MU) W psi, for
-// W the FP16 link u16 (FWD) or its adjoint.  The spinor psi (planes of stride
-// ps from site offset base, in LDS or global memory) is read straight into its
-// spin projection: the full spinor is never held.
-template <int MU, bool FWD, class SP>
-__device__ __forceinline__ void hop_proj(const SP* src, int ps, size_t base, const half2_t* u16, float coef,
-                                         cplx<float> (&lo)[6], cplx<float> (&hi)[6]) {
-  using P = Proj<MU>;
-  constexpr int T0 = FWD ? P::t0 : (P::t0 ^ 2);
-  constexpr int T1 = FWD ? P::t1 : (P::t1 ^ 2);
-  constexpr int S0 = FWD ? P::s0 : (P::s0 ^ 2);
-  constexpr int S1 = FWD ? P::s1 : (P::s1 ^ 2);
-  auto rd = [&](int a) -> cplx<float> {
-    const SP v = src[(size_t)a * ps + base];
-    return {v.x, v.y};
-  };
-  cplx<float> h0[3], h1[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    h0[c] = rd(c) + unit<T0>(rd((2 + P::pi0) * 3 + c));
-    h1[c] = rd(3 + c) + unit<T1>(rd((2 + P::pi1) * 3 + c));
-  }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    cplx<float> x = {0, 0}, y = {0, 0};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (FWD) {
-        const cplx<float> u = h2f(u16[r * 3 + c]);
-        cmac(x, u, h0[c]);
-        cmac(y, u, h1[c]);
-      } else {
-        const cplx<float> u = h2f(u16[c * 3 + r]);
-        cjmac(x, u, h0[c]);
-        cjmac(y, u, h1[c]);
-      }
-    }
-    x = coef * x;
-    y = coef * y;
-    lo[r] = lo[r] + x;
-    lo[3 + r] = lo[3 + r] + y;
-    hi[r] = hi[r] + unit<S0>(P::pi0 == 0 ? x : y);
-    hi[3 + r] = hi[3 + r] + unit<S1>(P::pi1 == 0 ? x : y);
-  }
-}
-
-// the in-domain hops of direction MU (forward and backward), links from LDS
-template <int MU>
-__device__ __forceinline__ void pair_hops(const cplx<float>* lds, const half2_t* lu, const int* ninfo, int Vb, int l,
-                                          cplx<float> (&lo)[6], cplx<float> (&hi)[6]) {
-  half2_t ub[9];
-  int inf = ninfo[MU * Vb + l];
-  if (inf & (1 << 10)) {
-#pragma unroll
-    for (int e = 0; e < 9; ++e) ub[e] = lu[(MU * 9 + e) * Vb + l];
-    hop_proj<MU, true>(lds, Vb, (size_t)(inf & 1023), ub, 1.0f, lo, hi);
-  }
-  asm volatile("" ::: "memory");  // one hop after the other (register use)
-  inf = ninfo[(MU + 4) * Vb + l];
-  if (inf & (1 << 10)) {
-    const int nl = inf & 1023;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) ub[e] = lu[(MU * 9 + e) * Vb + nl];
-    hop_proj<MU, false>(lds, Vb, (size_t)nl, ub, 1.0f, lo, hi);
-  }
-}
-
-// neighbour table entries and scaled forward links of direction MU
-template <int MU>
-__device__ __forceinline__ void pair_stage(const Geo& g, int s, const SiteCoord& c, int blk, int l, int Vb,
-                                           float kappa, const half2_t* __restrict__ U, size_t fb36, half2_t* lu,
-                                           int* ninfo) {
-  int sign;
-  bool inb;
-  int nb = neighbour<true>(g, s, c, MU, sign, inb);
-  ninfo[MU * Vb + l] = (inb ? ((nb - blk * Vb) | (1 << 10)) : 0) | (sign < 0 ? (1 << 11) : 0);
-  const float f = -kappa * (float)sign;
-#pragma unroll
-  for (int e = 0; e < 9; ++e) st(lu, (size_t)(MU * 9 + e) * Vb + l, f * ld<float>(U, (size_t)(MU * 9 + e) * Vb + fb36));
-  nb = neighbour<false>(g, s, c, MU, sign, inb);
-  ninfo[(MU + 4) * Vb + l] = (inb ? ((nb - blk * Vb) | (1 << 10)) : 0) | (sign < 0 ? (1 << 11) : 0);
-}
-
-// the hop of direction MU (FWD or backward) from the correction delta of the
-// neighbouring domain when it leaves this one: lo/hi += kappa sign W delta
-template <int MU, bool FWD>
-__device__ __forceinline__ void pair_cross(const Geo& g, int s, const SiteCoord& c, int Vb, const int* ninfo, int l,
-                                           float kappa, const float2* __restrict__ dlt, const half2_t* __restrict__ U,
-                                           size_t fb36, cplx<float> (&lo)[6], cplx<float> (&hi)[6]) {
-  if (ninfo[(MU + (FWD ? 0 : 4)) * Vb + l] & (1 << 10)) return;
-  int sign, nblk;
-  bool inb;
-  const int nb = neighbour<FWD>(g, s, c, MU, sign, inb, nblk);
-  const size_t lb = FWD ? fb36 : fbase_b(g, 36, nb, nblk);
-  half2_t ub[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) ub[e] = U[(size_t)(MU * 9 + e) * Vb + lb];
-  hop_proj<MU, FWD>(dlt, Vb, fbase_b(g, 12, nb, nblk), ub, kappa * (float)sign, lo, hi);
-}
-
-// Split variant of the mixed-precision SAP half-sweep: two threads per site,
-// for twice the resident wavefronts of k_sap_dom.  Threads [0, Vb) take the
-// hops in the x and y directions and own spin-colour components 0..5 (the
-// upper two spins) of the residual, correction and MR direction; threads
-// [Vb, 2 Vb) take z and t and own components 6..11 (Vb is a multiple of 64,
-// so the split is uniform per wavefront).  After its hops a thread holds a
-// partial D_SAP result for all 12 components (own: its half, oth: the
-// partner's); the halves are exchanged through the residual's LDS buffer
-// (free at that point), and the clover block and the MR updates act on the
-// thread's own 6 components (the clover is block diagonal in chirality).
-// Arrays are only ever indexed with constants, so that they stay in
-// registers.  LDS as in k_sap_dom: residual [12][Vb], scaled forward links
-// [36][Vb], neighbour table [8][Vb].
-template <int VB>
-__global__ __launch_bounds__(1024) void k_sap_pair(Geo g, int colour, int flags, int mr, float kappa, int nrhs,
-                                                   const float2* __restrict__ b, float2* __restrict__ r,
-                                                   float2* __restrict__ x, float2* __restrict__ delta,
-                                                   const float2* __restrict__ xinit, size_t rs,
-                                                   const half2_t* __restrict__ U, const half2_t* __restrict__ C) {
-  extern __shared__ __align__(16) char smem[];
-  const int Vb = VB ? VB : g.Vb;
-  cplx<float>* lds = (cplx<float>*)smem;                           // [12][Vb]
-  half2_t* lu = (half2_t*)(smem + 12 * Vb * sizeof(cplx<float>));  // [36][Vb]
-  int* ninfo = (int*)(lu + 36 * Vb);                               // [8][Vb]
-  float* red = (float*)(ninfo + 8 * Vb);                           // [nwaves][3]
-  const int half = g.NB[0] >> 1;
-  int k = xcd_remap(blockIdx.x, g.nblk >> 1);
-  if (k >= (g.nblk >> 1)) return;
-  int row = k / half, j = k - row * half;
-  int by = row % g.NB[1];
-  int rz = row / g.NB[1];
-  int bz = rz % g.NB[2];
-  int bt = rz / g.NB[2];
-  int bx = 2 * j + ((colour + by + bz + bt) & 1);
-  int blk = bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
-  const int t = threadIdx.x;
-  const int hh = t >= Vb ? 1 : 0;  // uniform per wavefront (Vb % 64 == 0)
-  const int l = t - hh * Vb;
-  const int a0 = 6 * hh;
-  const int s = blk * Vb + l;
-  const int nw = blockDim.x >> 6;
-  const SiteCoord c = decompose(g, s);
-  const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
-
-  if (hh == 0) {
-    pair_stage<0>(g, s, c, blk, l, Vb, kappa, U, fb36, lu, ninfo);
-    pair_stage<1>(g, s, c, blk, l, Vb, kappa, U, fb36, lu, ninfo);
-  } else {
-    pair_stage<2>(g, s, c, blk, l, Vb, kappa, U, fb36, lu, ninfo);
-    pair_stage<3>(g, s, c, blk, l, Vb, kappa, U, fb36, lu, ninfo);
-  }
-  __syncthreads();
-
-  for (int rr = 0; rr < nrhs; ++rr) {
-    const size_t off = rr * rs;
-    cplx<float> rho[6], xm[6], pw[6], own[6], oth[6];
-    const float2* src = (flags & SAP_FIRST) ? b + off : r + off;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) rho[q] = ld<float>(src, (size_t)(a0 + q) * Vb + fb12);
-    if (flags & SAP_DELTA) {
-      // r -= D delta over the hops of this thread's directions that leave the domain
-#pragma unroll
-      for (int q = 0; q < 6; ++q) own[q] = oth[q] = {0, 0};
-      const float2* dl = delta + off;
-      // an opaque copy of the site index: the neighbours' addresses are
-      // recomputed here, not hoisted out of the loop over right-hand sides
-      // and held in registers through the MR iterations
-      int sq = s;
-      asm volatile("" : "+v"(sq));
-      const SiteCoord cq = decompose(g, sq);
-      if (hh == 0) {
-        pair_cross<0, true>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, own, oth);
-        asm volatile("" ::: "memory");
-        pair_cross<0, false>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, own, oth);
-        asm volatile("" ::: "memory");
-        pair_cross<1, true>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, own, oth);
-        asm volatile("" ::: "memory");
-        pair_cross<1, false>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, own, oth);
-      } else {
-        pair_cross<2, true>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, oth, own);
-        asm volatile("" ::: "memory");
-        pair_cross<2, false>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, oth, own);
-        asm volatile("" ::: "memory");
-        pair_cross<3, true>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, oth, own);
-        asm volatile("" ::: "memory");
-        pair_cross<3, false>(g, sq, cq, Vb, ninfo, l, kappa, dl, U, fb36, oth, own);
-      }
-      // exchange the halves: write the partner's components, read this thread's
-#pragma unroll
-      for (int q = 0; q < 6; ++q) lds[(6 - a0 + q) * Vb + l] = oth[q];
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 6; ++q) rho[q] = rho[q] + own[q] + lds[(a0 + q) * Vb + l];
-      __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) xm[q] = {0, 0};
-    for (int it = 0; it < mr; ++it) {
-#pragma unroll
-      for (int q = 0; q < 6; ++q) lds[(a0 + q) * Vb + l] = rho[q];
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 6; ++q) own[q] = oth[q] = {0, 0};
-      // opaque copy of the site index: the neighbour table and forward links
-      // are re-read from LDS each iteration rather than held in registers
-      int lq = l;
-      asm volatile("" : "+v"(lq));
-      if (hh == 0) {
-        pair_hops<0>(lds, lu, ninfo, Vb, lq, own, oth);
-        asm volatile("" ::: "memory");
-        pair_hops<1>(lds, lu, ninfo, Vb, lq, own, oth);
-      } else {
-        pair_hops<2>(lds, lu, ninfo, Vb, lq, oth, own);
-        asm volatile("" ::: "memory");
-        pair_hops<3>(lds, lu, ninfo, Vb, lq, oth, own);
-      }
-      __syncthreads();  // every hop has read the residual
-#pragma unroll
-      for (int q = 0; q < 6; ++q) lds[(6 - a0 + q) * Vb + l] = oth[q];
-      __syncthreads();
-      // p = (1 + F) rho + in-domain hops, this thread's components
-#pragma unroll
-      for (int q = 0; q < 6; ++q) pw[q] = rho[q] + own[q] + lds[(a0 + q) * Vb + l];
-      // the clover is the same in every iteration: an opaque copy of the
-      // chirality index keeps its loads here instead of hoisted out of the
-      // loops (36 more live registers all the time)
-      int hq = hh;
-      asm volatile("" : "+v"(hq));
-      clover_block(C, Vb, fb36, hq, rho, pw);
-      float pr_re = 0, pr_im = 0, pp = 0;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        pr_re += pw[q].x * rho[q].x + pw[q].y * rho[q].y;
-        pr_im += pw[q].x * rho[q].y - pw[q].y * rho[q].x;
-        pp += pw[q].x * pw[q].x + pw[q].y * pw[q].y;
-      }
-      pr_re = wave_sum(pr_re);
-      pr_im = wave_sum(pr_im);
-      pp = wave_sum(pp);
-      if ((t & 63) == 0) {
-        red[(t >> 6) * 3 + 0] = pr_re;
-        red[(t >> 6) * 3 + 1] = pr_im;
-        red[(t >> 6) * 3 + 2] = pp;
-      }
-      __syncthreads();
-      float sre = 0, sim = 0, spp = 0;
-      for (int w = 0; w < nw; ++w) {
-        sre += red[w * 3 + 0];
-        sim += red[w * 3 + 1];
-        spp += red[w * 3 + 2];
-      }
-      cplx<float> alpha = {0, 0};
-      if (spp > 0) alpha = {sre / spp, sim / spp};
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        xm[q] = xm[q] + alpha * rho[q];
-        rho[q] = rho[q] - alpha * pw[q];
-      }
-    }
-    float2* xr = x + off;
-    float2* rw = r + off;
-    float2* dw = delta + off;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const size_t o = (size_t)(a0 + q) * Vb + fb12;
-      cplx<float> x0 = {0, 0};
-      if (!(flags & SAP_FIRST)) x0 = ld<float>(xr, o);
-      else if (xinit) x0 = ld<float>(xinit + off, o);
-      st(xr, o, x0 + xm[q]);
-      if (!(flags & SAP_NO_R)) st(rw, o, rho[q]);
-      if (!(flags & SAP_NO_DELTA)) st(dw, o, xm[q]);
-    }
-    __syncthreads();  // the next right-hand side reuses lds and red
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Mixed-precision SAP half-sweep with the domain's residual exchanged in FP16.
-// As k_sap_dom (one workgroup per domain, all RHS in turn, prescaled FP16
-// links and the neighbour table in LDS, the site's FP16 clover in registers),
-// but the residual a site publishes to its neighbours is rounded to FP16
-// (24 KB of LDS at 512 sites instead of 48), and the SU(3) and clover products
-// run on v_dot2_f32_f16: FP16 x FP16 products (exact in FP32) accumulated in
-// FP32, two real multiply-adds per instruction.  The state of the MR
-// iteration (residual, correction, D_SAP r) and its dot products stay in FP32.
-// Complex numbers in packed form: (re, im).
-// ---------------------------------------------------------------------------
-typedef _Float16 h2v __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ h2v to_h2v(half2_t v) {
-  h2v r;
-  r.x = v.x;
-  r.y = v.y;
-  return r;
-}
-// c + a.b and c + a.x b.x - a.y b.y (the negation as an instruction
-// modifier) on v_dot2_f32_f16; the z forms start from zero
-__device__ __forceinline__ float dot2(h2v a, h2v b, float c) {
-  float d;
-  asm("v_dot2_f32_f16 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-  return d;
-}
-__device__ __forceinline__ float dot2n(h2v a, h2v b, float c) {
-  float d;
-  asm("v_dot2_f32_f16 %0, %1, %2, %3 neg_hi:[0,1,0]" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-  return d;
-}
-__device__ __forceinline__ float dot2z(h2v a, h2v b) {
-  float d;
-  asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(d) : "v"(a), "v"(b));
-  return d;
-}
-__device__ __forceinline__ float dot2nz(h2v a, h2v b) {
-  float d;
-  asm("v_dot2_f32_f16 %0, %1, %2, 0 neg_hi:[0,1,0]" : "=v"(d) : "v"(a), "v"(b));
-  return d;
-}
-
-template <int U>
-__device__ __forceinline__ h2v unit_h(h2v a) {
-  if constexpr (U == 0) return a;
-  else if constexpr (U == 1) return h2v{-a.y, a.x};
-  else if constexpr (U == 2) return -a;
-  else return h2v{a.y, -a.x};
-}
-__device__ __forceinline__ h2v swap_h(h2v a) { return h2v{a.y, a.x}; }
-
-// acc += (1 -/+ gamma_MU) W psi(nl), W = the prescaled FP16 link u16 (FWD) or
-// its adjoint, psi read in FP16 from the LDS planes [12][Vb].  With h the spin
-// projection (packed (re, im)) and hs = (h.y, h.x):
-//   Re(u h) = u.x h.x - u.y h.y = dot2n(u, h),  Im(u h) = u.hs,
-//   Re(u* h) = u.h,  Im(u* h) = u.x h.y - u.y h.x = dot2n(u, hs).
-template <int MU, bool FWD>
-__device__ __forceinline__ void hop_dot2(const h2v* lds16, int Vb, int nl, const half2_t* u16,
-                                         cplx<float> (&acc)[12]) {
-  using P = Proj<MU>;
-  constexpr int T0 = FWD ? P::t0 : (P::t0 ^ 2);
-  constexpr int T1 = FWD ? P::t1 : (P::t1 ^ 2);
-  constexpr int S0 = FWD ? P::s0 : (P::s0 ^ 2);
-  constexpr int S1 = FWD ? P::s1 : (P::s1 ^ 2);
-  h2v h0[3], hs0[3], h1[3], hs1[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const h2v a0 = lds16[c * Vb + nl], b0 = unit_h<T0>(lds16[((2 + P::pi0) * 3 + c) * Vb + nl]);
-    const h2v a1 = lds16[(3 + c) * Vb + nl], b1 = unit_h<T1>(lds16[((2 + P::pi1) * 3 + c) * Vb + nl]);
-    h0[c] = a0 + b0;
-    hs0[c] = swap_h(a0) + swap_h(b0);
-    h1[c] = a1 + b1;
-    hs1[c] = swap_h(a1) + swap_h(b1);
-  }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    float x0, y0, x1, y1;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const h2v u = to_h2v(FWD ? u16[r * 3 + c] : u16[c * 3 + r]);
-      if (c == 0) {
-        x0 = FWD ? dot2nz(u, h0[c]) : dot2z(u, h0[c]);
-        y0 = FWD ? dot2z(u, hs0[c]) : dot2nz(u, hs0[c]);
-        x1 = FWD ? dot2nz(u, h1[c]) : dot2z(u, h1[c]);
-        y1 = FWD ? dot2z(u, hs1[c]) : dot2nz(u, hs1[c]);
-      } else {
-        x0 = FWD ? dot2n(u, h0[c], x0) : dot2(u, h0[c], x0);
-        y0 = FWD ? dot2(u, hs0[c], y0) : dot2n(u, hs0[c], y0);
-        x1 = FWD ? dot2n(u, h1[c], x1) : dot2(u, h1[c], x1);
-        y1 = FWD ? dot2(u, hs1[c], y1) : dot2n(u, hs1[c], y1);
-      }
-    }
-    const cplx<float> g0 = {x0, y0}, g1 = {x1, y1};
-    acc[r] = acc[r] + g0;
-    acc[3 + r] = acc[3 + r] + g1;
-    acc[6 + r] = acc[6 + r] + unit<S0>(P::pi0 == 0 ? g0 : g1);
-    acc[9 + r] = acc[9 + r] + unit<S1>(P::pi1 == 0 ? g0 : g1);
-  }
-}
-
-// acc += F rho for the FP16 clover (two Hermitian 6x6 blocks: 6 real
-// diagonal entries in 3 packed numbers, then the 15 entries above the
-// diagonal row by row) and the FP16-rounded residual r16 (rs16: swapped);
-// the diagonal multiplies the FP32 residual.
-//   acc_i += F_ij rho_j:        Re = dot2n(F, r_j), Im = F.rs_j
-//   acc_j += conj(F_ij) rho_i:  Re = F.r_i,         Im = dot2n(F, rs_i)
-__device__ __forceinline__ void clover_dot2(const half2_t (&cl)[36], const cplx<float> (&rho)[12],
-                                            const h2v (&r16)[12], const h2v (&rs16)[12], cplx<float> (&acc)[12]) {
-#pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const float d[6] = {(float)cl[18 * b].x,     (float)cl[18 * b].y,     (float)cl[18 * b + 1].x,
-                        (float)cl[18 * b + 1].y, (float)cl[18 * b + 2].x, (float)cl[18 * b + 2].y};
-#pragma unroll
-    for (int i = 0; i < 6; ++i) acc[6 * b + i] = acc[6 * b + i] + d[i] * rho[6 * b + i];
-    int k = 18 * b + 3;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-#pragma unroll
-      for (int j = i + 1; j < 6; ++j) {
-        const h2v f = to_h2v(cl[k]);
-        acc[6 * b + i].x = dot2n(f, r16[6 * b + j], acc[6 * b + i].x);
-        acc[6 * b + i].y = dot2(f, rs16[6 * b + j], acc[6 * b + i].y);
-        acc[6 * b + j].x = dot2(f, r16[6 * b + i], acc[6 * b + j].x);
-        acc[6 * b + j].y = dot2n(f, rs16[6 * b + i], acc[6 * b + j].y);
-        ++k;
-      }
-    }
-  }
-}
-
-template <int VB>
-__global__ __launch_bounds__(512) void k_sap_h16(Geo g, int colour, int flags, int mr, float kappa, int nrhs,
-                                                 const float2* __restrict__ b, float2* __restrict__ r,
-                                                 float2* __restrict__ x, float2* __restrict__ delta,
-                                                 const float2* __restrict__ xinit, size_t rs,
-                                                 const half2_t* __restrict__ U, const half2_t* __restrict__ C) {
-  extern __shared__ __align__(16) char smem[];
-  const int Vb = VB ? VB : g.Vb;
-  h2v* lds16 = (h2v*)smem;                          // [12][Vb] residual, FP16
-  half2_t* lu = (half2_t*)(smem + 12 * Vb * 4);     // [4][9][Vb] -kappa sign U_mu(x) of the domain
-  int* ninfo = (int*)(lu + 36 * Vb);                // [8][Vb] neighbour info
-  float* red = (float*)(ninfo + 8 * Vb);            // [nwaves][3]
-  const int half = g.NB[0] >> 1;
-  int k = xcd_remap(blockIdx.x, g.nblk >> 1);
-  if (k >= (g.nblk >> 1)) return;
-  int row = k / half, j = k - row * half;
-  int by = row % g.NB[1];
-  int rz = row / g.NB[1];
-  int bz = rz % g.NB[2];
-  int bt = rz / g.NB[2];
-  int bx = 2 * j + ((colour + by + bz + bt) & 1);
-  int blk = bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
-  const int l = threadIdx.x;
-  const bool act = l < Vb;
-  const int s = blk * Vb + (act ? l : 0);
-  const int nw = (blockDim.x + 63) >> 6;
-  SiteCoord c = decompose(g, s);
-  const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
-
-  // neighbour table: in-domain neighbour's local index (bits 0..9), in-domain
-  // flag (bit 10), boundary sign -1 (bit 11)
-  float fsign[4];
-#pragma unroll
-  for (int d = 0; d < 8; ++d) {
-    int sign;
-    bool inb;
-    int mu = d & 3;
-    int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb) : neighbour<false>(g, s, c, mu, sign, inb);
-    if (d < 4) fsign[mu] = (float)sign;
-    if (act) ninfo[d * Vb + l] = (inb ? ((nb - blk * Vb) | (1 << 10)) : 0) | (sign < 0 ? (1 << 11) : 0);
-  }
-  if (act) {
-#pragma unroll
-    for (int q = 0; q < 36; ++q) {
-      const float f = -kappa * fsign[q / 9];
-      st(lu, (size_t)q * Vb + l, f * ld<float>(U, (size_t)q * Vb + fb36));
-    }
-  }
-  __syncthreads();
-
-  half2_t cl[36];
-#pragma unroll
-  for (int q = 0; q < 36; ++q) cl[q] = C[(size_t)q * Vb + fb36];
-  for (int rr = 0; rr < nrhs; ++rr) {
-    const size_t off = rr * rs;
-    cplx<float> rho[12], xm[12], p[12], psi[12];
-    if (act) {
-      ld_spinor<float>((flags & SAP_FIRST) ? b + off : r + off, Vb, fb12, rho);
-      if (flags & SAP_DELTA) {
-#pragma unroll 1
-        for (int d = 0; d < 8; ++d) {
-          if (ninfo[d * Vb + l] & (1 << 10)) continue;
-          int sign, nblk;
-          bool inb;
-          int mu = d & 3;
-          int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb, nblk)
-                         : neighbour<false>(g, s, c, mu, sign, inb, nblk);
-          ld_spinor<float>(delta + off, Vb, fbase_b(g, 12, nb, nblk), psi);
-          const size_t lb = d < 4 ? fb36 : fbase_b(g, 36, nb, nblk);
-          half2_t ub[9];
-#pragma unroll
-          for (int e = 0; e < 9; ++e) ub[e] = U[(size_t)(mu * 9 + e) * Vb + lb];
-          if (d < 4)
-            hop_h<true>(mu, psi, ub, kappa * (float)sign, rho);
-          else
-            hop_h<false>(mu, psi, ub, kappa * (float)sign, rho);
-        }
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < 12; ++a) xm[a] = {0, 0};
-    for (int it = 0; it < mr; ++it) {
-      h2v r16[12], rs16[12];
-#pragma unroll
-      for (int a = 0; a < 12; ++a) {
-        r16[a] = h2v{(_Float16)rho[a].x, (_Float16)rho[a].y};
-        rs16[a] = swap_h(r16[a]);
-      }
-      if (act) {
-#pragma unroll
-        for (int a = 0; a < 12; ++a) lds16[a * Vb + l] = r16[a];
-      }
-      __syncthreads();
-      float pr_re = 0, pr_im = 0, pp = 0;
-      if (act) {
-        // p = (1 + F) rho + in-domain hops
-#pragma unroll
-        for (int a = 0; a < 12; ++a) p[a] = rho[a];
-        clover_dot2(cl, rho, r16, rs16, p);
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-          const int inf = ninfo[d * Vb + l];
-          if (inf & (1 << 10)) {
-            const int nl = inf & 1023;
-            half2_t ub[9];
-            const int ls = d < 4 ? l : nl;  // U_mu(x) or U_mu(x - mu), scaled
-#pragma unroll
-            for (int e = 0; e < 9; ++e) ub[e] = lu[((d & 3) * 9 + e) * Vb + ls];
-            switch (d) {
-              case 0: hop_dot2<0, true>(lds16, Vb, nl, ub, p); break;
-              case 1: hop_dot2<1, true>(lds16, Vb, nl, ub, p); break;
-              case 2: hop_dot2<2, true>(lds16, Vb, nl, ub, p); break;
-              case 3: hop_dot2<3, true>(lds16, Vb, nl, ub, p); break;
-              case 4: hop_dot2<0, false>(lds16, Vb, nl, ub, p); break;
-              case 5: hop_dot2<1, false>(lds16, Vb, nl, ub, p); break;
-              case 6: hop_dot2<2, false>(lds16, Vb, nl, ub, p); break;
-              default: hop_dot2<3, false>(lds16, Vb, nl, ub, p); break;
-            }
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < 12; ++a) {
-          pr_re += p[a].x * rho[a].x + p[a].y * rho[a].y;
-          pr_im += p[a].x * rho[a].y - p[a].y * rho[a].x;
-          pp += p[a].x * p[a].x + p[a].y * p[a].y;
-        }
-      }
-      pr_re = wave_sum(pr_re);
-      pr_im = wave_sum(pr_im);
-      pp = wave_sum(pp);
-      if ((l & 63) == 0) {
-        red[(l >> 6) * 3 + 0] = pr_re;
-        red[(l >> 6) * 3 + 1] = pr_im;
-        red[(l >> 6) * 3 + 2] = pp;
-      }
-      __syncthreads();
-      float sre = 0, sim = 0, spp = 0;
-      for (int w = 0; w < nw; ++w) {
-        sre += red[w * 3 + 0];
-        sim += red[w * 3 + 1];
-        spp += red[w * 3 + 2];
-      }
-      cplx<float> alpha = {0, 0};
-      if (spp > 0) alpha = {sre / spp, sim / spp};
-      if (act) {
-#pragma unroll
-        for (int a = 0; a < 12; ++a) {
-          xm[a] = xm[a] + alpha * rho[a];
-          rho[a] = rho[a] - alpha * p[a];
-        }
-      }
-    }
-    if (act) {
-      float2* xr = x + off;
-      float2* rw = r + off;
-      float2* dw = delta + off;
-#pragma unroll
-      for (int a = 0; a < 12; ++a) {
-        size_t o = (size_t)a * Vb + fb12;
-        cplx<float> x0 = {0, 0};
-        if (!(flags & SAP_FIRST)) x0 = ld<float>(xr, o);
-        else if (xinit) x0 = ld<float>(xinit + off, o);
-        st(xr, o, x0 + xm[a]);
-        if (!(flags & SAP_NO_R)) st(rw, o, rho[a]);
-        if (!(flags & SAP_NO_DELTA)) st(dw, o, xm[a]);
-      }
-    }
-    __syncthreads();  // the next right-hand side reuses lds16 and red
-  }
-}
-
-int sap_h16_lds_bytes(const Geo& g) {
-  int nthr = ((g.Vb + 63) / 64) * 64;
-  return 12 * g.Vb * 4 + 36 * g.Vb * 4 + 8 * g.Vb * 4 + (nthr / 64) * 3 * 4;
-}
-
-bool sap_pair_ok(const Geo& g) { return g.Vb % 64 == 0 && g.Vb <= 512; }
-int sap_pair_lds_bytes(const Geo& g) { return 12 * g.Vb * 8 + 36 * g.Vb * 4 + 8 * g.Vb * 4 + (2 * g.Vb / 64) * 3 * 4; }
 int sap_dom_lds_bytes(const Geo& g) {
   int nthr = ((g.Vb + 63) / 64) * 64;
   return 12 * g.Vb * 8 + 36 * g.Vb * 4 + 8 * g.Vb * 4 + (nthr / 64) * 3 * 4;
@@ -1764,45 +1149,6 @@ void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st) {
                                           (float2*)a.r, (float2*)a.x, (float2*)a.delta, (const float2*)a.xinit, a.rs,
                                           (const half2_t*)a.U, (const half2_t*)a.C);
   };
-  if (a.variant == SAP_PAIR) {
-    static bool pair_attr[3] = {false, false, false};
-    if (!sap_pair_ok(g)) throw std::runtime_error("SAP split kernel: block volume must be a multiple of 64, at most 512");
-    auto gp = [&](auto kern, int id) {
-      if (!pair_attr[id]) {
-        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        pair_attr[id] = true;
-      }
-      kern<<<round8(ndom), 2 * g.Vb, sap_pair_lds_bytes(g), st>>>(
-          g, col, flags, a.mr, (float)a.kappa, a.nrhs, (const float2*)a.b, (float2*)a.r, (float2*)a.x,
-          (float2*)a.delta, (const float2*)a.xinit, a.rs, (const half2_t*)a.U, (const half2_t*)a.C);
-    };
-    if (g.Vb == 512)
-      gp(k_sap_pair<512>, 0);
-    else if (g.Vb == 256)
-      gp(k_sap_pair<256>, 1);
-    else
-      gp(k_sap_pair<0>, 2);
-    return;
-  }
-  if (a.variant == SAP_H16) {
-    static bool h16_attr[3] = {false, false, false};
-    auto gh = [&](auto kern, int id) {
-      if (!h16_attr[id]) {
-        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        h16_attr[id] = true;
-      }
-      kern<<<round8(ndom), nthr, sap_h16_lds_bytes(g), st>>>(
-          g, col, flags, a.mr, (float)a.kappa, a.nrhs, (const float2*)a.b, (float2*)a.r, (float2*)a.x,
-          (float2*)a.delta, (const float2*)a.xinit, a.rs, (const half2_t*)a.U, (const half2_t*)a.C);
-    };
-    if (g.Vb == 512)
-      gh(k_sap_h16<512>, 0);
-    else if (g.Vb == 256)
-      gh(k_sap_h16<256>, 1);
-    else
-      gh(k_sap_h16<0>, 2);
-    return;
-  }
   if (g.Vb == 512)
     go(k_sap_dom<512>, 0);
   else if (g.Vb == 256)

@@ -70,19 +70,11 @@ struct SapArgs {
   size_t rs = 0;                // per-rhs stride of all spinor fields
   const void* U = nullptr;
   const void* C = nullptr;
-  // mixed path: SAP_DOM (one thread per site), SAP_PAIR (two threads per
-  // site), SAP_H16 (one thread per site, residual exchanged in FP16, products
-  // on the FP16 dot-product instructions with FP32 accumulation)
-  int variant = 0;
 };
-enum { SAP_DOM = 0, SAP_PAIR = 1, SAP_H16 = 2 };
 // one half-sweep (colour col of sweep `sweep`) of the SAP listing
 void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st);
 int sap_lds_bytes(const Geo& g, int mixed);  // FP64 path
 int sap_dom_lds_bytes(const Geo& g);          // mixed path
-int sap_pair_lds_bytes(const Geo& g);         // mixed path, SAP_PAIR
-bool sap_pair_ok(const Geo& g);               // SAP_PAIR supports this block volume
-int sap_h16_lds_bytes(const Geo& g);          // mixed path, SAP_H16
 
 // ---------------------------------------------------------------- coarse level
 struct CGeo {

@@ -78,35 +78,6 @@ def test_sap_mixed(prob):
     assert rel(prob.N(x), want) < 1e-2
 
 
-@pytest.mark.parametrize('block', [(4, 4, 2, 2), (4, 4, 4, 4)])
-def test_sap_mixed_every_kernel(tmp_path, block):
-    """Every mixed-precision SAP kernel (one thread per site; two threads per
-    site with the hop directions split between them; one thread per site with
-    the residual exchanged in FP16 and the products on the FP16 dot-product
-    instructions) on 3 right-hand sides, domains of 64 and 256 sites, forced
-    in turn through the tuner's cache."""
-    import json
-    from paper_2111_05012_amd import PREC_MIXED
-    prob = Problem((8, 8, 8, 8), block, eps=0.5, seed=5, kappa=0.124, csw=1.1)
-    cache = str(tmp_path / 'tune.json')
-    prob.ctx.autotune(True, cache)
-    b = syn.gaussian_vectors(prob.dims, 3, 17)
-    want = np.stack([amg.sap(prob.op, b[i], 3, 5) for i in range(3)])
-    x = prob.zeros(b.shape)
-    prob.ctx.sap(prob.T(b), x, 3, 3, 5, PREC_MIXED)  # tunes and writes the cache
-    keys = json.load(open(cache))
-    assert any(k.split('|')[1] == 'sap' for k in keys)
-    for v in (0, 1, 2):
-        forced = {k: (v if k.split('|')[1] == 'sap' else val) for k, val in keys.items()}
-        with open(cache, 'w') as f:
-            json.dump(forced, f)
-        prob.ctx.autotune(True, cache)
-        x = prob.zeros(b.shape)
-        prob.ctx.sap(prob.T(b), x, 3, 3, 5, PREC_MIXED)
-        for i in range(3):
-            assert rel(prob.N(x)[i], want[i]) < 1e-2, (v, i)
-
-
 @pytest.mark.parametrize('nv', [6, 20])
 def test_orthonormalize_fp64(prob, nv):
     """FP64 block orthonormalisation (Gram matrices on the FP64 matrix cores;
