@@ -942,8 +942,7 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   const int Vb = VB ? VB : g.Vb;
   cplx<float>* lds = (cplx<float>*)smem;                   // [12][Vb] residual exchange
   half2_t* lu = (half2_t*)(smem + 12 * Vb * sizeof(cplx<float>));  // [4][9][Vb] -kappa sign U_mu(x) of the domain
-  int* ninfo = (int*)(lu + 36 * Vb);                       // [8][Vb] neighbour info
-  float* red = (float*)(ninfo + 8 * Vb);                   // [nwaves][3]
+  float* red = (float*)(lu + 36 * Vb);                     // [nwaves][3]
   const int half = g.NB[0] >> 1;
   int k = xcd_remap(blockIdx.x, g.nblk >> 1);
   if (k >= (g.nblk >> 1)) return;
@@ -961,9 +960,10 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   SiteCoord c = decompose(g, s);
   const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
 
-  // per direction: in-domain neighbour's local index (bits 0..9), in-domain
-  // flag (bit 10), boundary sign -1 (bit 11)
+  // per direction, held in registers for the whole launch: in-domain
+  // neighbour's local index (bits 0..9), in-domain flag (bit 10)
   float fsign[4];
+  int ninfo[8];
 #pragma unroll
   for (int d = 0; d < 8; ++d) {
     int sign;
@@ -971,7 +971,7 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
     int mu = d & 3;
     int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb) : neighbour<false>(g, s, c, mu, sign, inb);
     if (d < 4) fsign[mu] = (float)sign;
-    if (act) ninfo[d * Vb + l] = (inb ? ((nb - blk * Vb) | (1 << 10)) : 0) | (sign < 0 ? (1 << 11) : 0);
+    ninfo[d] = inb ? ((nb - blk * Vb) | (1 << 10)) : 0;
   }
   // the domain's forward links scaled by the hop coefficient, -kappa sign
   // U_mu(x) (sign: bc of a hop x -> x + mu that crosses the lattice boundary,
@@ -1000,12 +1000,12 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
       if (flags & SAP_DELTA) {
 #pragma unroll 1
         for (int d = 0; d < 8; ++d) {
-          if (ninfo[d * Vb + l] & (1 << 10)) continue;
           int sign, nblk;
           bool inb;
           int mu = d & 3;
           int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb, nblk)
                          : neighbour<false>(g, s, c, mu, sign, inb, nblk);
+          if (inb) continue;
           ld_spinor<float>(delta + off, Vb, fbase_b(g, 12, nb, nblk), psi);
           const size_t lb = d < 4 ? fb36 : fbase_b(g, 36, nb, nblk);
           half2_t ub[9];
@@ -1035,7 +1035,7 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
         // unrolled: direction and projection are compile-time constants
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
-          const int inf = ninfo[d * Vb + l];
+          const int inf = ninfo[d];
           if (inf & (1 << 10)) {
             int nl = inf & 1023;
 #pragma unroll
@@ -1103,7 +1103,7 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
 
 int sap_dom_lds_bytes(const Geo& g) {
   int nthr = ((g.Vb + 63) / 64) * 64;
-  return 12 * g.Vb * 8 + 36 * g.Vb * 4 + 8 * g.Vb * 4 + (nthr / 64) * 3 * 4;
+  return 12 * g.Vb * 8 + 36 * g.Vb * 4 + (nthr / 64) * 3 * 4;
 }
 
 int sap_lds_bytes(const Geo& g, int mixed) {
