@@ -769,7 +769,7 @@ void launch_dslash(const DslashArgs& a, hipStream_t st) {
 //   2. MR(mr) on D_SAP restricted to the domain from 0 (residual through LDS);
 //   3. x_X += correction, r_X = MR residual, delta_X = correction.
 // ---------------------------------------------------------------------------
-enum { SAP_FIRST = 1, SAP_DELTA = 2, SAP_NO_R = 4, SAP_NO_DELTA = 8 };
+enum { SAP_FIRST = 1, SAP_DELTA = 2, SAP_NO_R = 4, SAP_NO_DELTA = 8, SAP_R_IN = 16 };
 
 template <class R>
 __device__ __forceinline__ R wave_sum(R v) {
@@ -918,7 +918,7 @@ __global__ __launch_bounds__(512) void k_sap_half(Geo g, int colour, int flags, 
 // the right-hand sides then run in turn with the residual exchanged through
 // LDS and the clover (FP16, one contiguous range per domain) read through the
 // caches.  Links of hops that leave the domain are not needed by D_SAP; the
-// crossing-hop correction of step 1 reads them from memory.
+// crossing-hop correction of the residual runs before, in k_sap_cross.
 __device__ __forceinline__ cplx<float> h2f(half2_t v) { return {(float)v.x, (float)v.y}; }
 
 template <bool FWD>
@@ -928,6 +928,69 @@ __device__ __forceinline__ void hop_h(int mu, const cplx<float> (&psi)[12], cons
 #pragma unroll
   for (int e = 0; e < 9; ++e) u[e] = h2f(u16[e]);
   hop_any<FWD>(mu, psi, u, coef, acc);
+}
+
+// The crossing-hop correction of a mixed-precision SAP half-sweep as a
+// kernel of its own, ahead of the domain solves: for every site x of the
+// active colour's domains and every right-hand side,
+//   r(x) = src(x) + kappa sum_{hops x -> y leaving the domain} sign W delta(y)
+// (r = b - D x restricted to the active colour, updated with the other
+// colour's last block corrections delta).  src is b on a colour's first visit
+// (every site is then written), else r itself (sites without a crossing hop
+// are left alone).  One thread per (site, right-hand side): memory-bound
+// work at full occupancy, where inside the domain solve's single workgroup
+// per CU the dependent global loads of the hops stood exposed.
+__global__ __launch_bounds__(256) void k_sap_cross(Geo g, int colour, int first, float kappa,
+                                                   const float2* __restrict__ b, float2* __restrict__ r,
+                                                   const float2* __restrict__ delta, size_t rs,
+                                                   const half2_t* __restrict__ U) {
+  const int Vb = g.Vb;
+  const size_t nsite = (size_t)(g.nblk >> 1) * Vb;
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nsite) return;
+  const int k = (int)(e / Vb), loc = (int)(e - (size_t)k * Vb);
+  const int half = g.NB[0] >> 1;
+  const int row = k / half, j = k - row * half;
+  const int by = row % g.NB[1];
+  const int rz = row / g.NB[1];
+  const int bz = rz % g.NB[2];
+  const int bt = rz / g.NB[2];
+  const int bx = 2 * j + ((colour + by + bz + bt) & 1);
+  const int blk = bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
+  const int s = blk * Vb + loc;
+  const SiteCoord c = decompose(g, s);
+  const size_t off = (size_t)blockIdx.y * rs;
+  const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
+  const float2* src = (first ? b : r) + off;
+  cplx<float> acc[12], psi[12];
+#pragma unroll
+  for (int a = 0; a < 12; ++a) acc[a] = {0, 0};
+  bool any = false;
+#pragma unroll 1
+  for (int d = 0; d < 8; ++d) {
+    int sign, nblk;
+    bool inb;
+    const int mu = d & 3;
+    const int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb, nblk) : neighbour<false>(g, s, c, mu, sign, inb, nblk);
+    if (inb) continue;
+    any = true;
+    ld_spinor<float>(delta + off, Vb, fbase_b(g, 12, nb, nblk), psi);
+    const size_t lb = d < 4 ? fb36 : fbase_b(g, 36, nb, nblk);
+    half2_t ub[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) ub[q] = U[(size_t)(mu * 9 + q) * Vb + lb];
+    if (d < 4)
+      hop_h<true>(mu, psi, ub, kappa * (float)sign, acc);
+    else
+      hop_h<false>(mu, psi, ub, kappa * (float)sign, acc);
+  }
+  if (!any && !first) return;
+  float2* dst = r + off;
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    const size_t o = (size_t)a * Vb + fb12;
+    st(dst, o, ld<float>(src, o) + acc[a]);
+  }
 }
 
 // VB: the domain volume when known at compile time (LDS offsets become
@@ -996,27 +1059,8 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
     const size_t off = rr * rs;
     cplx<float> rho[12], xm[12], p[12], psi[12];
     if (act) {
-      ld_spinor<float>((flags & SAP_FIRST) ? b + off : r + off, Vb, fb12, rho);
-      if (flags & SAP_DELTA) {
-#pragma unroll 1
-        for (int d = 0; d < 8; ++d) {
-          int sign, nblk;
-          bool inb;
-          int mu = d & 3;
-          int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb, nblk)
-                         : neighbour<false>(g, s, c, mu, sign, inb, nblk);
-          if (inb) continue;
-          ld_spinor<float>(delta + off, Vb, fbase_b(g, 12, nb, nblk), psi);
-          const size_t lb = d < 4 ? fb36 : fbase_b(g, 36, nb, nblk);
-          half2_t ub[9];
-#pragma unroll
-          for (int e = 0; e < 9; ++e) ub[e] = U[(size_t)(mu * 9 + e) * Vb + lb];
-          if (d < 4)
-            hop_h<true>(mu, psi, ub, kappa * (float)sign, rho);
-          else
-            hop_h<false>(mu, psi, ub, kappa * (float)sign, rho);
-        }
-      }
+      // the crossing-hop correction has been applied by k_sap_cross (SAP_R_IN)
+      ld_spinor<float>(((flags & SAP_FIRST) && !(flags & SAP_R_IN)) ? b + off : r + off, Vb, fb12, rho);
     }
 #pragma unroll
     for (int a = 0; a < 12; ++a) xm[a] = {0, 0};
@@ -1135,6 +1179,15 @@ void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st) {
   // half-sweep's correction is never read either
   if (sweep == a.sweeps - 1) flags |= SAP_NO_R;
   if (sweep == a.sweeps - 1 && col == 1) flags |= SAP_NO_DELTA;
+  if (flags & SAP_DELTA) {
+    // the crossing-hop correction first, in a launch of its own; the domain
+    // solves then start from r
+    const size_t nsite = (size_t)(a.g.nblk / 2) * a.g.Vb;
+    k_sap_cross<<<dim3((unsigned)((nsite + 255) / 256), a.nrhs), 256, 0, st>>>(
+        a.g, col, (flags & SAP_FIRST) ? 1 : 0, (float)a.kappa, (const float2*)a.b, (float2*)a.r,
+        (const float2*)a.delta, a.rs, (const half2_t*)a.U);
+    flags = (flags & ~SAP_DELTA) | SAP_R_IN;
+  }
   const Geo& g = a.g;
   int nthr = ((g.Vb + 63) / 64) * 64;
   int lds = sap_dom_lds_bytes(g);
