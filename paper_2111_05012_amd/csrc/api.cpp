@@ -576,6 +576,7 @@ struct wcamg_ctx {
       if (g.Vb % v == 0) cands.push_back(v);
     if (cands.empty()) cands.push_back(0);
     if (h.prec == WCAMG_PREC_FP64 && h.nv <= 32 && nrhs <= 32) cands.push_back(RESTRICT_MFMA64);
+    if (h.prec == WCAMG_PREC_MIXED && h.nv <= 32 && nrhs <= 32) cands.push_back(RESTRICT_MFMA32);
     int tile = tune(key, cands, [&](int v) {
       launch_restrict(g, h.nv, nrhs, h.V.p, vec_t(), in, spin_t(h.prec), frs(), out, crs_t(), crs_n(), h.N, 0, st,
                       v);
@@ -587,9 +588,17 @@ struct wcamg_ctx {
   void prolong_(const void* xc, void* out, int nrhs) {
     double by = (double)g.V * 12 * (h.nv * ct_size(vec_t()) + nrhs * ct_size(spin_t(h.prec))) +
                 (double)nrhs * crs_n() * ct_size(crs_t());
+    std::vector<int> cands = {0};
+    if (h.prec == WCAMG_PREC_MIXED && h.nv <= 32 && nrhs <= 32) cands.push_back(PROLONG_MFMA32);
+    char key[160];
+    snprintf(key, sizeof(key), "prolong|nv%d|n%d|Vb%d|V%d|p%d", h.nv, nrhs, g.Vb, g.V, h.prec);
+    const int var = tune(key, cands, [&](int v) {
+      launch_prolong(g, h.nv, nrhs, h.V.p, vec_t(), xc, crs_t(), crs_n(), h.N, out, spin_t(h.prec), frs(), 0,
+                     h.prec == WCAMG_PREC_MIXED, st, v);
+    });
     Timed t(this, "prolong", by, 96.0 * g.V * h.nv * nrhs, nrhs);
     launch_prolong(g, h.nv, nrhs, h.V.p, vec_t(), xc, crs_t(), crs_n(), h.N, out, spin_t(h.prec), frs(), 0,
-                   h.prec == WCAMG_PREC_MIXED, st);
+                   h.prec == WCAMG_PREC_MIXED, st, var);
   }
   COp op1() { return COp{h.cg, h.N, h.Dc.p}; }
   COp op2() { return COp{h.cg2, h.N2, h.Dc2.p}; }

@@ -180,6 +180,111 @@ __global__ __launch_bounds__(256) void k_restrict_mf64(Geo g, int nv, int nrhs, 
   }
 }
 
+// Matrix-core restriction in FP32 (the mixed-precision V-cycle: FP16 or FP32
+// vectors and inputs, FP32 products and sums), nv <= 32, nrhs <= 32:
+//   out[r][X][s nv + i] = sum_{y in X, a in s} conj(v_i(y)_a) x_r(y)_a.
+// With x = xr + i xi stacked as the columns of B = [xr | xi] (2 nrhs columns,
+// one or two tiles of 32), T_r = vr^T B and T_i = vi^T B give
+//   Re out = T_r[:, r] + T_i[:, nrhs + r],  Im out = T_r[:, nrhs + r] - T_i[:, r]
+// (two real products per k-pair instead of four).  One workgroup per (block,
+// chirality); KC sites of one component plane are staged in LDS at a time
+// (coalesced along the sites), the four wavefronts take every fourth k-pair
+// of a stage with v_mfma_f32_32x32x2f32 (A: lane l holds row i = l % 32 of
+// k-slice l / 32; B: column l % 32 of k-slice l / 32; accumulator q of lane l
+// is element (8 (q / 4) + 4 (l / 32) + q % 4, l % 32)), and their partial
+// tiles are summed in LDS at the end in a fixed order.
+template <class TV, class TI>
+__global__ __launch_bounds__(256) void k_restrict_mf32(Geo g, int nv, int nrhs, const TV* __restrict__ V,
+                                                       const TI* __restrict__ in, size_t in_rs,
+                                                       float2* __restrict__ out, size_t out_rs, size_t out_xs) {
+  constexpr int KC = 64;
+  extern __shared__ __align__(16) float lds_r[];
+  float(*svr)[33] = (float(*)[33])lds_r;                  // [KC][33] Re v_i, i < 32
+  float(*svi)[33] = (float(*)[33])(lds_r + KC * 33);      // [KC][33] Im v_i
+  float(*sb)[65] = (float(*)[65])(lds_r + 2 * KC * 33);   // [KC][65] columns xr | xi | 0
+  const int nlog = g.nblk * 2;
+  const int lg = xcd_remap(blockIdx.x, nlog);
+  if (lg >= nlog) return;
+  const int X = lg >> 1, s = lg & 1;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int nct = 2 * nrhs > 32 ? 2 : 1;
+  f32x16 tr0, ti0, tr1, ti1;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tr0[q] = ti0[q] = tr1[q] = ti1[q] = 0.f;
+  const size_t base = (size_t)X * 12 * g.Vb;
+  for (int e = t; e < KC * 65; e += 256) (&sb[0][0])[e] = 0.f;  // columns >= 2 nrhs stay zero
+  for (int e = t; e < 2 * KC * 33; e += 256) lds_r[e] = 0.f;     // vectors i >= nv stay zero
+  __syncthreads();
+  for (int a6 = 0; a6 < 6; ++a6) {
+    const size_t pl = base + (size_t)(6 * s + a6) * g.Vb;
+    for (int l0 = 0; l0 < g.Vb; l0 += KC) {
+      for (int e = t; e < nv * KC; e += 256) {
+        const int c = e / KC, kk = e - c * KC;
+        const int loc = l0 + kk;
+        cplx<float> v = {0, 0};
+        if (loc < g.Vb) v = ld<float>(V, (size_t)c * 12 * g.V + pl + loc);
+        svr[kk][c] = v.x;
+        svi[kk][c] = v.y;
+      }
+      for (int e = t; e < nrhs * KC; e += 256) {
+        const int c = e / KC, kk = e - c * KC;
+        const int loc = l0 + kk;
+        cplx<float> x = {0, 0};
+        if (loc < g.Vb) x = ld<float>(in, (size_t)c * in_rs + pl + loc);
+        sb[kk][c] = x.x;
+        sb[kk][nrhs + c] = x.y;
+      }
+      __syncthreads();
+#pragma unroll 2
+      for (int kp = w; kp < KC / 2; kp += 4) {
+        const int k = 2 * kp + (lane >> 5), c = lane & 31;
+        const float ar = svr[k][c], ai = svi[k][c];
+        const float b0 = sb[k][c];
+        tr0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b0, tr0, 0, 0, 0);
+        ti0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b0, ti0, 0, 0, 0);
+        if (nct == 2) {
+          const float b1 = sb[k][32 + c];
+          tr1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b1, tr1, 0, 0, 0);
+          ti1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b1, ti1, 0, 0, 0);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // partial tiles of the four wavefronts: red[w][m][row][col], m = (T_r, T_i)
+  // for columns 0..31 and, with two column tiles, 32..63
+  float* red = lds_r;
+  const int ncol = 32 * nct;
+  const size_t wstride = (size_t)2 * 32 * ncol;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int row = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3), col = lane & 31;
+    red[w * wstride + (0 * 32 + row) * ncol + col] = tr0[q];
+    red[w * wstride + (1 * 32 + row) * ncol + col] = ti0[q];
+    if (nct == 2) {
+      red[w * wstride + (0 * 32 + row) * ncol + 32 + col] = tr1[q];
+      red[w * wstride + (1 * 32 + row) * ncol + 32 + col] = ti1[q];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < nv * nrhs; e += 256) {
+    const int i = e / nrhs, r = e - i * nrhs;
+    float re = 0.f, im = 0.f;
+    for (int ww = 0; ww < 4; ++ww) {
+      const float* R = red + ww * wstride;
+      re += R[(0 * 32 + i) * ncol + r] + R[(1 * 32 + i) * ncol + nrhs + r];
+      im += R[(0 * 32 + i) * ncol + nrhs + r] - R[(1 * 32 + i) * ncol + r];
+    }
+    out[(size_t)r * out_rs + (size_t)X * out_xs + s * nv + i] = make_float2(re, im);
+  }
+}
+
+int restrict_mf32_lds_bytes(int nrhs) {
+  const int staging = (2 * 64 * 33 + 64 * 65) * 4;
+  const int reduce = 4 * 2 * 32 * (2 * nrhs > 32 ? 64 : 32) * 4;
+  return staging > reduce ? staging : reduce;
+}
+
 void launch_restrict(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* in, int in_t,
                      size_t in_rs, void* out, int out_t, size_t out_rs, size_t out_xs, int acc64,
                      hipStream_t st, int tile) {
@@ -194,6 +299,28 @@ void launch_restrict(const Geo& g, int nv, int nrhs, const void* V, int v_t, con
     else
       k_restrict_mf64<float2><<<grid, 256, 0, st>>>(g, nv, nrhs, (const float2*)V, (const float2*)in, in_rs,
                                                     (double2*)out, out_rs, out_xs);
+    return;
+  }
+  if (tile == RESTRICT_MFMA32) {
+    if (nv > 32 || nrhs > 32 || out_t != C64 || acc64 || v_t != C32H || (in_t != C64 && in_t != C32H))
+      throw std::runtime_error("launch_restrict: the FP32 matrix-core path needs FP16 vectors, FP32 or FP16 inputs, "
+                               "FP32 output and nv, nrhs <= 32");
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void*)k_restrict_mf32<half2_t, float2>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+      (void)hipFuncSetAttribute((const void*)k_restrict_mf32<half2_t, half2_t>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+      attr = true;
+    }
+    const dim3 grid(round8(g.nblk * 2));
+    const int lds = restrict_mf32_lds_bytes(nrhs);
+    if (in_t == C64)
+      k_restrict_mf32<half2_t, float2><<<grid, 256, lds, st>>>(g, nv, nrhs, (const half2_t*)V, (const float2*)in,
+                                                               in_rs, (float2*)out, out_rs, out_xs);
+    else
+      k_restrict_mf32<half2_t, half2_t><<<grid, 256, lds, st>>>(g, nv, nrhs, (const half2_t*)V, (const half2_t*)in,
+                                                                in_rs, (float2*)out, out_rs, out_xs);
     return;
   }
   if (v_t == C128 && in_t == C128 && out_t == C128)
@@ -282,8 +409,9 @@ static void prolong_run(const Geo& g, int nv, int nrhs, const void* V, const voi
     go(std::integral_constant<int, 16>());
 }
 
-// Matrix-core prolongation for FP32 vectors and coefficients (the update
-// V' = V coef of the orthonormalisation), nv <= 32, nrhs <= 32:
+// Matrix-core prolongation for FP32 or FP16 vectors and FP32 coefficients
+// (the update V' = V coef of the orthonormalisation; the mixed V-cycle's
+// prolongation), FP32 products and sums, nv <= 32, nrhs <= 32:
 //   out_r(y, a) (+)= sum_i V_i(y, a) xc[r][X(y)][s(a) nv + i].
 // Computed transposed, out^T[r][k] = sum_i xc[i][r] V_i[k], so that a
 // wavefront's results for one right-hand side are 32 consecutive sites.  One
@@ -292,7 +420,8 @@ static void prolong_run(const Geo& g, int nv, int nrhs, const void* V, const voi
 // row r = l % 32, i-slice l / 32) and B = vectors (lane l: i-slice l / 32,
 // site l % 32); accumulator q of lane l is (r = 8 (q / 4) + 4 (l / 32) + q % 4,
 // site l % 32).
-__global__ __launch_bounds__(256) void k_prolong_mf(Geo g, int nv, int nrhs, const float2* __restrict__ V,
+template <class TV>
+__global__ __launch_bounds__(256) void k_prolong_mf(Geo g, int nv, int nrhs, const TV* __restrict__ V,
                                                     const float2* __restrict__ xc, size_t xc_rs, size_t xc_xs,
                                                     float2* __restrict__ out, size_t out_rs, int accumulate) {
   const int nlog = g.nblk * 2;
@@ -348,7 +477,19 @@ __global__ __launch_bounds__(256) void k_prolong_mf(Geo g, int nv, int nrhs, con
 
 void launch_prolong(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* xc, int xc_t, size_t xc_rs,
                     size_t xc_xs, void* out, int out_t, size_t out_rs, int accumulate, int compute32,
-                    hipStream_t st) {
+                    hipStream_t st, int variant) {
+  if (variant == PROLONG_MFMA32) {
+    if (!compute32 || (v_t != C32H && v_t != C64) || xc_t != C64 || out_t != C64 || nv > 32 || nrhs > 32)
+      throw std::runtime_error("launch_prolong: the matrix-core path needs FP32 arithmetic, FP16 or FP32 vectors, "
+                               "FP32 coefficients and output, nv, nrhs <= 32");
+    if (v_t == C32H)
+      k_prolong_mf<half2_t><<<round8(g.nblk * 2), 256, 0, st>>>(g, nv, nrhs, (const half2_t*)V, (const float2*)xc,
+                                                                xc_rs, xc_xs, (float2*)out, out_rs, accumulate);
+    else
+      k_prolong_mf<float2><<<round8(g.nblk * 2), 256, 0, st>>>(g, nv, nrhs, (const float2*)V, (const float2*)xc,
+                                                               xc_rs, xc_xs, (float2*)out, out_rs, accumulate);
+    return;
+  }
   if (!compute32 && v_t == C128 && xc_t == C128 && out_t == C128)
     return prolong_run<double, double2, double2, double2>(g, nv, nrhs, V, xc, xc_rs, xc_xs, out, out_rs,
                                                           accumulate, st);
@@ -357,8 +498,8 @@ void launch_prolong(const Geo& g, int nv, int nrhs, const void* V, int v_t, cons
                                                        st);
   if (compute32 && v_t == C64 && xc_t == C64 && out_t == C64) {
     if (nv <= 32 && nrhs <= 32) {
-      k_prolong_mf<<<round8(g.nblk * 2), 256, 0, st>>>(g, nv, nrhs, (const float2*)V, (const float2*)xc, xc_rs,
-                                                       xc_xs, (float2*)out, out_rs, accumulate);
+      k_prolong_mf<float2><<<round8(g.nblk * 2), 256, 0, st>>>(g, nv, nrhs, (const float2*)V, (const float2*)xc,
+                                                               xc_rs, xc_xs, (float2*)out, out_rs, accumulate);
       return;
     }
     return prolong_run<float, float2, float2, float2>(g, nv, nrhs, V, xc, xc_rs, xc_xs, out, out_rs, accumulate,

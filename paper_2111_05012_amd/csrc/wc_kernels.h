@@ -96,15 +96,20 @@ inline CGeo make_cgeo(const int* n) {
 // r*out_rs + X*out_xs + n.  acc64: accumulate in FP64.
 // tile: sites per LDS tile (0: largest that fits 48 KiB; else a power of two dividing Vb);
 // RESTRICT_MFMA64: FP64 matrix-core path (FP64 output, equal FP64 or FP32 operands,
-// nv, nrhs <= 32)
+// nv, nrhs <= 32); RESTRICT_MFMA32: FP32 matrix-core path (FP16 vectors, FP32 or
+// FP16 input, FP32 output, nv, nrhs <= 32)
 constexpr int RESTRICT_MFMA64 = -64;
+constexpr int RESTRICT_MFMA32 = -32;
 void launch_restrict(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* in, int in_t,
                      size_t in_rs, void* out, int out_t, size_t out_rs, size_t out_xs, int acc64,
                      hipStream_t st, int tile = 0);
 // prolongation eq.(6): out_r(y,a) (+)= sum_i V_i(y,a) xc[r][X(y)][s(a)*nv+i]
+// variant: 0 the default kernel for the types; PROLONG_MFMA32 the FP32 matrix-core
+// path (FP16 or FP32 vectors, FP32 coefficients and output, nv, nrhs <= 32)
+constexpr int PROLONG_MFMA32 = -32;
 void launch_prolong(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* xc, int xc_t,
                     size_t xc_rs, size_t xc_xs, void* out, int out_t, size_t out_rs, int accumulate,
-                    int compute32, hipStream_t st);
+                    int compute32, hipStream_t st, int variant = 0);
 // coarse 9-point stencil: y[r][X] = sum_d Dc[X][d] x[r][X+e_d]   (or y = b - Dc x)
 // Dc stored [X][d][m][n] (column-major blocks), vectors [nrhs][NC][N]
 // variant: right-hand sides per thread (0: automatic; else 1, 4, 8, 12 or 16), or

@@ -125,6 +125,49 @@ def test_restrict_prolong_fp64(prob):
     assert rel(prob.N(y), amg.prolong(V, yc, prob.dims, prob.block)) < 1e-13
 
 
+@pytest.mark.parametrize('nrhs', [3, 20])
+def test_restrict_prolong_mixed_every_variant(prob, nrhs, tmp_path):
+    """Mixed-precision restriction and prolongation (FP16 vectors, FP32
+    arithmetic) in every launch variant: the vector-ALU kernels with each
+    site tile and the FP32 matrix-core kernels (20 right-hand sides take two
+    column tiles of the stacked real and imaginary parts), forced through the
+    tuner's cache file, against the oracle with the same FP16-rounded
+    vectors."""
+    import json
+    from paper_2111_05012_amd import PREC_MIXED
+    nv = 12
+    cache = str(tmp_path / 'tune.json')
+    prob.ctx.autotune(True, cache)
+    V = _hier(prob, nv=nv, prec=PREC_MIXED)
+    V16 = V.real.astype(np.float16).astype(np.float64) + 1j * V.imag.astype(np.float16).astype(np.float64)
+    nX = amg.n_blocks(prob.dims, prob.block)
+    x = syn.gaussian_vectors(prob.dims, nrhs, 18)
+    yc = syn.gaussian_coarse(nX, 2 * nv, nrhs, 19)
+    want_r = amg.restrict(V16, x, prob.dims, prob.block)
+    want_p = amg.prolong(V16, yc, prob.dims, prob.block)
+    xc = prob.zeros((nrhs, nX, 2 * nv))
+    y = prob.zeros(x.shape)
+    prob.ctx.restrict(prob.T(x), xc, nrhs)  # tunes and writes the cache
+    prob.ctx.prolong(prob.T(yc), y, nrhs)
+    keys = json.load(open(cache))
+    assert any(k.split('|')[1] == 'restrict' for k in keys) and any(k.split('|')[1] == 'prolong' for k in keys)
+    for kind, variants in (('restrict', (4, 8, 16, 32, -32)), ('prolong', (0, -32))):
+        for v in variants:
+            forced = {k: (v if k.split('|')[1] == kind else val) for k, val in keys.items()}
+            with open(cache, 'w') as f:
+                json.dump(forced, f)
+            prob.ctx.autotune(True, cache)
+            if kind == 'restrict':
+                xc = prob.zeros((nrhs, nX, 2 * nv))
+                prob.ctx.restrict(prob.T(x), xc, nrhs)
+                assert rel(prob.N(xc), want_r) < 2e-5, (kind, v)
+            else:
+                y = prob.zeros(x.shape)
+                prob.ctx.prolong(prob.T(yc), y, nrhs)
+                assert rel(prob.N(y), want_p) < 2e-5, (kind, v)
+    prob.ctx.autotune(False, None)
+
+
 def test_coarse_operator_fp64(prob):
     V = _hier(prob)
     nX = amg.n_blocks(prob.dims, prob.block)
