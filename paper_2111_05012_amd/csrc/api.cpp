@@ -577,6 +577,7 @@ struct wcamg_ctx {
     if (cands.empty()) cands.push_back(0);
     if (h.prec == WCAMG_PREC_FP64 && h.nv <= 32 && nrhs <= 32) cands.push_back(RESTRICT_MFMA64);
     if (h.prec == WCAMG_PREC_MIXED && h.nv <= 32 && nrhs <= 32) cands.push_back(RESTRICT_MFMA32);
+    if (h.prec == WCAMG_PREC_MIXED && h.nv <= 32 && nrhs <= 32 && g.Vb % 32 == 0) cands.push_back(RESTRICT_MFMA32D);
     int tile = tune(key, cands, [&](int v) {
       launch_restrict(g, h.nv, nrhs, h.V.p, vec_t(), in, spin_t(h.prec), frs(), out, crs_t(), crs_n(), h.N, 0, st,
                       v);
@@ -725,11 +726,13 @@ struct wcamg_ctx {
     int* bad = (int*)W("or_bad", sizeof(int));
     launch_zero(bad, sizeof(int), st);
     size_t grs = (size_t)g.nblk * 2 * nv;
+    // pass 0: Vw -> tmp, pass 1: tmp -> Vw (no copies)
     for (int pass = 0; pass < 2; ++pass) {
-      launch_restrict(g, nv, nv, Vw, t, Vw, t, frs(), G, C128, grs, 2 * nv, 1, st, nv <= 32 ? RESTRICT_MFMA64 : 0);
+      void* src = pass == 0 ? Vw : tmp;
+      void* dst = pass == 0 ? tmp : Vw;
+      launch_restrict(g, nv, nv, src, t, src, t, frs(), G, C128, grs, 2 * nv, 1, st, nv <= 32 ? RESTRICT_MFMA64 : 0);
       launch_cholesky_coef(g.nblk, nv, G, grs, coef, t, grs, bad, st);
-      launch_prolong(g, nv, nv, Vw, t, coef, t, grs, 2 * nv, tmp, t, frs(), 0, prec == WCAMG_PREC_MIXED, st);
-      HIPCHK(hipMemcpyAsync(Vw, tmp, fsz(nv, prec), hipMemcpyDeviceToDevice, st));
+      launch_prolong(g, nv, nv, src, t, coef, t, grs, 2 * nv, dst, t, frs(), 0, prec == WCAMG_PREC_MIXED, st);
     }
     int hb = 0;
     HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -215,41 +215,59 @@ __global__ __launch_bounds__(256) void k_restrict_mf32(Geo g, int nv, int nrhs, 
   for (int e = t; e < KC * 65; e += 256) (&sb[0][0])[e] = 0.f;  // columns >= 2 nrhs stay zero
   for (int e = t; e < 2 * KC * 33; e += 256) lds_r[e] = 0.f;     // vectors i >= nv stay zero
   __syncthreads();
-  for (int a6 = 0; a6 < 6; ++a6) {
+  // stages (component a6, sites l0 .. l0 + KC - 1); the global loads of the
+  // next stage are issued before the products of the current one
+  const int nl = (g.Vb + KC - 1) / KC, nst = 6 * nl;
+  constexpr int PV = 32 * KC / 256, PX = 32 * KC / 256;  // loads per thread (nv, nrhs <= 32)
+  cplx<float> pv[PV], px[PX];
+  auto fetch = [&](int st_) {
+    const int a6 = st_ / nl, l0 = (st_ - a6 * nl) * KC;
     const size_t pl = base + (size_t)(6 * s + a6) * g.Vb;
-    for (int l0 = 0; l0 < g.Vb; l0 += KC) {
-      for (int e = t; e < nv * KC; e += 256) {
-        const int c = e / KC, kk = e - c * KC;
-        const int loc = l0 + kk;
-        cplx<float> v = {0, 0};
-        if (loc < g.Vb) v = ld<float>(V, (size_t)c * 12 * g.V + pl + loc);
-        svr[kk][c] = v.x;
-        svi[kk][c] = v.y;
-      }
-      for (int e = t; e < nrhs * KC; e += 256) {
-        const int c = e / KC, kk = e - c * KC;
-        const int loc = l0 + kk;
-        cplx<float> x = {0, 0};
-        if (loc < g.Vb) x = ld<float>(in, (size_t)c * in_rs + pl + loc);
-        sb[kk][c] = x.x;
-        sb[kk][nrhs + c] = x.y;
-      }
-      __syncthreads();
-#pragma unroll 2
-      for (int kp = w; kp < KC / 2; kp += 4) {
-        const int k = 2 * kp + (lane >> 5), c = lane & 31;
-        const float ar = svr[k][c], ai = svi[k][c];
-        const float b0 = sb[k][c];
-        tr0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b0, tr0, 0, 0, 0);
-        ti0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b0, ti0, 0, 0, 0);
-        if (nct == 2) {
-          const float b1 = sb[k][32 + c];
-          tr1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b1, tr1, 0, 0, 0);
-          ti1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b1, ti1, 0, 0, 0);
-        }
-      }
-      __syncthreads();
+#pragma unroll
+    for (int m = 0; m < PV; ++m) {
+      const int e = t + 256 * m, c = e / KC, loc = l0 + (e - c * KC);
+      pv[m] = (c < nv && loc < g.Vb) ? ld<float>(V, (size_t)c * 12 * g.V + pl + loc) : cplx<float>{0, 0};
     }
+#pragma unroll
+    for (int m = 0; m < PX; ++m) {
+      const int e = t + 256 * m, c = e / KC, loc = l0 + (e - c * KC);
+      px[m] = (c < nrhs && loc < g.Vb) ? ld<float>(in, (size_t)c * in_rs + pl + loc) : cplx<float>{0, 0};
+    }
+  };
+  fetch(0);
+  for (int st_ = 0; st_ < nst; ++st_) {
+#pragma unroll
+    for (int m = 0; m < PV; ++m) {
+      const int e = t + 256 * m, c = e / KC, kk = e - c * KC;
+      if (c < nv) {
+        svr[kk][c] = pv[m].x;
+        svi[kk][c] = pv[m].y;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < PX; ++m) {
+      const int e = t + 256 * m, c = e / KC, kk = e - c * KC;
+      if (c < nrhs) {
+        sb[kk][c] = px[m].x;
+        sb[kk][nrhs + c] = px[m].y;
+      }
+    }
+    __syncthreads();
+    if (st_ + 1 < nst) fetch(st_ + 1);
+#pragma unroll 2
+    for (int kp = w; kp < KC / 2; kp += 4) {
+      const int k = 2 * kp + (lane >> 5), c = lane & 31;
+      const float ar = svr[k][c], ai = svi[k][c];
+      const float b0 = sb[k][c];
+      tr0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b0, tr0, 0, 0, 0);
+      ti0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b0, ti0, 0, 0, 0);
+      if (nct == 2) {
+        const float b1 = sb[k][32 + c];
+        tr1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b1, tr1, 0, 0, 0);
+        ti1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b1, ti1, 0, 0, 0);
+      }
+    }
+    __syncthreads();
   }
   // partial tiles of the four wavefronts: red[w][m][row][col], m = (T_r, T_i)
   // for columns 0..31 and, with two column tiles, 32..63
@@ -264,6 +282,91 @@ __global__ __launch_bounds__(256) void k_restrict_mf32(Geo g, int nv, int nrhs, 
     if (nct == 2) {
       red[w * wstride + (0 * 32 + row) * ncol + 32 + col] = tr1[q];
       red[w * wstride + (1 * 32 + row) * ncol + 32 + col] = ti1[q];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < nv * nrhs; e += 256) {
+    const int i = e / nrhs, r = e - i * nrhs;
+    float re = 0.f, im = 0.f;
+    for (int ww = 0; ww < 4; ++ww) {
+      const float* R = red + ww * wstride;
+      re += R[(0 * 32 + i) * ncol + r] + R[(1 * 32 + i) * ncol + nrhs + r];
+      im += R[(0 * 32 + i) * ncol + nrhs + r] - R[(1 * 32 + i) * ncol + r];
+    }
+    out[(size_t)r * out_rs + (size_t)X * out_xs + s * nv + i] = make_float2(re, im);
+  }
+}
+
+// Register-operand variant of k_restrict_mf32 for Vb a multiple of 32: no
+// staging.  The k index of the products is (component, site) as before but
+// assigned so that every lane walks consecutive sites: for component a and
+// wavefront w, lane half h takes sites w Vb / 4 + h Vb / 8 + j at step j, and
+// loads 4 consecutive sites of its vector (16 bytes) or right-hand side per
+// load.  Lane l supplies A = v_{l % 32} and B = column l % 32 of [xr | xi].
+// The four wavefronts' partial tiles are summed in LDS in a fixed order.
+template <class TI>
+__global__ __launch_bounds__(256) void k_restrict_mf32d(Geo g, int nv, int nrhs, const half2_t* __restrict__ V,
+                                                        const TI* __restrict__ in, size_t in_rs,
+                                                        float2* __restrict__ out, size_t out_rs, size_t out_xs) {
+  extern __shared__ __align__(16) float lds_d[];
+  const int nlog = g.nblk * 2;
+  const int lg = xcd_remap(blockIdx.x, nlog);
+  if (lg >= nlog) return;
+  const int X = lg >> 1, s = lg & 1;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int c = lane & 31, h = lane >> 5;
+  const int nct = 2 * nrhs > 32 ? 2 : 1;
+  const int q8 = g.Vb >> 3;  // sites per lane half and wavefront
+  const bool va = c < nv;
+  // column c (and 32 + c) of B: real (c < nrhs) or imaginary part of rhs c mod nrhs
+  const int r0 = c < nrhs ? c : c - nrhs, r1 = 32 + c < 2 * nrhs ? 32 + c - nrhs : 0;
+  const bool b0ok = c < 2 * nrhs, b0im = c >= nrhs;
+  const bool b1ok = 32 + c < 2 * nrhs;
+  f32x16 tr0, ti0, tr1, ti1;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tr0[q] = ti0[q] = tr1[q] = ti1[q] = 0.f;
+  const size_t base = (size_t)X * 12 * g.Vb;
+  const int site0 = w * 2 * q8 + h * q8;
+  for (int a6 = 0; a6 < 6; ++a6) {
+    const size_t pl = base + (size_t)(6 * s + a6) * g.Vb + site0;
+    const half2_t* vp = V + (size_t)(va ? c : 0) * 12 * g.V + pl;
+    const TI* ip0 = in + (size_t)r0 * in_rs + pl;
+    const TI* ip1 = in + (size_t)r1 * in_rs + pl;
+    for (int j = 0; j < q8; j += 4) {
+      half2_t v4[4];
+      const uint4 raw = *(const uint4*)(vp + j);  // 16-byte aligned: Vb % 32 == 0
+      __builtin_memcpy(v4, &raw, sizeof(raw));
+      cplx<float> x0[4], x1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x0[u] = b0ok ? ld<float>(ip0, j + u) : cplx<float>{0, 0};
+        x1[u] = (nct == 2 && b1ok) ? ld<float>(ip1, j + u) : cplx<float>{0, 0};
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float ar = va ? (float)v4[u].x : 0.f, ai = va ? (float)v4[u].y : 0.f;
+        const float b0 = b0im ? x0[u].y : x0[u].x;
+        tr0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b0, tr0, 0, 0, 0);
+        ti0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b0, ti0, 0, 0, 0);
+        if (nct == 2) {
+          const float b1 = x1[u].y;  // columns 32.. are imaginary parts
+          tr1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b1, tr1, 0, 0, 0);
+          ti1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b1, ti1, 0, 0, 0);
+        }
+      }
+    }
+  }
+  float* red = lds_d;
+  const int ncol = 32 * nct;
+  const size_t wstride = (size_t)2 * 32 * ncol;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int row = 8 * (q >> 2) + 4 * h + (q & 3);
+    red[w * wstride + (0 * 32 + row) * ncol + c] = tr0[q];
+    red[w * wstride + (1 * 32 + row) * ncol + c] = ti0[q];
+    if (nct == 2) {
+      red[w * wstride + (0 * 32 + row) * ncol + 32 + c] = tr1[q];
+      red[w * wstride + (1 * 32 + row) * ncol + 32 + c] = ti1[q];
     }
   }
   __syncthreads();
@@ -299,6 +402,29 @@ void launch_restrict(const Geo& g, int nv, int nrhs, const void* V, int v_t, con
     else
       k_restrict_mf64<float2><<<grid, 256, 0, st>>>(g, nv, nrhs, (const float2*)V, (const float2*)in, in_rs,
                                                     (double2*)out, out_rs, out_xs);
+    return;
+  }
+  if (tile == RESTRICT_MFMA32D) {
+    if (nv > 32 || nrhs > 32 || out_t != C64 || acc64 || v_t != C32H || (in_t != C64 && in_t != C32H) ||
+        g.Vb % 32 != 0)
+      throw std::runtime_error("launch_restrict: the register-operand matrix-core path needs FP16 vectors, FP32 or "
+                               "FP16 inputs, FP32 output, nv, nrhs <= 32 and a block volume divisible by 32");
+    const dim3 grid(round8(g.nblk * 2));
+    const int lds = 4 * 2 * 32 * (2 * nrhs > 32 ? 64 : 32) * 4;
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void*)k_restrict_mf32d<float2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                64 * 1024);
+      (void)hipFuncSetAttribute((const void*)k_restrict_mf32d<half2_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                64 * 1024);
+      attr = true;
+    }
+    if (in_t == C64)
+      k_restrict_mf32d<float2><<<grid, 256, lds, st>>>(g, nv, nrhs, (const half2_t*)V, (const float2*)in, in_rs,
+                                                       (float2*)out, out_rs, out_xs);
+    else
+      k_restrict_mf32d<half2_t><<<grid, 256, lds, st>>>(g, nv, nrhs, (const half2_t*)V, (const half2_t*)in, in_rs,
+                                                        (float2*)out, out_rs, out_xs);
     return;
   }
   if (tile == RESTRICT_MFMA32) {
@@ -442,7 +568,23 @@ __global__ __launch_bounds__(256) void k_prolong_mf(Geo g, int nv, int nrhs, con
   }
   const int nst = (g.Vb + 31) / 32;  // site tiles per component plane
   const size_t base = (size_t)X * 12 * g.Vb;
-  for (int tl = w; tl < 6 * nst; tl += 4) {
+  // tiles of 32 sites of one component plane, every fourth to this wavefront;
+  // the vectors of the next tile are loaded before the products of this one
+  const int ntl = 6 * nst;
+  TV vb[16], vn[16];
+  auto fetch = [&](int tl, TV (&dst)[16]) {
+    const int a = 6 * s + tl / nst;
+    const int loc = (tl % nst) * 32 + lr;
+    const size_t o = base + (size_t)a * g.Vb + (loc < g.Vb ? loc : 0);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int i = 2 * q + lh;
+      dst[q] = V[(size_t)(i < nv ? i : 0) * 12 * g.V + o];
+    }
+  };
+  if (w < ntl) fetch(w, vb);
+  for (int tl = w; tl < ntl; tl += 4) {
+    if (tl + 4 < ntl) fetch(tl + 4, vn);
     const int a = 6 * s + tl / nst;
     const int loc = (tl % nst) * 32 + lr;
     const bool in = loc < g.Vb;
@@ -454,7 +596,7 @@ __global__ __launch_bounds__(256) void k_prolong_mf(Geo g, int nv, int nrhs, con
     for (int q = 0; q < 16; ++q) {
       const int i = 2 * q + lh;
       cplx<float> v = {0, 0};
-      if (in && i < nv) v = ld<float>(V, (size_t)i * 12 * g.V + o);
+      if (in && i < nv) v = ld<float>(vb, q);
       re = __builtin_amdgcn_mfma_f32_32x32x2f32(cr[q], v.x, re, 0, 0, 0);
       re = __builtin_amdgcn_mfma_f32_32x32x2f32(-ci[q], v.y, re, 0, 0, 0);
       im = __builtin_amdgcn_mfma_f32_32x32x2f32(cr[q], v.y, im, 0, 0, 0);
@@ -472,6 +614,8 @@ __global__ __launch_bounds__(256) void k_prolong_mf(Geo g, int nv, int nrhs, con
         }
       }
     }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) vb[q] = vn[q];
   }
 }
 

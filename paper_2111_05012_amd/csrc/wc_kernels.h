@@ -98,8 +98,11 @@ inline CGeo make_cgeo(const int* n) {
 // RESTRICT_MFMA64: FP64 matrix-core path (FP64 output, equal FP64 or FP32 operands,
 // nv, nrhs <= 32); RESTRICT_MFMA32: FP32 matrix-core path (FP16 vectors, FP32 or
 // FP16 input, FP32 output, nv, nrhs <= 32)
+// RESTRICT_MFMA32D: as RESTRICT_MFMA32 with register operands (no LDS staging),
+// block volume divisible by 32
 constexpr int RESTRICT_MFMA64 = -64;
 constexpr int RESTRICT_MFMA32 = -32;
+constexpr int RESTRICT_MFMA32D = -33;
 void launch_restrict(const Geo& g, int nv, int nrhs, const void* V, int v_t, const void* in, int in_t,
                      size_t in_rs, void* out, int out_t, size_t out_rs, size_t out_xs, int acc64,
                      hipStream_t st, int tile = 0);

@@ -129,9 +129,10 @@ def test_restrict_prolong_fp64(prob):
 def test_restrict_prolong_mixed_every_variant(prob, nrhs, tmp_path):
     """Mixed-precision restriction and prolongation (FP16 vectors, FP32
     arithmetic) in every launch variant: the vector-ALU kernels with each
-    site tile and the FP32 matrix-core kernels (20 right-hand sides take two
-    column tiles of the stacked real and imaginary parts), forced through the
-    tuner's cache file, against the oracle with the same FP16-rounded
+    site tile and the FP32 matrix-core kernels, staged through LDS or (block
+    volume divisible by 32) with register operands (20 right-hand sides take
+    two column tiles of the stacked real and imaginary parts), forced through
+    the tuner's cache file, against the oracle with the same FP16-rounded
     vectors."""
     import json
     from paper_2111_05012_amd import PREC_MIXED
@@ -151,7 +152,9 @@ def test_restrict_prolong_mixed_every_variant(prob, nrhs, tmp_path):
     prob.ctx.prolong(prob.T(yc), y, nrhs)
     keys = json.load(open(cache))
     assert any(k.split('|')[1] == 'restrict' for k in keys) and any(k.split('|')[1] == 'prolong' for k in keys)
-    for kind, variants in (('restrict', (4, 8, 16, 32, -32)), ('prolong', (0, -32))):
+    vb = int(np.prod(prob.block))
+    rvars = (4, 8, 16, 32, -32) + ((-33,) if vb % 32 == 0 else ())
+    for kind, variants in (('restrict', rvars), ('prolong', (0, -32))):
         for v in variants:
             forced = {k: (v if k.split('|')[1] == kind else val) for k, val in keys.items()}
             with open(cache, 'w') as f:
