@@ -27,8 +27,8 @@ FP64_PEAK_TFLOPS = 78.6
 
 # roofline of each kernel class: what bounds it, and its work unit for the
 # counter-based traffic (profiles/pmc_traffic.json, per unit of work)
-CLASS_BOUND = {'sap_half': 'alu32', 'coarse_mv': 'alu32', 'dslash64': 'hbm', 'dslash32': 'hbm', 'restrict': 'hbm',
-               'prolong': 'hbm', 'coarse_build': 'alu32', 'ortho': 'hbm'}
+CLASS_BOUND = {'sap_half': 'alu32', 'sap_cross': 'hbm', 'coarse_mv': 'alu32', 'dslash64': 'hbm', 'dslash32': 'hbm',
+               'restrict': 'hbm', 'prolong': 'hbm', 'coarse_build': 'alu32', 'ortho': 'hbm'}
 CLASS_SOURCES = {'sap_half': ['fine.hip', 'wc_dirac.h', 'wc_common.h'],
                  'dslash64': ['fine.hip', 'wc_dirac.h', 'wc_common.h']}
 
@@ -74,9 +74,9 @@ def run_step(ctx, U, b, x, V0, w, prec, rhs_chunk=0, nrhs=None):
     return t1 - t0, t2 - t1, info, rc
 
 
-CLASSES = ['dslash64', 'dslash32', 'sap_half', 'restrict', 'prolong', 'coarse_solve', 'coarse_mv', 'coarse_build',
-           'ortho']
-LEAVES = ['dslash64', 'dslash32', 'sap_half', 'restrict', 'prolong', 'coarse_mv', 'coarse_build', 'ortho']
+CLASSES = ['dslash64', 'dslash32', 'sap_half', 'sap_cross', 'restrict', 'prolong', 'coarse_solve', 'coarse_mv',
+           'coarse_build', 'ortho']
+LEAVES = ['dslash64', 'dslash32', 'sap_half', 'sap_cross', 'restrict', 'prolong', 'coarse_mv', 'coarse_build', 'ortho']
 
 
 def source_sha(files):
@@ -295,7 +295,7 @@ def main():
     for L in w['dims']:
         V *= L
     # units of the class per launch: RHS x sites (half the lattice for a SAP half-sweep)
-    units = d['units'] / nl * (V / 2 if dom == 'sap_half' else V)
+    units = d['units'] / nl * (V / 2 if dom in ('sap_half', 'sap_cross') else V)
     traffic = counter_traffic(dom, units)
     if CLASS_BOUND.get(dom, 'hbm') == 'hbm':
         achieved = d['bytes'] / (d['ms'] * 1e-3) / 1e9

@@ -553,8 +553,19 @@ struct wcamg_ctx {
     for (int sw = 0; sw < sweeps; ++sw)
       for (int col = 0; col < 2; ++col) {
         double xr = (sw > 0 || xinit) ? 1 : 0;
+        if (sap_needs_cross(a, sw, col)) {
+          // per site of the active colour and RHS: r in and out, the other
+          // colour's corrections at the crossing neighbours (sum over the
+          // directions of 2 / B_mu: 1.75 for 4^3x8 domains), ~240 flop each
+          double nc = 0;
+          for (int m = 0; m < 4; ++m) nc += 2.0 / g.B[m];
+          double byc = 0.5 * g.V * (nc * 36.0 + nrhs * 12.0 * sb * (2.0 + nc));
+          double flc = 0.5 * g.V * nrhs * nc * 240.0;
+          Timed t(this, "sap_cross", byc, flc, nrhs);
+          launch_sap_cross(a, sw, col, st);
+        }
         double by = 0.5 * g.V * (fld + nrhs * 12.0 * sb * (4.0 + xr));
-        double fl = 0.5 * g.V * nrhs * (mr * 2200.0 + 400.0);
+        double fl = 0.5 * g.V * nrhs * (mr * 2200.0 + (a.mixed ? 0.0 : 400.0));
         Timed t(this, "sap_half", by, fl, nrhs);
         launch_sap_half(a, sw, col, st);
       }

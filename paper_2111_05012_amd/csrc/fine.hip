@@ -1172,6 +1172,16 @@ static void sap_half_run(const SapArgs& a, int col, int flags, hipStream_t st) {
                                 (TS*)a.delta, (const TS*)a.xinit, a.rs, (const TL*)a.U, (const TC*)a.C);
 }
 
+bool sap_needs_cross(const SapArgs& a, int sweep, int col) { return a.mixed && (sweep > 0 || col == 1); }
+
+void launch_sap_cross(const SapArgs& a, int sweep, int col, hipStream_t st) {
+  if (!sap_needs_cross(a, sweep, col)) return;
+  const size_t nsite = (size_t)(a.g.nblk / 2) * a.g.Vb;
+  k_sap_cross<<<dim3((unsigned)((nsite + 255) / 256), a.nrhs), 256, 0, st>>>(
+      a.g, col, sweep == 0 ? 1 : 0, (float)a.kappa, (const float2*)a.b, (float2*)a.r, (const float2*)a.delta, a.rs,
+      (const half2_t*)a.U);
+}
+
 void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st) {
   int flags = (sweep == 0 ? SAP_FIRST : 0) | ((sweep > 0 || col == 1) ? SAP_DELTA : 0);
   if (!a.mixed) return sap_half_run<double, double2, double2, double2>(a, col, flags, st);
@@ -1179,15 +1189,9 @@ void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st) {
   // half-sweep's correction is never read either
   if (sweep == a.sweeps - 1) flags |= SAP_NO_R;
   if (sweep == a.sweeps - 1 && col == 1) flags |= SAP_NO_DELTA;
-  if (flags & SAP_DELTA) {
-    // the crossing-hop correction first, in a launch of its own; the domain
-    // solves then start from r
-    const size_t nsite = (size_t)(a.g.nblk / 2) * a.g.Vb;
-    k_sap_cross<<<dim3((unsigned)((nsite + 255) / 256), a.nrhs), 256, 0, st>>>(
-        a.g, col, (flags & SAP_FIRST) ? 1 : 0, (float)a.kappa, (const float2*)a.b, (float2*)a.r,
-        (const float2*)a.delta, a.rs, (const half2_t*)a.U);
-    flags = (flags & ~SAP_DELTA) | SAP_R_IN;
-  }
+  // the crossing-hop correction has been applied by launch_sap_cross; the
+  // domain solves start from r
+  if (flags & SAP_DELTA) flags = (flags & ~SAP_DELTA) | SAP_R_IN;
   const Geo& g = a.g;
   int nthr = ((g.Vb + 63) / 64) * 64;
   int lds = sap_dom_lds_bytes(g);

@@ -71,7 +71,11 @@ struct SapArgs {
   const void* U = nullptr;
   const void* C = nullptr;
 };
-// one half-sweep (colour col of sweep `sweep`) of the SAP listing
+// one half-sweep (colour col of sweep `sweep`) of the SAP listing.  Mixed
+// precision: launch_sap_cross (the crossing-hop correction of the residual,
+// when sap_needs_cross) must precede launch_sap_half on the same stream.
+bool sap_needs_cross(const SapArgs& a, int sweep, int col);
+void launch_sap_cross(const SapArgs& a, int sweep, int col, hipStream_t st);
 void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st);
 int sap_lds_bytes(const Geo& g, int mixed);  // FP64 path
 int sap_dom_lds_bytes(const Geo& g);          // mixed path
