@@ -235,12 +235,15 @@ int wcamg_net_train_step(wcamg_ctx* ctx, const void* r, const void* teacher, dou
 
 /* Launch-variant autotuner (on by default): the first time a kernel is
  * launched for a new key (kernel, shapes, precision, GPU architecture) each
- * candidate variant (Dslash workgroup size, coarse-matvec right-hand sides per
- * thread, restriction tile) is timed with HIP events on the real operands and
- * the fastest is kept; variants never change results.  cache_path (or the
- * environment variable WCAMG_AUTOTUNE_CACHE at create time) names a flat
- * JSON file {"key": variant} that is read now and rewritten after each newly
- * tuned key; NULL keeps the current file. */
+ * candidate variant (Dslash workgroup size or tiling, coarse-matvec right-hand
+ * sides per thread or matrix cores, restriction and prolongation kernel,
+ * coarse-operator contraction) is timed with HIP events on the real operands
+ * and the fastest is kept.  Variants compute the same quantities in the same
+ * precision; results may differ by rounding (summation order).  cache_path
+ * (or the environment variable WCAMG_AUTOTUNE_CACHE at create time) names a
+ * flat JSON file {"key": variant}: its entries are merged into the table now
+ * (they override known keys), the merged table is written back at once and
+ * again after each newly tuned key; NULL keeps the current file. */
 int wcamg_autotune(wcamg_ctx* ctx, int enable, const char* cache_path);
 /* Time spent tuning (ms, not part of any solve), keys tuned by this context
  * and keys known (tuned or loaded). Pointers may be NULL. */

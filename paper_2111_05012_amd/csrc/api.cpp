@@ -171,8 +171,14 @@ struct Tuner {
   double tune_ms = 0;
   int tuned = 0;
 
+  // merge the entries of the cache file p (if any) into the table, then
+  // write the merged table back: the file always lists every known key
   void load(const std::string& p) {
     path = p;
+    read(p);
+    save();
+  }
+  void read(const std::string& p) {
     std::ifstream f(p);
     if (!f) return;
     std::stringstream ss;
