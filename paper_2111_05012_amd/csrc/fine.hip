@@ -15,6 +15,19 @@
 
 namespace wc {
 
+// Logical (tile, right-hand-side group) of a workgroup in a 1-D grid of
+// round8(ntile * ng) workgroups, the groups fastest: the groups of one tile
+// are consecutive on one XCD, so the tile's links and clover are read from
+// memory once and then from that XCD's L2.  False for the padding workgroups.
+__device__ __forceinline__ bool tile_rhs(int ntile, int ng, int& tile, int& rg) {
+  const int n = ntile * ng;
+  const int L = xcd_remap(blockIdx.x, n);
+  if (L >= n) return false;
+  tile = L / ng;
+  rg = L - tile * ng;
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // Layout conversion
 // ---------------------------------------------------------------------------
@@ -250,14 +263,13 @@ __global__ __launch_bounds__(128) void k_clover_build(Geo g, const double2* __re
 template <class R, class TI, class TO, class TL, class TC, int OP>
 __global__ __launch_bounds__(512) void k_dslash(Geo g, const TI* __restrict__ in, size_t in_rs, TO* __restrict__ out,
                                                 size_t out_rs, const TO* __restrict__ b, const TL* __restrict__ U,
-                                                const TC* __restrict__ C, R kappa, int hopdir, int chir) {
+                                                const TC* __restrict__ C, R kappa, int hopdir, int chir, int ng) {
   const int bs = blockDim.x;
   int ntile = (g.V + bs - 1) / bs;
-  int tile = xcd_remap(blockIdx.x, ntile);
-  if (tile >= ntile) return;
+  int tile, r;
+  if (!tile_rhs(ntile, ng, tile, r)) return;
   int s = tile * bs + threadIdx.x;
   if (s >= g.V) return;
-  int r = blockIdx.y;
   const TI* inr = in + r * in_rs;
   SiteCoord c = decompose(g, s);
   const int ps = g.Vb;
@@ -353,14 +365,14 @@ __device__ __forceinline__ void hop_row_acc(const cplx<R> (&psi)[12], const cplx
 template <class R, class TI, class TO, class TL, class TC>
 __global__ __launch_bounds__(192) void k_dslash_cs(Geo g, const TI* __restrict__ in, size_t in_rs,
                                                    TO* __restrict__ out, size_t out_rs, const TO* __restrict__ b,
-                                                   const TL* __restrict__ U, const TC* __restrict__ C, R kappa) {
+                                                   const TL* __restrict__ U, const TC* __restrict__ C, R kappa,
+                                                   int ng) {
   const int ntile = (g.V + 63) >> 6;
-  const int tile = xcd_remap(blockIdx.x, ntile);
-  if (tile >= ntile) return;
+  int tile, rh;
+  if (!tile_rhs(ntile, ng, tile, rh)) return;
   const int r = threadIdx.x >> 6;  // colour row of this wavefront
   const int s = tile * 64 + (threadIdx.x & 63);
   if (s >= g.V) return;
-  const int rh = blockIdx.y;
   const TI* inr = in + rh * in_rs;
   SiteCoord c = decompose(g, s);
   const int ps = g.Vb;
@@ -441,11 +453,11 @@ __global__ __launch_bounds__(256) void k_dslash_nr(Geo g, int nrhs, const TI* __
                                                    TO* __restrict__ out, size_t out_rs, const TO* __restrict__ b,
                                                    const TL* __restrict__ U, const TC* __restrict__ C, R kappa) {
   const int ntile = (g.V + 255) >> 8;
-  const int tile = xcd_remap(blockIdx.x, ntile);
-  if (tile >= ntile) return;
+  int tile, rg;
+  if (!tile_rhs(ntile, (nrhs + NR - 1) / NR, tile, rg)) return;
   const int s = tile * 256 + threadIdx.x;
   if (s >= g.V) return;
-  const int r0 = blockIdx.y * NR;
+  const int r0 = rg * NR;
   const SiteCoord c = decompose(g, s);
   const int ps = g.Vb;
   const size_t fb12 = fbase_b(g, 12, s, c.blk), fb36 = fbase_b(g, 36, s, c.blk);
@@ -507,19 +519,19 @@ __global__ __launch_bounds__(256) void k_dslash_nr(Geo g, int nrhs, const TI* __
 template <class R, class TI, class TO, class TL, class TC>
 __global__ __launch_bounds__(256) void k_dslash_lds(Geo g, int tt, const TI* __restrict__ in, size_t in_rs,
                                                     TO* __restrict__ out, size_t out_rs, const TO* __restrict__ b,
-                                                    const TL* __restrict__ U, const TC* __restrict__ C, R kappa) {
+                                                    const TL* __restrict__ U, const TC* __restrict__ C, R kappa,
+                                                    int ng) {
   extern __shared__ __align__(16) char smem[];
   cplx<R>* sp = (cplx<R>*)smem;  // [12][TS]
   const int TS = blockDim.x;
   const int per_blk = g.B[3] / tt;
   const int ntile = g.nblk * per_blk;
-  const int tile = xcd_remap(blockIdx.x, ntile);
-  if (tile >= ntile) return;  // whole workgroup: no barrier is left waiting
+  int tile, rh;
+  if (!tile_rhs(ntile, ng, tile, rh)) return;  // whole workgroup: no barrier is left waiting
   const int blk = tile / per_blk, tb = tile - blk * per_blk;
   const int loc0 = tb * TS;
   const int l = threadIdx.x;
   const int s = blk * g.Vb + loc0 + l;
-  const int rh = blockIdx.y;
   const TI* inr = in + rh * in_rs;
   const SiteCoord c = decompose(g, s);
   const int ps = g.Vb;
@@ -581,20 +593,20 @@ __global__ __launch_bounds__(256) void k_dslash_lds(Geo g, int tt, const TI* __r
 template <class R, class TI, class TO, class TL, class TC>
 __global__ __launch_bounds__(256) void k_dslash_hx(Geo g, int tt, const TI* __restrict__ in, size_t in_rs,
                                                    TO* __restrict__ out, size_t out_rs, const TO* __restrict__ b,
-                                                   const TL* __restrict__ U, const TC* __restrict__ C, R kappa) {
+                                                   const TL* __restrict__ U, const TC* __restrict__ C, R kappa,
+                                                    int ng) {
   extern __shared__ __align__(16) char smem[];
   const int TS = blockDim.x;
   cplx<R>* sp = (cplx<R>*)smem;  // [12][TS] input spinors of the tile
   cplx<R>* hx = sp + 12 * TS;     // [6][TS] backward half-spinors by receiving site
   const int per_blk = g.B[3] / tt;
   const int ntile = g.nblk * per_blk;
-  const int tile = xcd_remap(blockIdx.x, ntile);
-  if (tile >= ntile) return;  // whole workgroup: no barrier is left waiting
+  int tile, rh;
+  if (!tile_rhs(ntile, ng, tile, rh)) return;  // whole workgroup: no barrier is left waiting
   const int blk = tile / per_blk, tb = tile - blk * per_blk;
   const int loc0 = tb * TS;
   const int l = threadIdx.x;
   const int s = blk * g.Vb + loc0 + l;
-  const int rh = blockIdx.y;
   const TI* inr = in + rh * in_rs;
   const SiteCoord c = decompose(g, s);
   const int ps = g.Vb;
@@ -684,7 +696,7 @@ static void dslash_dispatch(const DslashArgs& a, hipStream_t st) {
   if (a.block_size <= -12 && a.op == OP_D) {
     const int NR = -a.block_size - 10;
     const int nt = (a.g.V + 255) / 256;
-    dim3 grid(round8(nt), (a.nrhs + NR - 1) / NR);
+    dim3 grid(round8(nt * ((a.nrhs + NR - 1) / NR)));
     auto go = [&](auto kern) {
       kern<<<grid, 256, 0, st>>>(a.g, a.nrhs, (const TI*)a.in, a.in_rs, (TO*)a.out, a.out_rs, (const TO*)a.b,
                                  (const TL*)a.U, (const TC*)a.C, (R)a.kappa);
@@ -702,27 +714,27 @@ static void dslash_dispatch(const DslashArgs& a, hipStream_t st) {
     if (tt < 1) throw std::runtime_error("launch_dslash: no LDS tile for this block shape");
     const int TS = a.g.B[0] * a.g.B[1] * a.g.B[2] * tt;
     const int ntile = a.g.nblk * (a.g.B[3] / tt);
-    const dim3 grid(round8(ntile), a.nrhs);
+    const dim3 grid(round8(ntile * a.nrhs));
     if (a.block_size == -2)
       k_dslash_lds<R, TI, TO, TL, TC><<<grid, TS, (size_t)12 * TS * sizeof(cplx<R>), st>>>(
           a.g, tt, (const TI*)a.in, a.in_rs, (TO*)a.out, a.out_rs, (const TO*)a.b, (const TL*)a.U, (const TC*)a.C,
-          (R)a.kappa);
+          (R)a.kappa, a.nrhs);
     else
       k_dslash_hx<R, TI, TO, TL, TC><<<grid, TS, (size_t)18 * TS * sizeof(cplx<R>), st>>>(
           a.g, tt, (const TI*)a.in, a.in_rs, (TO*)a.out, a.out_rs, (const TO*)a.b, (const TL*)a.U, (const TC*)a.C,
-          (R)a.kappa);
+          (R)a.kappa, a.nrhs);
     return;
   }
   if (a.block_size < 0 && a.op == OP_D) {
     int nt = (a.g.V + 63) / 64;
-    k_dslash_cs<R, TI, TO, TL, TC><<<dim3(round8(nt), a.nrhs), 192, 0, st>>>(
+    k_dslash_cs<R, TI, TO, TL, TC><<<dim3(round8(nt * a.nrhs)), 192, 0, st>>>(
         a.g, (const TI*)a.in, a.in_rs, (TO*)a.out, a.out_rs, (const TO*)a.b, (const TL*)a.U, (const TC*)a.C,
-        (R)a.kappa);
+        (R)a.kappa, a.nrhs);
     return;
   }
   const int bs = a.block_size > 0 ? a.block_size : 256;
   int ntile = (a.g.V + bs - 1) / bs;
-  dim3 grid(round8(ntile), a.nrhs);
+  dim3 grid(round8(ntile * a.nrhs));
   const TI* in = (const TI*)a.in;
   TO* out = (TO*)a.out;
   const TO* b = (const TO*)a.b;
@@ -732,15 +744,15 @@ static void dslash_dispatch(const DslashArgs& a, hipStream_t st) {
   switch (a.op) {
     case OP_D:
       k_dslash<R, TI, TO, TL, TC, OP_D><<<grid, bs, 0, st>>>(a.g, in, a.in_rs, out, a.out_rs, b, U, C, kappa, 0,
-                                                              a.chir);
+                                                              a.chir, a.nrhs);
       break;
     case OP_DSAP:
       k_dslash<R, TI, TO, TL, TC, OP_DSAP><<<grid, bs, 0, st>>>(a.g, in, a.in_rs, out, a.out_rs, b, U, C, kappa,
-                                                                 0, a.chir);
+                                                                 0, a.chir, a.nrhs);
       break;
     default:
       k_dslash<R, TI, TO, TL, TC, OP_HOP><<<grid, bs, 0, st>>>(a.g, in, a.in_rs, out, a.out_rs, b, U, C, kappa,
-                                                                a.hopdir, a.chir);
+                                                                a.hopdir, a.chir, a.nrhs);
       break;
   }
 }
@@ -959,6 +971,8 @@ __global__ __launch_bounds__(256) void k_sap_cross(Geo g, int colour, int first,
   const int blk = bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
   const int s = blk * Vb + loc;
   const SiteCoord c = decompose(g, s);
+  // right-hand sides outermost (blockIdx.y): consecutive workgroups are
+  // neighbouring domains, which share the lines of their faces in the L2
   const size_t off = (size_t)blockIdx.y * rs;
   const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
   const float2* src = (first ? b : r) + off;
