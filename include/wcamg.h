@@ -212,6 +212,35 @@ typedef struct {
 int wcamg_solve(wcamg_ctx* ctx, const void* b, void* x, int nrhs, const wcamg_solve_params* p,
                 wcamg_solve_info* info);
 
+/* The paper's own outer solver (Sec. 2, "BiCGStab algorithm with flexible
+ * preconditioning", after Vogel 2007) in FP64, from x = 0, with the shadow
+ * vector r~ = b and the listing's last line read as
+ * p <- r + beta (p - omega D M p).  The preconditioner M is
+ *   WCAMG_PC_AMG:    the multigrid V-cycle (Sec. 3; needs wcamg_setup), or
+ *   WCAMG_PC_BICG32: the comparison solver's preconditioner (Sec. 5,
+ *                    "MBiCGs"): a BiCGStab on D in FP32 arithmetic (FP16
+ *                    links and clover, FP32 spinors) with the omega
+ *                    stabilisation of the coarse solve, from 0, stopping at
+ *                    inner_tol relative residual or inner_iters iterations.
+ * Each iteration applies M twice.  The listing's first break point (after
+ * s) is taken at the end of that iteration instead: the omega step it skips
+ * is then a correction of the order of the tolerance.  Right-hand sides are
+ * batched as in wcamg_solve (b, x: DEVICE pointers, canonical layout;
+ * synchronous); info->iters counts outer iterations and info->vcycles the
+ * batched applications of M. */
+#define WCAMG_PC_AMG 0
+#define WCAMG_PC_BICG32 1
+typedef struct {
+  double tol;        /* relative residual ||b - D x|| / ||b|| per right-hand side */
+  int max_iters;     /* outer iterations per right-hand side */
+  int rhs_chunk;     /* right-hand sides per batch (0: all) */
+  int precond;       /* WCAMG_PC_AMG or WCAMG_PC_BICG32 */
+  int inner_iters;   /* WCAMG_PC_BICG32: iterations of the inner solve (>= 1) */
+  double inner_tol;  /* WCAMG_PC_BICG32: relative residual of the inner solve */
+} wcamg_bicg_params;
+int wcamg_solve_bicgstab(wcamg_ctx* ctx, const void* b, void* x, int nrhs, const wcamg_bicg_params* p,
+                         wcamg_solve_info* info);
+
 /* Gauge-equivariant network proposing initial test vectors (replaces setup
  * step (0-a) when wcamg_setup_params.init_net is set).  Layers
  *   psi'_o(x) = sum_i sum_{d=0..8} W[d][o][i] (T_d psi_i)(x),

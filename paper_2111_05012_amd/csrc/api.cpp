@@ -674,6 +674,40 @@ struct wcamg_ctx {
     }
   }
 
+  // x = BiCGStab(D, b) on fine fields in FP32 arithmetic (FP16 links and
+  // clover, FP32 spinors), from 0, with the omega stabilisation of the coarse
+  // solve: the preconditioner of the comparison solver (Sec. 5)
+  void bicg32(const void* b, void* x, int nrhs, int iters, double tol) {
+    const int t = C64;
+    const size_t n = frs(), bytes = fsz(nrhs, WCAMG_PREC_MIXED);
+    void* r = W("mb_r", bytes);
+    void* rt = W("mb_rt", bytes);
+    void* p = W("mb_p", bytes);
+    void* v = W("mb_v", bytes);
+    void* s = W("mb_s", bytes);
+    void* tt = W("mb_t", bytes);
+    double2* part = (double2*)W("mb_part", (size_t)nrhs * reduce_nwg(n) * 3 * sizeof(double2));
+    BicgScal* sc = (BicgScal*)W("mb_sc", (size_t)nrhs * sizeof(BicgScal));
+    launch_bicg_init(b, x, r, rt, p, v, t, n, n, nrhs, tol, part, sc, st);
+    std::vector<BicgScal> hs(nrhs);
+    for (int it = 0; it < iters; ++it) {
+      launch_bicg_p(p, r, v, t, n, n, nrhs, sc, st);
+      dslash(p, C64, v, C64, nrhs, OP_D, WCAMG_PREC_MIXED);
+      launch_bicg_alpha(rt, v, t, n, n, nrhs, part, sc, st);
+      launch_bicg_s(s, r, v, t, n, n, nrhs, sc, st);
+      dslash(s, C64, tt, C64, nrhs, OP_D, WCAMG_PREC_MIXED);
+      launch_bicg_omega(tt, s, t, n, n, nrhs, part, sc, 0.7, st);
+      launch_bicg_xr(x, r, p, s, tt, rt, t, n, n, nrhs, part, sc, st);
+      if ((it % 4 == 3) && it + 1 < iters) {
+        HIPCHK(hipMemcpyAsync(hs.data(), sc, nrhs * sizeof(BicgScal), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool any = false;
+        for (auto& q : hs) any |= q.active != 0;
+        if (!any) break;
+      }
+    }
+  }
+
   // x += MR(A, r, iters) on coarse vectors (A = the level-1 stencil); r is overwritten
   void mr_smooth(const COp& o, void* x, void* r, int nrhs, int iters) {
     int t = crs_t();
@@ -1689,6 +1723,140 @@ int wcamg_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, const wcamg_solv
       double2* xx = (double2*)c->W("sv_x", (size_t)nr * n * sizeof(double2));
       launch_pack_spinor(g, (const double2*)b + (size_t)r0 * n, bb, C128, n, nr, c->st);
       fgmres_batch(c, bb, xx, nr, p, inf.iters + r0, inf.relres + r0, inf.converged + r0, &inf.vcycles);
+      launch_unpack_spinor(g, xx, C128, n, (double2*)x + (size_t)r0 * n, nr, c->st);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    inf.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int r = 0; r < nrhs; ++r)
+      if (!inf.converged[r]) status = WCAMG_NOT_CONVERGED;
+    if (info) *info = inf;
+  });
+  return rc != WCAMG_OK ? rc : status;
+}
+
+// The paper's flexible BiCGStab (Sec. 2) in FP64 on one batch of right-hand
+// sides, from x = 0, with M = the V-cycle or the FP32 BiCGStab.  Scalars per
+// right-hand side live on the device (BicgScal); a right-hand side stops
+// when its recursive residual reaches tol (relative to b).
+static void fbicg_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs, const wcamg_bicg_params* p,
+                        int* iters, double* relres, int* conv, int* vcycles) {
+  const Geo& g = c->g;
+  const size_t n = (size_t)12 * g.V, rs = n, vs = (size_t)nrhs * n;
+  const bool amg = p->precond == WCAMG_PC_AMG;
+  const int prec = amg ? c->h.prec : WCAMG_PREC_MIXED;
+  const int zt = c->spin_t(prec);
+  double2* r = (double2*)c->W("fb_r", vs * sizeof(double2));
+  double2* rt = (double2*)c->W("fb_rt", vs * sizeof(double2));
+  double2* pp = (double2*)c->W("fb_p", vs * sizeof(double2));
+  double2* v = (double2*)c->W("fb_v", vs * sizeof(double2));
+  double2* s = (double2*)c->W("fb_s", vs * sizeof(double2));
+  double2* t = (double2*)c->W("fb_t", vs * sizeof(double2));
+  void* Mp = c->W("fb_mp", vs * ct_size(zt));
+  void* Ms = c->W("fb_ms", vs * ct_size(zt));
+  float2* vin = prec == WCAMG_PREC_MIXED ? (float2*)c->W("fb_vin", vs * sizeof(float2)) : nullptr;
+  double2* part = (double2*)c->W("fb_part", (size_t)nrhs * reduce_nwg(n) * 3 * sizeof(double2));
+  BicgScal* sc = (BicgScal*)c->W("fb_sc", (size_t)nrhs * sizeof(BicgScal));
+  double* ones = (double*)c->W("fb_one", (size_t)nrhs * sizeof(double));
+  double* nrm = (double*)c->W("fb_nrm", (size_t)nrhs * sizeof(double));
+  {
+    std::vector<double> one(nrhs, 1.0);
+    HIPCHK(hipMemcpyAsync(ones, one.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
+  }
+  // out = M in (in: FP64 batch; the mixed preconditioners take an FP32 copy)
+  auto precond = [&](double2* in, void* out) {
+    const void* src = in;
+    if (vin) {
+      launch_scale(in, ones, in, vin, n, rs, nrhs, c->st);
+      src = vin;
+    }
+    if (amg)
+      c->vcycle(src, out, nrhs);
+    else
+      c->bicg32(src, out, nrhs, p->inner_iters, p->inner_tol);
+    *vcycles += 1;
+  };
+  launch_bicg_init(bb, xx, r, rt, pp, v, C128, n, rs, nrhs, p->tol, part, sc, c->st);
+  std::vector<BicgScal> hs(nrhs);
+  for (int it = 0; it < p->max_iters; ++it) {
+    launch_bicg_p(pp, r, v, C128, n, rs, nrhs, sc, c->st);  // p = r + beta (p - omega v)
+    precond(pp, Mp);
+    c->dslash(Mp, zt, v, C128, nrhs, OP_D, WCAMG_PREC_FP64);  // v = D M p
+    launch_bicg_alpha(rt, v, C128, n, rs, nrhs, part, sc, c->st);
+    launch_bicg_s(s, r, v, C128, n, rs, nrhs, sc, c->st);  // s = r - alpha v
+    precond(s, Ms);
+    c->dslash(Ms, zt, t, C128, nrhs, OP_D, WCAMG_PREC_FP64);  // t = D M s
+    launch_bicg_omega(t, s, C128, n, rs, nrhs, part, sc, 0.0, c->st);
+    launch_fbicg_x(xx, Mp, Ms, zt, n, rs, nrhs, sc, c->st);  // x += alpha M p + omega M s
+    launch_bicg_xr(nullptr, r, nullptr, s, t, rt, C128, n, rs, nrhs, part, sc, c->st);  // r = s - omega t
+    HIPCHK(hipMemcpyAsync(hs.data(), sc, nrhs * sizeof(BicgScal), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    bool any = false;
+    for (auto& q : hs) {
+      require(std::isfinite(q.rnorm2), "non-finite residual", WCAMG_ENUMERIC);
+      any |= q.active != 0;
+    }
+    if (!any) break;
+  }
+  // true residual with the FP64 operator
+  std::vector<double> bn2(nrhs), rn2(nrhs);
+  launch_norm2(bb, C128, n, rs, nrhs, part, nrm, c->st);
+  HIPCHK(hipMemcpyAsync(bn2.data(), nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  c->dslash(xx, C128, r, C128, nrhs, OP_D, WCAMG_PREC_FP64, bb);  // r = b - D x
+  launch_norm2(r, C128, n, rs, nrhs, part, nrm, c->st);
+  HIPCHK(hipMemcpyAsync(rn2.data(), nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  for (int q = 0; q < nrhs; ++q) {
+    relres[q] = bn2[q] > 0 ? std::sqrt(rn2[q] / bn2[q]) : 0.0;
+    iters[q] = hs[q].iters;
+    conv[q] = relres[q] <= p->tol;
+  }
+}
+
+int wcamg_solve_bicgstab(wcamg_ctx* c, const void* b, void* x, int nrhs, const wcamg_bicg_params* p,
+                         wcamg_solve_info* info) {
+  if (!c) return WCAMG_EINVAL;
+  int status = WCAMG_OK;
+  int rc = guard(c, [&] {
+    require(b && x && p, "null pointer");
+    check_nrhs(nrhs);
+    require(std::isfinite(p->tol) && p->tol >= 0, "invalid tol");
+    require(p->max_iters >= 0, "invalid max_iters");
+    require(p->precond == WCAMG_PC_AMG || p->precond == WCAMG_PC_BICG32, "unknown preconditioner");
+    if (p->precond == WCAMG_PC_AMG) require(c->have_hier, "no hierarchy: call wcamg_setup first", WCAMG_ESTATE);
+    if (p->precond == WCAMG_PC_BICG32)
+      require(p->inner_iters >= 1 && std::isfinite(p->inner_tol) && p->inner_tol >= 0,
+              "inner_iters must be >= 1 and inner_tol finite and >= 0");
+    auto t0 = std::chrono::steady_clock::now();
+    const Geo& g = c->g;
+    const size_t n = (size_t)12 * g.V;
+    const int chunk = p->rhs_chunk > 0 ? std::min(p->rhs_chunk, nrhs) : nrhs;
+    {
+      // packed b and x, the six FP64 vectors and two preconditioned ones of
+      // the iteration, and the fields inside the preconditioner
+      const bool amg = p->precond == WCAMG_PC_AMG;
+      const int prec = amg ? c->h.prec : WCAMG_PREC_MIXED;
+      const size_t cn = (size_t)chunk * n, d = cn * sizeof(double2), z = cn * ct_size(c->spin_t(prec));
+      const size_t f = c->fsz(chunk, prec);
+      std::vector<std::pair<std::string, size_t>> plan = {
+          {"sv_b", d}, {"sv_x", d}, {"fb_r", d}, {"fb_rt", d}, {"fb_p", d}, {"fb_v", d}, {"fb_s", d}, {"fb_t", d},
+          {"fb_mp", z}, {"fb_ms", z}};
+      if (prec == WCAMG_PREC_MIXED) plan.push_back({"fb_vin", cn * sizeof(float2)});
+      if (amg) {
+        for (const char* k : {"vc_r", "vc_x1", "sap_r", "sap_d"}) plan.push_back({k, f});
+      } else {
+        for (const char* k : {"mb_r", "mb_rt", "mb_p", "mb_v", "mb_s", "mb_t"}) plan.push_back({k, f});
+      }
+      c->reserve(plan);
+    }
+    wcamg_solve_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+      const int nr = std::min(chunk, nrhs - r0);
+      double2* bb = (double2*)c->W("sv_b", (size_t)nr * n * sizeof(double2));
+      double2* xx = (double2*)c->W("sv_x", (size_t)nr * n * sizeof(double2));
+      launch_pack_spinor(g, (const double2*)b + (size_t)r0 * n, bb, C128, n, nr, c->st);
+      fbicg_batch(c, bb, xx, nr, p, inf.iters + r0, inf.relres + r0, inf.converged + r0, &inf.vcycles);
       launch_unpack_spinor(g, xx, C128, n, (double2*)x + (size_t)r0 * n, nr, c->st);
     }
     HIPCHK(hipGetLastError());

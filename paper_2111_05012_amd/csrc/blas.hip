@@ -335,7 +335,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_bicg_xr(T* x, T* r, const T* p,
   if (act) {
     for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (size_t)gridDim.x * RED_THREADS) {
       cplx<R> ss = ld<R>(s + off, i);
-      st(x + off, i, ld<R>(x + off, i) + al * ld<R>(p + off, i) + om * ss);
+      if (x) st(x + off, i, ld<R>(x + off, i) + al * ld<R>(p + off, i) + om * ss);
       cplx<R> rn = ss - om * ld<R>(t + off, i);
       st(r + off, i, rn);
       cplx<double> rd = ld<double>(r + off, i);  // stored value
@@ -383,6 +383,29 @@ void launch_bicg_xr(void* x, void* r, const void* p, const void* s, const void* 
                                                            (const float2*)s, (const float2*)tt, (const float2*)rt, n,
                                                            rs, sc, part);
   k_bicg_rho_fin<<<nrhs, 64, 0, st>>>(part, reduce_nwg(n), sc);
+}
+
+// x += alpha M p + omega M s (the flexible BiCGStab's update of the iterate:
+// the preconditioned vectors, FP32 or FP64, into the FP64 iterate)
+template <class TZ>
+__global__ __launch_bounds__(256) void k_fbicg_x(double2* x, const TZ* mp, const TZ* ms, size_t n, size_t rs,
+                                                 const BicgScal* sc) {
+  const int rr = blockIdx.y;
+  if (!sc[rr].active) return;
+  const size_t off = rr * rs;
+  const cplx<double> al = {sc[rr].alpha.x, sc[rr].alpha.y}, om = {sc[rr].omega.x, sc[rr].omega.y};
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    st(x + off, i, ld<double>(x + off, i) + al * ld<double>(mp + off, i) + om * ld<double>(ms + off, i));
+}
+
+void launch_fbicg_x(double2* x, const void* mp, const void* ms, int zt, size_t n, size_t rs, int nrhs,
+                    const BicgScal* sc, hipStream_t st) {
+  if (zt == C128)
+    k_fbicg_x<double2><<<ew_grid(n, nrhs), 256, 0, st>>>(x, (const double2*)mp, (const double2*)ms, n, rs, sc);
+  else if (zt == C64)
+    k_fbicg_x<float2><<<ew_grid(n, nrhs), 256, 0, st>>>(x, (const float2*)mp, (const float2*)ms, n, rs, sc);
+  else
+    throw std::runtime_error("launch_fbicg_x: preconditioned vectors must be FP64 or FP32");
 }
 
 // ---------------------------------------------------------------- FGMRES (FP64 basis)

@@ -170,6 +170,9 @@ struct BicgScal {
 };
 void launch_bicg_init(const void* b, void* x, void* r, void* rt, void* p, void* v, int t, size_t n, size_t rs,
                       int nrhs, double tol, double2* part, BicgScal* sc, hipStream_t st);
+// x (FP64) += alpha mp + omega ms for the active right-hand sides; mp, ms of type zt (C128 or C64)
+void launch_fbicg_x(double2* x, const void* mp, const void* ms, int zt, size_t n, size_t rs, int nrhs,
+                    const BicgScal* sc, hipStream_t st);
 void launch_bicg_p(void* p, const void* r, const void* v, int t, size_t n, size_t rs, int nrhs,
                    const BicgScal* sc, hipStream_t st);
 void launch_bicg_alpha(const void* rt, const void* v, int t, size_t n, size_t rs, int nrhs, double2* part,
@@ -178,6 +181,7 @@ void launch_bicg_s(void* s, const void* r, const void* v, int t, size_t n, size_
                    const BicgScal* sc, hipStream_t st);
 void launch_bicg_omega(const void* tt, const void* s, int t, size_t n, size_t rs, int nrhs, double2* part,
                        BicgScal* sc, double stab, hipStream_t st);
+// x += alpha p + omega s (skipped when x is null); r = s - omega t; rho, |r|^2
 void launch_bicg_xr(void* x, void* r, const void* p, const void* s, const void* tt, const void* rt, int t,
                     size_t n, size_t rs, int nrhs, double2* part, BicgScal* sc, hipStream_t st);
 

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), 'libwcamg.so
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ESTATE, ENUMERIC = 0, 1, -1, -2, -3, -4, -5
 DEVICE, HOST = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
+PC_AMG, PC_BICG32 = 0, 1
 MAX_RHS = 64
 
 _c_int4 = ctypes.c_int * 4
@@ -38,6 +39,11 @@ class SetupParams(ctypes.Structure):
 class SolveParams(ctypes.Structure):
     _fields_ = [('restart', ctypes.c_int), ('tol', ctypes.c_double), ('max_iters', ctypes.c_int),
                 ('rhs_chunk', ctypes.c_int), ('use_graph', ctypes.c_int)]
+
+
+class BicgParams(ctypes.Structure):
+    _fields_ = [('tol', ctypes.c_double), ('max_iters', ctypes.c_int), ('rhs_chunk', ctypes.c_int),
+                ('precond', ctypes.c_int), ('inner_iters', ctypes.c_int), ('inner_tol', ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -78,6 +84,7 @@ SIGNATURES = {
     'wcamg_coarse_solve': (_I, [_P, _P, _P, _I, _I, _D, _I]),
     'wcamg_vcycle': (_I, [_P, _P, _P, _I, _I]),
     'wcamg_solve': (_I, [_P, _P, _P, _I, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo)]),
+    'wcamg_solve_bicgstab': (_I, [_P, _P, _P, _I, ctypes.POINTER(BicgParams), ctypes.POINTER(SolveInfo)]),
     'wcamg_net_init': (_I, [_P, _I, _I, _P, _I]),
     'wcamg_net_get_weights': (_I, [_P, _P, _I]),
     'wcamg_net_forward': (_I, [_P, _P, _P, _I]),
@@ -267,6 +274,21 @@ class Context:
         prm = SolveParams(restart, tol, max_iters, rhs_chunk, use_graph)
         info = SolveInfo()
         rc = self._chk(self.lib.wcamg_solve(self.h, pb, px, nrhs, ctypes.byref(prm), ctypes.byref(info)),
+                       allow=(OK, NOT_CONVERGED))
+        return rc, info
+
+    def solve_bicgstab(self, b, x, nrhs, tol=1e-10, max_iters=1000, rhs_chunk=0, precond=PC_AMG, inner_iters=50,
+                       inner_tol=0.1):
+        """The paper's flexible BiCGStab (FP64) preconditioned by the V-cycle
+        (PC_AMG) or by an FP32 BiCGStab on D (PC_BICG32, the comparison
+        solver).  b, x: device tensors.  Returns (status, SolveInfo)."""
+        pb, wb = _ptr(b)
+        px, wx = _ptr(x)
+        if wb != DEVICE or wx != DEVICE:
+            raise ValueError('solve_bicgstab takes device tensors')
+        prm = BicgParams(tol, max_iters, rhs_chunk, precond, inner_iters, inner_tol)
+        info = SolveInfo()
+        rc = self._chk(self.lib.wcamg_solve_bicgstab(self.h, pb, px, nrhs, ctypes.byref(prm), ctypes.byref(info)),
                        allow=(OK, NOT_CONVERGED))
         return rc, info
 

@@ -317,6 +317,52 @@ def test_setup_and_solve_mixed_c1():
         assert np.linalg.norm(b[k] - prob.op.D(xg[k])) / np.linalg.norm(b[k]) <= 1e-10
 
 
+# ---------------------------------------------------------------- the paper's outer solver
+def test_flexible_bicgstab_fp64_matches_oracle(prob):
+    """The paper's flexible BiCGStab (FP64) with the FP64 V-cycle as M,
+    against the oracle's flexible BiCGStab with the oracle's V-cycle on the
+    same hierarchy: the same outer iteration count and the same solution."""
+    from paper_2111_05012_amd import PC_AMG
+    if any((d // b) % 2 for d, b in zip(prob.dims, prob.block)):
+        pytest.skip('SAP colouring needs an even number of domains per direction')
+    V = _hier(prob, coarse_iters=10, coarse_tol=0.0)
+    mg = amg.TwoLevel(prob.op, V, 4, 6, coarse_iters=10, coarse_tol=0.0)
+    b = syn.z2_source(prob.dims, 3, nrhs=2)
+    x = prob.zeros(b.shape)
+    rc, info = prob.ctx.solve_bicgstab(prob.T(b), x, 2, tol=1e-10, precond=PC_AMG)
+    assert rc == 0
+    xg = prob.N(x)
+    for k in range(2):
+        xo, its, res = amg.flexible_bicgstab(prob.op.D, mg.vcycle, b[k], tol=1e-10)
+        assert info.iters[k] == its, (k, info.iters[k], its)
+        assert info.relres[k] <= 1e-10
+        assert np.linalg.norm(b[k] - prob.op.D(xg[k])) / np.linalg.norm(b[k]) <= 1e-10
+        assert rel(xg[k], xo) < 1e-8
+
+
+def test_flexible_bicgstab_mixed_amg_and_mbicgs_c1():
+    """Config-1 workload: the flexible BiCGStab preconditioned by the mixed
+    V-cycle, and the comparison solver (preconditioned by an FP32 BiCGStab on
+    D), both to 1e-10; residuals recomputed by the oracle's D.  The
+    multigrid preconditioner needs fewer outer iterations."""
+    from paper_2111_05012_amd import PREC_MIXED, PC_AMG, PC_BICG32
+    c = syn.CONFIGS['c1']
+    prob = Problem(c['dims'], c['block'], c['eps'], c['seed'], c['kappa'], c['csw'])
+    V0 = syn.gaussian_vectors(prob.dims, c['nv'], c['seed'])
+    prob.ctx.setup(prob.ctx.setup_params(c['nv'], PREC_MIXED, init_vectors=prob.T(V0)))
+    b = syn.z2_source(prob.dims, c['seed'], nrhs=3)
+    its = {}
+    for pc in (PC_AMG, PC_BICG32):
+        x = prob.zeros(b.shape)
+        rc, info = prob.ctx.solve_bicgstab(prob.T(b), x, 3, tol=1e-10, precond=pc, inner_iters=20, inner_tol=0.1)
+        assert rc == 0, pc
+        xg = prob.N(x)
+        for k in range(3):
+            assert np.linalg.norm(b[k] - prob.op.D(xg[k])) / np.linalg.norm(b[k]) <= 1e-10, (pc, k)
+        its[pc] = max(info.iters[:3])
+    assert its[PC_AMG] <= its[PC_BICG32], its
+
+
 # ---------------------------------------------------------------- three levels
 def _three_level_problem(prec=0, nv=4, nv1=4):
     """8^4 with 2^4 blocks (coarse 4^4), level-1 blocks 2^4 (level-2 2^4)."""
