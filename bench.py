@@ -247,6 +247,9 @@ def main():
     ap.add_argument('--plain-batched', type=int, default=1,
                     help='also time the FP64 AMG with all RHS batched (separates the batching and precision gains)')
     ap.add_argument('--no-cpu', action='store_true')
+    ap.add_argument('--paper-solvers', action='store_true',
+                    help="also time the paper's flexible BiCGStab with the mixed V-cycle and the comparison "
+                         'solver (flexible BiCGStab preconditioned by an FP32 BiCGStab) on the same system')
     ap.add_argument('--profile-kernels', action='store_true',
                     help='short kernel-only run for hardware counters: a 1 GiB copy, then D, SAP, V-cycle')
     args = ap.parse_args()
@@ -344,6 +347,29 @@ def main():
                        converged=rcb == 0, note='FP64 everywhere, all %d RHS batched' % w['nrhs'])
         log('plain fp64 batched: setup %.3f s, solve %.3f s' % (sb, vb))
 
+    paper = None
+    if args.paper_solvers:
+        from paper_2111_05012_amd import PC_AMG, PC_BICG32
+        paper = {}
+        # the paper's outer solver with the multigrid preconditioner (setup as in the step)
+        ctx.load_gauge(U)
+        ctx.setup(ctx.setup_params(w['nv'], PREC_MIXED, init_vectors=V0, **SETUP))
+        for name, pc, kw in (('fbicgstab_amg', PC_AMG, {}),
+                             ('mbicgs', PC_BICG32, dict(inner_iters=50, inner_tol=0.1))):
+            xq = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rcq, infq = ctx.solve_bicgstab(b, xq, w['nrhs'], tol=1e-10, max_iters=500, precond=pc, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            paper[name] = dict(solve_s=round(dt, 3), iters=list(infq.iters[:w['nrhs']]),
+                               precond_applications=infq.vcycles, relres_max=max(infq.relres[:w['nrhs']]),
+                               converged=rcq == 0)
+            log('%s: solve %.3f s, outer iterations %s' % (name, dt, list(infq.iters[:w['nrhs']])))
+        paper['note'] = ("Sec. 2 flexible BiCGStab, all RHS batched, FP64 outer; fbicgstab_amg: M = mixed V-cycle "
+                         "(solve only, the setup is the step's); mbicgs: M = FP32 stabilised BiCGStab on D "
+                         "(50 iterations or 0.1 relative residual), no setup")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, prof, iters)
@@ -367,6 +393,7 @@ def main():
         speedup_vs_plain=round(plain['tts_s'] / tts, 2) if plain else None,
         speedup_vs_plain_batched=round(plain_b['tts_s'] / tts, 2) if plain_b else None,
         autotune=ctx.autotune_info(),
+        paper_solvers=paper,
         cpu_baseline=cpu)
     print(json.dumps(res), flush=True)
 
