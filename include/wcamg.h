@@ -143,7 +143,17 @@ typedef struct {
    * wcamg_net_init applied to init_vectors (nv must equal its channels). */
   int init_net;
   unsigned long long seed; /* start vectors when init_vectors is NULL */
+  /* Position of the SAP smoother in the V-cycle (Sec. 3 allows it before,
+   * after, or before and after the coarse solve); each step is a Richardson
+   * step x <- x + M_i (b - D x) from x = 0:
+   * WCAMG_SMOOTH_POST (0, the paper's choice): coarse grid, then smoother;
+   * WCAMG_SMOOTH_PRE (1): smoother, then coarse grid;
+   * WCAMG_SMOOTH_BOTH (2): smoother, coarse grid, smoother. */
+  int smoothing;
 } wcamg_setup_params;
+#define WCAMG_SMOOTH_POST 0
+#define WCAMG_SMOOTH_PRE 1
+#define WCAMG_SMOOTH_BOTH 2
 
 /* Setup stage (0) of Sec. 3: (0-a) SAP applied n_init times to the start
  * vectors, block orthonormalisation (<I|J> = delta_IJ), coarse operator

@@ -337,8 +337,10 @@ class TwoLevel:
     (coarse_iters, coarse_tol); coarse='exact' a dense solve (for pins)."""
 
     def __init__(self, op, V, sap_sweeps=4, mr_iters=6, coarse_iters=50, coarse_tol=0.1,
-                 coarse='bicgstab'):
+                 coarse='bicgstab', smoothing='post'):
         self.op, self.V = op, V
+        assert smoothing in ('post', 'pre', 'both')
+        self.smoothing = smoothing
         self.sap_sweeps, self.mr_iters = sap_sweeps, mr_iters
         self.coarse_iters, self.coarse_tol, self.coarse = coarse_iters, coarse_tol, coarse
         self.cdims = coarse_dims(op.dims, op.block)
@@ -374,16 +376,26 @@ class TwoLevel:
             return np.zeros_like(r)
         return sap(self.op, r, self.sap_sweeps, self.mr_iters)
 
+    def coarse_correction(self, r):
+        """M_1 r: (1a) restrict, (1b) coarse solve, (1c) prolong."""
+        return self.P(self.coarse_solve(self.R(r)))
+
     def vcycle(self, v):
-        """M v: (1a) restrict, (1b) coarse solve, (1c) prolong, then (2) one
-        Richardson step with the SAP smoother on the new residual."""
-        x1 = self.P(self.coarse_solve(self.R(v)))
-        r = v - self.op.D(x1)
-        return x1 + self.smoother(r)
+        """M v as Richardson steps x <- x + M_i (v - D x) from x = 0 (Sec. 3).
+        'post' (the paper's choice): the coarse-grid step M_1, then the SAP
+        smoother M_2; 'pre': M_2 first, then M_1; 'both': M_2, M_1, M_2 (the
+        smoother before and after the coarse solve, which Sec. 3 allows)."""
+        steps = {'post': (self.coarse_correction, self.smoother),
+                 'pre': (self.smoother, self.coarse_correction),
+                 'both': (self.smoother, self.coarse_correction, self.smoother)}[self.smoothing]
+        x = steps[0](v)
+        for M in steps[1:]:
+            x = x + M(v - self.op.D(x))
+        return x
 
 
 def setup(op, V0, n_init=3, n_adapt=3, sap_sweeps=4, mr_iters=6, coarse_iters=50,
-          coarse_tol=0.1):
+          coarse_tol=0.1, smoothing='post'):
     """Setup stage (0): (0-a) SAP applied n_init times to the random start
     vectors as an approximate D^-1, block orthonormalisation, coarse operator;
     (0-b) n_adapt times: every vector replaced by M v with the current
@@ -392,11 +404,11 @@ def setup(op, V0, n_init=3, n_adapt=3, sap_sweeps=4, mr_iters=6, coarse_iters=50
     for _ in range(n_init):
         V = sap(op, V, sap_sweeps, mr_iters)
     V = block_orthonormalize(V, op.dims, op.block)
-    mg = TwoLevel(op, V, sap_sweeps, mr_iters, coarse_iters, coarse_tol)
+    mg = TwoLevel(op, V, sap_sweeps, mr_iters, coarse_iters, coarse_tol, smoothing=smoothing)
     for _ in range(n_adapt):
         V = mg.vcycle(V)
         V = block_orthonormalize(V, op.dims, op.block)
-        mg = TwoLevel(op, V, sap_sweeps, mr_iters, coarse_iters, coarse_tol)
+        mg = TwoLevel(op, V, sap_sweeps, mr_iters, coarse_iters, coarse_tol, smoothing=smoothing)
     return mg
 
 
@@ -696,9 +708,10 @@ def setup_level1(cop, W0, n_init=3, n_adapt=3, mr1_iters=4, coarse_iters=50, coa
 class ThreeLevel(TwoLevel):
     """Level 0 with a level-1 V-cycle as its coarse solve."""
 
-    def __init__(self, op, V, lv1, sap_sweeps=4, mr_iters=6):
+    def __init__(self, op, V, lv1, sap_sweeps=4, mr_iters=6, smoothing='post'):
         self.op, self.V = op, V
         self.sap_sweeps, self.mr_iters = sap_sweeps, mr_iters
+        self.smoothing = smoothing
         self.cdims = coarse_dims(op.dims, op.block)
         self.Dc = coarse_operator(op, V)
         self.lv1 = lv1

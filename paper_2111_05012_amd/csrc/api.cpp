@@ -90,6 +90,7 @@ struct Hier {
   int nv = 0, N = 0;
   CGeo cg{};
   int sap_sweeps = 4, mr_iters = 6, coarse_iters = 50;
+  int smoothing = WCAMG_SMOOTH_POST;
   double coarse_tol = 0.1;
   DevBuf V;   // stored test vectors [nv][12][V]
   DevBuf Dc;  // [NC][9][N][N]
@@ -369,7 +370,7 @@ struct wcamg_ctx {
   std::vector<double> hier_sig() const {
     std::vector<double> s = {(double)h.prec, (double)h.nv, (double)h.sap_sweeps, (double)h.mr_iters,
                              (double)h.coarse_iters, h.coarse_tol, (double)h.l1, (double)h.nw,
-                             (double)h.mr1_iters};
+                             (double)h.mr1_iters, (double)h.smoothing};
     for (int m = 0; m < 4; ++m) s.push_back(h.b1[m]);
     return s;
   }
@@ -603,20 +604,28 @@ struct wcamg_ctx {
     launch_restrict(g, h.nv, nrhs, h.V.p, vec_t(), in, spin_t(h.prec), frs(), out, crs_t(), crs_n(), h.N, 0, st,
                     tile);
   }
-  void prolong_(const void* xc, void* out, int nrhs) {
+  void prolong_(const void* xc, void* out, int nrhs, int accumulate = 0) {
     double by = (double)g.V * 12 * (h.nv * ct_size(vec_t()) + nrhs * ct_size(spin_t(h.prec))) +
                 (double)nrhs * crs_n() * ct_size(crs_t());
     std::vector<int> cands = {0};
     if (h.prec == WCAMG_PREC_MIXED && h.nv <= 32 && nrhs <= 32) cands.push_back(PROLONG_MFMA32);
     char key[160];
     snprintf(key, sizeof(key), "prolong|nv%d|n%d|Vb%d|V%d|p%d", h.nv, nrhs, g.Vb, g.V, h.prec);
-    const int var = tune(key, cands, [&](int v) {
-      launch_prolong(g, h.nv, nrhs, h.V.p, vec_t(), xc, crs_t(), crs_n(), h.N, out, spin_t(h.prec), frs(), 0,
-                     h.prec == WCAMG_PREC_MIXED, st, v);
-    });
+    // tuning runs the candidates repeatedly: only where the launch overwrites
+    // its output (an accumulating launch takes the tuned or the first choice)
+    int var = cands[0];
+    if (!accumulate) {
+      var = tune(key, cands, [&](int v) {
+        launch_prolong(g, h.nv, nrhs, h.V.p, vec_t(), xc, crs_t(), crs_n(), h.N, out, spin_t(h.prec), frs(), 0,
+                       h.prec == WCAMG_PREC_MIXED, st, v);
+      });
+    } else {
+      auto it = tuner.best.find(arch + "|" + std::string(key));
+      if (it != tuner.best.end()) var = it->second;
+    }
     Timed t(this, "prolong", by, 96.0 * g.V * h.nv * nrhs, nrhs);
-    launch_prolong(g, h.nv, nrhs, h.V.p, vec_t(), xc, crs_t(), crs_n(), h.N, out, spin_t(h.prec), frs(), 0,
-                   h.prec == WCAMG_PREC_MIXED, st, var);
+    launch_prolong(g, h.nv, nrhs, h.V.p, vec_t(), xc, crs_t(), crs_n(), h.N, out, spin_t(h.prec), frs(),
+                   accumulate, h.prec == WCAMG_PREC_MIXED, st, var);
   }
   COp op1() { return COp{h.cg, h.N, h.Dc.p}; }
   COp op2() { return COp{h.cg2, h.N2, h.Dc2.p}; }
@@ -750,20 +759,40 @@ struct wcamg_ctx {
   }
 
   // M v: restrict, coarse solve, prolong, residual, SAP started from the prolonged vector
+  // M in (Sec. 3): Richardson steps x <- x + M_i (in - D x) from x = 0 with
+  // the coarse-grid step M_1 = (1a) restrict, (1b) coarse solve, (1c)
+  // prolong, and the SAP smoother M_2, in the order h.smoothing names
   void vcycle(const void* in, void* out, int nrhs) {
-    int prec = h.prec;
+    int prec = h.prec, t = spin_t(prec);
     void* vc = W("vc_b", csz(nrhs));
     void* xc = W("vc_x", csz(nrhs));
     void* x1 = W("vc_x1", fsz(nrhs, prec));
     void* r = W("vc_r", fsz(nrhs, prec));
-    restrict_(in, vc, nrhs);
-    if (h.l1)
-      vcycle1(vc, xc, nrhs);
-    else
-      coarse_solve(vc, xc, nrhs, h.coarse_iters, h.coarse_tol);
-    prolong_(xc, x1, nrhs);
-    dslash(x1, spin_t(prec), r, spin_t(prec), nrhs, OP_D, prec, in);
-    sap(r, out, x1, nrhs, h.sap_sweeps, h.mr_iters, prec);
+    auto coarse = [&](const void* rhs) {
+      restrict_(rhs, vc, nrhs);
+      if (h.l1)
+        vcycle1(vc, xc, nrhs);
+      else
+        coarse_solve(vc, xc, nrhs, h.coarse_iters, h.coarse_tol);
+    };
+    if (h.smoothing == WCAMG_SMOOTH_POST) {
+      coarse(in);
+      prolong_(xc, x1, nrhs);
+      dslash(x1, t, r, t, nrhs, OP_D, prec, in);
+      sap(r, out, x1, nrhs, h.sap_sweeps, h.mr_iters, prec);
+      return;
+    }
+    // smoother first: x = M_2 in, then x += M_1 (in - D x)
+    void* x = h.smoothing == WCAMG_SMOOTH_PRE ? out : x1;
+    sap(in, x, nullptr, nrhs, h.sap_sweeps, h.mr_iters, prec);
+    dslash(x, t, r, t, nrhs, OP_D, prec, in);
+    coarse(r);
+    prolong_(xc, x, nrhs, 1);
+    if (h.smoothing == WCAMG_SMOOTH_BOTH) {
+      // and the smoother again: out = x + M_2 (in - D x)
+      dslash(x, t, r, t, nrhs, OP_D, prec, in);
+      sap(r, out, x, nrhs, h.sap_sweeps, h.mr_iters, prec);
+    }
   }
 
   // block orthonormalisation (CholQR, twice) of nv working fields in place
@@ -899,6 +928,10 @@ struct wcamg_ctx {
     require(p->sap_sweeps == 0 || (g.NB[0] % 2 == 0 && g.NB[1] % 2 == 0 && g.NB[2] % 2 == 0 && g.NB[3] % 2 == 0),
             "SAP needs an even number of blocks per direction");
     require(std::isfinite(p->coarse_tol) && p->coarse_tol >= 0, "invalid coarse_tol");
+    require(p->smoothing == WCAMG_SMOOTH_POST || p->smoothing == WCAMG_SMOOTH_PRE ||
+                p->smoothing == WCAMG_SMOOTH_BOTH,
+            "invalid smoothing");
+    h.smoothing = p->smoothing;
     h.prec = p->prec;
     h.nv = p->nv;
     h.N = 2 * p->nv;

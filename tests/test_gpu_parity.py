@@ -103,11 +103,11 @@ def test_orthonormalize_mixed(prob, nv):
     assert rel(prob.N(out), want) < 2e-5
 
 
-def _hier(prob, nv=4, prec=0, coarse_iters=20, coarse_tol=0.0, seed=17):
+def _hier(prob, nv=4, prec=0, coarse_iters=20, coarse_tol=0.0, seed=17, smoothing=0):
     V = amg.block_orthonormalize(syn.gaussian_vectors(prob.dims, nv, seed), prob.dims, prob.block)
     odd = any((d // b) % 2 for d, b in zip(prob.dims, prob.block))
     p = prob.ctx.setup_params(nv, prec, coarse_iters=coarse_iters, coarse_tol=coarse_tol,
-                              sap_sweeps=0 if odd else 4)
+                              sap_sweeps=0 if odd else 4, smoothing=smoothing)
     prob.ctx.set_test_vectors(prob.T(V), p)
     return V
 
@@ -260,11 +260,15 @@ def test_coarse_solve_fp64(prob):
         assert rel(prob.N(x)[k], want) < 1e-10
 
 
-def test_vcycle_fp64(prob):
+@pytest.mark.parametrize('smoothing', ['post', 'pre', 'both'])
+def test_vcycle_fp64(prob, smoothing):
+    """The FP64 V-cycle with the smoother after (the paper's choice), before,
+    or before and after the coarse-grid step, against the oracle's."""
     if any((d // b) % 2 for d, b in zip(prob.dims, prob.block)):
         pytest.skip('SAP colouring needs an even number of domains per direction')
-    V = _hier(prob, coarse_iters=10, coarse_tol=0.0)
-    mg = amg.TwoLevel(prob.op, V, 4, 6, coarse_iters=10, coarse_tol=0.0)
+    code = {'post': 0, 'pre': 1, 'both': 2}[smoothing]
+    V = _hier(prob, coarse_iters=10, coarse_tol=0.0, smoothing=code)
+    mg = amg.TwoLevel(prob.op, V, 4, 6, coarse_iters=10, coarse_tol=0.0, smoothing=smoothing)
     v = syn.gaussian_vectors(prob.dims, 2, 22)
     out = prob.zeros(v.shape)
     prob.ctx.vcycle(prob.T(v), out, 2)
@@ -338,6 +342,24 @@ def test_flexible_bicgstab_fp64_matches_oracle(prob):
         assert info.relres[k] <= 1e-10
         assert np.linalg.norm(b[k] - prob.op.D(xg[k])) / np.linalg.norm(b[k]) <= 1e-10
         assert rel(xg[k], xo) < 1e-8
+
+
+@pytest.mark.parametrize('smoothing', [1, 2])
+def test_setup_and_solve_mixed_c1_smoothing(smoothing):
+    """Config-1 workload with the smoother before (1), or before and after
+    (2), the coarse-grid step, in setup and solve: FGMRES(16) to 1e-10."""
+    from paper_2111_05012_amd import PREC_MIXED
+    c = syn.CONFIGS['c1']
+    prob = Problem(c['dims'], c['block'], c['eps'], c['seed'], c['kappa'], c['csw'])
+    V0 = syn.gaussian_vectors(prob.dims, c['nv'], c['seed'])
+    prob.ctx.setup(prob.ctx.setup_params(c['nv'], PREC_MIXED, init_vectors=prob.T(V0), smoothing=smoothing))
+    b = syn.z2_source(prob.dims, c['seed'], nrhs=2)
+    x = prob.zeros(b.shape)
+    rc, info = prob.ctx.solve(prob.T(b), x, 2, restart=16, tol=1e-10)
+    assert rc == 0
+    xg = prob.N(x)
+    for k in range(2):
+        assert np.linalg.norm(b[k] - prob.op.D(xg[k])) / np.linalg.norm(b[k]) <= 1e-10
 
 
 def test_flexible_bicgstab_mixed_amg_and_mbicgs_c1():

@@ -186,13 +186,18 @@ def test_bicgstab_converges_to_dense_solution(small):
     assert np.linalg.norm(A @ x - bb) <= 1e-11 * np.linalg.norm(bb)
 
 
-def test_vcycle_error_propagator(small):
+@pytest.mark.parametrize('smoothing', ['post', 'pre', 'both'])
+def test_vcycle_error_propagator(small, smoothing):
     """With an exact coarse solve and exact block solves in SAP (both linear),
-    the preconditioner satisfies 1 - M D = (1 - S D)(1 - P Dc^-1 P^dag D)."""
+    the preconditioner's error propagator 1 - M D is the product of the
+    Richardson steps' (1 - S D) for the smoother and (1 - P Dc^-1 P^dag D)
+    for the coarse grid, in the order of the cycle (post: coarse grid first;
+    pre: smoother first; both: smoother, coarse grid, smoother), built here
+    from dense matrices."""
     op, D = small
     n = D.shape[0]
     V = amg.block_orthonormalize(syn.gaussian_vectors(DIMS, 4, 16), DIMS, BLOCK)
-    mg = amg.TwoLevel(op, V, sap_sweeps=2, coarse='exact')
+    mg = amg.TwoLevel(op, V, sap_sweeps=2, coarse='exact', smoothing=smoothing)
     Ds = od.dense_D(op.U, op.Fb, op.kappa, BC_AP, DIMS, block=BLOCK)
     mg.smoother = lambda r: amg.sap(op, r, 2, block_solver=lambda rc: np.linalg.solve(
         Ds, rc.reshape(-1)).reshape(rc.shape))
@@ -206,7 +211,8 @@ def test_vcycle_error_propagator(small):
     Esap = np.linalg.matrix_power((np.eye(n) - Sc[1] @ D) @ (np.eye(n) - Sc[0] @ D), 2)
     P = _dense_P(V, DIMS, BLOCK)
     Cc = P @ np.linalg.inv(P.conj().T @ D @ P) @ P.conj().T
-    E = Esap @ (np.eye(n) - Cc @ D)
+    Ec = np.eye(n) - Cc @ D
+    E = {'post': Esap @ Ec, 'pre': Ec @ Esap, 'both': Esap @ Ec @ Esap}[smoothing]
     v = syn.gaussian_vectors(DIMS, 1, 17)
     Mv = mg.vcycle(v).reshape(-1)
     want = (np.eye(n) - E) @ np.linalg.solve(D, v.reshape(-1))
