@@ -998,35 +998,30 @@ __global__ __launch_bounds__(256) void k_coarse_build(Geo g, int nv, R kappa, co
 // (8 (v / 4) + 4 (l / 32) + v % 4, l % 32)).  Indices i, j >= nv are padding
 // held at zero in LDS.
 
-//
 // Work units per block X: the in-block part (d = 0) split into nch chunks of
-// site tiles for each sp, then (d, sp) for the 8 crossing directions.  All
-// units of a block are consecutive logical indices on one XCD, so that few
-// blocks are in flight per XCD and their vectors stay in its L2.  A d = 0
-// chunk writes its partial block to part[X][chunk][(sp, j)][(s, i)]; the
-// partials are summed in chunk order by k_coarse_build_sum (deterministic).
+// site tiles, then the 8 crossing directions d.  A unit forms g_j for both
+// source chiralities sp from one set of vector and link loads and contracts
+// all four (s, sp) blocks.  All units of a block are consecutive logical
+// indices on one XCD, so that few blocks are in flight per XCD and their
+// vectors stay in its L2.  A d = 0 chunk writes its partial block to
+// part[X][chunk][(sp, j)][(s, i)]; the partials are summed in chunk order by
+// k_coarse_build_sum (deterministic).
 template <int T>
 __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float kappa, const half2_t* __restrict__ V,
                                                          const half2_t* __restrict__ U,
                                                          const half2_t* __restrict__ C, float2* __restrict__ Dc,
                                                          int nch, int tpc, float2* __restrict__ part) {
   constexpr int K = T * 6;  // k per tile and chirality
-  __shared__ float svr[2][K][32], svi[2][K][32], sgr[2][K][32], sgi[2][K][32];
+  // svr/svi[s][k][i]: v_i; sgr/sgi[sp][s][k][j]: g_j of source chirality sp
+  __shared__ float svr[2][K][32], svi[2][K][32], sgr[2][2][K][32], sgi[2][2][K][32];
   const int N = 2 * nv;
-  const int nu = 2 * nch + 16;
+  const int nu = nch + 8;
   const int nlog = g.nblk * nu;
   const int lg = xcd_remap(blockIdx.x, nlog);
   if (lg >= nlog) return;
   const int X = lg / nu, u = lg - X * nu;
-  int d, sp, chunk = 0;
-  if (u < 2 * nch) {
-    d = 0;
-    sp = u & 1;
-    chunk = u >> 1;
-  } else {
-    d = 1 + ((u - 2 * nch) >> 1);
-    sp = u & 1;
-  }
+  const int d = u < nch ? 0 : 1 + (u - nch);
+  const int chunk = u < nch ? u : 0;
   const int t = threadIdx.x;
   const int Vg = g.V;
   const int mu = (d - 1) & 3;
@@ -1036,18 +1031,19 @@ __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float ka
     nsites = g.Vb;
   else
     nsites = g.NB[mu] == 1 ? 0 : g.Vb / g.B[mu];
-  const int a0 = sp * 6;
   for (int e = t; e < 2 * K * 32; e += 256) {
     (&svr[0][0][0])[e] = 0.f;
     (&svi[0][0][0])[e] = 0.f;
-    (&sgr[0][0][0])[e] = 0.f;
-    (&sgi[0][0][0])[e] = 0.f;
+  }
+  for (int e = t; e < 4 * K * 32; e += 256) {
+    (&sgr[0][0][0][0])[e] = 0.f;
+    (&sgi[0][0][0][0])[e] = 0.f;
   }
   const int w = t >> 6, lane = t & 63;
   const int ws = w >> 1, part_ = w & 1;
-  f32x16 acc;
+  f32x16 acc[2];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+  for (int q = 0; q < 16; ++q) acc[0][q] = acc[1][q] = 0.f;
   __syncthreads();
 
   const int tbeg = d == 0 ? chunk * tpc * T : 0;
@@ -1056,7 +1052,7 @@ __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float ka
     if (t < T * nv) {
       const int j = t / T, st_ = t - j * T;  // lanes run over sites: coalesced vector loads
       const int f = tile0 + st_;
-      cplx<float> vj[12], gj[12];
+      cplx<float> vj[12], g0[12], g1[12];  // g0 / g1: source chirality 0 / 1
       if (f < tend) {
         int loc;
         if (d == 0) {
@@ -1078,33 +1074,50 @@ __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float ka
         const half2_t* vjp = V + (size_t)j * 12 * Vg;
         ld_spinor<float>(vjp, ps, fb12, vj);
         SiteCoord c = decompose(g, sx);
-        cplx<float> psi[12], u[9];
+        cplx<float> psi[12], p0[12], p1[12], u[9];
 #pragma unroll
-        for (int a = 0; a < 12; ++a) gj[a] = {0, 0};
+        for (int a = 0; a < 12; ++a) g0[a] = g1[a] = {0, 0};
         if (d == 0) {
+          // the clover term is block diagonal in chirality: one application
+          // of (1 + F) to v_j, split by rows, serves both sp
 #pragma unroll
-          for (int a = 0; a < 12; ++a) psi[a] = (a >= a0 && a < a0 + 6) ? vj[a] : cplx<float>{0, 0};
+          for (int a = 0; a < 12; ++a) psi[a] = vj[a];
+          clover_acc<float>(C, ps, fb36, vj, psi);
 #pragma unroll
-          for (int a = 0; a < 12; ++a) gj[a] = psi[a];
-          clover_acc<float>(C, ps, fb36, psi, gj);
+          for (int a = 0; a < 12; ++a) {
+            g0[a] = a < 6 ? psi[a] : cplx<float>{0, 0};
+            g1[a] = a < 6 ? cplx<float>{0, 0} : psi[a];
+          }
+          // both hops of direction m are loaded before either is applied
+          // (more loads in flight); a neighbour outside the block reads this
+          // site instead and enters with coefficient zero
 #pragma unroll 1
-          for (int dir = 0; dir < 8; ++dir) {
-            const int m = dir & 3;
-            int sign;
-            bool inb;
-            int nb = dir < 4 ? neighbour<true>(g, sx, c, m, sign, inb) : neighbour<false>(g, sx, c, m, sign, inb);
-            if (!inb) continue;
-            ld_spinor<float>(vjp, ps, fbase_b(g, 12, nb, X), psi);
+          for (int m = 0; m < 4; ++m) {
+            int sf, sb;
+            bool inf, inbk;
+            const int nf = neighbour<true>(g, sx, c, m, sf, inf);
+            const int nk = neighbour<false>(g, sx, c, m, sb, inbk);
+            const int nf_ = inf ? nf : sx, nk_ = inbk ? nk : sx;
+            cplx<float> pk[12], uk[9];
+            ld_spinor<float>(vjp, ps, fbase_b(g, 12, nf_, X), psi);
+            ld_link<float>(U, ps, m, fb36, u);
+            ld_spinor<float>(vjp, ps, fbase_b(g, 12, nk_, X), pk);
+            ld_link<float>(U, ps, m, fbase_b(g, 36, nk_, X), uk);
+            const float cf = inf ? -kappa * (float)sf : 0.f, ck = inbk ? -kappa * (float)sb : 0.f;
 #pragma unroll
-            for (int a = 0; a < 12; ++a)
-              if (a < a0 || a >= a0 + 6) psi[a] = {0, 0};
-            if (dir < 4) {
-              ld_link<float>(U, ps, m, fb36, u);
-              hop_any<true>(m, psi, u, -kappa * (float)sign, gj);
-            } else {
-              ld_link<float>(U, ps, m, fbase_b(g, 36, nb, X), u);
-              hop_any<false>(m, psi, u, -kappa * (float)sign, gj);
+            for (int a = 0; a < 12; ++a) {
+              p0[a] = a < 6 ? psi[a] : cplx<float>{0, 0};
+              p1[a] = a < 6 ? cplx<float>{0, 0} : psi[a];
             }
+            hop_any<true>(m, p0, u, cf, g0);
+            hop_any<true>(m, p1, u, cf, g1);
+#pragma unroll
+            for (int a = 0; a < 12; ++a) {
+              p0[a] = a < 6 ? pk[a] : cplx<float>{0, 0};
+              p1[a] = a < 6 ? cplx<float>{0, 0} : pk[a];
+            }
+            hop_any<false>(m, p0, uk, ck, g0);
+            hop_any<false>(m, p1, uk, ck, g1);
           }
         } else {
           int sign, nblk;
@@ -1113,27 +1126,33 @@ __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float ka
                        : neighbour<false>(g, sx, c, mu, sign, inb, nblk);
           ld_spinor<float>(vjp, ps, fbase_b(g, 12, nb, nblk), psi);
 #pragma unroll
-          for (int a = 0; a < 12; ++a)
-            if (a < a0 || a >= a0 + 6) psi[a] = {0, 0};
+          for (int a = 0; a < 12; ++a) {
+            p0[a] = a < 6 ? psi[a] : cplx<float>{0, 0};
+            p1[a] = a < 6 ? cplx<float>{0, 0} : psi[a];
+          }
           if (fwd) {
             ld_link<float>(U, ps, mu, fb36, u);
-            hop_any<true>(mu, psi, u, -kappa * (float)sign, gj);
+            hop_any<true>(mu, p0, u, -kappa * (float)sign, g0);
+            hop_any<true>(mu, p1, u, -kappa * (float)sign, g1);
           } else {
             ld_link<float>(U, ps, mu, fbase_b(g, 36, nb, nblk), u);
-            hop_any<false>(mu, psi, u, -kappa * (float)sign, gj);
+            hop_any<false>(mu, p0, u, -kappa * (float)sign, g0);
+            hop_any<false>(mu, p1, u, -kappa * (float)sign, g1);
           }
         }
       } else {
 #pragma unroll
-        for (int a = 0; a < 12; ++a) vj[a] = gj[a] = {0, 0};
+        for (int a = 0; a < 12; ++a) vj[a] = g0[a] = g1[a] = {0, 0};
       }
 #pragma unroll
       for (int a = 0; a < 12; ++a) {
         const int s = a / 6, k = st_ * 6 + (a % 6);
         svr[s][k][j] = vj[a].x;
         svi[s][k][j] = vj[a].y;
-        sgr[s][k][j] = gj[a].x;
-        sgi[s][k][j] = gj[a].y;
+        sgr[0][s][k][j] = g0[a].x;
+        sgi[0][s][k][j] = g0[a].y;
+        sgr[1][s][k][j] = g1[a].x;
+        sgi[1][s][k][j] = g1[a].y;
       }
     }
     __syncthreads();
@@ -1143,13 +1162,16 @@ __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float ka
     for (int kk = 0; kk < K; kk += 2) {
       const int k = kk + kh;
       const float ar = svr[ws][k][r], ai = svi[ws][k][r];
-      const float br = sgr[ws][k][r], bi = sgi[ws][k][r];
-      if (part_ == 0) {
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, acc, 0, 0, 0);
-      } else {
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, br, acc, 0, 0, 0);
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) {
+        const float br = sgr[sp][ws][k][r], bi = sgi[sp][ws][k][r];
+        if (part_ == 0) {
+          acc[sp] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, acc[sp], 0, 0, 0);
+          acc[sp] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, acc[sp], 0, 0, 0);
+        } else {
+          acc[sp] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, acc[sp], 0, 0, 0);
+          acc[sp] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, br, acc[sp], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -1160,9 +1182,12 @@ __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float ka
   const size_t blk0 = d == 0 ? (size_t)X * nch + chunk : (size_t)X * 9 + d;
   const int j = lane & 31;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int i = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-    if (i < nv && j < nv) out[2 * ((blk0 * N + (sp * nv + j)) * N + (ws * nv + i)) + part_] = acc[q];
+  for (int sp = 0; sp < 2; ++sp) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int i = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+      if (i < nv && j < nv) out[2 * ((blk0 * N + (sp * nv + j)) * N + (ws * nv + i)) + part_] = acc[sp][q];
+    }
   }
 }
 
@@ -1223,7 +1248,7 @@ void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, cons
     const int tpc = 8;    // tiles per in-block chunk (64 sites)
     const int nch = coarse_build_chunks(g);
     const int N = 2 * nv;
-    k_coarse_build_mf<T><<<dim3(round8(g.nblk * (2 * nch + 16))), 256, 0, st>>>(
+    k_coarse_build_mf<T><<<dim3(round8(g.nblk * (nch + 8))), 256, 0, st>>>(
         g, nv, (float)kappa, (const half2_t*)V, (const half2_t*)U, (const half2_t*)C, (float2*)Dc, nch, tpc,
         (float2*)part);
     const size_t ne = (size_t)g.nblk * N * N;
