@@ -37,6 +37,11 @@ WORKLOADS = {
                nrhs=12, source='point'),
     'c2': dict(dims=(16, 16, 16, 16), eps=0.35, seed=1, kappa=0.1355, csw=1.0, block=(4, 4, 4, 4), nv=16,
                nrhs=1, source='z2'),
+    # a pure-gauge heat-bath field (Wilson action, beta 6.0, 60 sweeps from a
+    # cold start) instead of random links: smooth, physically distributed
+    # gauge fields as a stand-in for the paper's ensembles
+    'hb16': dict(dims=(16, 16, 16, 16), gauge=('heatbath', 6.0, 60), seed=1, kappa=0.1345, csw=1.769,
+                 block=(4, 4, 4, 4), nv=16, nrhs=12, source='point'),
 }
 SETUP = dict(n_init=3, n_adapt=3, sap_sweeps=4, mr_iters=6, coarse_iters=30, coarse_tol=0.1)
 
@@ -45,11 +50,36 @@ def log(*a):
     print('[bench]', *a, file=sys.stderr, flush=True)
 
 
+def gauge_numpy(w, dims):
+    """The workload's gauge field on the host (random links of spread eps, or
+    a heat-bath field), at lattice dims."""
+    import synthetic as syn
+    if 'gauge' not in w:
+        return syn.gauge_field(dims, w['eps'], w['seed'])
+    from synthetic import heatbath as hb
+    kind, beta, sweeps = w['gauge']
+
+    def progress(n, U):
+        if (n + 1) % 10 == 0:
+            log('heat-bath %s beta %g: sweep %d of %d, plaquette %.5f' % ('x'.join(map(str, dims)), beta, n + 1,
+                                                                        sweeps, hb.plaquette(U)))
+    return hb.heatbath_field(dims, beta, sweeps, w['seed'], record=progress)
+
+
+def gauge_desc(w):
+    if 'gauge' in w:
+        return 'heat-bath gauge field (Wilson action, beta %g, %d sweeps)' % (w['gauge'][1], w['gauge'][2])
+    return 'eps %g' % w['eps']
+
+
 def make_inputs(w, dev):
     import torch
     import synthetic as syn
     dims = w['dims']
-    U = syn.gauge_field_torch(dims, w['eps'], w['seed'], dev)
+    if 'gauge' in w:
+        U = torch.from_numpy(gauge_numpy(w, dims)).to(dev)
+    else:
+        U = syn.gauge_field_torch(dims, w['eps'], w['seed'], dev)
     if w['source'] == 'point':
         b = torch.from_numpy(syn.point_sources(dims, w['nrhs'])).to(dev)
     else:
@@ -147,7 +177,7 @@ def cpu_baseline(w, units, gpu_iters):
     scale = syn.volume(w['dims']) / Vs
     bc = (1, 1, 1, -1)
     t_wall0, t_cpu0 = time.perf_counter(), time.process_time()
-    U = syn.gauge_field(dims_s, w['eps'], w['seed'])
+    U = gauge_numpy(w, dims_s)
     Fb = od.clover_blocks(U, w['kappa'], w['csw'])
     op = amg.FineOp(U, Fb, w['kappa'], bc, blk)
     nv = w['nv']
@@ -380,10 +410,10 @@ def main():
         value=round(tts, 4), unit='s', n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=round(tts * 1e3, 2), higher_is_better=False, scaling='weak', vs_baseline=None,
         dtype='f32', data='synthetic',
-        config=dict(workload='%s Wilson-clover AMG solve: %s lattice, eps %g, kappa %g, c_sw %g, %d %s sources, '
+        config=dict(workload='%s Wilson-clover AMG solve: %s lattice, %s, kappa %g, c_sw %g, %d %s sources, '
                              'blocks %s, N_v %d, SAP(4,6), mixed precision (FP16 links/vectors, FP32 inner, '
                              'FP64 FGMRES(16)), tol 1e-10'
-                             % (args.workload, 'x'.join(map(str, w['dims'])), w['eps'], w['kappa'], w['csw'],
+                             % (args.workload, 'x'.join(map(str, w['dims'])), gauge_desc(w), w['kappa'], w['csw'],
                                 w['nrhs'], w['source'], 'x'.join(map(str, w['block'])), w['nv']),
                     global_batch=w['nrhs'], parallelism='single GPU'),
         setup_s=round(sum(t[0] for t in times) / len(times), 4),
