@@ -9,12 +9,12 @@ BC_AP = (1, 1, 1, -1)
 
 
 class Problem:
-    def __init__(self, dims, block, eps=0.5, seed=1, kappa=0.124, csw=1.0, bc=BC_AP):
+    def __init__(self, dims, block, eps=0.5, seed=1, kappa=0.124, csw=1.0, bc=BC_AP, U=None):
         import torch
         from paper_2111_05012_amd import Context
         self.dims, self.block, self.bc = tuple(dims), tuple(block), tuple(bc)
         self.kappa, self.csw = kappa, csw
-        self.U = syn.gauge_field(dims, eps, seed)
+        self.U = syn.gauge_field(dims, eps, seed) if U is None else U
         self.Fb = od.clover_blocks(self.U, kappa, csw)
         self.op = amg.FineOp(self.U, self.Fb, kappa, bc, block)
         self.dev = torch.device('cuda:0')
