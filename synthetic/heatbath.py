@@ -164,3 +164,126 @@ def heatbath_field(dims, beta, sweeps, seed, start=None, record=None):
         if record is not None:
             record(n, U)
     return U
+
+
+# ---------------------------------------------------------------------------
+# The same sampler in torch, for lattices where the host version is too slow
+# (it runs on whatever device the field is on).  Same scheme, update order and
+# layout; its random stream is a torch generator seeded with seed * 1000003 + 7,
+# so its fields are not bit-identical to the numpy version's.
+# ---------------------------------------------------------------------------
+def _t_shift(f, mu, s):
+    import torch
+    return torch.roll(f, shifts=-s, dims=3 - mu)
+
+
+def _t_dag(a):
+    return a.conj().transpose(-1, -2).contiguous()
+
+
+def staple_sum_torch(U, mu):
+    import torch
+    A = torch.zeros_like(U[mu])
+    for nu in range(4):
+        if nu == mu:
+            continue
+        A += _t_shift(U[nu], mu, 1) @ _t_dag(_t_shift(U[mu], nu, 1)) @ _t_dag(U[nu])
+        unm = _t_shift(U[nu], nu, -1)
+        A += _t_dag(_t_shift(unm, mu, 1)) @ _t_dag(_t_shift(U[mu], nu, -1)) @ unm
+    return A
+
+
+def plaquette_torch(U):
+    import torch
+    s = 0.0
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            P = U[mu] @ _t_shift(U[nu], mu, 1) @ _t_dag(_t_shift(U[mu], nu, 1)) @ _t_dag(U[nu])
+            s += float(torch.diagonal(P, dim1=-2, dim2=-1).sum(-1).real.mean()) / 3.0
+    return s / 6.0
+
+
+def kp_x0_torch(alpha, g):
+    import torch
+    out = torch.empty_like(alpha)
+    todo = torch.ones(alpha.shape, dtype=torch.bool, device=alpha.device)
+    while bool(todo.any()):
+        idx = torch.nonzero(todo).flatten()
+        a = alpha[idx]
+        n = a.numel()
+        r1, r2, r3, r4 = (1.0 - torch.rand(n, generator=g, dtype=torch.float64, device=alpha.device)
+                          for _ in range(4))
+        lam2 = -(torch.log(r1) + torch.cos(2.0 * torch.pi * r2) ** 2 * torch.log(r3)) / (2.0 * a)
+        ok = r4 * r4 <= 1.0 - lam2
+        out[idx[ok]] = 1.0 - 2.0 * lam2[ok]
+        todo[idx[ok]] = False
+    return out
+
+
+def _t_su2_from(q0, q1, q2, q3):
+    import torch
+    m = torch.empty(q0.shape + (2, 2), dtype=torch.complex128, device=q0.device)
+    m[..., 0, 0] = torch.complex(q0, q3)
+    m[..., 0, 1] = torch.complex(q2, q1)
+    m[..., 1, 0] = torch.complex(-q2, q1)
+    m[..., 1, 1] = torch.complex(q0, -q3)
+    return m
+
+
+def su2_heatbath_torch(w, beta, g):
+    import torch
+    c0 = (w[..., 0, 0] + w[..., 1, 1]).real / 2
+    c1 = (w[..., 0, 1] + w[..., 1, 0]).imag / 2
+    c2 = (w[..., 0, 1] - w[..., 1, 0]).real / 2
+    c3 = (w[..., 0, 0] - w[..., 1, 1]).imag / 2
+    k = torch.sqrt(c0 * c0 + c1 * c1 + c2 * c2 + c3 * c3)
+    kk = torch.clamp(k, min=1e-300)
+    v = _t_su2_from(c0 / kk, c1 / kk, c2 / kk, c3 / kk)
+    x0 = kp_x0_torch(torch.clamp(2.0 * beta * k / 3.0, min=1e-12), g)
+    dev = k.device
+    ct = 2.0 * torch.rand(k.shape, generator=g, dtype=torch.float64, device=dev) - 1.0
+    ph = 2.0 * torch.pi * torch.rand(k.shape, generator=g, dtype=torch.float64, device=dev)
+    rr = torch.sqrt(torch.clamp(1.0 - x0 * x0, min=0.0))
+    st = torch.sqrt(torch.clamp(1.0 - ct * ct, min=0.0))
+    x = _t_su2_from(x0, rr * st * torch.cos(ph), rr * st * torch.sin(ph), rr * ct)
+    return x @ _t_dag(v)
+
+
+def reunitarize_torch(U):
+    import torch
+    a = U[..., 0, :]
+    a = a / torch.linalg.vector_norm(a, dim=-1, keepdim=True)
+    b = U[..., 1, :]
+    b = b - (a.conj() * b).sum(-1, keepdim=True) * a
+    b = b / torch.linalg.vector_norm(b, dim=-1, keepdim=True)
+    c = torch.stack([a[..., 1] * b[..., 2] - a[..., 2] * b[..., 1],
+                     a[..., 2] * b[..., 0] - a[..., 0] * b[..., 2],
+                     a[..., 0] * b[..., 1] - a[..., 1] * b[..., 0]], dim=-1).conj()
+    return torch.stack([a, b, c], dim=-2)
+
+
+def heatbath_field_torch(dims, beta, sweeps, seed, device, record=None):
+    """As heatbath_field, in torch on `device` (cold start)."""
+    import torch
+    lx, ly, lz, lt = dims
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 1000003 + STREAM_HEATBATH)
+    U = torch.zeros((4, lt, lz, ly, lx, 3, 3), dtype=torch.complex128, device=device)
+    U[..., 0, 0] = U[..., 1, 1] = U[..., 2, 2] = 1.0
+    odd = torch.from_numpy(parity_mask(dims)).to(device)
+    for n in range(sweeps):
+        for mu in range(4):
+            for par in (False, True):
+                sel = odd == par
+                A = staple_sum_torch(U, mu)[sel]
+                Ul = U[mu][sel]
+                for (i, j) in SUBGROUPS:
+                    W = Ul @ A
+                    w = W[:, [i, j]][:, :, [i, j]]
+                    r = su2_heatbath_torch(w, beta, g)
+                    Ul[:, [i, j], :] = r @ Ul[:, [i, j], :]
+                U[mu][sel] = Ul
+        U = reunitarize_torch(U)
+        if record is not None:
+            record(n, U)
+    return U

@@ -76,3 +76,52 @@ def test_strong_coupling_plaquette():
     hb.heatbath_field((4, 4, 4, 4), beta, 60, 5, record=lambda n, U: ps.append(hb.plaquette(U)))
     p = np.mean(ps[10:])
     assert abs(p - (beta / 18 + beta ** 2 / 216)) < 0.003
+
+
+# ---------------------------------------------------------------- the torch version (run here on the CPU)
+def test_torch_kp_sampler_mean():
+    import torch
+    g = torch.Generator()
+    g.manual_seed(21)
+    alpha = 2.0
+    x = hb.kp_x0_torch(torch.full((400000,), alpha, dtype=torch.float64), g)
+    err = float(x.std()) / np.sqrt(x.numel())
+    assert abs(float(x.mean()) - iv(2, alpha) / iv(1, alpha)) < 5 * err
+
+
+def test_torch_su2_update_moment():
+    import torch
+    g = torch.Generator()
+    g.manual_seed(22)
+    beta = 4.0
+    w = np.random.default_rng(23).normal(size=(2, 2)) + 1j * np.random.default_rng(24).normal(size=(2, 2))
+    r = hb.su2_heatbath_torch(torch.from_numpy(w).expand(100000, 2, 2).contiguous(), beta, g).numpy()
+    assert np.abs(np.linalg.det(r) - 1).max() < 1e-13
+    sig = [np.eye(2), np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]), np.array([[1, 0], [0, -1]])]
+    e = [sig[0]] + [1j * s for s in sig[1:]]
+    k = np.sqrt(sum((np.trace(np.conj(b.T) @ w).real / 2) ** 2 for b in e))
+    alpha = 2 * beta * k / 3
+    val = np.trace(r @ w, axis1=-2, axis2=-1).real
+    assert abs(val.mean() - 2 * k * iv(2, alpha) / iv(1, alpha)) < 5 * val.std() / np.sqrt(val.size)
+
+
+def test_torch_staples_and_plaquette_match_numpy():
+    import torch
+    dims = (4, 4, 2, 6)
+    U = syn.gauge_field(dims, 0.8, 3)
+    Ut = torch.from_numpy(U)
+    assert hb.plaquette_torch(Ut) == pytest.approx(hb.plaquette(U), rel=1e-13)
+    for mu in range(4):
+        assert np.abs(hb.staple_sum_torch(Ut, mu).numpy() - hb.staple_sum(U, mu)).max() < 1e-12
+    R = hb.reunitarize_torch(Ut * 1.001).numpy()
+    assert np.abs(R - hb.reunitarize(U * 1.001)).max() < 1e-13
+
+
+def test_torch_strong_coupling_plaquette_and_group():
+    beta = 0.5
+    ps = []
+    U = hb.heatbath_field_torch((4, 4, 4, 4), beta, 40, 5, 'cpu', record=lambda n, U: ps.append(hb.plaquette_torch(U)))
+    assert abs(np.mean(ps[10:]) - (beta / 18 + beta ** 2 / 216)) < 0.004
+    u = U.numpy()
+    assert np.abs(u @ np.conj(np.swapaxes(u, -1, -2)) - np.eye(3)).max() < 1e-12
+    assert np.abs(np.linalg.det(u) - 1).max() < 1e-12
