@@ -724,11 +724,12 @@ __global__ __launch_bounds__(256) void k_coarse_mv(CGeo cg, int N, const TC* __r
 // with v_mfma_f32_32x32x2f32: A = the stencil block (lane l: row l % 32 of
 // column-slice l / 32), B = the neighbour's vectors staged in LDS (lane l:
 // slice l / 32, right-hand side l % 32).  The results pass through LDS so that
-// each right-hand side's 2 nv entries are written contiguously.
-__global__ __launch_bounds__(256) void k_coarse_mv_mf(CGeo cg, int N, const float2* __restrict__ Dc,
-                                                      const float2* __restrict__ x, float2* __restrict__ y,
-                                                      const float2* __restrict__ b, size_t rs, int nrhs,
-                                                      const int* __restrict__ active, int astride) {
+// each right-hand side's 2 nv entries are written contiguously.  Registers
+// are capped for two waves per SIMD (the double-buffered operands would
+// otherwise leave one).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_coarse_mv_mf(
+    CGeo cg, int N, const float2* __restrict__ Dc, const float2* __restrict__ x, float2* __restrict__ y,
+    const float2* __restrict__ b, size_t rs, int nrhs, const int* __restrict__ active, int astride) {
   __shared__ float2 sx[64][33];    // [m][r]
   __shared__ float sy[2][32][65];  // [re, im][r][n]
   const int X = xcd_remap(blockIdx.x, cg.NC);
@@ -752,7 +753,19 @@ __global__ __launch_bounds__(256) void k_coarse_mv_mf(CGeo cg, int N, const floa
   f32x16 acc;
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.f;
-  for (int d = 0; d < 9; ++d) {
+  // the stencil block of the next direction is loaded while the current one
+  // is contracted (all 32 loads of a block in flight at once)
+  auto load_block = [&](int d, float2(&dst)[32]) {
+    const float2* B = Dc + (size_t)(X * 9 + d) * N * N;
+#pragma unroll
+    for (int s = 0; s < 32; ++s) {
+      const int m = 2 * s + (lane >> 5);
+      dst[s] = (m < N && n < N) ? B[(size_t)m * N + n] : make_float2(0.f, 0.f);
+    }
+  };
+  // likewise the neighbour's vectors: thread t holds entries t + 256 q of the
+  // [r][m] tile in registers until they are staged in LDS
+  auto load_x = [&](int d, float2(&dst)[8]) {
     int Y = X;
     if (d > 0) {
       const int mu = (d - 1) & 3;
@@ -761,29 +774,40 @@ __global__ __launch_bounds__(256) void k_coarse_mv_mf(CGeo cg, int N, const floa
       if (cc < 0) cc = cg.N[mu] - 1;
       Y = X + (cc - c[mu]) * cg.sN[mu];
     }
-    for (int e = t; e < 64 * 32; e += 256) {
-      const int r = e >> 6, m = e & 63;
-      float2 v = make_float2(0.f, 0.f);
-      if (r < nrhs && m < N) v = x[(size_t)r * rs + (size_t)Y * N + m];
-      sx[m][r] = v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q, r = e >> 6, m = e & 63;
+      dst[q] = (r < nrhs && m < N) ? x[(size_t)r * rs + (size_t)Y * N + m] : make_float2(0.f, 0.f);
+    }
+  };
+  float2 av[32], an[32], xr[8];
+  load_block(0, av);
+  load_x(0, xr);
+  for (int d = 0; d < 9; ++d) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q;
+      sx[e & 63][e >> 6] = xr[q];
     }
     __syncthreads();
-    const float2* B = Dc + (size_t)(X * 9 + d) * N * N;
-#pragma unroll 4
-    for (int kk = 0; kk < 64; kk += 2) {
-      const int m = kk + (lane >> 5);
-      float2 av = make_float2(0.f, 0.f);
-      if (m < N && n < N) av = B[(size_t)m * N + n];
-      const float2 xb = sx[m][lane & 31];
+    if (d < 8) {
+      load_block(d + 1, an);
+      load_x(d + 1, xr);
+    }
+#pragma unroll
+    for (int s = 0; s < 32; ++s) {
+      const float2 xb = sx[2 * s + (lane >> 5)][lane & 31];
       if (part == 0) {
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, xb.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y, xb.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s].x, xb.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(-av[s].y, xb.y, acc, 0, 0, 0);
       } else {
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, xb.y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, xb.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s].x, xb.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s].y, xb.x, acc, 0, 0, 0);
       }
     }
     __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 32; ++s) av[s] = an[s];
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) sy[part][lane & 31][32 * nt + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3)] = acc[q];
