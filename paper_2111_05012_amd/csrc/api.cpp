@@ -638,6 +638,7 @@ struct wcamg_ctx {
     for (int v : {1, 4, 8, 12, 16})
       if (v == 1 || v <= nrhs + 3) cands.push_back(v);
     if (h.prec == WCAMG_PREC_MIXED && o.N <= 64 && nrhs <= 32) cands.push_back(COARSE_MV_MFMA);
+    if (h.prec == WCAMG_PREC_MIXED && o.N <= 64 && nrhs <= 16) cands.push_back(COARSE_MV_MFMA16);
     char key[160];
     snprintf(key, sizeof(key), "coarse_mv|N%d|NC%d|n%d|p%d|res%d", o.N, o.cg.NC, nrhs, h.prec, b ? 1 : 0);
     int var = tune(key, cands, [&](int v) {

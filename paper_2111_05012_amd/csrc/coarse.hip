@@ -823,6 +823,108 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
+// Matrix-core coarse stencil for nrhs <= 16.  The real and imaginary parts
+// share one 32-column B operand and one accumulator: with A = Re of the
+// stencil block, column c < 16 holds Re x of right-hand side c and column
+// 16 + c its Im x; with A = Im of the block, column c holds -Im x and column
+// 16 + c Re x.  Column c then accumulates Re y and column 16 + c Im y: two
+// products per k-slice give both parts, half the matrix-core work of the
+// 32-wide kernel when there are at most 16 right-hand sides.  Wave w owns rows
+// 32 (w & 1) .. + 31 and the k (= m) half w >> 1; the halves are summed in a
+// fixed order through LDS.  As in k_coarse_mv_mf, the next direction's block
+// and neighbour vectors are loaded while the current one is contracted.
+__global__ __launch_bounds__(256) void k_coarse_mv_mf16(CGeo cg, int N, const float2* __restrict__ Dc,
+                                                        const float2* __restrict__ x, float2* __restrict__ y,
+                                                        const float2* __restrict__ b, size_t rs, int nrhs,
+                                                        const int* __restrict__ active, int astride) {
+  __shared__ float2 sx[64][17];    // [m][r]
+  __shared__ float sy[2][32][65];  // [k half][column][n]
+  const int X = xcd_remap(blockIdx.x, cg.NC);
+  if (X >= cg.NC) return;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  bool any = active == nullptr;
+  for (int r = 0; r < nrhs && !any; ++r) any = active[(size_t)r * astride] != 0;
+  if (!any) return;
+  int c[4];
+  {
+    int q = X;
+    for (int m = 0; m < 3; ++m) {
+      c[m] = q % cg.N[m];
+      q /= cg.N[m];
+    }
+    c[3] = q;
+  }
+  const int nt = w & 1, kh = w >> 1;
+  const int n = 32 * nt + (lane & 31);
+  const int col = lane & 31, rr = col & 15;
+  const bool lo = col < 16;
+  f32x16 acc;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+  auto load_block = [&](int d, float2(&dst)[16]) {
+    const float2* B = Dc + (size_t)(X * 9 + d) * N * N;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int m = 32 * kh + 2 * s + (lane >> 5);
+      dst[s] = (m < N && n < N) ? B[(size_t)m * N + n] : make_float2(0.f, 0.f);
+    }
+  };
+  // thread t stages entries t + 256 q (q < 4) of the [r][m] tile, r < 16
+  auto load_x = [&](int d, float2(&dst)[4]) {
+    int Y = X;
+    if (d > 0) {
+      const int mu = (d - 1) & 3;
+      int cc = c[mu] + (d <= 4 ? 1 : -1);
+      if (cc == cg.N[mu]) cc = 0;
+      if (cc < 0) cc = cg.N[mu] - 1;
+      Y = X + (cc - c[mu]) * cg.sN[mu];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q, r = e >> 6, m = e & 63;
+      dst[q] = (r < nrhs && m < N) ? x[(size_t)r * rs + (size_t)Y * N + m] : make_float2(0.f, 0.f);
+    }
+  };
+  float2 av[16], an[16], xr[4];
+  load_block(0, av);
+  load_x(0, xr);
+  for (int d = 0; d < 9; ++d) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q;
+      sx[e & 63][e >> 6] = xr[q];
+    }
+    __syncthreads();
+    if (d < 8) {
+      load_block(d + 1, an);
+      load_x(d + 1, xr);
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const float2 xv = sx[32 * kh + 2 * s + (lane >> 5)][rr];
+      const float b1 = lo ? xv.x : xv.y, b2 = lo ? -xv.y : xv.x;
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s].x, b1, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s].y, b2, acc, 0, 0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 16; ++s) av[s] = an[s];
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    sy[kh][col][32 * nt + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3)] = acc[q];
+  __syncthreads();
+  for (int e = t; e < 16 * 64; e += 256) {
+    const int r = e >> 6, nn = e & 63;
+    if (r < nrhs && nn < N && (!active || active[(size_t)r * astride])) {
+      const size_t o = (size_t)r * rs + (size_t)X * N + nn;
+      float2 v = make_float2(sy[0][r][nn] + sy[1][r][nn], sy[0][16 + r][nn] + sy[1][16 + r][nn]);
+      if (b) v = make_float2(b[o].x - v.x, b[o].y - v.y);
+      y[o] = v;
+    }
+  }
+}
+
 template <class R, class TC, class TX>
 static void coarse_mv_run(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
                           size_t rs, hipStream_t st, int variant, const int* active, int astride) {
@@ -853,6 +955,13 @@ void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void
       throw std::runtime_error("coarse matvec: the matrix-core path needs complex64, 2 nv <= 64 and nrhs <= 32");
     k_coarse_mv_mf<<<round8(cg.NC), 256, 0, st>>>(cg, N, (const float2*)Dc, (const float2*)x, (float2*)y,
                                                  (const float2*)b, rs, nrhs, active, astride);
+    return;
+  }
+  if (variant == COARSE_MV_MFMA16) {
+    if (!prec32 || N > 64 || nrhs > 16)
+      throw std::runtime_error("coarse matvec: the 16-wide matrix-core path needs complex64, 2 nv <= 64 and nrhs <= 16");
+    k_coarse_mv_mf16<<<round8(cg.NC), 256, 0, st>>>(cg, N, (const float2*)Dc, (const float2*)x, (float2*)y,
+                                                   (const float2*)b, rs, nrhs, active, astride);
     return;
   }
   if (prec32)

@@ -120,9 +120,12 @@ void launch_prolong(const Geo& g, int nv, int nrhs, const void* V, int v_t, cons
 // coarse 9-point stencil: y[r][X] = sum_d Dc[X][d] x[r][X+e_d]   (or y = b - Dc x)
 // Dc stored [X][d][m][n] (column-major blocks), vectors [nrhs][NC][N]
 // variant: right-hand sides per thread (0: automatic; else 1, 4, 8, 12 or 16), or
-// COARSE_MV_MFMA (complex64, 2 nv <= 64, nrhs <= 32: matrix cores).
+// COARSE_MV_MFMA (complex64, 2 nv <= 64, nrhs <= 32: matrix cores) or
+// COARSE_MV_MFMA16 (the same for nrhs <= 16, real and imaginary parts in one
+// 32-column operand).
 // active (optional): per-rhs flags at active[r * astride]; rhs with a zero flag are skipped.
 constexpr int COARSE_MV_MFMA = -1;
+constexpr int COARSE_MV_MFMA16 = -2;
 void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void* y, const void* b, int nrhs,
                       size_t rs, int prec32, hipStream_t st, int variant = 0, const int* active = nullptr,
                       int astride = 0);

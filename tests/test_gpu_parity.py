@@ -213,17 +213,17 @@ def test_coarse_operator_mixed_every_variant(prob, nv, tmp_path):
     prob.ctx.autotune(False, None)
 
 
+@pytest.mark.parametrize('nv', [8, 32])
 @pytest.mark.parametrize('nrhs', [3, 12])
-def test_apply_coarse_mixed_every_variant(prob, nrhs, tmp_path):
+def test_apply_coarse_mixed_every_variant(prob, nrhs, nv, tmp_path):
     """Mixed-precision coarse stencil (complex64) in every launch variant
-    (right-hand sides per thread and the matrix-core kernel), forced through
-    the tuner's cache file, against the oracle's 9-point stencil with the
-    library's own coarse operator."""
+    (right-hand sides per thread and the two matrix-core kernels), forced
+    through the tuner's cache file, against the oracle's 9-point stencil with
+    the library's own coarse operator."""
     import json
     from paper_2111_05012_amd import PREC_MIXED
     cache = str(tmp_path / 'tune.json')
     prob.ctx.autotune(True, cache)
-    nv = 8
     _hier(prob, nv=nv, prec=PREC_MIXED)
     nX = amg.n_blocks(prob.dims, prob.block)
     Dc = prob.zeros((nX, 9, 2 * nv, 2 * nv))
@@ -236,7 +236,7 @@ def test_apply_coarse_mixed_every_variant(prob, nrhs, tmp_path):
     prob.ctx.apply_coarse(prob.T(x), y, nrhs)
     keys = json.load(open(cache))
     assert any(k.split('|')[1] == 'coarse_mv' for k in keys)
-    for v in (1, 4, 8, 12, 16, -1):
+    for v in (1, 4, 8, 12, 16, -1, -2):
         forced = {k: (v if k.split('|')[1] == 'coarse_mv' else val) for k, val in keys.items()}
         with open(cache, 'w') as f:
             json.dump(forced, f)
