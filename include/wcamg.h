@@ -292,7 +292,8 @@ int wcamg_autotune_info(wcamg_ctx* ctx, double* tune_ms, int* keys_tuned, int* k
  * roofline measurements: enable (1) / disable (0, also clears nothing).
  * When enabled, the work of each class is bracketed by events: "dslash64",
  * "dslash32" (one launch of the fine operator), "sap_half" (one SAP
- * half-sweep launch), "restrict", "prolong", "coarse_mv",
+ * half-sweep launch: the domain solves), "sap_cross" (the crossing-hop
+ * correction launched before a mixed half-sweep), "restrict", "prolong", "coarse_mv",
  * "coarse_solve" (one whole coarse BiCGStab), "coarse_build" (one coarse
  * operator construction), "ortho" (one block orthonormalisation).  Classes
  * nest ("coarse_mv" launches inside "coarse_solve" are recorded in both),
