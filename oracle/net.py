@@ -21,7 +21,9 @@ by the library:
 Pins (tests/test_oracle_net.py): transport adjointness (T_d^dag = T_{-d});
 gauge equivariance net(U^Om, Om r) = Om net(U, r); loss invariant under a
 change of basis of the output and of the teacher, 0 when the teacher lies in
-span(A); the backward against central finite differences of the loss.
+span(A); the backward against central finite differences of the loss;
+Adam against iterates worked out by hand for gradient sequences that separate
+beta1 and beta2.
 """
 import numpy as np
 

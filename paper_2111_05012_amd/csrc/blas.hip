@@ -296,14 +296,17 @@ void launch_bicg_s(void* s, const void* r, const void* v, int t, size_t n, size_
                                                               sc);
 }
 
-// omega = <t,s>/<t,t>, enlarged to omega*stab/|cos| when |cos(t,s)| < stab
+// omega = <t,s>/<t,t>, enlarged to omega*stab/|cos| when |cos(t,s)| < stab.
+// t = 0 or <t,s> = 0 (with s != 0) is a breakdown: omega = 0 (the enlarged
+// omega would be 0 * stab / 0) and this is the right-hand side's last step,
+// which keeps x + alpha p.
 __global__ void k_bicg_omega_fin(const double2* part, int nwg, BicgScal* sc, double stab) {
   int r = blockIdx.x;
   if (threadIdx.x != 0 || !sc[r].active) return;
   cplx<double> ts = sum_parts(part, nwg, 3, r, 0);
   double tt = sum_parts(part, nwg, 3, r, 1).x;
   double ss = sum_parts(part, nwg, 3, r, 2).x;
-  if (tt == 0.0) {
+  if (tt == 0.0 || (ts.x == 0.0 && ts.y == 0.0)) {
     sc[r].omega = make_double2(0.0, 0.0);
     sc[r].final_step = 1;
     return;

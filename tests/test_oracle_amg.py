@@ -322,3 +322,128 @@ def test_three_level_solve_matches_dense_lu(small):
     assert np.linalg.norm(x.reshape(-1) - want) <= np.linalg.cond(D) * 1e-10 * np.linalg.norm(want)
     _, its_plain, _ = amg.fgmres(op.D, lambda v: v, b, tol=1e-10, restart=16)
     assert its < its_plain
+
+
+# ---------------------------------------------------------------- the omega stabilisation of step (1b)
+def _first_step(A, b):
+    """alpha, s and t of the first BiCGStab step from x = 0 (p = r = r~ = b)."""
+    v = A @ b
+    alpha = np.vdot(b, b) / np.vdot(b, v)
+    s = b - alpha * v
+    return alpha, s, A @ s
+
+
+def _rotations(n2, cos_t):
+    c, d = cos_t, np.sqrt(1 - cos_t ** 2)
+    return np.kron(np.eye(n2), np.array([[c, -d], [d, c]])).astype(complex)
+
+
+@pytest.mark.parametrize('case', ['rot50', 'rot90pct', 'nonnormal'])
+def test_bicgstab_omega_stabilisation_residual_ratio(case):
+    """After one step from x = 0 the residual is s - omega t.  With the
+    minimising omega = <t,s>/<t,t> its squared norm relative to ||s||^2 is
+    1 - rho^2, rho = |cos(t, s)|.  Sleijpen and van der Vorst enlarge omega
+    by stab/rho whenever rho < stab = 0.7, which makes the ratio
+    1 - 2 (0.7 rho) + 0.7^2 = 1.49 - 1.4 rho.  Both branches are checked, and
+    that the enlarged one differs from the plain one."""
+    rng = np.random.default_rng(5)
+    if case == 'rot50':
+        A, b = _rotations(20, 0.5), rng.standard_normal(40) + 0j  # rho = 0.5 exactly
+    elif case == 'rot90pct':
+        A, b = _rotations(20, 0.9), rng.standard_normal(40) + 0j  # rho = 0.9: no enlargement
+    else:
+        A = (np.diag(np.exp(2j * np.pi * rng.random(50))) + 0.2 * np.diag(rng.standard_normal(49), 1)
+             + 0.05 * (rng.standard_normal((50, 50)) + 1j * rng.standard_normal((50, 50))))
+        b = rng.standard_normal(50) + 1j * rng.standard_normal(50)
+    _, s, t = _first_step(A, b)
+    rho = abs(np.vdot(t, s)) / (np.linalg.norm(t) * np.linalg.norm(s))
+    x1, its = amg.bicgstab(lambda z: A @ z, b, 1)
+    assert its == 1
+    ratio = np.linalg.norm(b - A @ x1) ** 2 / np.linalg.norm(s) ** 2
+    if case == 'rot50':
+        assert abs(rho - 0.5) < 1e-12
+    if case == 'rot90pct':
+        assert abs(rho - 0.9) < 1e-12
+        assert abs(ratio - (1 - rho ** 2)) < 1e-12
+    else:
+        assert rho < 0.7  # the stabilisation engages
+        assert abs(ratio - (1.49 - 1.4 * rho)) < 1e-12
+        assert abs(ratio - (1 - rho ** 2)) > 1e-3
+
+
+def test_bicgstab_stops_when_t_is_orthogonal_to_s():
+    """<t, s> = 0 with t != 0: the minimising omega is 0 and the enlarged one
+    undefined (0 * 0.7 / 0); the next beta would divide by omega.  The
+    solver keeps x + alpha p and stops instead of producing a NaN.  The
+    operator is a stub returning chosen vectors: v = (1, 1) for p = b =
+    (1, 0) gives alpha = 1 and s = (0, -1); t = (1, 0) is orthogonal to s."""
+    calls = []
+
+    def stub(z):
+        calls.append(z.copy())
+        return np.array([1.0 + 0j, 1.0]) if len(calls) == 1 else np.array([1.0 + 0j, 0.0])
+
+    b = np.array([1.0 + 0j, 0.0])
+    x, its = amg.bicgstab(stub, b, 5)
+    assert len(calls) == 2 and its == 1
+    assert np.all(np.isfinite(x)) and np.abs(x - b).max() == 0.0
+
+
+# ---------------------------------------------------------------- setup (0-a), (0-b) as dense algebra
+def _block_qr(V, dims, block):
+    """Per block X and chirality s, the QR factorisation of the columns
+    P_s v_i restricted to X in the order i = 1..N_v, with a positive real R
+    diagonal (numpy's Householder QR, signs fixed)."""
+    Vb = amg.to_blocks(V, dims, block)
+    out = np.empty_like(Vb)
+    for X in range(Vb.shape[1]):
+        for s in (0, 1):
+            q, r = np.linalg.qr(Vb[:, X, s, :].T)
+            out[:, X, s, :] = (q * (np.diag(r) / np.abs(np.diag(r)))).T
+    return amg.from_blocks(out, dims, block)
+
+
+def test_setup_equals_dense_construction(small):
+    """With exact SAP block solves and an exact coarse solve every step of the
+    setup is linear algebra that can be written with dense matrices:
+      (0-a) SAP = (1 - E_sap) D^-1 with E_sap = [(1 - S_o D)(1 - S_e D)]^n
+            (red-black block Gauss-Seidel, S_c the inverse of D on the
+            colour-c domains), applied n_init times to V0, then a blockwise QR;
+      (0-b) M = (1 - E_sap (1 - P (P^dag D P)^-1 P^dag D)) D^-1 (coarse grid
+            then smoother) applied to every vector, then the blockwise QR,
+            n_adapt times, P rebuilt from the new vectors each time.
+    The oracle's setup must give the same vectors."""
+    op, D = small
+    n = D.shape[0]
+    sweeps, n_init, n_adapt, nv = 2, 2, 2, 4
+    col = _colour_index(DIMS, BLOCK)
+    S = []
+    for c in (0, 1):
+        idx = np.where(col == c)[0]
+        Sc = np.zeros((n, n), complex)
+        Sc[np.ix_(idx, idx)] = np.linalg.inv(D[np.ix_(idx, idx)])
+        S.append(Sc)
+    I = np.eye(n)
+    Esap = np.linalg.matrix_power((I - S[1] @ D) @ (I - S[0] @ D), sweeps)
+    Dinv = np.linalg.inv(D)
+    Msap = (I - Esap) @ Dinv
+    V0 = syn.gaussian_vectors(DIMS, nv, 61)
+    shp = V0.shape
+    W = V0.reshape(nv, n).T
+    for _ in range(n_init):
+        W = Msap @ W
+    V = _block_qr(W.T.reshape(shp), DIMS, BLOCK)
+    for _ in range(n_adapt):
+        P = _dense_P(V, DIMS, BLOCK)
+        Ec = I - P @ np.linalg.solve(P.conj().T @ D @ P, P.conj().T @ D)
+        M = (I - Esap @ Ec) @ Dinv
+        V = _block_qr((M @ V.reshape(nv, n).T).T.reshape(shp), DIMS, BLOCK)
+
+    Ds_inv = np.linalg.inv(od.dense_D(op.U, op.Fb, op.kappa, BC_AP, DIMS, block=BLOCK))
+
+    def exact_block(rc):
+        return (Ds_inv @ rc.reshape(-1, n).T).T.reshape(rc.shape)
+
+    mg = amg.setup(op, V0, n_init=n_init, n_adapt=n_adapt, sap_sweeps=sweeps, coarse='exact',
+                   block_solver=exact_block)
+    assert np.abs(mg.V - V).max() < 1e-9 * np.abs(V).max()

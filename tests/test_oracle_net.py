@@ -99,3 +99,32 @@ def test_adam_reduces_loss():
         gWs, _ = net.backward(U, Ws, acts, g, BC)
         Ws = opt.step(Ws, gWs)
     assert losses[-1] < losses[0]
+
+
+def test_adam_matches_hand_computed_iterates():
+    """Adam as Kingma and Ba define it (Algorithm 1; beta1 0.9, beta2 0.999,
+    eps 1e-8) on one complex weight, whose real and imaginary parts see the
+    real gradient sequences (1, -1, 1) and (1, 2, 2).  Bias-corrected
+    moments, worked out by hand from the recursions m_t = b1 m_{t-1} +
+    (1 - b1) g_t, v_t = b2 v_{t-1} + (1 - b2) g_t^2:
+      (1, -1, 1): m_hat = 1, -(1 - b1)/(1 + b1) = -1/19,
+                  (b1^2 - b1 + 1)/(1 + b1 + b1^2) = 91/271; v_hat = 1 always;
+      (1, 2, 2):  m_hat = 1, (b1 + 2)/(1 + b1) = 29/19,
+                  (b1^2 + 2 b1 + 2)/(1 + b1 + b1^2) = 461/271;
+                  v_hat = 1, (b2 + 4)/(1 + b2) = 4.999/1.999,
+                  (b2^2 + 4 b2 + 4)/(1 + b2 + b2^2) = 8.994001/2.997001.
+    Each step moves a part by -lr m_hat / (sqrt(v_hat) + eps).  A wrong
+    beta1 changes the first sequence's steps, a wrong beta2 the second's."""
+    lr, eps = 0.01, 1e-8
+    re_g, im_g = (1.0, -1.0, 1.0), (1.0, 2.0, 2.0)
+    mh_re = (1.0, -1.0 / 19.0, 91.0 / 271.0)
+    mh_im = (1.0, 29.0 / 19.0, 461.0 / 271.0)
+    vh_im = (1.0, 4.999 / 1.999, 8.994001 / 2.997001)
+    W = [np.array([0.3 + 0.7j])]
+    want = W[0].copy()
+    opt = net.Adam(lr=lr)
+    for t in range(3):
+        # the oracle's gradients are dL/d conj(W): the real gradient of a part is twice its part
+        W = opt.step(W, [np.array([0.5 * re_g[t] + 0.5j * im_g[t]])])
+        want = want - lr * (mh_re[t] / (1.0 + eps) + 1j * mh_im[t] / (np.sqrt(vh_im[t]) + eps))
+        assert abs(W[0][0] - want[0]) < 1e-15, t
