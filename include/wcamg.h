@@ -187,12 +187,25 @@ int wcamg_get_coarse_op(wcamg_ctx* ctx, int level, void* Dc, int where);
 int wcamg_set_level1_vectors(wcamg_ctx* ctx, const void* W, int where);
 /* Copy the level-1 test vectors out (complex128 [nv1][NC][2nv]). */
 int wcamg_get_level1_vectors(wcamg_ctx* ctx, void* W, int where);
-/* out = Dc in on coarse vectors (the 9-point block stencil). */
-int wcamg_apply_coarse(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int where);
-/* x = coarse solve of Dc x = b: BiCGStab from x = 0 with the stabilised
- * omega (Sec. 3 step (1b)), at most iters iterations, stopping per
- * right-hand side at ||r|| <= tol ||b||. */
-int wcamg_coarse_solve(wcamg_ctx* ctx, const void* b, void* x, int nrhs, int iters, double tol, int where);
+/* Replace the coarse operator of a level (1: Dc of eq. (7); 2: the level-2
+ * operator of a three-level hierarchy) by Dc (the canonical coarse-operator
+ * layout, complex128), converted to the hierarchy's coarse precision
+ * (complex64 with round to nearest even in mixed precision).  Component test
+ * hook: the coarse matvec, the coarse solve and the V-cycle then use it; the
+ * level-2 operator is not rebuilt from a replaced level 1, and the next
+ * setup or set_test_vectors builds both anew.  ESTATE without a hierarchy
+ * (or without level 2 when level = 2). */
+int wcamg_set_coarse_op(wcamg_ctx* ctx, int level, const void* Dc, int where);
+/* out = D_c in on coarse vectors of a level (1 or 2, as above): the 9-point
+ * block stencil y(X) = sum_d D_c(X, X + e_d) x(X + e_d) of eq. (7);
+ * complex128 [nrhs][NC][2nv] (level 2: [nrhs][NC2][2nv1]). */
+int wcamg_apply_coarse(wcamg_ctx* ctx, int level, const void* in, void* out, int nrhs, int where);
+/* x = coarse solve of D_c x = b on a level (1 or 2): BiCGStab from x = 0 with
+ * the stabilised omega (Sec. 3 step (1b)), at most iters iterations,
+ * stopping per right-hand side at ||r|| <= tol ||b||; in mixed precision in
+ * FP32 on the complex64 operator. */
+int wcamg_coarse_solve(wcamg_ctx* ctx, int level, const void* b, void* x, int nrhs, int iters, double tol,
+                       int where);
 /* out = M in: one application of the multigrid preconditioner, Sec. 3
  * steps (1a)-(1c) then (2). */
 int wcamg_vcycle(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int where);
@@ -203,6 +216,8 @@ typedef struct {
   int max_iters; /* total Arnoldi steps per right-hand side */
   int rhs_chunk; /* right-hand sides per batch (0: all) */
   int use_graph; /* capture the V-cycle in a HIP graph and replay it */
+  int phase_times; /* nonzero: time the solve's phases (the info's t_precond ... t_outer) with HIP
+                      events; the V-cycles then run without graphs */
 } wcamg_solve_params;
 
 #define WCAMG_MAX_RHS 64
@@ -212,6 +227,16 @@ typedef struct {
   int converged[WCAMG_MAX_RHS];
   int vcycles;                     /* preconditioner applications (batched) */
   double t_solve;                  /* seconds, wall clock of the whole solve */
+  /* Seconds per phase of the solve, in the split of the paper's Table 1
+   * (Sec. 5), measured with HIP events on the context's stream when the
+   * solve parameters ask for phase_times, else 0.  t_precond: every
+   * application of the preconditioner M; within it t_coarse: the coarse
+   * solves (step (1b); with three levels, the whole level-1 cycle),
+   * t_smoother: the SAP smoother (step (2)), t_rp: restriction and
+   * prolongation (steps (1a), (1c)), t_prec_other: the rest of M (the
+   * residual with D before the smoother, conversions); t_outer = t_solve -
+   * t_precond: the outer solver (FP64 D, orthogonalisation, host work). */
+  double t_precond, t_coarse, t_smoother, t_rp, t_prec_other, t_outer;
 } wcamg_solve_info;
 
 /* Solve D x = b for nrhs right-hand sides (canonical layout, DEVICE
@@ -222,7 +247,7 @@ typedef struct {
 int wcamg_solve(wcamg_ctx* ctx, const void* b, void* x, int nrhs, const wcamg_solve_params* p,
                 wcamg_solve_info* info);
 
-/* The paper's own outer solver (Sec. 2, "BiCGStab algorithm with flexible
+/* The paper's own outer solver (Sec. 3, "BiCGStab algorithm with flexible
  * preconditioning", after Vogel 2007) in FP64, from x = 0, with the shadow
  * vector r~ = b and the listing's last line read as
  * p <- r + beta (p - omega D M p).  The preconditioner M is
@@ -247,6 +272,7 @@ typedef struct {
   int precond;       /* WCAMG_PC_AMG or WCAMG_PC_BICG32 */
   int inner_iters;   /* WCAMG_PC_BICG32: iterations of the inner solve (>= 1) */
   double inner_tol;  /* WCAMG_PC_BICG32: relative residual of the inner solve */
+  int phase_times;   /* as in wcamg_solve_params (WCAMG_PC_AMG splits t_precond) */
 } wcamg_bicg_params;
 int wcamg_solve_bicgstab(wcamg_ctx* ctx, const void* b, void* x, int nrhs, const wcamg_bicg_params* p,
                          wcamg_solve_info* info);

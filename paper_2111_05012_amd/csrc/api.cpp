@@ -456,6 +456,48 @@ struct wcamg_ctx {
       }
     }
   };
+  // ---- solve phases (Table 1's split of the solve time), timed with events
+  // on the library stream while phase_on is set (V-cycles then run without
+  // graphs)
+  enum { PH_PRECOND = 0, PH_COARSE, PH_SMOOTH, PH_RP, PH_N };
+  bool phase_on = false;
+  struct PhaseEv {
+    int ph;
+    hipEvent_t a, b;
+  };
+  std::vector<PhaseEv> phase_pending;
+  double phase_ms[PH_N] = {0, 0, 0, 0};
+  struct Phase {
+    wcamg_ctx* c;
+    int ph;
+    hipEvent_t a = nullptr, b = nullptr;
+    Phase(wcamg_ctx* c_, int p) : c(c_), ph(p) {
+      if (c->phase_on && !c->capturing) {
+        a = c->ev();
+        b = c->ev();
+        HIPCHK(hipEventRecord(a, c->st));
+      }
+    }
+    ~Phase() {
+      if (a) {
+        (void)hipEventRecord(b, c->st);
+        c->phase_pending.push_back({ph, a, b});
+      }
+    }
+  };
+  void collect_phases() {
+    if (phase_pending.empty()) return;
+    HIPCHK(hipStreamSynchronize(st));
+    for (auto& p : phase_pending) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+      phase_ms[p.ph] += ms;
+      evpool.push_back(p.a);
+      evpool.push_back(p.b);
+    }
+    phase_pending.clear();
+  }
+
   void collect_timing() {
     if (pending.empty()) return;
     HIPCHK(hipStreamSynchronize(st));
@@ -572,7 +614,19 @@ struct wcamg_ctx {
           launch_sap_cross(a, sw, col, st);
         }
         double by = 0.5 * g.V * (fld + nrhs * 12.0 * sb * (4.0 + xr));
-        double fl = 0.5 * g.V * nrhs * (mr * 2200.0 + (a.mixed ? 0.0 : 400.0));
+        // per site of the active colour, RHS and MR iteration: D_SAP with its
+        // in-domain hops only (sum over mu of 2 (B_mu - 1) / B_mu hops of 165
+        // flop each, plus 552 for the clover and 48 for the identity and the
+        // sums) and MR's vector work (<p, r>, <p, p>, x += alpha r,
+        // r -= alpha p: 336 flop); the FP64 kernel also applies the
+        // crossing-hop correction (~240 flop per crossing hop)
+        double hops_in = 0, hops_x = 0;
+        for (int m = 0; m < 4; ++m) {
+          hops_in += 2.0 * (g.B[m] - 1) / g.B[m];
+          hops_x += 2.0 / g.B[m];
+        }
+        double fl = 0.5 * g.V * nrhs *
+                    (mr * (165.0 * hops_in + 600.0 + 336.0) + (a.mixed || (sw == 0 && col == 0) ? 0.0 : 240.0 * hops_x));
         Timed t(this, "sap_half", by, fl, nrhs);
         launch_sap_half(a, sw, col, st);
       }
@@ -633,7 +687,10 @@ struct wcamg_ctx {
 
   void coarse_mv(const COp& o, const void* x, void* y, const void* b, int nrhs, const BicgScal* live = nullptr) {
     double nc = o.cg.NC, N = o.N, cb = ct_size(crs_t());
-    double by = nc * 9 * N * N * cb + nrhs * nc * N * cb * (b ? 3 : 2);
+    // compulsory operator bytes: the self block and the 4 forward blocks,
+    // from which coarse gamma_5-hermiticity gives the backward ones (the
+    // library stores and streams all 9)
+    double by = nc * 5 * N * N * cb + nrhs * nc * N * cb * (b ? 3 : 2);
     std::vector<int> cands;
     for (int v : {1, 4, 8, 12, 16})
       if (v == 1 || v <= nrhs + 3) cands.push_back(v);
@@ -770,29 +827,41 @@ struct wcamg_ctx {
     void* x1 = W("vc_x1", fsz(nrhs, prec));
     void* r = W("vc_r", fsz(nrhs, prec));
     auto coarse = [&](const void* rhs) {
-      restrict_(rhs, vc, nrhs);
+      {
+        Phase ph(this, PH_RP);
+        restrict_(rhs, vc, nrhs);
+      }
+      Phase ph(this, PH_COARSE);
       if (h.l1)
         vcycle1(vc, xc, nrhs);
       else
         coarse_solve(vc, xc, nrhs, h.coarse_iters, h.coarse_tol);
     };
+    auto prolong_p = [&](void* x, int acc) {
+      Phase ph(this, PH_RP);
+      prolong_(xc, x, nrhs, acc);
+    };
+    auto smooth = [&](const void* rhs, void* x, const void* x0) {
+      Phase ph(this, PH_SMOOTH);
+      sap(rhs, x, x0, nrhs, h.sap_sweeps, h.mr_iters, prec);
+    };
     if (h.smoothing == WCAMG_SMOOTH_POST) {
       coarse(in);
-      prolong_(xc, x1, nrhs);
+      prolong_p(x1, 0);
       dslash(x1, t, r, t, nrhs, OP_D, prec, in);
-      sap(r, out, x1, nrhs, h.sap_sweeps, h.mr_iters, prec);
+      smooth(r, out, x1);
       return;
     }
     // smoother first: x = M_2 in, then x += M_1 (in - D x)
     void* x = h.smoothing == WCAMG_SMOOTH_PRE ? out : x1;
-    sap(in, x, nullptr, nrhs, h.sap_sweeps, h.mr_iters, prec);
+    smooth(in, x, nullptr);
     dslash(x, t, r, t, nrhs, OP_D, prec, in);
     coarse(r);
-    prolong_(xc, x, nrhs, 1);
+    prolong_p(x, 1);
     if (h.smoothing == WCAMG_SMOOTH_BOTH) {
       // and the smoother again: out = x + M_2 (in - D x)
       dslash(x, t, r, t, nrhs, OP_D, prec, in);
-      sap(r, out, x, nrhs, h.sap_sweeps, h.mr_iters, prec);
+      smooth(r, out, x);
     }
   }
 
@@ -1148,6 +1217,7 @@ static int apply_op(wcamg_ctx* c, const void* in, void* out, int nrhs, int prec,
 int wcamg_apply_D(wcamg_ctx* c, const void* in, void* out, int nrhs, int prec, int where) {
   return apply_op(c, in, out, nrhs, prec, where, OP_D);
 }
+
 int wcamg_apply_Dsap(wcamg_ctx* c, const void* in, void* out, int nrhs, int prec, int where) {
   return apply_op(c, in, out, nrhs, prec, where, OP_DSAP);
 }
@@ -1427,44 +1497,79 @@ int wcamg_get_level1_vectors(wcamg_ctx* c, void* Wv, int where) {
   });
 }
 
-int wcamg_apply_coarse(wcamg_ctx* c, const void* in, void* out, int nrhs, int where) {
+// the coarse operator of a level (1: Dc; 2: the level-2 operator of a
+// three-level hierarchy), with the state checks of the coarse-level entry points
+static COp level_op(wcamg_ctx* c, int level) {
+  require(level == 1 || level == 2, "level must be 1 or 2");
+  require(c->have_hier, "no hierarchy", WCAMG_ESTATE);
+  require(level == 1 || c->h.l1, "no level-2 operator (nlevels < 3)", WCAMG_ESTATE);
+  return level == 1 ? c->op1() : c->op2();
+}
+
+int wcamg_set_coarse_op(wcamg_ctx* c, int level, const void* Dc, int where) {
+  if (!c) return WCAMG_EINVAL;
+  return guard(c, [&] {
+    check_where(where);
+    require(Dc, "null pointer");
+    COp o = level_op(c, level);
+    int N = o.N;
+    size_t nel = (size_t)o.cg.NC * 9 * N * N;
+    std::vector<double2> hst(nel), tr(nel);
+    HIPCHK(hipMemcpy(hst.data(), Dc, nel * sizeof(double2),
+                     where == WCAMG_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+    // canonical [X][d][n][m] -> internal [X][d][m][n]
+    for (size_t xd = 0; xd < (size_t)o.cg.NC * 9; ++xd)
+      for (int m = 0; m < N; ++m)
+        for (int n = 0; n < N; ++n) tr[(xd * N + m) * N + n] = hst[(xd * N + n) * N + m];
+    void* tmp = c->W("gc_tmp", nel * sizeof(double2));
+    HIPCHK(hipMemcpyAsync(tmp, tr.data(), nel * sizeof(double2), hipMemcpyHostToDevice, c->st));
+    launch_convert(tmp, C128, o.Dc, c->crs_t(), nel, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+  });
+}
+
+int wcamg_apply_coarse(wcamg_ctx* c, int level, const void* in, void* out, int nrhs, int where) {
   if (!c) return WCAMG_EINVAL;
   return guard(c, [&] {
     check_where(where);
     check_nrhs(nrhs);
     require(in && out && in != out, "null or aliasing pointers");
-    require(c->have_hier, "no hierarchy", WCAMG_ESTATE);
-    size_t cb = (size_t)nrhs * c->crs_n() * sizeof(double2);
+    COp o = level_op(c, level);
+    size_t n = (size_t)nrhs * o.n();
+    size_t cb = n * sizeof(double2);
     HostIO io(c);
     const double2* ind = (const double2*)io.in(in, cb, where, "io_in");
     double2* outd = (double2*)io.out(out, cb, where, "io_out");
-    void* a = c->W("ap_c", c->csz(nrhs));
-    void* b = c->W("ap_c2", c->csz(nrhs));
-    launch_convert(ind, C128, a, c->crs_t(), (size_t)nrhs * c->crs_n(), c->st);
-    c->coarse_mv(a, b, nullptr, nrhs);
-    launch_convert(b, c->crs_t(), outd, C128, (size_t)nrhs * c->crs_n(), c->st);
+    void* a = c->W("ap_c", c->csz(o, nrhs));
+    void* b = c->W("ap_c2", c->csz(o, nrhs));
+    launch_convert(ind, C128, a, c->crs_t(), n, c->st);
+    c->coarse_mv(o, a, b, nullptr, nrhs);
+    launch_convert(b, c->crs_t(), outd, C128, n, c->st);
     HIPCHK(hipGetLastError());
     io.finish(out, outd, cb, where);
   });
 }
 
-int wcamg_coarse_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, int iters, double tol, int where) {
+int wcamg_coarse_solve(wcamg_ctx* c, int level, const void* b, void* x, int nrhs, int iters, double tol,
+                       int where) {
   if (!c) return WCAMG_EINVAL;
   return guard(c, [&] {
     check_where(where);
     check_nrhs(nrhs);
     require(b && x && b != x, "null or aliasing pointers");
     require(iters >= 0 && std::isfinite(tol) && tol >= 0, "invalid iteration count or tolerance");
-    require(c->have_hier, "no hierarchy", WCAMG_ESTATE);
-    size_t cb = (size_t)nrhs * c->crs_n() * sizeof(double2);
+    COp o = level_op(c, level);
+    size_t n = (size_t)nrhs * o.n();
+    size_t cb = n * sizeof(double2);
     HostIO io(c);
     const double2* bd = (const double2*)io.in(b, cb, where, "io_in");
     double2* xd = (double2*)io.out(x, cb, where, "io_out");
-    void* a = c->W("ap_c", c->csz(nrhs));
-    void* y = c->W("ap_c2", c->csz(nrhs));
-    launch_convert(bd, C128, a, c->crs_t(), (size_t)nrhs * c->crs_n(), c->st);
-    c->coarse_solve(a, y, nrhs, iters, tol);
-    launch_convert(y, c->crs_t(), xd, C128, (size_t)nrhs * c->crs_n(), c->st);
+    void* a = c->W("ap_c", c->csz(o, nrhs));
+    void* y = c->W("ap_c2", c->csz(o, nrhs));
+    launch_convert(bd, C128, a, c->crs_t(), n, c->st);
+    c->coarse_solve(o, a, y, nrhs, iters, tol);
+    launch_convert(y, c->crs_t(), xd, C128, n, c->st);
     HIPCHK(hipGetLastError());
     io.finish(x, xd, cb, where);
   });
@@ -1535,7 +1640,8 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
   auto run_vcycle = [&](int j) {
     void* zj = (char*)Z + (size_t)j * vs * ct_size(zt);
     const void* in = prec == WCAMG_PREC_MIXED ? vin : (const void*)(V + (size_t)j * vs);
-    if (!p->use_graph || c->timing) {
+    wcamg_ctx::Phase ph(c, wcamg_ctx::PH_PRECOND);
+    if (!p->use_graph || c->timing || c->phase_on) {
       c->vcycle(in, zj, nrhs);
       return;
     }
@@ -1717,6 +1823,36 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
   }
 }
 
+// Solve-phase timing for one solve call: switched on when the caller asks
+// for it, switched off on every exit; fill() writes the split into info.
+struct PhaseScope {
+  wcamg_ctx* c;
+  PhaseScope(wcamg_ctx* c_, bool on) : c(c_) {
+    c->phase_on = on;
+    for (double& v : c->phase_ms) v = 0;
+    c->phase_pending.clear();
+  }
+  ~PhaseScope() {
+    c->phase_on = false;
+    for (auto& p : c->phase_pending) {
+      c->evpool.push_back(p.a);
+      c->evpool.push_back(p.b);
+    }
+    c->phase_pending.clear();
+  }
+  void fill(wcamg_solve_info& inf) {
+    if (!c->phase_on) return;
+    c->collect_phases();
+    const double* ms = c->phase_ms;
+    inf.t_precond = ms[wcamg_ctx::PH_PRECOND] * 1e-3;
+    inf.t_coarse = ms[wcamg_ctx::PH_COARSE] * 1e-3;
+    inf.t_smoother = ms[wcamg_ctx::PH_SMOOTH] * 1e-3;
+    inf.t_rp = ms[wcamg_ctx::PH_RP] * 1e-3;
+    inf.t_prec_other = std::max(0.0, inf.t_precond - inf.t_coarse - inf.t_smoother - inf.t_rp);
+    inf.t_outer = std::max(0.0, inf.t_solve - inf.t_precond);
+  }
+};
+
 int wcamg_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, const wcamg_solve_params* p,
                 wcamg_solve_info* info) {
   if (!c) return WCAMG_EINVAL;
@@ -1728,6 +1864,7 @@ int wcamg_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, const wcamg_solv
     require(std::isfinite(p->tol) && p->tol >= 0, "invalid tol");
     require(p->max_iters >= 0, "invalid max_iters");
     require(c->have_hier, "no hierarchy: call wcamg_setup first", WCAMG_ESTATE);
+    PhaseScope phases(c, p->phase_times != 0);
     auto t0 = std::chrono::steady_clock::now();
     const Geo& g = c->g;
     size_t n = (size_t)12 * g.V;
@@ -1762,6 +1899,7 @@ int wcamg_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, const wcamg_solv
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
     inf.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    phases.fill(inf);
     for (int r = 0; r < nrhs; ++r)
       if (!inf.converged[r]) status = WCAMG_NOT_CONVERGED;
     if (info) *info = inf;
@@ -1769,7 +1907,7 @@ int wcamg_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, const wcamg_solv
   return rc != WCAMG_OK ? rc : status;
 }
 
-// The paper's flexible BiCGStab (Sec. 2) in FP64 on one batch of right-hand
+// The paper's flexible BiCGStab (Sec. 3) in FP64 on one batch of right-hand
 // sides, from x = 0, with M = the V-cycle or the FP32 BiCGStab.  Scalars per
 // right-hand side live on the device (BicgScal); a right-hand side stops
 // when its recursive residual reaches tol (relative to b).
@@ -1804,6 +1942,7 @@ static void fbicg_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs, 
       launch_scale(in, ones, in, vin, n, rs, nrhs, c->st);
       src = vin;
     }
+    wcamg_ctx::Phase ph(c, wcamg_ctx::PH_PRECOND);
     if (amg)
       c->vcycle(src, out, nrhs);
     else
@@ -1861,6 +2000,7 @@ int wcamg_solve_bicgstab(wcamg_ctx* c, const void* b, void* x, int nrhs, const w
     if (p->precond == WCAMG_PC_BICG32)
       require(p->inner_iters >= 1 && std::isfinite(p->inner_tol) && p->inner_tol >= 0,
               "inner_iters must be >= 1 and inner_tol finite and >= 0");
+    PhaseScope phases(c, p->phase_times != 0);
     auto t0 = std::chrono::steady_clock::now();
     const Geo& g = c->g;
     const size_t n = (size_t)12 * g.V;
@@ -1896,6 +2036,7 @@ int wcamg_solve_bicgstab(wcamg_ctx* c, const void* b, void* x, int nrhs, const w
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
     inf.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    phases.fill(inf);
     for (int r = 0; r < nrhs; ++r)
       if (!inf.converged[r]) status = WCAMG_NOT_CONVERGED;
     if (info) *info = inf;

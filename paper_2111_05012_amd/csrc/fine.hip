@@ -1018,7 +1018,7 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   extern __shared__ __align__(16) char smem[];
   const int Vb = VB ? VB : g.Vb;
   cplx<float>* lds = (cplx<float>*)smem;                   // [12][Vb] residual exchange
-  half2_t* lu = (half2_t*)(smem + 12 * Vb * sizeof(cplx<float>));  // [4][9][Vb] -kappa sign U_mu(x) of the domain
+  half2_t* lu = (half2_t*)(smem + 12 * Vb * sizeof(cplx<float>));  // [4][9][Vb] sign U_mu(x) of the domain
   float* red = (float*)(lu + 36 * Vb);                     // [nwaves][3]
   const int half = g.NB[0] >> 1;
   int k = xcd_remap(blockIdx.x, g.nblk >> 1);
@@ -1050,15 +1050,21 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
     if (d < 4) fsign[mu] = (float)sign;
     ninfo[d] = inb ? ((nb - blk * Vb) | (1 << 10)) : 0;
   }
-  // the domain's forward links scaled by the hop coefficient, -kappa sign
+  // the domain's forward links times the boundary sign of their hop, sign
   // U_mu(x) (sign: bc of a hop x -> x + mu that crosses the lattice boundary,
-  // which is also the sign of the backward hop x + mu -> x), read by the site
-  // (forward hops) and by its in-domain neighbours (their backward hops)
+  // which is also the sign of the backward hop x + mu -> x; a sign change is
+  // exact in FP16, so the stored links are the FP16 links), read by the site
+  // (forward hops) and by its in-domain neighbours (their backward hops).
+  // -kappa multiplies the sum of the hops in FP32.
   if (act) {
 #pragma unroll
     for (int q = 0; q < 36; ++q) {
-      const float f = -kappa * fsign[q / 9];
-      st(lu, (size_t)q * Vb + l, f * ld<float>(U, (size_t)q * Vb + fb36));
+      half2_t u = U[(size_t)q * Vb + fb36];
+      if (fsign[q / 9] < 0) {
+        u.x = -u.x;
+        u.y = -u.y;
+      }
+      lu[(size_t)q * Vb + l] = u;
     }
   }
   __syncthreads();
@@ -1086,10 +1092,9 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
       __syncthreads();
       float pr_re = 0, pr_im = 0, pp = 0;
       if (act) {
-        // p = (1 + F) rho + in-domain hops
+        // p = (1 + F) rho - kappa (sum of the in-domain hops)
 #pragma unroll
-        for (int a = 0; a < 12; ++a) p[a] = rho[a];
-        clover_acc<float>(cl, 1, 0, rho, p);
+        for (int a = 0; a < 12; ++a) p[a] = {0, 0};
         // unrolled: direction and projection are compile-time constants
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
@@ -1108,6 +1113,9 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
               hop_h<false>(d & 3, psi, ub, 1.0f, p);
           }
         }
+#pragma unroll
+        for (int a = 0; a < 12; ++a) p[a] = rho[a] + (-kappa) * p[a];
+        clover_acc<float>(cl, 1, 0, rho, p);
 #pragma unroll
         for (int a = 0; a < 12; ++a) {
           pr_re += p[a].x * rho[a].x + p[a].y * rho[a].y;

@@ -40,17 +40,25 @@ class SetupParams(ctypes.Structure):
 
 class SolveParams(ctypes.Structure):
     _fields_ = [('restart', ctypes.c_int), ('tol', ctypes.c_double), ('max_iters', ctypes.c_int),
-                ('rhs_chunk', ctypes.c_int), ('use_graph', ctypes.c_int)]
+                ('rhs_chunk', ctypes.c_int), ('use_graph', ctypes.c_int), ('phase_times', ctypes.c_int)]
 
 
 class BicgParams(ctypes.Structure):
     _fields_ = [('tol', ctypes.c_double), ('max_iters', ctypes.c_int), ('rhs_chunk', ctypes.c_int),
-                ('precond', ctypes.c_int), ('inner_iters', ctypes.c_int), ('inner_tol', ctypes.c_double)]
+                ('precond', ctypes.c_int), ('inner_iters', ctypes.c_int), ('inner_tol', ctypes.c_double),
+                ('phase_times', ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [('iters', ctypes.c_int * MAX_RHS), ('relres', ctypes.c_double * MAX_RHS),
-                ('converged', ctypes.c_int * MAX_RHS), ('vcycles', ctypes.c_int), ('t_solve', ctypes.c_double)]
+                ('converged', ctypes.c_int * MAX_RHS), ('vcycles', ctypes.c_int), ('t_solve', ctypes.c_double),
+                ('t_precond', ctypes.c_double), ('t_coarse', ctypes.c_double), ('t_smoother', ctypes.c_double),
+                ('t_rp', ctypes.c_double), ('t_prec_other', ctypes.c_double), ('t_outer', ctypes.c_double)]
+
+    def phases(self):
+        """The solve's phase split (seconds) as a dict."""
+        return {k: getattr(self, k) for k in ('t_solve', 't_precond', 't_coarse', 't_smoother', 't_rp',
+                                               't_prec_other', 't_outer')}
 
 
 class WcamgError(RuntimeError):
@@ -82,8 +90,9 @@ SIGNATURES = {
     'wcamg_get_coarse_op': (_I, [_P, _I, _P, _I]),
     'wcamg_set_level1_vectors': (_I, [_P, _P, _I]),
     'wcamg_get_level1_vectors': (_I, [_P, _P, _I]),
-    'wcamg_apply_coarse': (_I, [_P, _P, _P, _I, _I]),
-    'wcamg_coarse_solve': (_I, [_P, _P, _P, _I, _I, _D, _I]),
+    'wcamg_set_coarse_op': (_I, [_P, _I, _P, _I]),
+    'wcamg_apply_coarse': (_I, [_P, _I, _P, _P, _I, _I]),
+    'wcamg_coarse_solve': (_I, [_P, _I, _P, _P, _I, _I, _D, _I]),
     'wcamg_vcycle': (_I, [_P, _P, _P, _I, _I]),
     'wcamg_solve': (_I, [_P, _P, _P, _I, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo)]),
     'wcamg_solve_bicgstab': (_I, [_P, _P, _P, _I, ctypes.POINTER(BicgParams), ctypes.POINTER(SolveInfo)]),
@@ -256,32 +265,36 @@ class Context:
         p, w = _ptr(W)
         self._done(self.lib.wcamg_get_level1_vectors(self.h, p, w), W)
 
-    def apply_coarse(self, x, out, nrhs):
-        w = _same_where(x, out)
-        self._done(self.lib.wcamg_apply_coarse(self.h, _ptr(x)[0], _ptr(out)[0], nrhs, w), out)
+    def set_coarse_op(self, Dc, level=1):
+        p, w = _ptr(Dc)
+        self._chk(self.lib.wcamg_set_coarse_op(self.h, level, p, w))
 
-    def coarse_solve(self, b, x, nrhs, iters, tol):
+    def apply_coarse(self, x, out, nrhs, level=1):
+        w = _same_where(x, out)
+        self._done(self.lib.wcamg_apply_coarse(self.h, level, _ptr(x)[0], _ptr(out)[0], nrhs, w), out)
+
+    def coarse_solve(self, b, x, nrhs, iters, tol, level=1):
         w = _same_where(b, x)
-        self._done(self.lib.wcamg_coarse_solve(self.h, _ptr(b)[0], _ptr(x)[0], nrhs, iters, tol, w), x)
+        self._done(self.lib.wcamg_coarse_solve(self.h, level, _ptr(b)[0], _ptr(x)[0], nrhs, iters, tol, w), x)
 
     def vcycle(self, v, out, nrhs):
         w = _same_where(v, out)
         self._done(self.lib.wcamg_vcycle(self.h, _ptr(v)[0], _ptr(out)[0], nrhs, w), out)
 
-    def solve(self, b, x, nrhs, restart=16, tol=1e-10, max_iters=2000, rhs_chunk=0, use_graph=1):
+    def solve(self, b, x, nrhs, restart=16, tol=1e-10, max_iters=2000, rhs_chunk=0, use_graph=1, phase_times=0):
         """b, x: device tensors.  Returns (status, SolveInfo)."""
         pb, wb = _ptr(b)
         px, wx = _ptr(x)
         if wb != DEVICE or wx != DEVICE:
             raise ValueError('solve takes device tensors')
-        prm = SolveParams(restart, tol, max_iters, rhs_chunk, use_graph)
+        prm = SolveParams(restart, tol, max_iters, rhs_chunk, use_graph, phase_times)
         info = SolveInfo()
         rc = self._chk(self.lib.wcamg_solve(self.h, pb, px, nrhs, ctypes.byref(prm), ctypes.byref(info)),
                        allow=(OK, NOT_CONVERGED))
         return rc, info
 
     def solve_bicgstab(self, b, x, nrhs, tol=1e-10, max_iters=1000, rhs_chunk=0, precond=PC_AMG, inner_iters=50,
-                       inner_tol=0.1):
+                       inner_tol=0.1, phase_times=0):
         """The paper's flexible BiCGStab (FP64) preconditioned by the V-cycle
         (PC_AMG) or by an FP32 BiCGStab on D (PC_BICG32, the comparison
         solver).  b, x: device tensors.  Returns (status, SolveInfo)."""
@@ -289,7 +302,7 @@ class Context:
         px, wx = _ptr(x)
         if wb != DEVICE or wx != DEVICE:
             raise ValueError('solve_bicgstab takes device tensors')
-        prm = BicgParams(tol, max_iters, rhs_chunk, precond, inner_iters, inner_tol)
+        prm = BicgParams(tol, max_iters, rhs_chunk, precond, inner_iters, inner_tol, phase_times)
         info = SolveInfo()
         rc = self._chk(self.lib.wcamg_solve_bicgstab(self.h, pb, px, nrhs, ctypes.byref(prm), ctypes.byref(info)),
                        allow=(OK, NOT_CONVERGED))

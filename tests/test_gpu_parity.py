@@ -412,6 +412,30 @@ def test_level2_operator_fp64():
     assert rel(prob.N(Wg), W) == 0.0
 
 
+def test_level2_apply_and_solve_fp64():
+    """The coarse matvec and the coarse solve on level 2 of a three-level
+    hierarchy through the level argument of the C ABI, against the oracle's
+    stencil and stabilised BiCGStab on the oracle's level-2 operator (loaded
+    with set_coarse_op)."""
+    prob, V, cop, W = _three_level_problem()
+    D2 = amg.coarse_coarse_operator(cop, W)
+    prob.ctx.set_coarse_op(prob.T(D2), level=2)
+    got = prob.zeros(D2.shape)
+    prob.ctx.get_coarse_op(got, level=2)
+    assert rel(prob.N(got), D2) == 0.0
+    n2, dof = D2.shape[0], D2.shape[2]
+    cd2 = amg.coarse_dims(cop.cdims, cop.block)
+    x = syn.gaussian_coarse(n2, dof, 2, 55)
+    y = prob.zeros(x.shape)
+    prob.ctx.apply_coarse(prob.T(x), y, 2, level=2)
+    assert rel(prob.N(y), amg.coarse_apply(D2, x, cd2)) < 1e-13
+    z = prob.zeros(x.shape)
+    prob.ctx.coarse_solve(prob.T(x), z, 2, 6, 0.0, level=2)
+    for k in range(2):
+        want, _ = amg.bicgstab(lambda v: amg.coarse_apply(D2, v, cd2), x[k], 6, 0.0)
+        assert rel(prob.N(z)[k], want) < 1e-10
+
+
 def test_three_level_vcycle_fp64():
     prob, V, cop, W = _three_level_problem()
     lv1 = amg.Level1(cop, W, mr1_iters=3, coarse_iters=8, coarse_tol=0.0)
@@ -463,3 +487,34 @@ def test_dslash_every_launch_variant(tmp_path):
             out = prob.zeros(psi.shape)
             prob.ctx.apply_D(prob.T(psi), out, 2, prec)
             assert rel(prob.N(out), want) < tol, (prec, v)
+
+
+@pytest.mark.parametrize('prec', [0, 1])
+def test_solve_phase_times(prec):
+    """Table 1's split of the solve time (coarse solve, smoother, R/P, rest of
+    the preconditioner, outer solver) through the C ABI: every phase is
+    timed, the parts add up, and the timed (graph-free) solve gives the same
+    iterations and solution as the graph-replayed one."""
+    c = syn.CONFIGS['c1']
+    prob = Problem(c['dims'], c['block'], c['eps'], c['seed'], c['kappa'], c['csw'])
+    V0 = syn.gaussian_vectors(prob.dims, c['nv'], c['seed'])
+    prob.ctx.setup(prob.ctx.setup_params(c['nv'], prec, init_vectors=prob.T(V0)))
+    b = syn.z2_source(prob.dims, c['seed'], nrhs=2)
+    x0 = prob.zeros(b.shape)
+    rc0, inf0 = prob.ctx.solve(prob.T(b), x0, 2, tol=1e-10)
+    assert rc0 == 0 and inf0.t_precond == 0.0 and inf0.t_outer == 0.0
+    x1 = prob.zeros(b.shape)
+    rc1, inf1 = prob.ctx.solve(prob.T(b), x1, 2, tol=1e-10, phase_times=1)
+    assert rc1 == 0
+    ph = inf1.phases()
+    for k in ('t_precond', 't_coarse', 't_smoother', 't_rp', 't_outer'):
+        assert ph[k] > 0, (k, ph)
+    assert ph['t_coarse'] + ph['t_smoother'] + ph['t_rp'] <= ph['t_precond'] * (1 + 1e-9)
+    assert abs(ph['t_prec_other'] - (ph['t_precond'] - ph['t_coarse'] - ph['t_smoother'] - ph['t_rp'])) < 1e-9
+    assert abs(ph['t_outer'] - (ph['t_solve'] - ph['t_precond'])) < 1e-9
+    assert list(inf1.iters[:2]) == list(inf0.iters[:2])
+    assert rel(prob.N(x1), prob.N(x0)) < 1e-12
+    # the paper's outer solver splits its time the same way
+    x2 = prob.zeros(b.shape)
+    rc2, inf2 = prob.ctx.solve_bicgstab(prob.T(b), x2, 2, tol=1e-10, phase_times=1)
+    assert rc2 == 0 and inf2.t_precond > 0 and inf2.t_smoother > 0 and inf2.t_coarse > 0
