@@ -104,6 +104,24 @@ int wcamg_get_clover(wcamg_ctx* ctx, void* F, int where);
  * (FP64 throughout) or WCAMG_PREC_MIXED (FP32 arithmetic on FP32-rounded
  * input, FP16 links and clover).  in and out must not alias. */
 int wcamg_apply_D(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int prec, int where);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): out = D in
+ * exactly as wcamg_apply_D with device pointers (canonical layout, complex128
+ * [nrhs][V][4][3]), but its two staging fields in the internal layout are
+ * taken from a fixed scratch area of WCAMG_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on (from the loading of its code object
+ * until the process ends), instead of the context's workspaces.  Limit:
+ * 2 * nrhs * 12 * V * (16 bytes in FP64, 8 in WCAMG_PREC_MIXED), each field
+ * rounded up to 256 bytes, must not exceed WCAMG_NOALLOC_SCRATCH_BYTES
+ * (EINVAL before any device work otherwise; e.g. 16^4 sites: 2 right-hand
+ * sides in FP64, 5 in mixed precision).  The call allocates nothing and
+ * runs no autotuning: the launch variant is the one already tuned for this
+ * shape, else the default one.  Stream-ordered and asynchronous on the
+ * context's stream.  Every call on one GPU shares that GPU's scratch area
+ * (whatever the context): calls that overlap on one GPU, from different
+ * streams or host threads, race and must be ordered by the caller. */
+#define WCAMG_NOALLOC_SCRATCH_BYTES (64 << 20)
+int wcamg_apply_D_noalloc(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int prec);
 /* out = D_SAP in: eq. (1) with every hop between distinct blocks removed
  * (Sec. 3, SAP paragraph). */
 int wcamg_apply_Dsap(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int prec, int where);

@@ -16,6 +16,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -68,7 +69,7 @@ struct DevBuf {
   }
   void* ensure(size_t bytes, bool frozen) {
     if (bytes <= n) return p;
-    require(!frozen, "internal: workspace growth during graph capture", WCAMG_ESTATE);
+    require(!frozen, "internal: workspace growth during graph capture or a no-allocation call", WCAMG_ESTATE);
     ++g_alloc_epoch;
     if (p) HIPCHK(hipFree(p));
     p = nullptr;
@@ -225,6 +226,10 @@ struct wcamg_ctx {
   std::map<std::string, std::unique_ptr<DevBuf>> ws;
   std::string err;
   bool capturing = false;
+  // inside wcamg_apply_D_noalloc: no tuning runs, no timing events, and any
+  // workspace growth is an error
+  bool no_alloc = false;
+  void* scratch = nullptr;  // this device's no-allocation scratch area (device address)
   // kernel timing
   bool timing = false;
   struct Pending {
@@ -314,7 +319,7 @@ struct wcamg_ctx {
     std::string key = arch + "|" + key0;
     auto it = tuner.best.find(key);
     if (it != tuner.best.end()) return it->second;
-    if (!tuner.enabled || capturing) return cands[0];
+    if (!tuner.enabled || capturing || no_alloc) return cands[0];
     bool tm = timing;
     timing = false;
     hipEvent_t e0, e1;
@@ -360,7 +365,7 @@ struct wcamg_ctx {
   void* W(const std::string& name, size_t bytes) {
     auto& b = ws[name];
     if (!b) b.reset(new DevBuf());
-    return b->ensure(bytes, capturing);
+    return b->ensure(bytes, capturing || no_alloc);
   }
   void drop_graphs() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -441,7 +446,7 @@ struct wcamg_ctx {
     bool excl;
     Timed(wcamg_ctx* c_, const char* n, double by = 0, double fl = 0, double un = 0, bool exclusive = false)
         : c(c_), name(n), bytes(by), flops(fl), units(un), excl(exclusive) {
-      if (c->timing && !c->capturing && c->timing_excl == 0) {
+      if (c->timing && !c->capturing && !c->no_alloc && c->timing_excl == 0) {
         a = c->ev();
         b = c->ev();
         HIPCHK(hipEventRecord(a, c->st));
@@ -1014,6 +1019,35 @@ struct wcamg_ctx {
 };
 
 // ---------------------------------------------------------------------------
+// Fixed scratch area of wcamg_apply_D_noalloc: one copy per GPU, held from the
+// loading of the library's code object until the process ends.  In host code
+// `scratch` names a host-side stand-in, not device memory: kernels and copies
+// only ever get the device address that hipGetSymbolAddress returns for the
+// current device (scratch_address).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[WCAMG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;  // device id -> device address of its scratch array
+
+// Device address of the current device's scratch array, looked up once per
+// device (with that device current).
+void* scratch_address() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* ptr = nullptr;
+  HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  require(ptr != nullptr, "no device address for the no-allocation scratch area", WCAMG_EHIP);
+  g_scratch_addr[dev] = ptr;
+  return ptr;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // helpers for the ABI wrappers
 // ---------------------------------------------------------------------------
 namespace {
@@ -1111,6 +1145,7 @@ int wcamg_create(wcamg_ctx** out, const wcamg_lattice* lat, void* hip_stream) {
     c->arch = c->arch.substr(0, c->arch.find(':'));
     const char* cache = std::getenv("WCAMG_AUTOTUNE_CACHE");
     if (cache && *cache) c->tuner.load(cache);
+    c->scratch = scratch_address();
   });
   if (rc != WCAMG_OK) {
     delete c;
@@ -1218,6 +1253,35 @@ int wcamg_apply_D(wcamg_ctx* c, const void* in, void* out, int nrhs, int prec, i
   return apply_op(c, in, out, nrhs, prec, where, OP_D);
 }
 
+int wcamg_apply_D_noalloc(wcamg_ctx* c, const void* in, void* out, int nrhs, int prec) {
+  if (!c) return WCAMG_EINVAL;
+  struct NoAlloc {  // the flag is cleared on every exit, errors included
+    wcamg_ctx* c;
+    explicit NoAlloc(wcamg_ctx* c_) : c(c_) { c->no_alloc = true; }
+    ~NoAlloc() { c->no_alloc = false; }
+  };
+  return guard(c, [&] {
+    check_nrhs(nrhs);
+    check_prec(prec);
+    require(in && out && in != out, "null or aliasing pointers");
+    require(c->have_gauge, "no gauge field", WCAMG_ESTATE);
+    require(c->scratch != nullptr, "no scratch area on this context's device", WCAMG_ESTATE);
+    const Geo& g = c->g;
+    // two staging fields in the internal layout, each starting on a 256-byte boundary
+    const size_t fb = (c->fsz(nrhs, prec) + 255) / 256 * 256;
+    require(2 * fb <= (size_t)WCAMG_NOALLOC_SCRATCH_BYTES,
+            "nrhs * lattice volume too large for the no-allocation scratch area (" +
+                std::to_string(2 * fb) + " > " + std::to_string((size_t)WCAMG_NOALLOC_SCRATCH_BYTES) + " bytes)");
+    NoAlloc guard_flag(c);
+    char* a = (char*)c->scratch;
+    char* b = a + fb;
+    int t = c->spin_t(prec);
+    launch_pack_spinor(g, (const double2*)in, a, t, c->frs(), nrhs, c->st);
+    c->dslash(a, t, b, t, nrhs, OP_D, prec);
+    launch_unpack_spinor(g, b, t, c->frs(), (double2*)out, nrhs, c->st);
+    HIPCHK(hipGetLastError());
+  });
+}
 int wcamg_apply_Dsap(wcamg_ctx* c, const void* in, void* out, int nrhs, int prec, int where) {
   return apply_op(c, in, out, nrhs, prec, where, OP_DSAP);
 }

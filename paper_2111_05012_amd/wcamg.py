@@ -19,6 +19,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 PC_AMG, PC_BICG32 = 0, 1
 SMOOTH_POST, SMOOTH_PRE, SMOOTH_BOTH = 0, 1, 2
 MAX_RHS = 64
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _c_int4 = ctypes.c_int * 4
 
@@ -79,6 +80,7 @@ SIGNATURES = {
     'wcamg_load_clover': (_I, [_P, _P, _I]),
     'wcamg_get_clover': (_I, [_P, _P, _I]),
     'wcamg_apply_D': (_I, [_P, _P, _P, _I, _I, _I]),
+    'wcamg_apply_D_noalloc': (_I, [_P, _P, _P, _I, _I]),
     'wcamg_apply_Dsap': (_I, [_P, _P, _P, _I, _I, _I]),
     'wcamg_sap': (_I, [_P, _P, _P, _I, _I, _I, _I, _I]),
     'wcamg_setup': (_I, [_P, ctypes.POINTER(SetupParams)]),
@@ -203,6 +205,13 @@ class Context:
     def apply_D(self, x, out, nrhs, prec=PREC_FP64):
         w = _same_where(x, out)
         self._done(self.lib.wcamg_apply_D(self.h, _ptr(x)[0], _ptr(out)[0], nrhs, prec, w), out)
+
+    def apply_D_noalloc(self, x, out, nrhs, prec=PREC_FP64):
+        """out = D x with the library's fixed scratch area (no allocation);
+        device tensors only.  Asynchronous: synchronises like the others."""
+        if _ptr(x)[1] != DEVICE or _ptr(out)[1] != DEVICE:
+            raise ValueError('apply_D_noalloc takes device tensors')
+        self._done(self.lib.wcamg_apply_D_noalloc(self.h, _ptr(x)[0], _ptr(out)[0], nrhs, prec), out)
 
     def apply_Dsap(self, x, out, nrhs, prec=PREC_FP64):
         w = _same_where(x, out)
