@@ -66,7 +66,8 @@ extern "C" {
 #define WCAMG_HOST 1
 
 #define WCAMG_PREC_FP64 0  /* everything in FP64 */
-#define WCAMG_PREC_MIXED 1 /* FP16 links/clover/test vectors, FP32 arithmetic, FP64 outer solver */
+#define WCAMG_PREC_MIXED 1 /* FP16 hop matrices -kappa U, clover and test vectors, FP32 arithmetic,
+                              FP64 outer solver */
 
 typedef struct wcamg_ctx wcamg_ctx;
 
@@ -102,7 +103,8 @@ int wcamg_get_clover(wcamg_ctx* ctx, void* F, int where);
 
 /* out = D in for nrhs spinor fields, eq. (1).  prec = WCAMG_PREC_FP64
  * (FP64 throughout) or WCAMG_PREC_MIXED (FP32 arithmetic on FP32-rounded
- * input, FP16 links and clover).  in and out must not alias. */
+ * input, with the hop matrices -kappa U_mu and the clover term F stored in
+ * FP16, each rounded once from FP64).  in and out must not alias. */
 int wcamg_apply_D(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int prec, int where);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): out = D in
@@ -271,8 +273,8 @@ int wcamg_solve(wcamg_ctx* ctx, const void* b, void* x, int nrhs, const wcamg_so
  * p <- r + beta (p - omega D M p).  The preconditioner M is
  *   WCAMG_PC_AMG:    the multigrid V-cycle (Sec. 3; needs wcamg_setup), or
  *   WCAMG_PC_BICG32: the comparison solver's preconditioner (Sec. 5,
- *                    "MBiCGs"): a BiCGStab on D in FP32 arithmetic (FP16
- *                    links and clover, FP32 spinors) with the omega
+ *                    "MBiCGs"): a BiCGStab on D in FP32 arithmetic (FP32
+ *                    links, clover and spinors) with the omega
  *                    stabilisation of the coarse solve, from 0, stopping at
  *                    inner_tol relative residual or inner_iters iterations.
  * Each iteration applies M twice.  The listing's first break point (after
@@ -339,7 +341,8 @@ int wcamg_autotune_info(wcamg_ctx* ctx, double* tune_ms, int* keys_tuned, int* k
  * half-sweep launch: the domain solves), "sap_cross" (the crossing-hop
  * correction launched before a mixed half-sweep), "restrict", "prolong", "coarse_mv",
  * "coarse_solve" (one whole coarse BiCGStab), "coarse_build" (one coarse
- * operator construction), "ortho" (one block orthonormalisation).  Classes
+ * operator construction), "ortho" (one block orthonormalisation), "gs" (the
+ * classical Gram-Schmidt of one FGMRES Arnoldi step, both passes).  Classes
  * nest ("coarse_mv" launches inside "coarse_solve" are recorded in both),
  * except that nothing inside "coarse_build" or "ortho" is recorded
  * separately.  Graph replay is disabled while timing is on. */

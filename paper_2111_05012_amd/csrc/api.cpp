@@ -221,6 +221,10 @@ struct wcamg_ctx {
   bool own_stream = false;
   bool have_gauge = false;
   DevBuf U64, U16, Cl64, Cl16;
+  // FP32 copies of the links and clover, made on first use by the comparison
+  // solver's inner BiCGStab (single-precision fields, as the paper's)
+  DevBuf U32, Cl32;
+  bool have_f32 = false;
   Hier h;
   bool have_hier = false;
   std::map<std::string, std::unique_ptr<DevBuf>> ws;
@@ -526,6 +530,21 @@ struct wcamg_ctx {
   size_t fsz(int nrhs, int prec) const { return (size_t)nrhs * 12 * g.V * ct_size(spin_t(prec)); }
   size_t frs() const { return (size_t)12 * g.V; }
 
+  // internal precision code of the FP32-field operator (never accepted at the ABI)
+  static constexpr int PREC_F32 = 2;
+  // The FP16 link field holds the hop matrices -kappa U (rounded once from
+  // FP64), so the kernels that apply it take the hop coefficient -kappa = 1,
+  // i.e. kappa = -1.
+  static constexpr double HOP16_KAPPA = -1.0;
+  void ensure_f32() {
+    if (have_f32) return;
+    U32.ensure((size_t)36 * g.V * sizeof(float2), capturing);
+    Cl32.ensure((size_t)36 * g.V * sizeof(float2), capturing);
+    launch_convert(U64.p, C128, U32.p, C64, (size_t)36 * g.V, st);
+    launch_convert(Cl64.p, C128, Cl32.p, C64, (size_t)36 * g.V, st);
+    have_f32 = true;
+  }
+
   // ---- D family on internal fields
   void dslash(const void* in, int in_t, void* out, int out_t, int nrhs, int op, int prec, const void* b = nullptr,
               int hopdir = 0, int chir = -1) {
@@ -548,16 +567,24 @@ struct wcamg_ctx {
       a.C = Cl16.p;
       a.fields16 = 1;
       a.compute32 = 1;
+      a.kappa = HOP16_KAPPA;
+    } else if (prec == PREC_F32) {
+      ensure_f32();
+      a.U = U32.p;
+      a.C = Cl32.p;
+      a.fields32 = 1;
+      a.compute32 = 1;
     } else {
       a.U = U64.p;
       a.C = Cl64.p;
     }
     double site = (double)g.V;
-    double fld = 4.0 * 9 * (a.fields16 ? 4 : 16) + 36.0 * (a.fields16 ? 4 : 16);
+    const double fb = a.fields16 ? 4 : a.fields32 ? 8 : 16;
+    double fld = 4.0 * 9 * fb + 36.0 * fb;
     double by = site * (fld + nrhs * 12.0 * (ct_size(in_t) + ct_size(out_t) * (b ? 2 : 1)));
     char key[160];
-    snprintf(key, sizeof(key), "dslash|op%d|in%d|out%d|f%d|c%d|res%d|V%d|Vb%d|n%d", op, in_t, out_t, a.fields16,
-             a.compute32, b ? 1 : 0, g.V, g.Vb, nrhs);
+    snprintf(key, sizeof(key), "dslash|op%d|in%d|out%d|f%d|c%d|res%d|V%d|Vb%d|n%d", op, in_t, out_t,
+             a.fields16 ? 1 : a.fields32 ? 2 : 0, a.compute32, b ? 1 : 0, g.V, g.Vb, nrhs);
     std::vector<int> dcands = {64, 128, 256, 512};
     if (op == OP_D) dcands.push_back(-1);                                // colour-split variant
     if (op == OP_D && dslash_lds_slices(g) > 0) {
@@ -746,8 +773,8 @@ struct wcamg_ctx {
     }
   }
 
-  // x = BiCGStab(D, b) on fine fields in FP32 arithmetic (FP16 links and
-  // clover, FP32 spinors), from 0, with the omega stabilisation of the coarse
+  // x = BiCGStab(D, b) on fine fields in FP32 arithmetic (FP32 links,
+  // clover and spinors), from 0, with the omega stabilisation of the coarse
   // solve: the preconditioner of the comparison solver (Sec. 5)
   void bicg32(const void* b, void* x, int nrhs, int iters, double tol) {
     const int t = C64;
@@ -764,10 +791,10 @@ struct wcamg_ctx {
     std::vector<BicgScal> hs(nrhs);
     for (int it = 0; it < iters; ++it) {
       launch_bicg_p(p, r, v, t, n, n, nrhs, sc, st);
-      dslash(p, C64, v, C64, nrhs, OP_D, WCAMG_PREC_MIXED);
+      dslash(p, C64, v, C64, nrhs, OP_D, PREC_F32);
       launch_bicg_alpha(rt, v, t, n, n, nrhs, part, sc, st);
       launch_bicg_s(s, r, v, t, n, n, nrhs, sc, st);
-      dslash(s, C64, tt, C64, nrhs, OP_D, WCAMG_PREC_MIXED);
+      dslash(s, C64, tt, C64, nrhs, OP_D, PREC_F32);
       launch_bicg_omega(tt, s, t, n, n, nrhs, part, sc, 0.7, st);
       launch_bicg_xr(x, r, p, s, tt, rt, t, n, n, nrhs, part, sc, st);
       if ((it % 4 == 3) && it + 1 < iters) {
@@ -902,6 +929,7 @@ struct wcamg_ctx {
     bool mixed = h.prec == WCAMG_PREC_MIXED;
     const void* Uf = mixed ? U16.p : U64.p;
     const void* Cf = mixed ? Cl16.p : Cl64.p;
+    const double kh = mixed ? HOP16_KAPPA : kappa;
     std::vector<int> cands = {0};
     if (mixed && nv <= 32) cands = {1, 0};  // matrix-core contraction first
     char key[96];
@@ -910,9 +938,9 @@ struct wcamg_ctx {
     if (mixed && nv <= 32)
       part = W("cb_part", (size_t)coarse_build_chunks(g) * g.nblk * N * N * sizeof(float2));
     int var = tune(key, cands,
-                   [&](int v) { launch_coarse_build(g, nv, kappa, h.V.p, Uf, Cf, h.Dc.p, mixed, st, v, part); });
+                   [&](int v) { launch_coarse_build(g, nv, kh, h.V.p, Uf, Cf, h.Dc.p, mixed, st, v, part); });
     Timed tb(this, "coarse_build", 0, 0, 1, true);
-    launch_coarse_build(g, nv, kappa, h.V.p, Uf, Cf, h.Dc.p, mixed, st, var, part);
+    launch_coarse_build(g, nv, kh, h.V.p, Uf, Cf, h.Dc.p, mixed, st, var, part);
   }
 
   // level-1 block orthonormalisation of W in place (CholQR twice, FP64 Gram)
@@ -1181,7 +1209,7 @@ int wcamg_load_gauge(wcamg_ctx* c, const void* U, int where) {
     c->U16.ensure((size_t)4 * 9 * g.V * sizeof(half2_t), false);
     c->Cl64.ensure((size_t)36 * g.V * sizeof(double2), false);
     c->Cl16.ensure((size_t)36 * g.V * sizeof(half2_t), false);
-    launch_pack_gauge(g, Ud, (double2*)c->U64.p, (half2_t*)c->U16.p, c->st);
+    launch_pack_gauge(g, Ud, (double2*)c->U64.p, (half2_t*)c->U16.p, -c->kappa, c->st);
     std::vector<double> sig = sigma_table();
     launch_clover_build(g, (const double2*)c->U64.p, c->kappa, c->csw, sig.data(), (double2*)c->Cl64.p,
                         (half2_t*)c->Cl16.p, c->st);
@@ -1189,6 +1217,7 @@ int wcamg_load_gauge(wcamg_ctx* c, const void* U, int where) {
     HIPCHK(hipStreamSynchronize(c->st));
     c->have_gauge = true;
     c->have_hier = false;
+    c->have_f32 = false;
   });
 }
 
@@ -1205,6 +1234,7 @@ int wcamg_load_clover(wcamg_ctx* c, const void* F, int where) {
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
     c->have_hier = false;
+    c->have_f32 = false;
   });
 }
 
@@ -1797,15 +1827,21 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
       double2* w = V + (size_t)(j + 1) * vs;
       c->dslash(zj, zt, w, C128, nrhs, OP_D, WCAMG_PREC_FP64);
       // classical Gram-Schmidt twice; the update of the first pass and the
-      // projections of the second share one sweep over the basis
-      launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h1, c->st);
-      if (j + 1 <= 16) {
-        launch_multiaxpy_dot(V, vs, j + 1, h1, w, n, rs, nrhs, part, h2, c->st);
-      } else {
-        launch_multiaxpy(V, vs, j + 1, h1, w, n, rs, nrhs, part, nullptr, c->st);
-        launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h2, c->st);
+      // projections of the second share one sweep over the basis.  Timed as
+      // the class "gs": algorithmic bytes = the j + 1 basis vectors read three
+      // times, w read three times and written twice (FP64, all RHS)
+      {
+        const double vb = (double)vs * sizeof(double2);
+        wcamg_ctx::Timed tg(c, "gs", vb * (3.0 * (j + 1) + 5.0), 8.0 * 3 * (j + 1) * (double)vs, nrhs);
+        launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h1, c->st);
+        if (j + 1 <= 16) {
+          launch_multiaxpy_dot(V, vs, j + 1, h1, w, n, rs, nrhs, part, h2, c->st);
+        } else {
+          launch_multiaxpy(V, vs, j + 1, h1, w, n, rs, nrhs, part, nullptr, c->st);
+          launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h2, c->st);
+        }
+        launch_multiaxpy(V, vs, j + 1, h2, w, n, rs, nrhs, part, nrm, c->st);
       }
-      launch_multiaxpy(V, vs, j + 1, h2, w, n, rs, nrhs, part, nrm, c->st);
       HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
                             c->st));
       HIPCHK(hipMemcpyAsync(hh2.data(), h2, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,

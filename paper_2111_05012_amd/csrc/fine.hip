@@ -5,7 +5,8 @@
 //
 // Internal layouts (blocked site order, block-major planes, see wc_common.h):
 //   spinor  [rhs][blk][12 = spin*3 + colour][Vb]          complex (double2 / float2)
-//   links   [blk][36 = mu*9 + row*3 + col][Vb]           complex (double2 / half2)
+//   links   [blk][36 = mu*9 + row*3 + col][Vb]           complex (double2: U;
+//           half2: the hop matrices -kappa U, the form the FP32 kernels use)
 //   clover  [blk][36 pairs][Vb]: per chirality b (pairs 18b..18b+17) the
 //           Hermitian 6x6 block as 6 real diagonal entries (pairs 0..2)
 //           followed by the 15 upper entries (i<j, row-major) as complex
@@ -76,8 +77,10 @@ __global__ __launch_bounds__(256) void k_unpack_spinor(Geo g, const TI* __restri
   for (int a = 0; a < 12; ++a) st(dst, a, ld<double>(src, (size_t)a * g.Vb + fb));
 }
 
+// U64 = U; U16 = the hop matrices h U in FP16 (h = -kappa: one rounding of the
+// FP64 product), the form in which the mixed-precision kernels apply them
 __global__ __launch_bounds__(256) void k_pack_gauge(Geo g, const double2* __restrict__ canon,
-                                                    double2* __restrict__ U64, half2_t* __restrict__ U16) {
+                                                    double2* __restrict__ U64, half2_t* __restrict__ U16, double h) {
   int cs = blockIdx.x * 256 + threadIdx.x;
   if (cs >= g.V) return;
   int mu = blockIdx.y;
@@ -88,7 +91,7 @@ __global__ __launch_bounds__(256) void k_pack_gauge(Geo g, const double2* __rest
     double2 v = src[e];
     size_t o = (size_t)(mu * 9 + e) * g.Vb + fbase(g, 36, s);
     U64[o] = v;
-    st(U16, o, cplx<double>{v.x, v.y});
+    st(U16, o, cplx<double>{h * v.x, h * v.y});
   }
 }
 
@@ -764,6 +767,9 @@ void launch_dslash(const DslashArgs& a, hipStream_t st) {
     if (a.in_t == C64 && a.out_t == C128)
       return dslash_dispatch<double, float2, double2, double2, double2>(a, st);
   }
+  if (a.fields32 && a.compute32) {
+    if (a.in_t == C64 && a.out_t == C64) return dslash_dispatch<float, float2, float2, float2, float2>(a, st);
+  }
   if (a.fields16 && a.compute32) {
     if (a.in_t == C64 && a.out_t == C64) return dslash_dispatch<float, float2, float2, half2_t, half2_t>(a, st);
     if (a.in_t == C32H && a.out_t == C64) return dslash_dispatch<float, half2_t, float2, half2_t, half2_t>(a, st);
@@ -945,14 +951,15 @@ __device__ __forceinline__ void hop_h(int mu, const cplx<float> (&psi)[12], cons
 // The crossing-hop correction of a mixed-precision SAP half-sweep as a
 // kernel of its own, ahead of the domain solves: for every site x of the
 // active colour's domains and every right-hand side,
-//   r(x) = src(x) + kappa sum_{hops x -> y leaving the domain} sign W delta(y)
+//   r(x) = src(x) - sum_{hops x -> y leaving the domain} sign H delta(y)
+// with H the hop's FP16 matrix -kappa U (or its adjoint) spin-projected
 // (r = b - D x restricted to the active colour, updated with the other
 // colour's last block corrections delta).  src is b on a colour's first visit
 // (every site is then written), else r itself (sites without a crossing hop
 // are left alone).  One thread per (site, right-hand side): memory-bound
 // work at full occupancy, where inside the domain solve's single workgroup
 // per CU the dependent global loads of the hops stood exposed.
-__global__ __launch_bounds__(256) void k_sap_cross(Geo g, int colour, int first, float kappa,
+__global__ __launch_bounds__(256) void k_sap_cross(Geo g, int colour, int first,
                                                    const float2* __restrict__ b, float2* __restrict__ r,
                                                    const float2* __restrict__ delta, size_t rs,
                                                    const half2_t* __restrict__ U) {
@@ -994,9 +1001,9 @@ __global__ __launch_bounds__(256) void k_sap_cross(Geo g, int colour, int first,
 #pragma unroll
     for (int q = 0; q < 9; ++q) ub[q] = U[(size_t)(mu * 9 + q) * Vb + lb];
     if (d < 4)
-      hop_h<true>(mu, psi, ub, kappa * (float)sign, acc);
+      hop_h<true>(mu, psi, ub, -(float)sign, acc);
     else
-      hop_h<false>(mu, psi, ub, kappa * (float)sign, acc);
+      hop_h<false>(mu, psi, ub, -(float)sign, acc);
   }
   if (!any && !first) return;
   float2* dst = r + off;
@@ -1010,7 +1017,7 @@ __global__ __launch_bounds__(256) void k_sap_cross(Geo g, int colour, int first,
 // VB: the domain volume when known at compile time (LDS offsets become
 // immediates), 0 for any volume.
 template <int VB>
-__global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, int mr, float kappa, int nrhs,
+__global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, int mr, int nrhs,
                                                  const float2* __restrict__ b, float2* __restrict__ r,
                                                  float2* __restrict__ x, float2* __restrict__ delta,
                                                  const float2* __restrict__ xinit, size_t rs,
@@ -1018,7 +1025,7 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   extern __shared__ __align__(16) char smem[];
   const int Vb = VB ? VB : g.Vb;
   cplx<float>* lds = (cplx<float>*)smem;                   // [12][Vb] residual exchange
-  half2_t* lu = (half2_t*)(smem + 12 * Vb * sizeof(cplx<float>));  // [4][9][Vb] sign U_mu(x) of the domain
+  half2_t* lu = (half2_t*)(smem + 12 * Vb * sizeof(cplx<float>));  // [4][9][Vb] -kappa sign U_mu(x) of the domain
   float* red = (float*)(lu + 36 * Vb);                     // [nwaves][3]
   const int half = g.NB[0] >> 1;
   int k = xcd_remap(blockIdx.x, g.nblk >> 1);
@@ -1050,12 +1057,11 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
     if (d < 4) fsign[mu] = (float)sign;
     ninfo[d] = inb ? ((nb - blk * Vb) | (1 << 10)) : 0;
   }
-  // the domain's forward links times the boundary sign of their hop, sign
-  // U_mu(x) (sign: bc of a hop x -> x + mu that crosses the lattice boundary,
-  // which is also the sign of the backward hop x + mu -> x; a sign change is
-  // exact in FP16, so the stored links are the FP16 links), read by the site
-  // (forward hops) and by its in-domain neighbours (their backward hops).
-  // -kappa multiplies the sum of the hops in FP32.
+  // the domain's forward hop matrices (FP16 -kappa U_mu(x)) times the
+  // boundary sign of their hop (bc of a hop x -> x + mu that crosses the
+  // lattice boundary, which is also the sign of the backward hop x + mu -> x;
+  // a sign change is exact in FP16), read by the site (forward hops) and by
+  // its in-domain neighbours (their backward hops)
   if (act) {
 #pragma unroll
     for (int q = 0; q < 36; ++q) {
@@ -1092,9 +1098,11 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
       __syncthreads();
       float pr_re = 0, pr_im = 0, pp = 0;
       if (act) {
-        // p = (1 + F) rho - kappa (sum of the in-domain hops)
+        // p = (1 + F) rho + in-domain hops (the stored links are the hop
+        // matrices -kappa U)
 #pragma unroll
-        for (int a = 0; a < 12; ++a) p[a] = {0, 0};
+        for (int a = 0; a < 12; ++a) p[a] = rho[a];
+        clover_acc<float>(cl, 1, 0, rho, p);
         // unrolled: direction and projection are compile-time constants
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
@@ -1113,9 +1121,6 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
               hop_h<false>(d & 3, psi, ub, 1.0f, p);
           }
         }
-#pragma unroll
-        for (int a = 0; a < 12; ++a) p[a] = rho[a] + (-kappa) * p[a];
-        clover_acc<float>(cl, 1, 0, rho, p);
 #pragma unroll
         for (int a = 0; a < 12; ++a) {
           pr_re += p[a].x * rho[a].x + p[a].y * rho[a].y;
@@ -1200,7 +1205,7 @@ void launch_sap_cross(const SapArgs& a, int sweep, int col, hipStream_t st) {
   if (!sap_needs_cross(a, sweep, col)) return;
   const size_t nsite = (size_t)(a.g.nblk / 2) * a.g.Vb;
   k_sap_cross<<<dim3((unsigned)((nsite + 255) / 256), a.nrhs), 256, 0, st>>>(
-      a.g, col, sweep == 0 ? 1 : 0, (float)a.kappa, (const float2*)a.b, (float2*)a.r, (const float2*)a.delta, a.rs,
+      a.g, col, sweep == 0 ? 1 : 0, (const float2*)a.b, (float2*)a.r, (const float2*)a.delta, a.rs,
       (const half2_t*)a.U);
 }
 
@@ -1224,7 +1229,7 @@ void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st) {
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       attr_set[id] = true;
     }
-    kern<<<round8(ndom), nthr, lds, st>>>(g, col, flags, a.mr, (float)a.kappa, a.nrhs, (const float2*)a.b,
+    kern<<<round8(ndom), nthr, lds, st>>>(g, col, flags, a.mr, a.nrhs, (const float2*)a.b,
                                           (float2*)a.r, (float2*)a.x, (float2*)a.delta, (const float2*)a.xinit, a.rs,
                                           (const half2_t*)a.U, (const half2_t*)a.C);
   };
@@ -1261,9 +1266,9 @@ void launch_unpack_spinor(const Geo& g, const void* in, int in_t, size_t in_rs, 
     k_unpack_spinor<half2_t><<<grid, 256, 0, st>>>(g, (const half2_t*)in, in_rs, canon);
 }
 
-void launch_pack_gauge(const Geo& g, const double2* canon, double2* U64, half2_t* U16, hipStream_t st) {
+void launch_pack_gauge(const Geo& g, const double2* canon, double2* U64, half2_t* U16, double h, hipStream_t st) {
   dim3 grid((g.V + 255) / 256, 4);
-  k_pack_gauge<<<grid, 256, 0, st>>>(g, canon, U64, U16);
+  k_pack_gauge<<<grid, 256, 0, st>>>(g, canon, U64, U16, h);
 }
 
 void launch_clover_build(const Geo& g, const double2* U64, double kappa, double csw, const double* sigma,

@@ -18,7 +18,8 @@ void launch_pack_spinor(const Geo& g, const double2* canon, void* out, int out_t
 void launch_unpack_spinor(const Geo& g, const void* in, int in_t, size_t in_rs, double2* canon, int nrhs,
                           hipStream_t st);
 // canonical complex128 [4][V][3][3] -> internal [4][9][V] in FP64 and FP16
-void launch_pack_gauge(const Geo& g, const double2* canon, double2* U64, half2_t* U16, hipStream_t st);
+// U64 = U; U16 = FP16 rounding of h U (h = -kappa: the hop matrices)
+void launch_pack_gauge(const Geo& g, const double2* canon, double2* U64, half2_t* U16, double h, hipStream_t st);
 // clover F(x) from the FP64 links: packed Hermitian chiral blocks [36 pairs][V] in FP64 and FP16.
 // sigma: the chiral 2x2 blocks of sigma_{mu nu}, [6 planes][2 chiralities][2][2] complex (re, im).
 void launch_clover_build(const Geo& g, const double2* U64, double kappa, double csw, const double* sigma,
@@ -45,6 +46,7 @@ struct DslashArgs {
   const void* U = nullptr;
   const void* C = nullptr;
   int fields16 = 0;  // 0: FP64 links/clover, 1: FP16
+  int fields32 = 0;  // 1: FP32 links/clover (with compute32)
   int compute32 = 0; // 0: FP64 arithmetic, 1: FP32
   double kappa = 0;
   int block_size = 256;  // threads per workgroup (64 .. 512, autotuned); -1: colour-split variant,
@@ -60,7 +62,7 @@ int dslash_lds_slices(const Geo& g);
 struct SapArgs {
   Geo g;
   int nrhs = 1, sweeps = 4, mr = 6;
-  int mixed = 0;  // 0: FP64 everything; 1: FP32 spinors and arithmetic, FP16 links/clover
+  int mixed = 0;  // 0: FP64 everything; 1: FP32 spinors and arithmetic, FP16 hop matrices/clover
   double kappa = 0;
   const void* b = nullptr;      // source
   void* x = nullptr;            // solution (output)

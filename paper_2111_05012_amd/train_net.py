@@ -35,6 +35,67 @@ def eps_of(seed):
     return float(syn.rng(seed, syn.STREAM_EPS).uniform(0.3, 0.5))
 
 
+SETUPS = ('plain', 'ablate', 'net')
+
+
+def evaluate_seed(ctx, nv, b, r_net, V0, n_adapt_plain=3, k=1, tol=1e-10):
+    """The three setups on the loaded gauge field, each followed by a solve of
+    b to tol: plain ((0-a) SAP x3 from V0, then n_adapt_plain (0-b) passes),
+    ablate (V0 orthonormalised, then k (0-b) passes) and net (the loaded
+    network applied to r_net in place of (0-a), then k passes).  A setup that
+    fails (e.g. network outputs linearly dependent on a block) is recorded
+    with its error.  Returns {name: {setup_s, iters, relres, converged,
+    solve_s[, error]}}."""
+    import torch
+    from paper_2111_05012_amd import PREC_MIXED, WcamgError
+    row = {}
+    for name, kw in (('plain', dict(n_init=3, n_adapt=n_adapt_plain, init_vectors=V0)),
+                     ('ablate', dict(n_init=0, n_adapt=k, init_vectors=V0)),
+                     ('net', dict(n_init=0, n_adapt=k, init_net=1, init_vectors=r_net))):
+        p = ctx.setup_params(nv, PREC_MIXED, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        try:
+            ctx.setup(p)
+        except WcamgError as e:
+            row[name] = dict(setup_s=None, iters=None, relres=None, converged=False, solve_s=None, error=str(e))
+            continue
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t
+        x = torch.zeros_like(b)
+        rc, info = ctx.solve(b, x, 1, tol=tol)
+        row[name] = dict(setup_s=round(ts, 4), iters=int(info.iters[0]), relres=float(info.relres[0]),
+                         converged=bool(rc == 0), solve_s=round(info.t_solve, 4))
+    return row
+
+
+def choose_setup(rows):
+    """The plain adaptive setup is the learned one's fallback and judge: the
+    network-initialised setup is kept ('net') only if on every validation
+    seed it ran, converged, and needed at most as many outer iterations as
+    the plain setup; otherwise 'plain'."""
+    if not rows:
+        return 'plain'
+    for r in rows:
+        n, p = r['net'], r['plain']
+        if 'error' in n or not n['converged'] or not p['converged'] or n['iters'] > p['iters']:
+            return 'plain'
+    return 'net'
+
+
+def summarize(rows):
+    """Mean setup time, outer iterations and setup + solve time per setup over
+    the seeds where it ran."""
+    out = {}
+    for name in SETUPS:
+        ok = [r[name] for r in rows if 'error' not in r[name]]
+        out[name] = dict(runs=len(ok), failed=len(rows) - len(ok),
+                         setup_s=float(np.mean([q['setup_s'] for q in ok])) if ok else None,
+                         iters=float(np.mean([q['iters'] for q in ok])) if ok else None,
+                         tts_s=float(np.mean([q['setup_s'] + q['solve_s'] for q in ok])) if ok else None)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument('--dims', type=int, nargs=4, default=[16, 16, 16, 16])
@@ -65,14 +126,9 @@ def main(argv=None):
     def log(*a):
         print('[train_net]', *a, file=sys.stderr, flush=True)
 
-    def plain_setup(seed, n_init=3, n_adapt=3, init_net=0, r=None):
-        V0 = r if r is not None else syn.gaussian_vectors_torch(dims, C, seed, dev)
-        p = ctx.setup_params(C, PREC_MIXED, init_vectors=V0, n_init=n_init, n_adapt=n_adapt, init_net=init_net)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        ctx.setup(p)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t
+    def plain_setup(seed):
+        V0 = syn.gaussian_vectors_torch(dims, C, seed, dev)
+        ctx.setup(ctx.setup_params(C, PREC_MIXED, init_vectors=V0, n_init=3, n_adapt=3))
 
     def net_input(seed):
         return syn.gaussian_vectors_torch(dims, C, seed + 100000, dev)
@@ -121,35 +177,24 @@ def main(argv=None):
         U = syn.gauge_field_torch(dims, eps_of(s), s, dev)
         ctx.load_gauge(U)
         b = torch.from_numpy(syn.z2_source(dims, s)).to(dev)
-        x = torch.zeros_like(b)
         row = dict(seed=s, eps=eps_of(s))
-        for name, kw in (('plain', dict(n_init=3, n_adapt=args.n_adapt_plain)),
-                         ('ablate', dict(n_init=0, n_adapt=args.k)),
-                         ('net', dict(n_init=0, n_adapt=args.k, init_net=1, r=net_input(s)))):
-            ts = plain_setup(s, **kw)
-            rc, info = ctx.solve(b, x, 1, tol=1e-10)
-            row[name] = dict(setup_s=round(ts, 4), iters=int(info.iters[0]), relres=float(info.relres[0]),
-                             converged=bool(rc == 0), solve_s=round(info.t_solve, 4))
-        # the network's loss against this seed's plain-setup vectors
+        row.update(evaluate_seed(ctx, C, b, net_input(s), syn.gaussian_vectors_torch(dims, C, s, dev),
+                                 n_adapt_plain=args.n_adapt_plain, k=args.k))
         rows.append(row)
         log('seed %d: plain %s | ablate %s | net %s' % (s, row['plain'], row['ablate'], row['net']))
 
-    def mean(key, f):
-        return float(np.mean([r[key][f] for r in rows]))
-
-    summary = {name: dict(setup_s=mean(name, 'setup_s'), iters=mean(name, 'iters'),
-                          tts_s=mean(name, 'setup_s') + mean(name, 'solve_s'))
-               for name in ('plain', 'ablate', 'net')}
-    use_net = summary['net']['iters'] <= summary['plain']['iters'] and all(r['net']['converged'] for r in rows)
+    summary = summarize(rows)
+    decision = choose_setup(rows)
     report = dict(config=dict(dims=dims, block=block, kappa=args.kappa, csw=args.csw, layers=args.layers,
                               channels=C, epochs=args.epochs, lr=args.lr, k=args.k, train_seeds=args.train,
                               eval_seeds=args.eval),
                   teacher_s=round(t_teach, 2), train_s=round(t_train, 2), loss_history=hist,
                   eval=rows, summary=summary,
-                  net_gain_vs_ablation_iters=summary['ablate']['iters'] - summary['net']['iters'],
-                  decision='net' if use_net else 'plain (fallback)')
+                  net_gain_vs_ablation_iters=(summary['ablate']['iters'] - summary['net']['iters']
+                                              if summary['net']['iters'] is not None else None),
+                  decision=decision)
     print(json.dumps(report['summary']), flush=True)
-    log('decision:', report['decision'])
+    log('decision:', decision)
     if args.report:
         with open(args.report, 'w') as f:
             json.dump(report, f, indent=1)

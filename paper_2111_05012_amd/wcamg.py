@@ -120,6 +120,13 @@ def load_library(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise FileNotFoundError('libwcamg.so not built (%s); run __graft_entry__.build()' % path)
+    # torch first: its HIP runtime is then the one the library binds to, so
+    # that device pointers, streams and the library's device symbols share one
+    # runtime (loading the library first would bring in a second one)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

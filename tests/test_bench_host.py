@@ -42,3 +42,39 @@ def test_counter_traffic_lookup():
     # a class without counters, or with counters taken on other sources, has none
     assert bench.counter_traffic('no_such_class', 1.0) is None
     assert bench.counter_traffic('coarse_mv', 1.0) is None or bench.counter_traffic('coarse_mv', 1.0) > 0
+
+
+def _write_counter_csv(path, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, 'x_counter_collection.csv'), 'w') as f:
+        f.write('Correlation_Id,Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n')
+        for d, k, v in rows:
+            f.write('%d,%d,"%s",C,%r\n' % (d, d, k, v))
+
+
+def test_counter_summary_calibrates_and_divides_by_units(tmp_path):
+    """The counter summary scales by the 1 GiB calibration copies, keeps only
+    the dispatches after them, and divides by the measured pass's units."""
+    import json
+    V = 1024
+    units = dict(V=V, workload=[8, 8, 4, 4], classes={c: dict(units=0.0, bytes=0.0) for c in bench.CLASSES})
+    units['classes']['sap_half'] = dict(units=12.0, bytes=5e6)  # 12 RHS-launches of a half-sweep
+    units['classes']['dslash64'] = dict(units=2.0, bytes=3e6)
+    uj = tmp_path / 'units.json'
+    uj.write_text(json.dumps(units))
+    copy = 'void at::native::elementwise_kernel<copy>(int)'
+    # fetch counter reads half the bytes (factor 2), write counter all of them (factor 1)
+    fetch = [(1, 'k_sap_dom<512>(Geo)', 999.0)] + [(2 + i, copy, 524288.0) for i in range(3)] + \
+            [(5, 'k_sap_dom<512>(Geo)', 100.0), (6, 'k_dslash_lds<double, double2>(Geo)', 50.0)]
+    write = [(1, 'k_sap_dom<512>(Geo)', 999.0)] + [(2 + i, copy, 1048576.0) for i in range(3)] + \
+            [(5, 'k_sap_dom<512>(Geo)', 30.0), (6, 'k_dslash_lds<double, double2>(Geo)', 10.0)]
+    _write_counter_csv(str(tmp_path / 'f'), fetch)
+    _write_counter_csv(str(tmp_path / 'w'), write)
+    out = bench.summarize_counters(str(tmp_path / 'f'), str(tmp_path / 'w'), str(uj), str(tmp_path / 'o.json'))
+    k = out['kernels']
+    assert k['sap_half']['dispatches'] == 1
+    assert k['sap_half']['fetch_bytes'] == pytest.approx(100 * 1024 * 2.0)
+    assert k['sap_half']['write_bytes'] == pytest.approx(30 * 1024 * 1.0)
+    assert k['sap_half']['fetch_per_unit'] == pytest.approx(100 * 1024 * 2.0 / (12 * V / 2))
+    assert k['dslash64']['write_per_unit'] == pytest.approx(10 * 1024 / (2 * V))
+    assert k['coarse_mv']['dispatches'] == 0

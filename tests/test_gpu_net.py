@@ -1,5 +1,8 @@
-"""GPU parity of the equivariant network (FP32 kernels vs the FP64 oracle):
-forward, loss, gradient, one Adam step; network-initialised setup."""
+"""GPU parity of the equivariant network (FP32 kernels vs the FP64 oracle)
+with the production depth of 4 layers: forward, loss, gradient, Adam over
+three steps; network-initialised setup; a short training run with the
+learned setup's evaluation against the plain setup and the ablation, and the
+plain setup's fallback."""
 import numpy as np
 import pytest
 
@@ -9,16 +12,17 @@ from gpu_common import Problem, rel, BC_AP
 
 pytestmark = pytest.mark.gpu
 C = 16
+L = 4
 
 
 @pytest.fixture(scope='module')
 def setup():
     prob = Problem((4, 4, 4, 8), (2, 2, 2, 2), eps=0.4, seed=5, kappa=0.124, csw=1.0)
-    Ws = syn.net_weights(C, 2, 7, scale=0.05)
+    Ws = syn.net_weights(C, L, 7, scale=0.05)
     r = syn.gaussian_vectors(prob.dims, C, 8)
     Q = amg.block_orthonormalize(syn.gaussian_vectors(prob.dims, C, 9), prob.dims, prob.block)
     wflat = np.ascontiguousarray(np.stack(Ws).astype(np.complex64))
-    prob.ctx.net_init(prob.T(wflat), 2, C)
+    prob.ctx.net_init(prob.T(wflat), L, C)
     return prob, Ws, r, Q
 
 
@@ -33,7 +37,7 @@ def test_net_forward(setup):
 def test_net_gradient(setup):
     prob, Ws, r, Q = setup
     import torch
-    g = torch.zeros((2, 9, C, C, 4, 4), dtype=torch.complex64, device=prob.dev)
+    g = torch.zeros((L, 9, C, C, 4, 4), dtype=torch.complex64, device=prob.dev)
     loss = prob.ctx.net_gradient(prob.T(r), prob.T(Q), g)
     acts = net.forward(prob.U, Ws, r, BC_AP)
     l_o, gA = net.subspace_loss(acts[-1], Q, prob.dims, prob.block)
@@ -50,7 +54,7 @@ def test_net_adam_step(setup):
     _, gA = net.subspace_loss(acts[-1], Q, prob.dims, prob.block)
     gWs, _ = net.backward(prob.U, Ws, acts, gA, BC_AP)
     W1 = net.Adam(lr=1e-3).step(Ws, gWs)
-    got = torch.zeros((2, 9, C, C, 4, 4), dtype=torch.complex64, device=prob.dev)
+    got = torch.zeros((L, 9, C, C, 4, 4), dtype=torch.complex64, device=prob.dev)
     prob.ctx.net_get_weights(got)
     # the first Adam step moves each real and imaginary part by
     # lr * g / (|g| + eps) ~ lr * sign(g); compare it where the gradient part is
@@ -65,7 +69,49 @@ def test_net_adam_step(setup):
         assert np.abs(part(upd_g) - part(upd_o))[m].max() < 1e-5
     assert np.isfinite(loss)
     # restore the weights for the other tests
-    prob.ctx.net_init(prob.T(np.ascontiguousarray(np.stack(Ws).astype(np.complex64))), 2, C)
+    prob.ctx.net_init(prob.T(np.ascontiguousarray(np.stack(Ws).astype(np.complex64))), L, C)
+
+
+def test_net_adam_three_steps(setup):
+    """Adam's moment recursions and bias corrections over three steps: two
+    steps with learning rate 0 on two different inputs (the weights stay, the
+    moments take the gradients g1 and g2), then a step with the first input,
+    against the oracle's Adam fed its own FP64 gradients.  Unlike a first
+    step (lr sign(g) for any beta1, beta2), this update depends on both."""
+    prob, Ws, r, Q = setup
+    import torch
+    r2 = syn.gaussian_vectors(prob.dims, C, 10)
+    Q2 = amg.block_orthonormalize(syn.gaussian_vectors(prob.dims, C, 12), prob.dims, prob.block)
+    wflat = np.ascontiguousarray(np.stack(Ws).astype(np.complex64))
+    prob.ctx.net_init(prob.T(wflat), L, C)  # fresh moments, t = 0
+    lr = 1e-3
+    for rr, qq, l in ((r, Q, 0.0), (r2, Q2, 0.0), (r, Q, lr)):
+        prob.ctx.net_train_step(prob.T(rr), prob.T(qq), l)
+    got = torch.zeros((L, 9, C, C, 4, 4), dtype=torch.complex64, device=prob.dev)
+    prob.ctx.net_get_weights(got)
+
+    def grads(rr, qq):
+        acts = net.forward(prob.U, Ws, rr, BC_AP)
+        _, gA = net.subspace_loss(acts[-1], qq, prob.dims, prob.block)
+        return net.backward(prob.U, Ws, acts, gA, BC_AP)[0]
+
+    g1, g2 = grads(r, Q), grads(r2, Q2)
+    opt = net.Adam(lr=0.0)
+    opt.step(Ws, g1)
+    opt.step(Ws, g2)
+    opt.lr = lr
+    W3 = opt.step(Ws, g1)
+    upd_g = got.cpu().numpy() - np.stack(Ws)
+    upd_o = np.stack(W3) - np.stack(Ws)
+    a1, a2 = np.stack(g1), np.stack(g2)
+    for part in (np.real, np.imag):
+        # where both gradients stand well above the FP32 gradient's rounding
+        m = (np.abs(part(a1)) > 0.05 * np.abs(a1).max()) & (np.abs(part(a2)) > 0.05 * np.abs(a2).max())
+        assert m.sum() > 100
+        assert np.abs(part(upd_g) - part(upd_o))[m].max() < 2e-5
+        # the update is not lr sign(g1) everywhere: it depends on g2 through the moments
+        assert np.abs(np.abs(part(upd_o))[m] - lr).max() > 1e-4
+    prob.ctx.net_init(prob.T(wflat), L, C)
 
 
 def test_net_initialised_setup_and_solve(setup):
@@ -79,3 +125,83 @@ def test_net_initialised_setup_and_solve(setup):
     assert rc == 0
     xg = prob.N(x)
     assert np.linalg.norm(b - prob.op.D(xg)) / np.linalg.norm(b) <= 1e-10
+
+
+def test_learned_setup_gain_and_fallback():
+    """A short training run and the evaluation of what the learned start
+    gains: 8^4 lattices (eps per seed in [0.3, 0.5], kappa 0.1355, c_sw 1.0,
+    blocks 4^4, N_v = 16, mixed), teachers from the plain setup on 8 seeds,
+    3 epochs of Adam on the library's kernels, then on 2 held-out seeds the
+    plain setup, the ablation and the network setup each solve a Z2 source to
+    1e-10.  The test asserts that training lowers the loss, that every setup
+    converges, and that the plain setup judges the network (kept only when it
+    needs no more outer iterations on every seed).  A degenerate network
+    (all output channels equal: linearly dependent start vectors) makes the
+    network setup fail, and the fallback then picks and solves with the
+    plain setup."""
+    import torch
+    from paper_2111_05012_amd import Context, PREC_MIXED
+    from paper_2111_05012_amd.train_net import eps_of, evaluate_seed, choose_setup, summarize
+    dims, block, kappa, csw = (8, 8, 8, 8), (4, 4, 4, 4), 0.1355, 1.0
+    dev = torch.device('cuda:0')
+    ctx = Context(dims, block, BC_AP, kappa, csw)
+    train, held = range(100, 108), (300, 301)
+
+    def load(s):
+        ctx.load_gauge(syn.gauge_field_torch(dims, eps_of(s), s, dev))
+
+    def net_in(s):
+        return syn.gaussian_vectors_torch(dims, C, s + 100000, dev)
+
+    teachers = {}
+    for s in train:
+        load(s)
+        ctx.setup(ctx.setup_params(C, PREC_MIXED, init_vectors=syn.gaussian_vectors_torch(dims, C, s, dev)))
+        Q = torch.zeros((C,) + syn.shape_of(dims) + (4, 3), dtype=torch.complex128, device=dev)
+        ctx.get_test_vectors(Q)
+        teachers[s] = Q
+    W = np.ascontiguousarray(np.stack(syn.net_weights(C, L, 1)).astype(np.complex64))
+    ctx.net_init(torch.from_numpy(W).to(dev), L, C)
+    hist = []
+    for ep in range(3):
+        tot = 0.0
+        for s in train:
+            load(s)
+            tot += ctx.net_train_step(net_in(s), teachers[s], 2e-3)
+        hist.append(tot / len(train))
+    assert hist[-1] < hist[0], hist
+
+    def evaluate():
+        rows = []
+        for s in held:
+            load(s)
+            b = torch.from_numpy(syn.z2_source(dims, s)).to(dev)
+            row = evaluate_seed(ctx, C, b, net_in(s), syn.gaussian_vectors_torch(dims, C, s, dev))
+            rows.append(row)
+        return rows
+
+    rows = evaluate()
+    summary = summarize(rows)
+    print('learned setup on 8^4:', summary, 'loss', hist)
+    for r in rows:
+        for name in ('plain', 'ablate', 'net'):
+            assert r[name]['converged'] and r[name]['relres'] <= 1e-10, (name, r[name])
+    wins = all(r['net']['iters'] <= r['plain']['iters'] for r in rows)
+    assert choose_setup(rows) == ('net' if wins else 'plain'), (summary, rows)
+
+    # a network whose 16 outputs coincide: the network setup fails on every
+    # seed, and the plain setup is chosen and solves
+    Wd = W.copy()
+    Wd[:, :, :, :, :, :] = Wd[:, :, :1, :, :, :]
+    ctx.net_init(torch.from_numpy(np.ascontiguousarray(Wd)).to(dev), L, C)
+    bad = evaluate()
+    assert all('error' in r['net'] for r in bad), bad
+    assert choose_setup(bad) == 'plain'
+    s = held[0]
+    load(s)
+    ctx.setup(ctx.setup_params(C, PREC_MIXED, init_vectors=syn.gaussian_vectors_torch(dims, C, s, dev)))
+    b = torch.from_numpy(syn.z2_source(dims, s)).to(dev)
+    x = torch.zeros_like(b)
+    rc, info = ctx.solve(b, x, 1, tol=1e-10)
+    assert rc == 0 and info.relres[0] <= 1e-10
+    ctx.close()

@@ -7,7 +7,7 @@ SAP domains per direction) with the benchmark's parameters (eps 0.3, kappa
 0.1365, c_sw 1.1).
 
 Mixed-precision results are compared with the FP64 oracle evaluated on the
-same FP16-rounded links, clover and test vectors, the same FP32-rounded
+same FP16-rounded hop matrices -kappa U, clover and test vectors, the same FP32-rounded
 inputs and (for the coarse level) the same complex64-rounded coarse
 operator.  What remains between the two is the FP32 arithmetic of the
 kernels, so the tolerances are FP32-rounding bounds (at most 1e-5 relative
@@ -61,8 +61,9 @@ def r32(a):
 @pytest.fixture(scope='module')
 def prod():
     prob = Problem(DIMS, BLOCK, eps=EPS, seed=1, kappa=KAPPA, csw=CSW)
-    # the oracle's operator on the library's FP16 storage of links and clover
-    prob.op16 = amg.FineOp(r16(prob.U), r16(prob.Fb), KAPPA, prob.bc, BLOCK)
+    # the oracle's operator on the library's FP16 storage: the hop matrices
+    # -kappa U (one rounding of the FP64 product) and the clover term
+    prob.op16 = amg.FineOp(r16(-KAPPA * prob.U) / -KAPPA, r16(prob.Fb), KAPPA, prob.bc, BLOCK)
     prob.V = amg.block_orthonormalize(syn.gaussian_vectors(DIMS, NV, 71), DIMS, BLOCK)
     prob.V16 = r16(prob.V)
     prob.nX = amg.n_blocks(DIMS, BLOCK)
