@@ -130,9 +130,20 @@ int wcamg_apply_Dsap(wcamg_ctx* ctx, const void* in, void* out, int nrhs, int pr
 /* x = SAP(b): the Schwarz alternating procedure with fixed iterations
  * (Sec. 3 listing): x = 0, r = b; per sweep, even then odd domains
  * (colour = parity of the sum of block coordinates) get x += M r with M
- * mr_iters minimal-residual iterations on D_SAP of the domain, and
- * r = b - D x.  Needs an even number of blocks per direction (EINVAL). */
-int wcamg_sap(wcamg_ctx* ctx, const void* b, void* x, int nrhs, int sweeps, int mr_iters, int prec, int where);
+ * the block solve, and r = b - D x.  Needs an even number of blocks per
+ * direction (EINVAL).  block_solve:
+ *   WCAMG_BLOCK_MR: mr_iters minimal-residual iterations on D_SAP of the
+ *     domain from 0 (the paper's choice);
+ *   WCAMG_BLOCK_EO_MR: the even-odd preconditioned variant (mixed precision,
+ *     even block extents): with A = 1 + F and H the in-domain hops split by
+ *     site parity, mr_iters MR iterations on the Schur complement
+ *     S = A_e - H_eo A_o^-1 H_oe for c_e = b_e - H_eo A_o^-1 b_o, then
+ *     x_o = A_o^-1 (b_o - H_oe x_e), with A_o^-1 stored in FP16 as
+ *     (1 + F)^-1 - 1. */
+#define WCAMG_BLOCK_MR 0
+#define WCAMG_BLOCK_EO_MR 1
+int wcamg_sap(wcamg_ctx* ctx, const void* b, void* x, int nrhs, int sweeps, int mr_iters, int block_solve, int prec,
+              int where);
 
 typedef struct {
   int nv;            /* test vectors N_v (<= 64) */
@@ -170,6 +181,9 @@ typedef struct {
    * WCAMG_SMOOTH_PRE (1): smoother, then coarse grid;
    * WCAMG_SMOOTH_BOTH (2): smoother, coarse grid, smoother. */
   int smoothing;
+  /* SAP block solve: 0 = WCAMG_BLOCK_MR (default), 1 = WCAMG_BLOCK_EO_MR
+   * (the even-odd preconditioned variant of wcamg_sap; mixed precision). */
+  int sap_eo;
 } wcamg_setup_params;
 #define WCAMG_SMOOTH_POST 0
 #define WCAMG_SMOOTH_PRE 1

@@ -2,7 +2,8 @@
 
 Objects and the passages they follow:
   * minimal-residual block solve (SAP paragraph: "MINRES" with a fixed number
-    of iterations; read as MR because D_SAP is not Hermitian);
+    of iterations; read as MR because D_SAP is not Hermitian), and as a
+    variant the same MR on the even-odd Schur complement of each domain;
   * SAP with fixed iterations (the SAP listing of Sec. 3): domains = the
     multigrid blocks, even/odd domain colour = parity of the sum of the block
     coordinates, even colour first;
@@ -27,7 +28,8 @@ d = 0 (self), 1+mu (forward mu), 5+mu (backward mu); hops that reach the same
 neighbour block (extent 2) stay in separate blocks and are summed on use.
 
 Pins (tests/test_oracle_amg.py): MR's one-step optimality and monotone
-residual; SAP with exact block solves equal to the dense red-black block
+residual; the even-odd variant's Schur complement against the dense one, its
+zero odd-site residual and its convergence to the dense block solve; SAP with exact block solves equal to the dense red-black block
 Gauss-Seidel iteration, and its convergence to D^-1 b; orthonormality, span
 and agreement with a sign-fixed library QR; R P = 1, P R an orthogonal
 projector, Dc = P^dag D P by dense brute force, coarse gamma_5-hermiticity,
@@ -163,6 +165,72 @@ def mr_domains(op, b, iters):
         x = x + _per_domain(r, alpha, op.dims, op.block)
         r = r - _per_domain(p, alpha, op.dims, op.block)
     return x, r
+
+
+def site_parity(dims):
+    """Per-site parity (x + y + z + t) mod 2, shaped [Lt,Lz,Ly,Lx,1,1]."""
+    cs = []
+    for mu in range(4):
+        shp = [1, 1, 1, 1]
+        shp[3 - mu] = dims[mu]
+        cs.append(np.arange(dims[mu]).reshape(shp))
+    return ((cs[0] + cs[1] + cs[2] + cs[3]) % 2)[..., None, None]
+
+
+def clover_inverse(Fb):
+    """Per-site inverse of the site-local part 1 + F(x), as its two chiral
+    6x6 blocks (like the clover field)."""
+    return np.linalg.inv(np.eye(6) + Fb)
+
+
+def eo_mr_domains(op, b, iters, Ainv=None):
+    """Even-odd preconditioned MR block solve on every domain (the smoother
+    variant of the SAP block solve).  In a domain, D_SAP splits by site
+    parity into [[A_e, H_eo], [H_oe, A_o]] with A = 1 + F (site-local) and H
+    the in-domain hops.  With the Schur complement S = A_e - H_eo A_o^-1 H_oe
+    on the even sites:
+        c_e = b_e - H_eo A_o^-1 b_o,
+        x_e = MR(iters) on S x_e = c_e from 0 (domain inner products over
+              the even sites),
+        x_o = A_o^-1 (b_o - H_oe x_e).
+    Ainv: the per-site blocks used for A^-1 (default: the exact inverse).
+    Returns (x, r) with r = b - D_SAP x, the block solve's true residual."""
+    dims, block = op.dims, op.block
+    if Ainv is None:
+        Ainv = clover_inverse(op.Fb)
+    odd = site_parity(dims) == 1
+
+    def ev(f):
+        return np.where(odd, 0.0, f)
+
+    def od(f):
+        return np.where(odd, f, 0.0)
+
+    def A(f):
+        return f + dirac.clover_apply(op.Fb, f)
+
+    def Ai(f):
+        return dirac.clover_apply(Ainv, f)
+
+    def H(f):
+        return op.Dsap(f) - A(f)
+
+    def S(v):
+        return ev(A(v)) - ev(H(od(Ai(od(H(v))))))
+
+    c = ev(b) - ev(H(od(Ai(od(b)))))
+    xe = np.zeros_like(b)
+    r = c
+    for _ in range(iters):
+        p = S(r)
+        pr = domain_sums(np.conj(p) * r, dims, block)
+        pp = domain_sums(np.abs(p) ** 2, dims, block).real
+        alpha = np.where(pp > 0, pr / np.where(pp > 0, pp, 1.0), 0.0)
+        xe = xe + _per_domain(r, alpha, dims, block)
+        r = r - _per_domain(p, alpha, dims, block)
+    xo = od(Ai(od(b) - od(H(xe))))
+    x = xe + xo
+    return x, b - op.Dsap(x)
 
 
 def sap(op, b, sweeps=4, mr_iters=6, block_solver=None):

@@ -92,6 +92,7 @@ struct Hier {
   CGeo cg{};
   int sap_sweeps = 4, mr_iters = 6, coarse_iters = 50;
   int smoothing = WCAMG_SMOOTH_POST;
+  int sap_eo = 0;  // even-odd preconditioned SAP block solve
   double coarse_tol = 0.1;
   DevBuf V;   // stored test vectors [nv][12][V]
   DevBuf Dc;  // [NC][9][N][N]
@@ -225,6 +226,10 @@ struct wcamg_ctx {
   // solver's inner BiCGStab (single-precision fields, as the paper's)
   DevBuf U32, Cl32;
   bool have_f32 = false;
+  // FP16 (1 + F)^-1 - 1, made on first use by the even-odd preconditioned
+  // SAP block solve
+  DevBuf Mi16;
+  bool have_minv = false;
   Hier h;
   bool have_hier = false;
   std::map<std::string, std::unique_ptr<DevBuf>> ws;
@@ -379,7 +384,7 @@ struct wcamg_ctx {
   std::vector<double> hier_sig() const {
     std::vector<double> s = {(double)h.prec, (double)h.nv, (double)h.sap_sweeps, (double)h.mr_iters,
                              (double)h.coarse_iters, h.coarse_tol, (double)h.l1, (double)h.nw,
-                             (double)h.mr1_iters, (double)h.smoothing};
+                             (double)h.mr1_iters, (double)h.smoothing, (double)h.sap_eo};
     for (int m = 0; m < 4; ++m) s.push_back(h.b1[m]);
     return s;
   }
@@ -536,6 +541,12 @@ struct wcamg_ctx {
   // FP64), so the kernels that apply it take the hop coefficient -kappa = 1,
   // i.e. kappa = -1.
   static constexpr double HOP16_KAPPA = -1.0;
+  void ensure_minv() {
+    if (have_minv) return;
+    Mi16.ensure((size_t)36 * g.V * sizeof(half2_t), capturing);
+    launch_clover_inverse(g, (const double2*)Cl64.p, (half2_t*)Mi16.p, st);
+    have_minv = true;
+  }
   void ensure_f32() {
     if (have_f32) return;
     U32.ensure((size_t)36 * g.V * sizeof(float2), capturing);
@@ -602,9 +613,17 @@ struct wcamg_ctx {
     launch_dslash(a, st);
   }
 
-  void sap(const void* b, void* x, const void* xinit, int nrhs, int sweeps, int mr, int prec) {
+  void sap(const void* b, void* x, const void* xinit, int nrhs, int sweeps, int mr, int prec, int eo = 0) {
     SapArgs a;
     a.g = g;
+    if (eo) {
+      require(prec == WCAMG_PREC_MIXED, "the even-odd block solve runs in mixed precision only");
+      require(g.B[0] % 2 == 0 && g.B[1] % 2 == 0 && g.B[2] % 2 == 0 && g.B[3] % 2 == 0,
+              "the even-odd block solve needs even block extents");
+      ensure_minv();
+      a.eo = 1;
+      a.M = Mi16.p;
+    }
     a.nrhs = nrhs;
     a.sweeps = sweeps;
     a.mr = mr;
@@ -875,7 +894,7 @@ struct wcamg_ctx {
     };
     auto smooth = [&](const void* rhs, void* x, const void* x0) {
       Phase ph(this, PH_SMOOTH);
-      sap(rhs, x, x0, nrhs, h.sap_sweeps, h.mr_iters, prec);
+      sap(rhs, x, x0, nrhs, h.sap_sweeps, h.mr_iters, prec, h.sap_eo);
     };
     if (h.smoothing == WCAMG_SMOOTH_POST) {
       coarse(in);
@@ -1034,6 +1053,11 @@ struct wcamg_ctx {
     require(p->smoothing == WCAMG_SMOOTH_POST || p->smoothing == WCAMG_SMOOTH_PRE ||
                 p->smoothing == WCAMG_SMOOTH_BOTH,
             "invalid smoothing");
+    require(p->sap_eo == 0 || p->sap_eo == 1, "sap_eo must be 0 or 1");
+    require(!p->sap_eo || p->prec == WCAMG_PREC_MIXED, "the even-odd block solve runs in mixed precision only");
+    require(!p->sap_eo || (g.B[0] % 2 == 0 && g.B[1] % 2 == 0 && g.B[2] % 2 == 0 && g.B[3] % 2 == 0),
+            "the even-odd block solve needs even block extents");
+    h.sap_eo = p->sap_eo;
     h.smoothing = p->smoothing;
     h.prec = p->prec;
     h.nv = p->nv;
@@ -1218,6 +1242,7 @@ int wcamg_load_gauge(wcamg_ctx* c, const void* U, int where) {
     c->have_gauge = true;
     c->have_hier = false;
     c->have_f32 = false;
+    c->have_minv = false;
   });
 }
 
@@ -1235,6 +1260,7 @@ int wcamg_load_clover(wcamg_ctx* c, const void* F, int where) {
     HIPCHK(hipStreamSynchronize(c->st));
     c->have_hier = false;
     c->have_f32 = false;
+    c->have_minv = false;
   });
 }
 
@@ -1316,13 +1342,15 @@ int wcamg_apply_Dsap(wcamg_ctx* c, const void* in, void* out, int nrhs, int prec
   return apply_op(c, in, out, nrhs, prec, where, OP_DSAP);
 }
 
-int wcamg_sap(wcamg_ctx* c, const void* b, void* x, int nrhs, int sweeps, int mr_iters, int prec, int where) {
+int wcamg_sap(wcamg_ctx* c, const void* b, void* x, int nrhs, int sweeps, int mr_iters, int block_solve, int prec,
+              int where) {
   if (!c) return WCAMG_EINVAL;
   return guard(c, [&] {
     check_where(where);
     check_nrhs(nrhs);
     check_prec(prec);
     require(b && x, "null pointer");
+    require(block_solve == WCAMG_BLOCK_MR || block_solve == WCAMG_BLOCK_EO_MR, "invalid block_solve");
     require(sweeps >= 0 && mr_iters >= 0, "negative iteration count");
     require(c->have_gauge, "no gauge field", WCAMG_ESTATE);
     const Geo& g = c->g;
@@ -1338,7 +1366,7 @@ int wcamg_sap(wcamg_ctx* c, const void* b, void* x, int nrhs, int sweeps, int mr
     void* bi = c->W("ap_a", c->fsz(nrhs, prec));
     void* xi = c->W("ap_b", c->fsz(nrhs, prec));
     launch_pack_spinor(g, bd, bi, t, c->frs(), nrhs, c->st);
-    c->sap(bi, xi, nullptr, nrhs, sweeps, mr_iters, prec);
+    c->sap(bi, xi, nullptr, nrhs, sweeps, mr_iters, prec, block_solve == WCAMG_BLOCK_EO_MR);
     launch_unpack_spinor(g, xi, t, c->frs(), xd, nrhs, c->st);
     HIPCHK(hipGetLastError());
     io.finish(x, xd, cbytes, where);
@@ -1412,7 +1440,7 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
     } else {
       start(Vw, t);
       for (int k = 0; k < p->n_init; ++k) {
-        c->sap(Vw, Vt, nullptr, nv, p->sap_sweeps, p->mr_iters, prec);
+        c->sap(Vw, Vt, nullptr, nv, p->sap_sweeps, p->mr_iters, prec, p->sap_eo);
         std::swap(Vw, Vt);
       }
     }

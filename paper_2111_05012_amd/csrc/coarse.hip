@@ -989,12 +989,14 @@ __global__ __launch_bounds__(256) void k_coarse_build(Geo g, int nv, R kappa, co
   const int T = 256 / nv;  // sites per tile (threads t < T nv compute the vectors g)
   cplx<R>* sv = (cplx<R>*)smem;     // [T][nv][12]
   cplx<R>* sgv = sv + T * nv * 12;  // [T][nv][12]
-  // one workgroup per (X, d, sp), X slowest; consecutive logical indices run on
-  // one XCD, so the 18 workgroups of a block share that XCD's L2
-  const int nlog = g.nblk * 18;
+  // one workgroup per (X, d, sp) for the self block and the 4 forward blocks
+  // (k_coarse_mirror derives the backward ones), X slowest; consecutive
+  // logical indices run on one XCD, so the 10 workgroups of a block share
+  // that XCD's L2
+  const int nlog = g.nblk * 10;
   const int lg = xcd_remap(blockIdx.x, nlog);
   if (lg >= nlog) return;
-  const int X = lg / 18, d = (lg % 18) >> 1, sp = lg & 1;
+  const int X = lg / 10, d = (lg % 10) >> 1, sp = lg & 1;
   const int t = threadIdx.x;
   const int Vg = g.V;
   const int mu = (d - 1) & 3;
@@ -1132,7 +1134,8 @@ __global__ __launch_bounds__(256) void k_coarse_build(Geo g, int nv, R kappa, co
 // held at zero in LDS.
 
 // Work units per block X: the in-block part (d = 0) split into nch chunks of
-// site tiles, then the 8 crossing directions d.  A unit forms g_j for both
+// site tiles, then the 4 forward crossing directions d (k_coarse_mirror
+// derives the backward blocks).  A unit forms g_j for both
 // source chiralities sp from one set of vector and link loads and contracts
 // all four (s, sp) blocks.  All units of a block are consecutive logical
 // indices on one XCD, so that few blocks are in flight per XCD and their
@@ -1148,7 +1151,7 @@ __global__ __launch_bounds__(256) void k_coarse_build_mf(Geo g, int nv, float ka
   // svr/svi[s][k][i]: v_i; sgr/sgi[sp][s][k][j]: g_j of source chirality sp
   __shared__ float svr[2][K][32], svi[2][K][32], sgr[2][2][K][32], sgi[2][2][K][32];
   const int N = 2 * nv;
-  const int nu = nch + 8;
+  const int nu = nch + 4;
   const int nlog = g.nblk * nu;
   const int lg = xcd_remap(blockIdx.x, nlog);
   if (lg >= nlog) return;
@@ -1348,7 +1351,7 @@ static void coarse_build_run(const Geo& g, int nv, double kappa, const void* V, 
   const int ncg = 256 / N;
   const int cpg = (nv + ncg - 1) / ncg;
   const size_t lds = 2 * (size_t)(256 / nv) * nv * 12 * sizeof(cplx<R>);
-  dim3 grid(round8(g.nblk * 18));
+  dim3 grid(round8(g.nblk * 10));
   auto go = [&](auto tag) {
     constexpr int CPG = decltype(tag)::value;
     auto kern = k_coarse_build<R, TV, TL, TC, TO, CPG>;
@@ -1381,18 +1384,82 @@ void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, cons
     const int tpc = 8;    // tiles per in-block chunk (64 sites)
     const int nch = coarse_build_chunks(g);
     const int N = 2 * nv;
-    k_coarse_build_mf<T><<<dim3(round8(g.nblk * (nch + 8))), 256, 0, st>>>(
+    k_coarse_build_mf<T><<<dim3(round8(g.nblk * (nch + 4))), 256, 0, st>>>(
         g, nv, (float)kappa, (const half2_t*)V, (const half2_t*)U, (const half2_t*)C, (float2*)Dc, nch, tpc,
         (float2*)part);
     const size_t ne = (size_t)g.nblk * N * N;
     k_coarse_build_sum<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(g.nblk, N, nch, (const float2*)part,
                                                                      (float2*)Dc);
-    return;
-  }
-  if (mixed)
+  } else if (mixed) {
     coarse_build_run<float, half2_t, half2_t, half2_t, float2>(g, nv, kappa, V, U, C, Dc, st);
-  else
+  } else {
     coarse_build_run<double, double2, double2, double2, double2>(g, nv, kappa, V, U, C, Dc, st);
+  }
+  launch_coarse_mirror(make_cgeo(g.NB), nv, Dc, mixed, st);
+}
+
+// Backward blocks of the coarse operator from the forward ones.  The
+// backward hop in direction mu is the gamma_5-conjugated adjoint of the
+// forward hop of the neighbour (eq. (2)), and the basis vectors P_s v_i are
+// gamma_5 eigenvectors with eigenvalue +-1 (s = 0: +1), so with
+// Gamma = diag(1, ..., 1 (s = 0), -1, ..., -1 (s = 1)) eq. (7) gives
+//   Dc(X, X - mu) = Gamma Dc(X - mu, X)^dag Gamma.
+// In the stored layout (block d of X at [X][d][m][n] = <X, n| D |X + e_d, m>)
+//   [X][5 + mu][m][n] = g(n) g(m) conj([Y][1 + mu][n][m]),  Y = X - e_mu,
+// g(k) = +1 for k < nv, -1 otherwise.  One 32x32 tile of an output block per
+// workgroup, transposed through LDS so that reads and writes are coalesced.
+template <class T>
+__global__ __launch_bounds__(256) void k_coarse_mirror(CGeo cg, int nv, T* __restrict__ Dc) {
+  __shared__ T tile[32][33];
+  const int N = 2 * nv;
+  const int nt = (N + 31) / 32;
+  int q = blockIdx.x;
+  const int tn = q % nt;
+  q /= nt;
+  const int tm = q % nt;
+  q /= nt;
+  const int mu = q & 3;
+  const int X = q >> 2;
+  if (X >= cg.NC) return;
+  int r = X, c[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    c[m] = r % cg.N[m];
+    r /= cg.N[m];
+  }
+  const int cm = c[mu] == 0 ? cg.N[mu] - 1 : c[mu] - 1;
+  const int Y = X + (cm - c[mu]) * cg.sN[mu];
+  const T* src = Dc + ((size_t)Y * 9 + 1 + mu) * N * N;
+  T* dst = Dc + ((size_t)X * 9 + 5 + mu) * N * N;
+  const int m0 = tm * 32, n0 = tn * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // source rows n0 + i, columns m0 + j
+  for (int i = ty; i < 32; i += 8) {
+    const int n = n0 + i, m = m0 + tx;
+    if (n < N && m < N) tile[i][tx] = src[(size_t)n * N + m];
+  }
+  __syncthreads();
+  // destination rows m0 + j, columns n0 + i
+  for (int j = ty; j < 32; j += 8) {
+    const int m = m0 + j, n = n0 + tx;
+    if (n < N && m < N) {
+      const T v = tile[tx][j];
+      const bool neg = (n < nv) != (m < nv);
+      T o;
+      o.x = neg ? -v.x : v.x;
+      o.y = neg ? v.y : -v.y;
+      dst[(size_t)m * N + n] = o;
+    }
+  }
+}
+
+void launch_coarse_mirror(const CGeo& cg, int nv, void* Dc, int prec32, hipStream_t st) {
+  const int nt = (2 * nv + 31) / 32;
+  const unsigned nb = (unsigned)((size_t)cg.NC * 4 * nt * nt);
+  if (prec32)
+    k_coarse_mirror<float2><<<nb, 256, 0, st>>>(cg, nv, (float2*)Dc);
+  else
+    k_coarse_mirror<double2><<<nb, 256, 0, st>>>(cg, nv, (double2*)Dc);
 }
 
 // ---------------------------------------------------------------------------

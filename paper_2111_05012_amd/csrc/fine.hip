@@ -156,6 +156,77 @@ __global__ __launch_bounds__(256) void k_unpack_clover(Geo g, const double2* __r
   }
 }
 
+// M(x) = (1 + F(x))^-1 - 1 per chirality block, from the packed FP64 clover,
+// in the packed clover format, FP16 (one rounding of the FP64 result): the
+// site-local inverse of the even-odd preconditioned domain solve.  Gauss-
+// Jordan elimination with partial pivoting in FP64, one thread per (site,
+// chirality block).
+__global__ __launch_bounds__(256) void k_clover_inverse(Geo g, const double2* __restrict__ C64,
+                                                        half2_t* __restrict__ M16) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (size_t)2 * g.V) return;
+  const int s = (int)(e >> 1), bb = (int)(e & 1);
+  const size_t base = fbase(g, 36, s);
+  double2 pr[18];
+  for (int q = 0; q < 18; ++q) pr[q] = C64[(size_t)(18 * bb + q) * g.Vb + base];
+  cplx<double> a[6][12];  // [A | 1]
+  const double d[6] = {pr[0].x, pr[0].y, pr[1].x, pr[1].y, pr[2].x, pr[2].y};
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 12; ++j) a[i][j] = {0, 0};
+  int k = 3;
+  for (int i = 0; i < 6; ++i) {
+    a[i][i] = {1.0 + d[i], 0};
+    a[i][6 + i] = {1.0, 0};
+    for (int j = i + 1; j < 6; ++j) {
+      const double2 u = pr[k++];
+      a[i][j] = {u.x, u.y};
+      a[j][i] = {u.x, -u.y};
+    }
+  }
+  for (int col = 0; col < 6; ++col) {
+    int piv = col;
+    double best = a[col][col].x * a[col][col].x + a[col][col].y * a[col][col].y;
+    for (int i = col + 1; i < 6; ++i) {
+      const double m2 = a[i][col].x * a[i][col].x + a[i][col].y * a[i][col].y;
+      if (m2 > best) {
+        best = m2;
+        piv = i;
+      }
+    }
+    if (piv != col)
+      for (int j = 0; j < 12; ++j) {
+        const cplx<double> t = a[col][j];
+        a[col][j] = a[piv][j];
+        a[piv][j] = t;
+      }
+    const cplx<double> pv = a[col][col];
+    const double n2 = pv.x * pv.x + pv.y * pv.y;
+    const cplx<double> inv = {pv.x / n2, -pv.y / n2};
+    for (int j = 0; j < 12; ++j) a[col][j] = inv * a[col][j];
+    for (int i = 0; i < 6; ++i) {
+      if (i == col) continue;
+      const cplx<double> f = a[i][col];
+      for (int j = 0; j < 12; ++j) a[i][j] = a[i][j] - f * a[col][j];
+    }
+  }
+  // the inverse of a Hermitian matrix is Hermitian: pack its diagonal (real)
+  // and upper triangle, minus the identity
+  double2 out[18];
+  out[0] = make_double2(a[0][6].x - 1.0, a[1][7].x - 1.0);
+  out[1] = make_double2(a[2][8].x - 1.0, a[3][9].x - 1.0);
+  out[2] = make_double2(a[4][10].x - 1.0, a[5][11].x - 1.0);
+  k = 3;
+  for (int i = 0; i < 6; ++i)
+    for (int j = i + 1; j < 6; ++j) out[k++] = make_double2(a[i][6 + j].x, a[i][6 + j].y);
+  for (int q = 0; q < 18; ++q)
+    st(M16, (size_t)(18 * bb + q) * g.Vb + base, cplx<double>{out[q].x, out[q].y});
+}
+
+void launch_clover_inverse(const Geo& g, const double2* C64, half2_t* M16, hipStream_t st) {
+  const size_t n = (size_t)2 * g.V;
+  k_clover_inverse<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(g, C64, M16);
+}
+
 // ---------------------------------------------------------------------------
 // Clover construction: F(x) = i c_sw kappa sum_{mu<nu} sigma_{mu nu} (x) Fhat_{mu nu}(x),
 // Fhat = (Q - Q^dag) / 8, Q = sum of the four plaquette leaves at x in the
@@ -1172,6 +1243,226 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   }
 }
 
+// Even-odd preconditioned variant of the mixed domain solve.  In a domain,
+// D_SAP splits by site parity into [[A_e, H_eo], [H_oe, A_o]] (A = 1 + F
+// site-local, H the in-domain hops); with S = A_e - H_eo A_o^-1 H_oe on the
+// even sites the block solve is
+//   c_e = b_e - H_eo A_o^-1 b_o;  x_e = MR(mr) on S x_e = c_e from 0;
+//   x_o = A_o^-1 (b_o - H_oe x_e),
+// and its residual is c_e - S x_e on the even sites (equal to b - D_SAP x
+// there) and b_o - H_oe x_e - A_o x_o on the odd ones.  A_o^-1 is applied as
+// psi + M psi with M = (1 + F)^-1 - 1 stored in FP16 like the clover.  The
+// threads are sorted by parity (the first Vb/2 take the even sites), so the
+// phases that only one parity works in leave whole wavefronts idle instead
+// of half of every wavefront.  One workgroup per domain of the active colour,
+// all right-hand sides in turn; links, exchange buffer and reduction as in
+// k_sap_dom (the buffer holds even-site values in even slots and odd-site
+// values in odd slots, so one buffer serves both directions).
+template <int VB>
+__global__ __launch_bounds__(512) void k_sap_dom_eo(Geo g, int colour, int flags, int mr, int nrhs,
+                                                    const float2* __restrict__ b, float2* __restrict__ r,
+                                                    float2* __restrict__ x, float2* __restrict__ delta,
+                                                    const float2* __restrict__ xinit, size_t rs,
+                                                    const half2_t* __restrict__ U, const half2_t* __restrict__ C,
+                                                    const half2_t* __restrict__ M) {
+  extern __shared__ __align__(16) char smem[];
+  const int Vb = VB ? VB : g.Vb;
+  cplx<float>* lds = (cplx<float>*)smem;                            // [12][Vb] exchange, indexed by site
+  half2_t* lu = (half2_t*)(smem + 12 * Vb * sizeof(cplx<float>));  // [4][9][Vb] -kappa sign U_mu(x)
+  float* red = (float*)(lu + 36 * Vb);                              // [nwaves][3]
+  const int half = g.NB[0] >> 1;
+  int k = xcd_remap(blockIdx.x, g.nblk >> 1);
+  if (k >= (g.nblk >> 1)) return;
+  int row = k / half, j = k - row * half;
+  int by = row % g.NB[1];
+  int rz = row / g.NB[1];
+  int bz = rz % g.NB[2];
+  int bt = rz / g.NB[2];
+  int bx = 2 * j + ((colour + by + bz + bt) & 1);
+  int blk = bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
+  const int l = threadIdx.x;
+  const int hv = Vb >> 1;
+  const bool act = l < Vb;
+  const bool ev = l < hv;  // even-site thread (odd-site threads: hv <= l < Vb)
+  // the site of thread l: the (l mod hv)-th site of its parity in the block
+  // (block extents even: every x-row holds B_x / 2 sites of each parity)
+  int loc = 0;
+  {
+    const int q = act ? (ev ? l : l - hv) : 0;
+    const int hx = g.B[0] >> 1;
+    const int rrow = q / hx, kx = q - rrow * hx;
+    int t = rrow, rp = 0;
+#pragma unroll
+    for (int m = 1; m < 4; ++m) {
+      rp += t % g.B[m];
+      t /= g.B[m];
+    }
+    loc = rrow * g.B[0] + 2 * kx + ((rp + (ev ? 0 : 1)) & 1);
+  }
+  const int s = blk * Vb + loc;
+  const int nw = (blockDim.x + 63) >> 6;
+  SiteCoord c = decompose(g, s);
+  const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
+  float fsign[4];
+  int ninfo[8];
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    int sign;
+    bool inb;
+    int mu = d & 3;
+    int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb) : neighbour<false>(g, s, c, mu, sign, inb);
+    if (d < 4) fsign[mu] = (float)sign;
+    ninfo[d] = inb ? ((nb - blk * Vb) | (1 << 10)) : 0;
+  }
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < 36; ++q) {
+      half2_t u = U[(size_t)q * Vb + fb36];
+      if (fsign[q / 9] < 0) {
+        u.x = -u.x;
+        u.y = -u.y;
+      }
+      lu[(size_t)q * Vb + loc] = u;
+    }
+  }
+  // even sites hold their clover F, odd sites M = (1 + F)^-1 - 1
+  half2_t cl[36];
+  if (act) {
+    const half2_t* src = ev ? C : M;
+#pragma unroll
+    for (int q = 0; q < 36; ++q) cl[q] = src[(size_t)q * Vb + fb36];
+  }
+  __syncthreads();
+
+  // acc += coef * (sum of the in-domain hops applied to the exchange buffer)
+  auto hops = [&](float coef, cplx<float>(&acc)[12]) {
+    cplx<float> psi[12];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      const int inf = ninfo[d];
+      if (inf & (1 << 10)) {
+        const int nl = inf & 1023;
+#pragma unroll
+        for (int a = 0; a < 12; ++a) psi[a] = lds[a * Vb + nl];
+        half2_t ub[9];
+        const int ls = d < 4 ? loc : nl;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) ub[e] = lu[((d & 3) * 9 + e) * Vb + ls];
+        if (d < 4)
+          hop_h<true>(d & 3, psi, ub, coef, acc);
+        else
+          hop_h<false>(d & 3, psi, ub, coef, acc);
+      }
+    }
+  };
+  // v + cl v (even: (1 + F) v; odd: (1 + F)^-1 v)
+  auto site_op = [&](const cplx<float>(&v)[12], cplx<float>(&out)[12]) {
+#pragma unroll
+    for (int a = 0; a < 12; ++a) out[a] = v[a];
+    clover_acc<float>(cl, 1, 0, v, out);
+  };
+  auto put = [&](const cplx<float>(&v)[12]) {
+#pragma unroll
+    for (int a = 0; a < 12; ++a) lds[a * Vb + loc] = v[a];
+  };
+
+  for (int rr = 0; rr < nrhs; ++rr) {
+    const size_t off = rr * rs;
+    // rho: even sites the Schur residual, odd sites b_o (kept to the end)
+    cplx<float> rho[12], xm[12], p[12];
+    if (act) ld_spinor<float>(((flags & SAP_FIRST) && !(flags & SAP_R_IN)) ? b + off : r + off, Vb, fb12, rho);
+#pragma unroll
+    for (int a = 0; a < 12; ++a) xm[a] = {0, 0};
+    // c_e = b_e - H_eo A_o^-1 b_o
+    if (act && !ev) {
+      site_op(rho, p);
+      put(p);
+    }
+    __syncthreads();
+    if (ev) hops(-1.0f, rho);
+    for (int it = 0; it < mr; ++it) {
+      if (ev) put(rho);
+      __syncthreads();
+      if (act && !ev) {
+        // t_o = A_o^-1 H_oe rho_e (xm, unused by odd sites until the end,
+        // holds H_oe rho_e)
+#pragma unroll
+        for (int a = 0; a < 12; ++a) xm[a] = {-0.0f, -0.0f};
+        hops(1.0f, xm);
+        site_op(xm, p);
+        put(p);
+      }
+      __syncthreads();
+      float pr_re = 0, pr_im = 0, pp = 0;
+      if (ev) {
+        // p = S rho = A_e rho - H_eo t_o
+        site_op(rho, p);
+        hops(-1.0f, p);
+#pragma unroll
+        for (int a = 0; a < 12; ++a) {
+          pr_re += p[a].x * rho[a].x + p[a].y * rho[a].y;
+          pr_im += p[a].x * rho[a].y - p[a].y * rho[a].x;
+          pp += p[a].x * p[a].x + p[a].y * p[a].y;
+        }
+      }
+      pr_re = wave_sum(pr_re);
+      pr_im = wave_sum(pr_im);
+      pp = wave_sum(pp);
+      if ((l & 63) == 0) {
+        red[(l >> 6) * 3 + 0] = pr_re;
+        red[(l >> 6) * 3 + 1] = pr_im;
+        red[(l >> 6) * 3 + 2] = pp;
+      }
+      __syncthreads();
+      float sre = 0, sim = 0, spp = 0;
+      for (int w = 0; w < nw; ++w) {
+        sre += red[w * 3 + 0];
+        sim += red[w * 3 + 1];
+        spp += red[w * 3 + 2];
+      }
+      cplx<float> alpha = {0, 0};
+      if (spp > 0) alpha = {sre / spp, sim / spp};
+      if (ev) {
+#pragma unroll
+        for (int a = 0; a < 12; ++a) {
+          xm[a] = xm[a] + alpha * rho[a];
+          rho[a] = rho[a] - alpha * p[a];
+        }
+      }
+    }
+    // x_o = A_o^-1 (b_o - H_oe x_e); odd residual b_o - H_oe x_e - A_o x_o
+    if (ev) put(xm);
+    __syncthreads();
+    if (act && !ev) {
+      hops(-1.0f, rho);  // q = b_o - H_oe x_e
+      site_op(rho, xm);  // x_o = A_o^-1 q
+      // residual q - A_o x_o = q - x_o - F x_o (F read once per block solve)
+      cplx<float> fx[12];
+#pragma unroll
+      for (int a = 0; a < 12; ++a) fx[a] = {-0.0f, -0.0f};
+      clover_acc<float>(C, Vb, fb36, xm, fx);
+#pragma unroll
+      for (int a = 0; a < 12; ++a) rho[a] = (rho[a] - xm[a]) - fx[a];
+    }
+    if (act) {
+      float2* xr = x + off;
+      float2* rw = r + off;
+      float2* dw = delta + off;
+#pragma unroll
+      for (int a = 0; a < 12; ++a) {
+        size_t o = (size_t)a * Vb + fb12;
+        cplx<float> x0 = {0, 0};
+        if (!(flags & SAP_FIRST)) x0 = ld<float>(xr, o);
+        else if (xinit) x0 = ld<float>(xinit + off, o);
+        st(xr, o, x0 + xm[a]);
+        if (!(flags & SAP_NO_R)) st(rw, o, rho[a]);
+        if (!(flags & SAP_NO_DELTA)) st(dw, o, xm[a]);
+      }
+    }
+    __syncthreads();  // the next right-hand side reuses lds
+  }
+}
+
 int sap_dom_lds_bytes(const Geo& g) {
   int nthr = ((g.Vb + 63) / 64) * 64;
   return 12 * g.Vb * 8 + 36 * g.Vb * 4 + (nthr / 64) * 3 * 4;
@@ -1233,6 +1524,28 @@ void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st) {
                                           (float2*)a.r, (float2*)a.x, (float2*)a.delta, (const float2*)a.xinit, a.rs,
                                           (const half2_t*)a.U, (const half2_t*)a.C);
   };
+  if (a.eo) {
+    if (!a.M) throw std::runtime_error("even-odd SAP: no inverse clover field");
+    if (g.B[0] % 2 || g.B[1] % 2 || g.B[2] % 2 || g.B[3] % 2)
+      throw std::runtime_error("even-odd SAP: block extents must be even");
+    static bool attr_eo[3] = {false, false, false};
+    auto go_eo = [&](auto kern, int id) {
+      if (!attr_eo[id]) {
+        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_eo[id] = true;
+      }
+      kern<<<round8(ndom), nthr, lds, st>>>(g, col, flags, a.mr, a.nrhs, (const float2*)a.b, (float2*)a.r,
+                                            (float2*)a.x, (float2*)a.delta, (const float2*)a.xinit, a.rs,
+                                            (const half2_t*)a.U, (const half2_t*)a.C, (const half2_t*)a.M);
+    };
+    if (g.Vb == 512)
+      go_eo(k_sap_dom_eo<512>, 0);
+    else if (g.Vb == 256)
+      go_eo(k_sap_dom_eo<256>, 1);
+    else
+      go_eo(k_sap_dom_eo<0>, 2);
+    return;
+  }
   if (g.Vb == 512)
     go(k_sap_dom<512>, 0);
   else if (g.Vb == 256)

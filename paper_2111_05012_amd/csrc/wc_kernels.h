@@ -25,6 +25,8 @@ void launch_pack_gauge(const Geo& g, const double2* canon, double2* U64, half2_t
 void launch_clover_build(const Geo& g, const double2* U64, double kappa, double csw, const double* sigma,
                          double2* C64, half2_t* C16, hipStream_t st);
 // canonical clover complex128 [V][2][6][6] <-> packed
+// M16 = FP16 of (1 + F)^-1 - 1 per site and chirality block (packed like the clover)
+void launch_clover_inverse(const Geo& g, const double2* C64, half2_t* M16, hipStream_t st);
 void launch_pack_clover(const Geo& g, const double2* canon, double2* C64, half2_t* C16, hipStream_t st);
 void launch_unpack_clover(const Geo& g, const double2* C64, double2* canon, hipStream_t st);
 
@@ -72,6 +74,10 @@ struct SapArgs {
   size_t rs = 0;                // per-rhs stride of all spinor fields
   const void* U = nullptr;
   const void* C = nullptr;
+  // even-odd preconditioned block solve (mixed precision only): M holds the
+  // FP16 (1 + F)^-1 - 1 (launch_clover_inverse)
+  int eo = 0;
+  const void* M = nullptr;
 };
 // one half-sweep (colour col of sweep `sweep`) of the SAP listing.  Mixed
 // precision: launch_sap_cross (the crossing-hop correction of the residual,
@@ -135,6 +141,9 @@ void launch_coarse_mv(const CGeo& cg, int N, const void* Dc, const void* x, void
 // links, clover; FP32 arithmetic; complex64 Dc) into Dc [X][9][m][n].
 // variant (mixed only): 0 vector-ALU contraction, 1 matrix-core contraction (nv <= 32),
 // which needs a workspace `part` of coarse_build_chunks(g) * nblk * (2 nv)^2 complex64
+// backward blocks [X][5 + mu] of a coarse operator from the forward ones by
+// coarse gamma_5-hermiticity (the build computes d = 0..4 only)
+void launch_coarse_mirror(const CGeo& cg, int nv, void* Dc, int prec32, hipStream_t st);
 void launch_coarse_build(const Geo& g, int nv, double kappa, const void* V, const void* U, const void* C, void* Dc,
                          int mixed, hipStream_t st, int variant = 0, void* part = nullptr);
 int coarse_build_chunks(const Geo& g);

@@ -16,6 +16,11 @@ reporting setup time and outer iterations; the plain setup stays the fallback
 whenever the network setup needs more outer iterations.
 
     python -m paper_2111_05012_amd.train_net --epochs 4 --out weights.npy --report report.json
+
+With --gauge heatbath the configurations come from two heat-bath chains of
+the Wilson action (beta 6.0, cold start, every 5th sweep after 60): one for
+training, an independent one for evaluation (use with the smooth-field
+parameters, e.g. --kappa 0.1345 --csw 1.769).
 """
 import argparse
 import json
@@ -96,6 +101,19 @@ def summarize(rows):
     return out
 
 
+def heatbath_configs(dims, beta, therm, sep, count, seed, device):
+    """count configurations of one heat-bath chain (Wilson action, cold
+    start): after therm sweeps, every sep-th sweep."""
+    from synthetic import heatbath as hb
+    out = []
+
+    def keep(n, U):
+        if n + 1 >= therm and (n + 1 - therm) % sep == 0 and len(out) < count:
+            out.append(U.clone())
+    hb.heatbath_field_torch(dims, beta, therm + sep * (count - 1), seed, device, record=keep)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument('--dims', type=int, nargs=4, default=[16, 16, 16, 16])
@@ -109,6 +127,12 @@ def main(argv=None):
     ap.add_argument('--lr', type=float, default=2e-3)
     ap.add_argument('--k', type=int, default=1, help='(0-b) passes after the network / ablation start')
     ap.add_argument('--n-adapt-plain', type=int, default=3)
+    ap.add_argument('--gauge', choices=('random', 'heatbath'), default='random',
+                    help='random: links of spread eps per seed; heatbath: configurations of a heat-bath chain '
+                         '(one chain for training, an independent one for evaluation)')
+    ap.add_argument('--beta', type=float, default=6.0)
+    ap.add_argument('--therm', type=int, default=60)
+    ap.add_argument('--sep', type=int, default=5)
     ap.add_argument('--out', default=None)
     ap.add_argument('--report', default=None)
     args = ap.parse_args(argv)
@@ -133,12 +157,27 @@ def main(argv=None):
     def net_input(seed):
         return syn.gaussian_vectors_torch(dims, C, seed + 100000, dev)
 
-    # teachers
     train = list(range(args.train[0], args.train[1] + 1))
+    held = list(range(args.eval[0], args.eval[1] + 1))
+    if args.gauge == 'heatbath':
+        t0 = time.perf_counter()
+        chain_t = heatbath_configs(dims, args.beta, args.therm, args.sep, len(train), train[0], dev)
+        chain_e = heatbath_configs(dims, args.beta, args.therm, args.sep, len(held), held[0], dev)
+        fields = dict(zip(train, chain_t))
+        fields.update(zip(held, chain_e))
+        log('heat-bath configurations: %d + %d in %.1f s' % (len(train), len(held), time.perf_counter() - t0))
+
+        def gauge_of(s):
+            return fields[s]
+    else:
+        def gauge_of(s):
+            return syn.gauge_field_torch(dims, eps_of(s), s, dev)
+
+    # teachers
     gauges, teachers = {}, {}
     t0 = time.perf_counter()
     for s in train:
-        U = syn.gauge_field_torch(dims, eps_of(s), s, dev)
+        U = gauge_of(s)
         ctx.load_gauge(U)
         plain_setup(s)
         Q = torch.zeros((C,) + syn.shape_of(dims) + (4, 3), dtype=torch.complex128, device=dev)
@@ -173,11 +212,10 @@ def main(argv=None):
 
     # evaluation
     rows = []
-    for s in range(args.eval[0], args.eval[1] + 1):
-        U = syn.gauge_field_torch(dims, eps_of(s), s, dev)
-        ctx.load_gauge(U)
+    for s in held:
+        ctx.load_gauge(gauge_of(s))
         b = torch.from_numpy(syn.z2_source(dims, s)).to(dev)
-        row = dict(seed=s, eps=eps_of(s))
+        row = dict(seed=s, eps=eps_of(s) if args.gauge == 'random' else None)
         row.update(evaluate_seed(ctx, C, b, net_input(s), syn.gaussian_vectors_torch(dims, C, s, dev),
                                  n_adapt_plain=args.n_adapt_plain, k=args.k))
         rows.append(row)
@@ -187,7 +225,9 @@ def main(argv=None):
     decision = choose_setup(rows)
     report = dict(config=dict(dims=dims, block=block, kappa=args.kappa, csw=args.csw, layers=args.layers,
                               channels=C, epochs=args.epochs, lr=args.lr, k=args.k, train_seeds=args.train,
-                              eval_seeds=args.eval),
+                              eval_seeds=args.eval, gauge=args.gauge,
+                              heatbath=dict(beta=args.beta, therm=args.therm, sep=args.sep)
+                              if args.gauge == 'heatbath' else None),
                   teacher_s=round(t_teach, 2), train_s=round(t_train, 2), loss_history=hist,
                   eval=rows, summary=summary,
                   net_gain_vs_ablation_iters=(summary['ablate']['iters'] - summary['net']['iters']

@@ -18,6 +18,7 @@ DEVICE, HOST = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 PC_AMG, PC_BICG32 = 0, 1
 SMOOTH_POST, SMOOTH_PRE, SMOOTH_BOTH = 0, 1, 2
+BLOCK_MR, BLOCK_EO_MR = 0, 1
 MAX_RHS = 64
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -36,7 +37,7 @@ class SetupParams(ctypes.Structure):
                 ('init_where', ctypes.c_int), ('nlevels', ctypes.c_int), ('block1', _c_int4), ('nv1', ctypes.c_int),
                 ('mr1_iters', ctypes.c_int), ('init_mr1_iters', ctypes.c_int), ('init_vectors1', ctypes.c_void_p),
                 ('seed1', ctypes.c_ulonglong), ('init_net', ctypes.c_int), ('seed', ctypes.c_ulonglong),
-                ('smoothing', ctypes.c_int)]
+                ('smoothing', ctypes.c_int), ('sap_eo', ctypes.c_int)]
 
 
 class SolveParams(ctypes.Structure):
@@ -82,7 +83,7 @@ SIGNATURES = {
     'wcamg_apply_D': (_I, [_P, _P, _P, _I, _I, _I]),
     'wcamg_apply_D_noalloc': (_I, [_P, _P, _P, _I, _I]),
     'wcamg_apply_Dsap': (_I, [_P, _P, _P, _I, _I, _I]),
-    'wcamg_sap': (_I, [_P, _P, _P, _I, _I, _I, _I, _I]),
+    'wcamg_sap': (_I, [_P, _P, _P, _I, _I, _I, _I, _I, _I]),
     'wcamg_setup': (_I, [_P, ctypes.POINTER(SetupParams)]),
     'wcamg_set_test_vectors': (_I, [_P, _P, ctypes.POINTER(SetupParams), _I]),
     'wcamg_get_test_vectors': (_I, [_P, _P, _I]),
@@ -224,17 +225,19 @@ class Context:
         w = _same_where(x, out)
         self._done(self.lib.wcamg_apply_Dsap(self.h, _ptr(x)[0], _ptr(out)[0], nrhs, prec, w), out)
 
-    def sap(self, b, x, nrhs, sweeps=4, mr_iters=6, prec=PREC_FP64):
+    def sap(self, b, x, nrhs, sweeps=4, mr_iters=6, prec=PREC_FP64, block_solve=BLOCK_MR):
         w = _same_where(b, x)
-        self._done(self.lib.wcamg_sap(self.h, _ptr(b)[0], _ptr(x)[0], nrhs, sweeps, mr_iters, prec, w), x)
+        self._done(self.lib.wcamg_sap(self.h, _ptr(b)[0], _ptr(x)[0], nrhs, sweeps, mr_iters, block_solve, prec, w),
+                   x)
 
     @staticmethod
     def setup_params(nv, prec=PREC_FP64, n_init=3, n_adapt=3, sap_sweeps=4, mr_iters=6, coarse_iters=50,
                      coarse_tol=0.1, init_vectors=None, nlevels=2, block1=(1, 1, 1, 1), nv1=0, mr1_iters=4,
-                     init_mr1_iters=8, init_vectors1=None, seed1=1, init_net=0, seed=1, smoothing=SMOOTH_POST):
+                     init_mr1_iters=8, init_vectors1=None, seed1=1, init_net=0, seed=1, smoothing=SMOOTH_POST,
+                     sap_eo=0):
         p = SetupParams(nv, n_init, n_adapt, sap_sweeps, mr_iters, coarse_iters, coarse_tol, prec, None, DEVICE,
                         nlevels, _c_int4(*block1), nv1, mr1_iters, init_mr1_iters, None, seed1, init_net, seed,
-                        smoothing)
+                        smoothing, sap_eo)
         if init_vectors is not None:
             ptr, w = _ptr(init_vectors)
             p.init_vectors = ptr

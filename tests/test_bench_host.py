@@ -62,12 +62,14 @@ def test_counter_summary_calibrates_and_divides_by_units(tmp_path):
     units['classes']['dslash64'] = dict(units=2.0, bytes=3e6)
     uj = tmp_path / 'units.json'
     uj.write_text(json.dumps(units))
-    copy = 'void at::native::elementwise_kernel<copy>(int)'
+    copy = '__amd_rocclr_copyBuffer'
     # fetch counter reads half the bytes (factor 2), write counter all of them (factor 1)
-    fetch = [(1, 'k_sap_dom<512>(Geo)', 999.0)] + [(2 + i, copy, 524288.0) for i in range(3)] + \
-            [(5, 'k_sap_dom<512>(Geo)', 100.0), (6, 'k_dslash_lds<double, double2>(Geo)', 50.0)]
-    write = [(1, 'k_sap_dom<512>(Geo)', 999.0)] + [(2 + i, copy, 1048576.0) for i in range(3)] + \
-            [(5, 'k_sap_dom<512>(Geo)', 30.0), (6, 'k_dslash_lds<double, double2>(Geo)', 10.0)]
+    fetch = [(1, 'void wc::k_sap_dom<512>(wc::Geo)', 999.0)] + [(2 + i, copy, 524288.0) for i in range(3)] + \
+            [(5, 'void wc::k_sap_dom<512>(wc::Geo)', 100.0), (6, 'void wc::k_dslash_lds<double, double2>(wc::Geo)', 50.0),
+             (7, copy, 10.0)]
+    write = [(1, 'void wc::k_sap_dom<512>(wc::Geo)', 999.0)] + [(2 + i, copy, 1048576.0) for i in range(3)] + \
+            [(5, 'void wc::k_sap_dom<512>(wc::Geo)', 30.0), (6, 'void wc::k_dslash_lds<double, double2>(wc::Geo)', 10.0),
+             (7, copy, 10.0)]
     _write_counter_csv(str(tmp_path / 'f'), fetch)
     _write_counter_csv(str(tmp_path / 'w'), write)
     out = bench.summarize_counters(str(tmp_path / 'f'), str(tmp_path / 'w'), str(uj), str(tmp_path / 'o.json'))

@@ -362,6 +362,28 @@ def test_setup_and_solve_mixed_c1_smoothing(smoothing):
         assert np.linalg.norm(b[k] - prob.op.D(xg[k])) / np.linalg.norm(b[k]) <= 1e-10
 
 
+def test_setup_and_solve_mixed_even_odd_smoother():
+    """8^4 lattice with 4^4 blocks: setup and FGMRES(16) to 1e-10 with the
+    even-odd preconditioned SAP block solve; residual by the oracle's D.
+    The even-odd variant is rejected in FP64 and for odd block extents."""
+    from paper_2111_05012_amd import PREC_MIXED, PREC_FP64, WcamgError, BLOCK_EO_MR, EINVAL
+    prob = Problem((8, 8, 8, 8), (4, 4, 4, 4), eps=0.5, seed=1, kappa=0.124, csw=1.0)
+    V0 = syn.gaussian_vectors(prob.dims, 8, 5)
+    prob.ctx.setup(prob.ctx.setup_params(8, PREC_MIXED, init_vectors=prob.T(V0), sap_eo=1))
+    b = syn.z2_source(prob.dims, 6, nrhs=2)
+    x = prob.zeros(b.shape)
+    rc, info = prob.ctx.solve(prob.T(b), x, 2, tol=1e-10)
+    assert rc == 0
+    xg = prob.N(x)
+    for k in range(2):
+        assert np.linalg.norm(b[k] - prob.op.D(xg[k])) / np.linalg.norm(b[k]) <= 1e-10
+    with pytest.raises(WcamgError) as e:
+        prob.ctx.setup(prob.ctx.setup_params(8, PREC_FP64, init_vectors=prob.T(V0), sap_eo=1))
+    assert e.value.code == EINVAL
+    with pytest.raises(WcamgError):
+        prob.ctx.sap(prob.T(b), x, 2, 4, 6, PREC_FP64, block_solve=BLOCK_EO_MR)
+
+
 def test_flexible_bicgstab_mixed_amg_and_mbicgs_c1():
     """Config-1 workload: the flexible BiCGStab preconditioned by the mixed
     V-cycle, and the comparison solver (preconditioned by an FP32 BiCGStab on

@@ -72,6 +72,12 @@ def prod():
 
 
 @pytest.fixture(scope='module')
+def ainv16(prod):
+    """The library's FP16 storage of (1 + F)^-1 - 1, as the oracle's blocks of A^-1."""
+    return np.eye(6) + r16(amg.clover_inverse(prod.Fb) - np.eye(6))
+
+
+@pytest.fixture(scope='module')
 def dc16(prod):
     """The oracle's coarse operator (eq. (7)) from the FP16 vectors, links and clover."""
     return amg.coarse_operator(prod.op16, prod.V16)
@@ -149,6 +155,22 @@ def test_sap_mixed_12rhs(prod):
     xg = prod.N(x)
     for k in SAMPLE:
         want = amg.sap(prod.op16, r32(b[k:k + 1]), 4, 6)[0]
+        assert rel(xg[k], want) < TOL_SAP, k
+
+
+def test_sap_mixed_even_odd_12rhs(prod, ainv16):
+    """The even-odd preconditioned block solve (the NEXT-2 smoother variant):
+    SAP(4, 6) on 12 right-hand sides against the oracle's SAP with its
+    even-odd block solve on the same FP16 hop matrices, clover and inverse
+    clover."""
+    from paper_2111_05012_amd import PREC_MIXED, BLOCK_EO_MR
+    b = syn.gaussian_vectors(DIMS, NRHS, 81)
+    x = prod.zeros(b.shape)
+    prod.ctx.sap(prod.T(b), x, NRHS, 4, 6, PREC_MIXED, block_solve=BLOCK_EO_MR)
+    xg = prod.N(x)
+    for k in (0, NRHS - 1):
+        want = amg.sap(prod.op16, r32(b[k:k + 1]), 4, 6,
+                       block_solver=lambda r: amg.eo_mr_domains(prod.op16, r, 6, ainv16)[0])[0]
         assert rel(xg[k], want) < TOL_SAP, k
 
 
@@ -278,5 +300,25 @@ def test_vcycle_mixed_12rhs(prod, dc16):
     prod.ctx.vcycle(prod.T(v), out, NRHS)
     og = prod.N(out)
     for k in SAMPLE:
+        want = mg.vcycle(r32(v[k:k + 1]))[0]
+        assert rel(og[k], want) < TOL_VCYCLE, k
+
+
+def test_vcycle_mixed_even_odd(prod, dc16, ainv16):
+    """The mixed V-cycle with the even-odd preconditioned SAP block solve
+    (setup parameter sap_eo) against the oracle's V-cycle with that block
+    solve, on 12 right-hand sides (two checked)."""
+    from paper_2111_05012_amd import PREC_MIXED
+    p = prod.ctx.setup_params(NV, PREC_MIXED, coarse_iters=8, coarse_tol=0.0, sap_eo=1)
+    prod.ctx.set_test_vectors(prod.T(prod.V), p)
+    prod.ctx.set_coarse_op(prod.T(dc16))
+    mg = amg.TwoLevel(prod.op16, prod.V16, 4, 6, coarse_iters=8, coarse_tol=0.0,
+                      block_solver=lambda r: amg.eo_mr_domains(prod.op16, r, 6, ainv16)[0])
+    mg.Dc = r32(dc16)
+    v = syn.gaussian_vectors(DIMS, NRHS, 82)
+    out = prod.zeros(v.shape)
+    prod.ctx.vcycle(prod.T(v), out, NRHS)
+    og = prod.N(out)
+    for k in (0, NRHS - 1):
         want = mg.vcycle(r32(v[k:k + 1]))[0]
         assert rel(og[k], want) < TOL_VCYCLE, k
