@@ -867,6 +867,28 @@ __device__ __forceinline__ R wave_sum(R v) {
   return v;
 }
 
+// One DPP move of a float (lanes that the row mask leaves out, or whose
+// source lies outside the row, read 0).
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xf, true));
+}
+
+// Sum over the wavefront, valid in lane 63 only: an inclusive scan within
+// each row of 16 lanes (row_shr 1, 2, 4, 8), then row 0's total into row 1
+// and row 2's into row 3 (row_bcast:15), then rows 0+1 into rows 2 and 3
+// (row_bcast:31).  Six dependent VALU steps, where a butterfly of lane
+// shuffles makes six round trips through the LDS crossbar.
+__device__ __forceinline__ float wave_sum_hi(float v) {
+  v += dpp_mov<0x111>(v);
+  v += dpp_mov<0x112>(v);
+  v += dpp_mov<0x114>(v);
+  v += dpp_mov<0x118>(v);
+  v += dpp_mov<0x142, 0xa>(v);
+  v += dpp_mov<0x143, 0xc>(v);
+  return v;
+}
+
 template <class R, class TS, class TL, class TC>
 __global__ __launch_bounds__(512) void k_sap_half(Geo g, int colour, int flags, int mr, R kappa,
                                                    const TS* __restrict__ b, TS* __restrict__ r, TS* __restrict__ x,
@@ -1085,6 +1107,10 @@ __global__ __launch_bounds__(256) void k_sap_cross(Geo g, int colour, int first,
   }
 }
 
+// Zero slots after the Vb sites of each residual component in the domain
+// kernel's LDS exchange buffer (64 keeps paired LDS offsets in 512-byte units).
+constexpr int SAP_DOM_PAD = 64;
+
 // VB: the domain volume when known at compile time (LDS offsets become
 // immediates), 0 for any volume.
 template <int VB>
@@ -1095,8 +1121,11 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
                                                  const half2_t* __restrict__ U, const half2_t* __restrict__ C) {
   extern __shared__ __align__(16) char smem[];
   const int Vb = VB ? VB : g.Vb;
-  cplx<float>* lds = (cplx<float>*)smem;                   // [12][Vb] residual exchange
-  half2_t* lu = (half2_t*)(smem + 12 * Vb * sizeof(cplx<float>));  // [4][9][Vb] -kappa sign U_mu(x) of the domain
+  // residual exchange [12][Vbp]: slots Vb .. Vbp-1 of every component hold
+  // zeros, the neighbour of a hop that leaves the domain
+  const int Vbp = Vb + SAP_DOM_PAD;
+  cplx<float>* lds = (cplx<float>*)smem;
+  half2_t* lu = (half2_t*)(smem + 12 * Vbp * sizeof(cplx<float>));  // [4][9][Vb] -kappa sign U_mu(x) of the domain
   float* red = (float*)(lu + 36 * Vb);                     // [nwaves][3]
   const int half = g.NB[0] >> 1;
   int k = xcd_remap(blockIdx.x, g.nblk >> 1);
@@ -1109,14 +1138,20 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   int bx = 2 * j + ((colour + by + bz + bt) & 1);
   int blk = bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
   const int l = threadIdx.x;
-  const bool act = l < Vb;
+  // with the volume known at compile time the launch has exactly Vb threads
+  const bool act = VB ? true : l < Vb;
   const int s = blk * Vb + (act ? l : 0);
-  const int nw = (blockDim.x + 63) >> 6;
+  const int nw = VB ? (VB + 63) / 64 : (blockDim.x + 63) >> 6;
   SiteCoord c = decompose(g, s);
   const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
 
-  // per direction, held in registers for the whole launch: in-domain
-  // neighbour's local index (bits 0..9), in-domain flag (bit 10)
+  // per direction, held in registers for the whole launch: the slot of the
+  // neighbour's residual (its local index in the domain, or the zero slot Vb
+  // for a hop that leaves it; bits 0..15) and, for backward hops, the local
+  // index whose stored link the hop uses (the neighbour's, or any valid one:
+  // it multiplies zeros; bits 16..31).  Every hop is then computed, with no
+  // branch per direction, so the loads of the next hop can be issued while
+  // the current one is multiplied.
   float fsign[4];
   int ninfo[8];
 #pragma unroll
@@ -1126,7 +1161,12 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
     int mu = d & 3;
     int nb = d < 4 ? neighbour<true>(g, s, c, mu, sign, inb) : neighbour<false>(g, s, c, mu, sign, inb);
     if (d < 4) fsign[mu] = (float)sign;
-    ninfo[d] = inb ? ((nb - blk * Vb) | (1 << 10)) : 0;
+    const int nl = act ? nb - blk * Vb : 0;
+    ninfo[d] = inb ? (nl | (nl << 16)) : (Vb | ((act ? l : 0) << 16));
+  }
+  if (l < SAP_DOM_PAD) {
+#pragma unroll
+    for (int a = 0; a < 12; ++a) lds[a * Vbp + Vb + l] = {0, 0};
   }
   // the domain's forward hop matrices (FP16 -kappa U_mu(x)) times the
   // boundary sign of their hop (bc of a hop x -> x + mu that crosses the
@@ -1146,25 +1186,49 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   }
   __syncthreads();
 
-  // the site's clover (FP16): reloaded at the end of every MR iteration for the
-  // next one, so that the load is in flight during the reduction and barrier
-  // instead of stalling the start of the iteration
+  // the site's clover (FP16), held in registers for the whole launch
   half2_t cl[36];
 #pragma unroll
   for (int q = 0; q < 36; ++q) cl[q] = C[(size_t)q * Vb + fb36];
+  // the residual of the current right-hand side; the crossing-hop correction
+  // has been applied by k_sap_cross (SAP_R_IN)
+  const float2* rsrc = ((flags & SAP_FIRST) && !(flags & SAP_R_IN)) ? b : r;
+  cplx<float> rho[12];
+  if (act) ld_spinor<float>(rsrc, Vb, fb12, rho);
+  // wait for the first residual and the clover here: inside the loop both
+  // then always come from registers whose loads are complete, and no
+  // instruction of an MR iteration waits for the previous right-hand side's
+  // stores
+#pragma unroll
+  for (int a = 0; a < 12; ++a) asm volatile("" ::"v"(rho[a].x), "v"(rho[a].y));
+#pragma unroll
+  for (int q = 0; q < 36; ++q) asm volatile("" ::"v"(__builtin_bit_cast(uint32_t, cl[q])));
   for (int rr = 0; rr < nrhs; ++rr) {
     const size_t off = rr * rs;
-    cplx<float> rho[12], xm[12], p[12], psi[12];
-    if (act) {
-      // the crossing-hop correction has been applied by k_sap_cross (SAP_R_IN)
-      ld_spinor<float>(((flags & SAP_FIRST) && !(flags & SAP_R_IN)) ? b + off : r + off, Vb, fb12, rho);
-    }
+    cplx<float> xm[12], p[12], psi[12];
 #pragma unroll
     for (int a = 0; a < 12; ++a) xm[a] = {0, 0};
+    // The global loads that this right-hand side's end needs (its x, the
+    // next one's residual) are issued now and arrive during the MR
+    // iterations, which touch only LDS and registers; the stores of the
+    // previous right-hand side, issued just before, drain meanwhile (a wait
+    // for a load also waits for every store issued before it).
+    // Both loads are unconditional (x itself stands in when there is no
+    // start vector, the current residual after the last right-hand side) so
+    // that every path through the loop has the same loads in flight and the
+    // compiler's wait counts do not fall to the path without them.
+    float2* xr = x + off;
+    const bool have_x0 = !(flags & SAP_FIRST) || xinit;
+    const float2* x0src = !(flags & SAP_FIRST) ? xr : (xinit ? xinit + off : xr);
+    cplx<float> x0[12], nrho[12];
+    if (act) {
+      ld_spinor<float>(x0src, Vb, fb12, x0);
+      ld_spinor<float>(rsrc + off + (rr + 1 < nrhs ? rs : 0), Vb, fb12, nrho);
+    }
     for (int it = 0; it < mr; ++it) {
       if (act) {
 #pragma unroll
-        for (int a = 0; a < 12; ++a) lds[a * Vb + l] = rho[a];
+        for (int a = 0; a < 12; ++a) lds[a * Vbp + l] = rho[a];
       }
       __syncthreads();
       float pr_re = 0, pr_im = 0, pp = 0;
@@ -1173,24 +1237,33 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
         // matrices -kappa U)
 #pragma unroll
         for (int a = 0; a < 12; ++a) p[a] = rho[a];
-        clover_acc<float>(cl, 1, 0, rho, p);
+        // the clover stays FP16 in registers (36 VGPRs) and enters the
+        // products as FP16 operands of mixed-precision FMAs: the empty asm
+        // keeps the compiler from hoisting 72 FP32 conversions out of the
+        // loop, which would hold 72 VGPRs instead
+        half2_t clv[36];
+#pragma unroll
+        for (int q = 0; q < 36; ++q) {
+          uint32_t bits = __builtin_bit_cast(uint32_t, cl[q]);
+          asm volatile("" : "+v"(bits));
+          clv[q] = __builtin_bit_cast(half2_t, bits);
+        }
+        clover_acc<float>(clv, 1, 0, rho, p);
         // unrolled: direction and projection are compile-time constants
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
           const int inf = ninfo[d];
-          if (inf & (1 << 10)) {
-            int nl = inf & 1023;
+          const int nl = inf & 0xffff;
 #pragma unroll
-            for (int a = 0; a < 12; ++a) psi[a] = lds[a * Vb + nl];
-            half2_t ub[9];
-            const int ls = d < 4 ? l : nl;  // U_mu(x) or U_mu(x - mu), scaled
+          for (int a = 0; a < 12; ++a) psi[a] = lds[a * Vbp + nl];
+          half2_t ub[9];
+          const int ls = d < 4 ? l : (inf >> 16);  // U_mu(x) or U_mu(x - mu), scaled
 #pragma unroll
-            for (int e = 0; e < 9; ++e) ub[e] = lu[((d & 3) * 9 + e) * Vb + ls];
-            if (d < 4)
-              hop_h<true>(d & 3, psi, ub, 1.0f, p);
-            else
-              hop_h<false>(d & 3, psi, ub, 1.0f, p);
-          }
+          for (int e = 0; e < 9; ++e) ub[e] = lu[((d & 3) * 9 + e) * Vb + ls];
+          if (d < 4)
+            hop_h<true>(d & 3, psi, ub, 1.0f, p);
+          else
+            hop_h<false>(d & 3, psi, ub, 1.0f, p);
         }
 #pragma unroll
         for (int a = 0; a < 12; ++a) {
@@ -1199,16 +1272,19 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
           pp += p[a].x * p[a].x + p[a].y * p[a].y;
         }
       }
-      pr_re = wave_sum(pr_re);
-      pr_im = wave_sum(pr_im);
-      pp = wave_sum(pp);
-      if ((l & 63) == 0) {
+      pr_re = wave_sum_hi(pr_re);
+      pr_im = wave_sum_hi(pr_im);
+      pp = wave_sum_hi(pp);
+      if ((l & 63) == 63) {
         red[(l >> 6) * 3 + 0] = pr_re;
         red[(l >> 6) * 3 + 1] = pr_im;
         red[(l >> 6) * 3 + 2] = pp;
       }
       __syncthreads();
+      // (unrolled when the wave count is known at compile time, so that the
+      // partial sums are read with one LDS round trip, not one per wave)
       float sre = 0, sim = 0, spp = 0;
+#pragma unroll
       for (int w = 0; w < nw; ++w) {
         sre += red[w * 3 + 0];
         sim += red[w * 3 + 1];
@@ -1217,29 +1293,35 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
       cplx<float> alpha = {0, 0};
       if (spp > 0) alpha = {sre / spp, sim / spp};
       if (act) {
+        const cplx<float> malpha = {-alpha.x, -alpha.y};
 #pragma unroll
         for (int a = 0; a < 12; ++a) {
-          xm[a] = xm[a] + alpha * rho[a];
-          rho[a] = rho[a] - alpha * p[a];
+          cmac(xm[a], alpha, rho[a]);
+          cmac(rho[a], malpha, p[a]);
         }
       }
     }
     if (act) {
-      float2* xr = x + off;
+      // the prefetched values are waited for before the first store, so
+      // that no wait comes to stand behind this right-hand side's stores
+#pragma unroll
+      for (int a = 0; a < 12; ++a) asm volatile("" ::"v"(nrho[a].x), "v"(nrho[a].y));
       float2* rw = r + off;
       float2* dw = delta + off;
 #pragma unroll
       for (int a = 0; a < 12; ++a) {
         size_t o = (size_t)a * Vb + fb12;
-        cplx<float> x0 = {0, 0};
-        if (!(flags & SAP_FIRST)) x0 = ld<float>(xr, o);
-        else if (xinit) x0 = ld<float>(xinit + off, o);
-        st(xr, o, x0 + xm[a]);
+        st(xr, o, have_x0 ? x0[a] + xm[a] : xm[a]);
         if (!(flags & SAP_NO_R)) st(rw, o, rho[a]);
         if (!(flags & SAP_NO_DELTA)) st(dw, o, xm[a]);
       }
+#pragma unroll
+      for (int a = 0; a < 12; ++a) rho[a] = nrho[a];
     }
-    __syncthreads();  // the next right-hand side reuses lds and red
+    // No barrier before the next right-hand side: every thread has passed
+    // the last iteration's reduction barrier after its last read of lds, and
+    // the next write to red follows the next iteration's first barrier, which
+    // no thread reaches before it has read red.
   }
 }
 
@@ -1300,7 +1382,7 @@ __global__ __launch_bounds__(512) void k_sap_dom_eo(Geo g, int colour, int flags
     loc = rrow * g.B[0] + 2 * kx + ((rp + (ev ? 0 : 1)) & 1);
   }
   const int s = blk * Vb + loc;
-  const int nw = (blockDim.x + 63) >> 6;
+  const int nw = VB ? (VB + 63) / 64 : (blockDim.x + 63) >> 6;
   SiteCoord c = decompose(g, s);
   const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
   float fsign[4];
@@ -1405,16 +1487,19 @@ __global__ __launch_bounds__(512) void k_sap_dom_eo(Geo g, int colour, int flags
           pp += p[a].x * p[a].x + p[a].y * p[a].y;
         }
       }
-      pr_re = wave_sum(pr_re);
-      pr_im = wave_sum(pr_im);
-      pp = wave_sum(pp);
-      if ((l & 63) == 0) {
+      pr_re = wave_sum_hi(pr_re);
+      pr_im = wave_sum_hi(pr_im);
+      pp = wave_sum_hi(pp);
+      if ((l & 63) == 63) {
         red[(l >> 6) * 3 + 0] = pr_re;
         red[(l >> 6) * 3 + 1] = pr_im;
         red[(l >> 6) * 3 + 2] = pp;
       }
       __syncthreads();
+      // (unrolled when the wave count is known at compile time, so that the
+      // partial sums are read with one LDS round trip, not one per wave)
       float sre = 0, sim = 0, spp = 0;
+#pragma unroll
       for (int w = 0; w < nw; ++w) {
         sre += red[w * 3 + 0];
         sim += red[w * 3 + 1];
@@ -1465,7 +1550,7 @@ __global__ __launch_bounds__(512) void k_sap_dom_eo(Geo g, int colour, int flags
 
 int sap_dom_lds_bytes(const Geo& g) {
   int nthr = ((g.Vb + 63) / 64) * 64;
-  return 12 * g.Vb * 8 + 36 * g.Vb * 4 + (nthr / 64) * 3 * 4;
+  return 12 * (g.Vb + SAP_DOM_PAD) * 8 + 36 * g.Vb * 4 + (nthr / 64) * 3 * 4;
 }
 
 int sap_lds_bytes(const Geo& g, int mixed) {
