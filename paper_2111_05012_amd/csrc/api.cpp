@@ -222,6 +222,9 @@ struct wcamg_ctx {
   bool own_stream = false;
   bool have_gauge = false;
   DevBuf U64, U16, Cl64, Cl16;
+  // the FP16 hop matrices of the hops that leave each SAP domain, in face
+  // order (launch_face_links), for the mixed SAP's crossing-hop correction
+  DevBuf FL16;
   // FP32 copies of the links and clover, made on first use by the comparison
   // solver's inner BiCGStab (single-precision fields, as the paper's)
   DevBuf U32, Cl32;
@@ -534,6 +537,13 @@ struct wcamg_ctx {
   int spin_t(int prec) const { return prec == WCAMG_PREC_MIXED ? C64 : C128; }
   size_t fsz(int nrhs, int prec) const { return (size_t)nrhs * 12 * g.V * ct_size(spin_t(prec)); }
   size_t frs() const { return (size_t)12 * g.V; }
+  // the SAP correction workspace: whole corrections (FP64 path, even-odd
+  // block solve) or the mixed path's face projections, whichever is larger
+  size_t face_rs() const { return (size_t)g.nblk * 6 * sap_face_slots(g); }
+  size_t sapd_sz(int nrhs, int prec) const {
+    size_t fb = prec == WCAMG_PREC_MIXED ? (size_t)nrhs * face_rs() * sizeof(float2) : 0;
+    return std::max(fsz(nrhs, prec), fb);
+  }
 
   // internal precision code of the FP32-field operator (never accepted at the ABI)
   static constexpr int PREC_F32 = 2;
@@ -633,10 +643,12 @@ struct wcamg_ctx {
     a.x = x;
     a.xinit = xinit;
     a.r = W("sap_r", fsz(nrhs, prec));
-    a.delta = W("sap_d", fsz(nrhs, prec));
+    a.delta = W("sap_d", sapd_sz(nrhs, prec));
     a.rs = frs();
+    a.fs = face_rs();
     a.U = a.mixed ? U16.p : U64.p;
     a.C = a.mixed ? Cl16.p : Cl64.p;
+    a.FL = FL16.p;
     if (sweeps <= 0) {
       // x = xinit (or 0)
       if (xinit)
@@ -654,17 +666,28 @@ struct wcamg_ctx {
       for (int col = 0; col < 2; ++col) {
         double xr = (sw > 0 || xinit) ? 1 : 0;
         if (sap_needs_cross(a, sw, col)) {
-          // per site of the active colour and RHS: r in and out, the other
-          // colour's corrections at the crossing neighbours (sum over the
-          // directions of 2 / B_mu: 1.75 for 4^3x8 domains), ~240 flop each
+          // per site of the active colour and RHS: r in and out, and per
+          // crossing hop (sum over the directions of 2 / B_mu: 1.75 for
+          // 4^3x8 domains) the neighbouring domain's spin-projected
+          // correction (6 complex) and the face copy of the FP16 hop matrix,
+          // ~170 flop (SU(3) times two colour vectors, reconstruction); the
+          // even-odd variant reads whole corrections (12 complex) and the
+          // links in site order, ~240 flop per hop
           double nc = 0;
           for (int m = 0; m < 4; ++m) nc += 2.0 / g.B[m];
-          double byc = 0.5 * g.V * (nc * 36.0 + nrhs * 12.0 * sb * (2.0 + nc));
-          double flc = 0.5 * g.V * nrhs * nc * 240.0;
+          double byc = a.eo ? 0.5 * g.V * (nc * 36.0 + nrhs * 12.0 * sb * (2.0 + nc))
+                            : 0.5 * g.V * (nc * 36.0 + nrhs * (24.0 * sb + nc * 6.0 * sb));
+          double flc = 0.5 * g.V * nrhs * nc * (a.eo ? 240.0 : 170.0);
           Timed t(this, "sap_cross", byc, flc, nrhs);
           launch_sap_cross(a, sw, col, st);
         }
-        double by = 0.5 * g.V * (fld + nrhs * 12.0 * sb * (4.0 + xr));
+        // per RHS: r in, x in (after the first visit), x and r out, and the
+        // correction out (whole, or its face projections on the mixed path:
+        // 6 complex per crossing hop)
+        double nc = 0;
+        for (int m = 0; m < 4; ++m) nc += 2.0 / g.B[m];
+        double dout = a.mixed && !a.eo ? nc * 6.0 * sb : 12.0 * sb;
+        double by = 0.5 * g.V * (fld + nrhs * (12.0 * sb * (3.0 + xr) + dout));
         // per site of the active colour, RHS and MR iteration: D_SAP with its
         // in-domain hops only (sum over mu of 2 (B_mu - 1) / B_mu hops of 165
         // flop each, plus 552 for the clover and 48 for the identity and the
@@ -1234,6 +1257,8 @@ int wcamg_load_gauge(wcamg_ctx* c, const void* U, int where) {
     c->Cl64.ensure((size_t)36 * g.V * sizeof(double2), false);
     c->Cl16.ensure((size_t)36 * g.V * sizeof(half2_t), false);
     launch_pack_gauge(g, Ud, (double2*)c->U64.p, (half2_t*)c->U16.p, -c->kappa, c->st);
+    c->FL16.ensure((size_t)g.nblk * 9 * sap_face_slots(g) * sizeof(half2_t), false);
+    launch_face_links(g, c->U16.p, c->FL16.p, c->st);
     std::vector<double> sig = sigma_table();
     launch_clover_build(g, (const double2*)c->U64.p, c->kappa, c->csw, sig.data(), (double2*)c->Cl64.p,
                         (half2_t*)c->Cl16.p, c->st);
@@ -1362,7 +1387,7 @@ int wcamg_sap(wcamg_ctx* c, const void* b, void* x, int nrhs, int sweeps, int mr
     double2* xd = (double2*)io.out(x, cbytes, where, "io_out");
     int t = c->spin_t(prec);
     c->reserve({{"ap_a", c->fsz(nrhs, prec)}, {"ap_b", c->fsz(nrhs, prec)}, {"sap_r", c->fsz(nrhs, prec)},
-                {"sap_d", c->fsz(nrhs, prec)}});
+                {"sap_d", c->sapd_sz(nrhs, prec)}});
     void* bi = c->W("ap_a", c->fsz(nrhs, prec));
     void* xi = c->W("ap_b", c->fsz(nrhs, prec));
     launch_pack_spinor(g, bd, bi, t, c->frs(), nrhs, c->st);
@@ -1414,7 +1439,8 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
     size_t cbytes = (size_t)nv * g.V * 12 * sizeof(double2);
     {
       const size_t f = c->fsz(nv, prec);
-      c->reserve({{"su_w", f}, {"su_t", f}, {"sap_r", f}, {"sap_d", f}, {"or_tmp", f}, {"vc_r", f}, {"vc_x1", f}});
+      c->reserve({{"su_w", f}, {"su_t", f}, {"sap_r", f}, {"sap_d", c->sapd_sz(nv, prec)}, {"or_tmp", f}, {"vc_r", f},
+                  {"vc_x1", f}});
     }
     HostIO io(c);
     const double2* Vd = nullptr;
@@ -1711,7 +1737,7 @@ int wcamg_vcycle(wcamg_ctx* c, const void* in, void* out, int nrhs, int where) {
     double2* outd = (double2*)io.out(out, fb, where, "io_out");
     int prec = c->h.prec, t = c->spin_t(prec);
     c->reserve({{"ap_a", c->fsz(nrhs, prec)}, {"ap_b", c->fsz(nrhs, prec)}, {"vc_r", c->fsz(nrhs, prec)},
-                {"vc_x1", c->fsz(nrhs, prec)}, {"sap_r", c->fsz(nrhs, prec)}, {"sap_d", c->fsz(nrhs, prec)}});
+                {"vc_x1", c->fsz(nrhs, prec)}, {"sap_r", c->fsz(nrhs, prec)}, {"sap_d", c->sapd_sz(nrhs, prec)}});
     void* a = c->W("ap_a", c->fsz(nrhs, prec));
     void* b = c->W("ap_b", c->fsz(nrhs, prec));
     launch_pack_spinor(g, ind, a, t, c->frs(), nrhs, c->st);
@@ -2010,7 +2036,7 @@ int wcamg_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, const wcamg_solv
           {"vc_r", f},
           {"vc_x1", f},
           {"sap_r", f},
-          {"sap_d", f}};
+          {"sap_d", c->sapd_sz(chunk, prec)}};
       if (prec == WCAMG_PREC_MIXED) plan.push_back({"fg_vin", cn * sizeof(float2)});
       c->reserve(plan);
     }
@@ -2145,7 +2171,8 @@ int wcamg_solve_bicgstab(wcamg_ctx* c, const void* b, void* x, int nrhs, const w
           {"fb_mp", z}, {"fb_ms", z}};
       if (prec == WCAMG_PREC_MIXED) plan.push_back({"fb_vin", cn * sizeof(float2)});
       if (amg) {
-        for (const char* k : {"vc_r", "vc_x1", "sap_r", "sap_d"}) plan.push_back({k, f});
+        for (const char* k : {"vc_r", "vc_x1", "sap_r"}) plan.push_back({k, f});
+        plan.push_back({"sap_d", c->sapd_sz(chunk, prec)});
       } else {
         for (const char* k : {"mb_r", "mb_rt", "mb_p", "mb_v", "mb_s", "mb_t"}) plan.push_back({k, f});
       }

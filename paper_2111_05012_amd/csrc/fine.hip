@@ -1111,13 +1111,201 @@ __global__ __launch_bounds__(256) void k_sap_cross(Geo g, int colour, int first,
 // kernel's LDS exchange buffer (64 keeps paired LDS offsets in 512-byte units).
 constexpr int SAP_DOM_PAD = 64;
 
+// Face bookkeeping of a domain: faces in the order (mu, side), side 0 at
+// local coordinate 0, side 1 at B_mu - 1; a face site is indexed
+// lexicographically by its other three local coordinates, so that the sites
+// of a face, taken in site order, have consecutive indices.
+__host__ __device__ __forceinline__ int face_slots(const Geo& g) {
+  return 2 * (g.Vb / g.B[0] + g.Vb / g.B[1] + g.Vb / g.B[2] + g.Vb / g.B[3]);
+}
+__host__ __device__ __forceinline__ int face_off(const Geo& g, int mu, int side) {
+  int o = 0;
+  for (int m = 0; m < mu; ++m) o += 2 * (g.Vb / g.B[m]);
+  return o + side * (g.Vb / g.B[mu]);
+}
+template <int MU>
+__device__ __forceinline__ int face_index(const Geo& g, const int (&lc)[4]) {
+  int f = 0, st = 1;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+    if (m != MU) {
+      f += lc[m] * st;
+      st *= g.B[m];
+    }
+  return f;
+}
+
+// Write the spin projections of a block correction psi for the hops that
+// enter the domain through face MU: on side 0 the hops y -> y + mu of the
+// sites y just outside (forward projection), on side 1 the hops y -> y - mu
+// (backward projection).  Layout [block][6][FT] (this block's fw given).
+template <int MU>
+__device__ __forceinline__ void face_put(const Geo& g, const SiteCoord& c, int FT, const cplx<float> (&psi)[12],
+                                         float2* fw) {
+  const int f = face_index<MU>(g, c.lc);
+  cplx<float> h0[3], h1[3];
+  if (c.lc[MU] == 0) {
+    hop_proj<MU, true>(psi, h0, h1);
+    float2* o = fw + face_off(g, MU, 0) + f;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      st(o, (size_t)q * FT, h0[q]);
+      st(o, (size_t)(3 + q) * FT, h1[q]);
+    }
+  }
+  if (c.lc[MU] == g.B[MU] - 1) {
+    hop_proj<MU, false>(psi, h0, h1);
+    float2* o = fw + face_off(g, MU, 1) + f;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      st(o, (size_t)q * FT, h0[q]);
+      st(o, (size_t)(3 + q) * FT, h1[q]);
+    }
+  }
+}
+
+// The crossing-hop correction from the face buffer (mixed path): for every
+// site y of the active colour's domains and every right-hand side,
+//   r(y) = src(y) - sum_{hops y -> x leaving the domain} W h(x)
+// with h the spin projection that the neighbouring domain wrote for that
+// hop (face_put) and W its FP16 hop matrix (boundary sign applied) from the
+// face-ordered copy FL, U for forward hops and U^dag for backward ones.
+// Sites of a face read consecutive face slots, so every load is coalesced
+// and no line brings a neighbour's interior.
+template <int MU>
+__device__ __forceinline__ void face_get(const Geo& g, const SiteCoord& c, int FT, const float2* __restrict__ fr,
+                                         const half2_t* __restrict__ FL, cplx<float> (&acc)[12], bool& any) {
+  const int F = g.Vb / g.B[MU];
+  const int f = face_index<MU>(g, c.lc);
+#pragma unroll
+  for (int side = 1; side >= 0; --side) {
+    if (c.lc[MU] != (side ? g.B[MU] - 1 : 0)) continue;
+    any = true;
+    // the neighbouring block across this face (the block count per
+    // direction is even, so it differs from this block)
+    int bk = c.bk[MU] + (side ? 1 : -1);
+    if (bk < 0) bk += g.NB[MU];
+    if (bk >= g.NB[MU]) bk -= g.NB[MU];
+    const int nblk = c.blk + (bk - c.bk[MU]) * g.sN[MU];
+    // the producer's face on the opposite side
+    const float2* hp = fr + (size_t)nblk * 6 * FT + face_off(g, MU, 1 - side) + f;
+    cplx<float> h0[3], h1[3], u[9];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      h0[q] = ld<float>(hp, (size_t)q * FT);
+      h1[q] = ld<float>(hp, (size_t)(3 + q) * FT);
+    }
+    const half2_t* up = FL + (size_t)c.blk * 9 * FT + (size_t)face_off(g, MU, side) * 9 + f;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = h2f(up[(size_t)e * F]);
+    cplx<float> g0[3], g1[3];
+    if (side) {
+      hop_mul<true>(h0, h1, u, -1.0f, g0, g1);
+      hop_recon<MU, true>(g0, g1, acc);
+    } else {
+      hop_mul<false>(h0, h1, u, -1.0f, g0, g1);
+      hop_recon<MU, false>(g0, g1, acc);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sap_cross_face(Geo g, int colour, int first,
+                                                        const float2* __restrict__ b, float2* __restrict__ r,
+                                                        const float2* __restrict__ face, size_t rs, size_t fs,
+                                                        const half2_t* __restrict__ FL) {
+  const int Vb = g.Vb;
+  const size_t nsite = (size_t)(g.nblk >> 1) * Vb;
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nsite) return;
+  const int k = (int)(e / Vb), loc = (int)(e - (size_t)k * Vb);
+  const int half = g.NB[0] >> 1;
+  const int row = k / half, j = k - row * half;
+  const int by = row % g.NB[1];
+  const int rz = row / g.NB[1];
+  const int bz = rz % g.NB[2];
+  const int bt = rz / g.NB[2];
+  const int bx = 2 * j + ((colour + by + bz + bt) & 1);
+  const int blk = bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
+  const int s = blk * Vb + loc;
+  const SiteCoord c = decompose(g, s);
+  const int FT = face_slots(g);
+  const size_t off = (size_t)blockIdx.y * rs;
+  const float2* fr = face + (size_t)blockIdx.y * fs;
+  cplx<float> acc[12];
+#pragma unroll
+  for (int a = 0; a < 12; ++a) acc[a] = {0, 0};
+  bool any = false;
+  face_get<0>(g, c, FT, fr, FL, acc, any);
+  face_get<1>(g, c, FT, fr, FL, acc, any);
+  face_get<2>(g, c, FT, fr, FL, acc, any);
+  face_get<3>(g, c, FT, fr, FL, acc, any);
+  if (!any && !first) return;
+  const size_t fb12 = fbase_b(g, 12, s, blk);
+  const float2* src = (first ? b : r) + off;
+  float2* dst = r + off;
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    const size_t o = (size_t)a * Vb + fb12;
+    st(dst, o, ld<float>(src, o) + acc[a]);
+  }
+}
+
+// FL (see launch_face_links): one thread per (block, face slot).
+__global__ __launch_bounds__(256) void k_face_links(Geo g, const half2_t* __restrict__ U, half2_t* __restrict__ FL) {
+  const int FT = face_slots(g);
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (size_t)g.nblk * FT) return;
+  const int blk = (int)(e / FT);
+  int j = (int)(e - (size_t)blk * FT);
+  int mu = 0, side = 0;
+  while (j >= 2 * (g.Vb / g.B[mu])) {
+    j -= 2 * (g.Vb / g.B[mu]);
+    ++mu;
+  }
+  const int F = g.Vb / g.B[mu];
+  side = j >= F;
+  const int f = j - side * F;
+  // local coordinates: the face's own coordinate, the others from f
+  int lc[4], rem = f;
+  for (int m = 0; m < 4; ++m) {
+    if (m == mu) {
+      lc[m] = side ? g.B[m] - 1 : 0;
+    } else {
+      lc[m] = rem % g.B[m];
+      rem /= g.B[m];
+    }
+  }
+  const int s = blk * g.Vb + lc[0] + g.B[0] * (lc[1] + g.B[1] * (lc[2] + g.B[2] * lc[3]));
+  const SiteCoord c = decompose(g, s);
+  int sign, nblk;
+  bool inb;
+  size_t base;
+  if (side) {
+    (void)neighbour<true>(g, s, c, mu, sign, inb, nblk);
+    base = fbase_b(g, 36, s, blk);
+  } else {
+    const int nb = neighbour<false>(g, s, c, mu, sign, inb, nblk);
+    base = fbase_b(g, 36, nb, nblk);
+  }
+  half2_t* o = FL + (size_t)blk * 9 * FT + (size_t)face_off(g, mu, side) * 9 + f;
+  for (int q = 0; q < 9; ++q) {
+    half2_t u = U[(size_t)(mu * 9 + q) * g.Vb + base];
+    if (sign < 0) {
+      u.x = -u.x;
+      u.y = -u.y;
+    }
+    o[(size_t)q * F] = u;
+  }
+}
+
+
 // VB: the domain volume when known at compile time (LDS offsets become
 // immediates), 0 for any volume.
 template <int VB>
 __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, int mr, int nrhs,
                                                  const float2* __restrict__ b, float2* __restrict__ r,
-                                                 float2* __restrict__ x, float2* __restrict__ delta,
-                                                 const float2* __restrict__ xinit, size_t rs,
+                                                 float2* __restrict__ x, float2* __restrict__ face,
+                                                 const float2* __restrict__ xinit, size_t rs, size_t fs,
                                                  const half2_t* __restrict__ U, const half2_t* __restrict__ C) {
   extern __shared__ __align__(16) char smem[];
   const int Vb = VB ? VB : g.Vb;
@@ -1144,6 +1332,7 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
   const int nw = VB ? (VB + 63) / 64 : (blockDim.x + 63) >> 6;
   SiteCoord c = decompose(g, s);
   const size_t fb12 = fbase_b(g, 12, s, blk), fb36 = fbase_b(g, 36, s, blk);
+  const int FT = face_slots(g);
 
   // per direction, held in registers for the whole launch: the slot of the
   // neighbour's residual (its local index in the domain, or the zero slot Vb
@@ -1307,13 +1496,20 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
 #pragma unroll
       for (int a = 0; a < 12; ++a) asm volatile("" ::"v"(nrho[a].x), "v"(nrho[a].y));
       float2* rw = r + off;
-      float2* dw = delta + off;
 #pragma unroll
       for (int a = 0; a < 12; ++a) {
         size_t o = (size_t)a * Vb + fb12;
         st(xr, o, have_x0 ? x0[a] + xm[a] : xm[a]);
         if (!(flags & SAP_NO_R)) st(rw, o, rho[a]);
-        if (!(flags & SAP_NO_DELTA)) st(dw, o, xm[a]);
+      }
+      // the correction's spin projections on the domain's faces, for the
+      // crossing hops of the other colour's next residual update
+      if (!(flags & SAP_NO_DELTA)) {
+        float2* fw = face + rr * fs + (size_t)blk * 6 * FT;
+        face_put<0>(g, c, FT, xm, fw);
+        face_put<1>(g, c, FT, xm, fw);
+        face_put<2>(g, c, FT, xm, fw);
+        face_put<3>(g, c, FT, xm, fw);
       }
 #pragma unroll
       for (int a = 0; a < 12; ++a) rho[a] = nrho[a];
@@ -1580,9 +1776,23 @@ bool sap_needs_cross(const SapArgs& a, int sweep, int col) { return a.mixed && (
 void launch_sap_cross(const SapArgs& a, int sweep, int col, hipStream_t st) {
   if (!sap_needs_cross(a, sweep, col)) return;
   const size_t nsite = (size_t)(a.g.nblk / 2) * a.g.Vb;
-  k_sap_cross<<<dim3((unsigned)((nsite + 255) / 256), a.nrhs), 256, 0, st>>>(
-      a.g, col, sweep == 0 ? 1 : 0, (const float2*)a.b, (float2*)a.r, (const float2*)a.delta, a.rs,
-      (const half2_t*)a.U);
+  const dim3 grid((unsigned)((nsite + 255) / 256), a.nrhs);
+  if (a.eo) {
+    // the even-odd block solve hands over whole corrections
+    k_sap_cross<<<grid, 256, 0, st>>>(a.g, col, sweep == 0 ? 1 : 0, (const float2*)a.b, (float2*)a.r,
+                                      (const float2*)a.delta, a.rs, (const half2_t*)a.U);
+    return;
+  }
+  if (!a.FL) throw std::runtime_error("SAP: no face hop matrices");
+  k_sap_cross_face<<<grid, 256, 0, st>>>(a.g, col, sweep == 0 ? 1 : 0, (const float2*)a.b, (float2*)a.r,
+                                         (const float2*)a.delta, a.rs, a.fs, (const half2_t*)a.FL);
+}
+
+int sap_face_slots(const Geo& g) { return face_slots(g); }
+
+void launch_face_links(const Geo& g, const void* U16, void* FL, hipStream_t st) {
+  const size_t n = (size_t)g.nblk * face_slots(g);
+  k_face_links<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(g, (const half2_t*)U16, (half2_t*)FL);
 }
 
 void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st) {
@@ -1607,7 +1817,7 @@ void launch_sap_half(const SapArgs& a, int sweep, int col, hipStream_t st) {
     }
     kern<<<round8(ndom), nthr, lds, st>>>(g, col, flags, a.mr, a.nrhs, (const float2*)a.b,
                                           (float2*)a.r, (float2*)a.x, (float2*)a.delta, (const float2*)a.xinit, a.rs,
-                                          (const half2_t*)a.U, (const half2_t*)a.C);
+                                          a.fs, (const half2_t*)a.U, (const half2_t*)a.C);
   };
   if (a.eo) {
     if (!a.M) throw std::runtime_error("even-odd SAP: no inverse clover field");

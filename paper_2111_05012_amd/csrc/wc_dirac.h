@@ -73,21 +73,24 @@ __device__ __forceinline__ void hop_accum(const cplx<R> (&psi)[12], const cplx<R
   }
 }
 
-// The two halves of hop_accum, for kernels that hand the projected result of
-// a hop to the site that receives it: g = coef * W h (h the spin projection
-// of psi), and acc += the spin reconstruction of g.
+// The pieces of hop_accum, for kernels that hand a hop's projected
+// half-spinor to the site that receives it: the spin projection h of psi,
+// g = coef * W h, and acc += the spin reconstruction of g (hop_recon).
 template <int MU, bool FWD, class R>
-__device__ __forceinline__ void hop_half(const cplx<R> (&psi)[12], const cplx<R> (&u)[9], R coef, cplx<R> (&g0)[3],
-                                         cplx<R> (&g1)[3]) {
+__device__ __forceinline__ void hop_proj(const cplx<R> (&psi)[12], cplx<R> (&h0)[3], cplx<R> (&h1)[3]) {
   using P = Proj<MU>;
   constexpr int T0 = FWD ? P::t0 : (P::t0 ^ 2);
   constexpr int T1 = FWD ? P::t1 : (P::t1 ^ 2);
-  cplx<R> h0[3], h1[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     h0[c] = psi[c] + unit<T0>(psi[(2 + P::pi0) * 3 + c]);
     h1[c] = psi[3 + c] + unit<T1>(psi[(2 + P::pi1) * 3 + c]);
   }
+}
+
+template <bool FWD, class R>
+__device__ __forceinline__ void hop_mul(const cplx<R> (&h0)[3], const cplx<R> (&h1)[3], const cplx<R> (&u)[9], R coef,
+                                        cplx<R> (&g0)[3], cplx<R> (&g1)[3]) {
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     cplx<R> a = {0, 0}, b = {0, 0};
@@ -104,6 +107,14 @@ __device__ __forceinline__ void hop_half(const cplx<R> (&psi)[12], const cplx<R>
     g0[r] = coef * a;
     g1[r] = coef * b;
   }
+}
+
+template <int MU, bool FWD, class R>
+__device__ __forceinline__ void hop_half(const cplx<R> (&psi)[12], const cplx<R> (&u)[9], R coef, cplx<R> (&g0)[3],
+                                         cplx<R> (&g1)[3]) {
+  cplx<R> h0[3], h1[3];
+  hop_proj<MU, FWD>(psi, h0, h1);
+  hop_mul<FWD>(h0, h1, u, coef, g0, g1);
 }
 
 template <int MU, bool FWD, class R>

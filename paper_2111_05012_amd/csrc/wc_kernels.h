@@ -70,15 +70,30 @@ struct SapArgs {
   void* x = nullptr;            // solution (output)
   const void* xinit = nullptr;  // optional: x starts from xinit instead of 0 (x = xinit + SAP(b))
   void* r = nullptr;            // workspace residual
-  void* delta = nullptr;        // workspace last block corrections
+  // workspace: the last block corrections (FP64 path, even-odd variant), or
+  // (mixed path) the spin-projected corrections on the domain faces,
+  // [rhs][block][6][sap_face_slots] complex64 with per-rhs stride fs
+  void* delta = nullptr;
   size_t rs = 0;                // per-rhs stride of all spinor fields
+  size_t fs = 0;                // per-rhs stride of the face buffer (mixed path)
   const void* U = nullptr;
   const void* C = nullptr;
+  const void* FL = nullptr;     // face hop matrices (launch_face_links), mixed path
   // even-odd preconditioned block solve (mixed precision only): M holds the
   // FP16 (1 + F)^-1 - 1 (launch_clover_inverse)
   int eo = 0;
   const void* M = nullptr;
 };
+// Faces of a domain (multigrid block), in the order (mu, side): side 0 is
+// the face at local coordinate 0, side 1 at B_mu - 1; face mu has Vb / B_mu
+// sites, indexed lexicographically by the other three local coordinates.
+// sap_face_slots = sum over mu of 2 Vb / B_mu.
+int sap_face_slots(const Geo& g);
+// FL[block][face][9][face site]: the FP16 hop matrix (-kappa U, times the
+// boundary sign of the hop) of the hop that leaves the block through that
+// face site: U_mu(y) for side 1, U_mu(y - mu) for side 0.  Built from the
+// FP16 links after every gauge load; nblk * 9 * sap_face_slots elements.
+void launch_face_links(const Geo& g, const void* U16, void* FL, hipStream_t st);
 // one half-sweep (colour col of sweep `sweep`) of the SAP listing.  Mixed
 // precision: launch_sap_cross (the crossing-hop correction of the residual,
 // when sap_needs_cross) must precede launch_sap_half on the same stream.
