@@ -184,6 +184,12 @@ typedef struct {
   /* SAP block solve: 0 = WCAMG_BLOCK_MR (default), 1 = WCAMG_BLOCK_EO_MR
    * (the even-odd preconditioned variant of wcamg_sap; mixed precision). */
   int sap_eo;
+  /* Test vectors per batch in the setup's SAP and V-cycle applications
+   * (0: all nv at once).  The vectors are independent there, so the result
+   * does not depend on it; smaller batches shrink four of the setup's
+   * workspaces (SAP residual and corrections, V-cycle fields) from nv to
+   * vec_chunk spinor fields, at some cost in speed. */
+  int vec_chunk;
 } wcamg_setup_params;
 #define WCAMG_SMOOTH_POST 0
 #define WCAMG_SMOOTH_PRE 1

@@ -939,14 +939,15 @@ struct wcamg_ctx {
     }
   }
 
-  // block orthonormalisation (CholQR, twice) of nv working fields in place
-  void orthonormalize(void* Vw, int nv, int prec) {
+  // block orthonormalisation (CholQR, twice) of nv working fields in place;
+  // tmp: nv fields of scratch (the workspace "or_tmp" when null)
+  void orthonormalize(void* Vw, int nv, int prec, void* tmp = nullptr) {
     int t = spin_t(prec);
     Timed tb(this, "ortho", 0, 0, 1, true);
     size_t gbytes = (size_t)nv * g.nblk * 2 * nv * sizeof(double2);
     double2* G = (double2*)W("or_G", gbytes);
     void* coef = W("or_c", (size_t)nv * g.nblk * 2 * nv * ct_size(t));
-    void* tmp = W("or_tmp", fsz(nv, prec));
+    if (!tmp) tmp = W("or_tmp", fsz(nv, prec));
     int* bad = (int*)W("or_bad", sizeof(int));
     launch_zero(bad, sizeof(int), st);
     size_t grs = (size_t)g.nblk * 2 * nv;
@@ -1436,12 +1437,22 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
     c->set_l1_params(p);
     const Geo& g = c->g;
     int nv = p->nv, prec = p->prec, t = c->spin_t(prec);
+    require(p->vec_chunk >= 0, "vec_chunk must be >= 0");
+    const int ch = p->vec_chunk > 0 ? std::min(p->vec_chunk, nv) : nv;
     size_t cbytes = (size_t)nv * g.V * 12 * sizeof(double2);
     {
-      const size_t f = c->fsz(nv, prec);
-      c->reserve({{"su_w", f}, {"su_t", f}, {"sap_r", f}, {"sap_d", c->sapd_sz(nv, prec)}, {"or_tmp", f}, {"vc_r", f},
-                  {"vc_x1", f}});
+      // the iterates and their update (which also serves as the
+      // orthonormalisation's scratch), and the SAP and V-cycle fields of one
+      // batch of ch vectors
+      const size_t f = c->fsz(nv, prec), fc = c->fsz(ch, prec);
+      c->reserve({{"su_w", f}, {"su_t", f}, {"sap_r", fc}, {"sap_d", c->sapd_sz(ch, prec)}, {"vc_r", fc},
+                  {"vc_x1", fc}});
     }
+    const size_t vstride = c->fsz(1, prec);
+    auto batched = [&](void* in, void* out, const std::function<void(const void*, void*, int)>& f) {
+      for (int v0 = 0; v0 < nv; v0 += ch)
+        f((const char*)in + v0 * vstride, (char*)out + v0 * vstride, std::min(ch, nv - v0));
+    };
     HostIO io(c);
     const double2* Vd = nullptr;
     if (p->init_vectors) Vd = (const double2*)io.in(p->init_vectors, cbytes, p->init_where, "io_in");
@@ -1466,20 +1477,22 @@ int wcamg_setup(wcamg_ctx* c, const wcamg_setup_params* p) {
     } else {
       start(Vw, t);
       for (int k = 0; k < p->n_init; ++k) {
-        c->sap(Vw, Vt, nullptr, nv, p->sap_sweeps, p->mr_iters, prec, p->sap_eo);
+        batched(Vw, Vt, [&](const void* in, void* out, int n) {
+          c->sap(in, out, nullptr, n, p->sap_sweeps, p->mr_iters, prec, p->sap_eo);
+        });
         std::swap(Vw, Vt);
       }
     }
-    c->orthonormalize(Vw, nv, prec);
+    c->orthonormalize(Vw, nv, prec, Vt);
     c->store_vectors(Vw, nv);
     c->build_coarse();
     // level 0 (0-b) runs with the two-level cycle; level 1 is set up on the final level-0 hierarchy
     bool l1 = c->h.l1;
     c->h.l1 = false;
     for (int k = 0; k < p->n_adapt; ++k) {
-      c->vcycle(Vw, Vt, nv);
+      batched(Vw, Vt, [&](const void* in, void* out, int n) { c->vcycle(in, out, n); });
       std::swap(Vw, Vt);
-      c->orthonormalize(Vw, nv, prec);
+      c->orthonormalize(Vw, nv, prec, Vt);
       c->store_vectors(Vw, nv);
       c->build_coarse();
     }

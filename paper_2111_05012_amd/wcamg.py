@@ -37,7 +37,7 @@ class SetupParams(ctypes.Structure):
                 ('init_where', ctypes.c_int), ('nlevels', ctypes.c_int), ('block1', _c_int4), ('nv1', ctypes.c_int),
                 ('mr1_iters', ctypes.c_int), ('init_mr1_iters', ctypes.c_int), ('init_vectors1', ctypes.c_void_p),
                 ('seed1', ctypes.c_ulonglong), ('init_net', ctypes.c_int), ('seed', ctypes.c_ulonglong),
-                ('smoothing', ctypes.c_int), ('sap_eo', ctypes.c_int)]
+                ('smoothing', ctypes.c_int), ('sap_eo', ctypes.c_int), ('vec_chunk', ctypes.c_int)]
 
 
 class SolveParams(ctypes.Structure):
@@ -234,10 +234,10 @@ class Context:
     def setup_params(nv, prec=PREC_FP64, n_init=3, n_adapt=3, sap_sweeps=4, mr_iters=6, coarse_iters=50,
                      coarse_tol=0.1, init_vectors=None, nlevels=2, block1=(1, 1, 1, 1), nv1=0, mr1_iters=4,
                      init_mr1_iters=8, init_vectors1=None, seed1=1, init_net=0, seed=1, smoothing=SMOOTH_POST,
-                     sap_eo=0):
+                     sap_eo=0, vec_chunk=0):
         p = SetupParams(nv, n_init, n_adapt, sap_sweeps, mr_iters, coarse_iters, coarse_tol, prec, None, DEVICE,
                         nlevels, _c_int4(*block1), nv1, mr1_iters, init_mr1_iters, None, seed1, init_net, seed,
-                        smoothing, sap_eo)
+                        smoothing, sap_eo, vec_chunk)
         if init_vectors is not None:
             ptr, w = _ptr(init_vectors)
             p.init_vectors = ptr

@@ -384,6 +384,39 @@ def test_setup_and_solve_mixed_even_odd_smoother():
         prob.ctx.sap(prob.T(b), x, 2, 4, 6, PREC_FP64, block_solve=BLOCK_EO_MR)
 
 
+@pytest.mark.parametrize('prec', [0, 1])
+def test_setup_vec_chunk_same_hierarchy(prec):
+    """The setup's SAP and V-cycles taken over the test vectors in batches
+    (vec_chunk 5 of 12: batches 5, 5, 2) give the hierarchy of the unbatched
+    setup: the test vectors agree to rounding (the kernels' variants may
+    differ with the batch size), and both solve to 1e-10 in the same number
+    of outer iterations."""
+    prob = Problem((8, 8, 8, 8), (4, 4, 4, 4), eps=0.5, seed=1, kappa=0.124, csw=1.0)
+    import torch
+    nv = 12
+    V0 = syn.gaussian_vectors(prob.dims, nv, 5)
+    b = syn.z2_source(prob.dims, 6, nrhs=2)
+    got = []
+    for ch in (0, 5):
+        prob.ctx.setup(prob.ctx.setup_params(nv, prec, init_vectors=prob.T(V0), vec_chunk=ch))
+        Q = torch.zeros((nv,) + syn.shape_of(prob.dims) + (4, 3), dtype=torch.complex128, device=prob.dev)
+        prob.ctx.get_test_vectors(Q)
+        x = prob.zeros(b.shape)
+        rc, info = prob.ctx.solve(prob.T(b), x, 2, tol=1e-10)
+        assert rc == 0
+        xg = prob.N(x)
+        for k in range(2):
+            assert np.linalg.norm(b[k] - prob.op.D(xg[k])) / np.linalg.norm(b[k]) <= 1e-10
+        got.append((Q.cpu().numpy(), list(info.iters[:2])))
+    # FP64: summation orders only; mixed: the FP16 storage of the test
+    # vectors can round a batch's vector to the neighbouring FP16 value
+    assert rel(got[1][0], got[0][0]) < (1e-10 if prec == 0 else 1e-2)
+    if prec == 0:
+        assert got[1][1] == got[0][1]
+    else:
+        assert max(abs(i - j) for i, j in zip(got[1][1], got[0][1])) <= 1
+
+
 def test_flexible_bicgstab_mixed_amg_and_mbicgs_c1():
     """Config-1 workload: the flexible BiCGStab preconditioned by the mixed
     V-cycle, and the comparison solver (preconditioned by an FP32 BiCGStab on
