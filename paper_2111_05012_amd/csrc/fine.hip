@@ -1443,6 +1443,11 @@ __global__ __launch_bounds__(512) void k_sap_dom(Geo g, int colour, int flags, i
         for (int d = 0; d < 8; ++d) {
           const int inf = ninfo[d];
           const int nl = inf & 0xffff;
+          // The t-hops that leave the domain are skipped: when the sites of
+          // one t-slice fill whole wavefronts (B_x B_y B_z a multiple of
+          // 64), a wavefront's t-hop leaves the domain for all its lanes or
+          // for none, and the skip is a branch the whole wavefront takes.
+          if ((d & 3) == 3 && nl == Vb) continue;
 #pragma unroll
           for (int a = 0; a < 12; ++a) psi[a] = lds[a * Vbp + nl];
           half2_t ub[9];
