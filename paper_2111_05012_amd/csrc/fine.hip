@@ -767,7 +767,7 @@ int dslash_lds_slices(const Geo& g) {
 
 template <class R, class TI, class TO, class TL, class TC>
 static void dslash_dispatch(const DslashArgs& a, hipStream_t st) {
-  if (a.block_size <= -12 && a.op == OP_D) {
+  if ((a.block_size == -12 || a.block_size == -14) && a.op == OP_D) {
     const int NR = -a.block_size - 10;
     const int nt = (a.g.V + 255) / 256;
     dim3 grid(round8(nt * ((a.nrhs + NR - 1) / NR)));

@@ -304,6 +304,32 @@ def test_vcycle_mixed_12rhs(prod, dc16):
         assert rel(og[k], want) < TOL_VCYCLE, k
 
 
+def test_vcycle_mixed_12rhs_every_dslash_tile(prod, dc16, tmp_path):
+    """The mixed V-cycle of test_vcycle_mixed_12rhs with its residual
+    b - D x (the D with a source term) forced onto each LDS-tile variant of
+    the mixed D."""
+    from paper_2111_05012_amd import PREC_MIXED
+    _install(prod, PREC_MIXED, coarse_iters=8)
+    prod.ctx.set_coarse_op(prod.T(dc16))
+    mg = amg.TwoLevel(prod.op16, prod.V16, 4, 6, coarse_iters=8, coarse_tol=0.0)
+    mg.Dc = r32(dc16)
+    v = syn.gaussian_vectors(DIMS, NRHS, 81)
+    cache = str(tmp_path / 'tune.json')
+    prod.ctx.autotune(True, cache)
+    out = prod.zeros(v.shape)
+    prod.ctx.vcycle(prod.T(v), out, NRHS)
+    keys = json.load(open(cache))
+    want = {k: mg.vcycle(r32(v[k:k + 1]))[0] for k in (0, NRHS - 1)}
+    for var in (-2, -3):
+        _force(prod, cache, 'dslash', var, keys)
+        out = prod.zeros(v.shape)
+        prod.ctx.vcycle(prod.T(v), out, NRHS)
+        og = prod.N(out)
+        for k, w in want.items():
+            assert rel(og[k], w) < TOL_VCYCLE, (var, k)
+    prod.ctx.autotune(False, None)
+
+
 def test_vcycle_mixed_even_odd(prod, dc16, ainv16):
     """The mixed V-cycle with the even-odd preconditioned SAP block solve
     (setup parameter sap_eo) against the oracle's V-cycle with that block
