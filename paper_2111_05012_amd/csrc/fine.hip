@@ -1024,12 +1024,14 @@ __global__ __launch_bounds__(512) void k_sap_half(Geo g, int colour, int flags, 
 }
 
 // Mixed-precision SAP half-sweep: one workgroup per domain of the active
-// colour for ALL right-hand sides.  The domain's forward links (FP16) and a
-// table of in-domain neighbours are staged in LDS once; the MR block solves of
-// the right-hand sides then run in turn with the residual exchanged through
-// LDS and the clover (FP16, one contiguous range per domain) read through the
-// caches.  Links of hops that leave the domain are not needed by D_SAP; the
-// crossing-hop correction of the residual runs before, in k_sap_cross.
+// colour for ALL right-hand sides.  The domain's FP16 hop matrices are staged
+// in LDS and its clover in registers once; the MR block solves of the
+// right-hand sides then run in turn with the residual exchanged through LDS.
+// Links of hops that leave the domain are not needed by D_SAP; the
+// crossing-hop correction of the residual runs before, in k_sap_cross_face
+// (from the spin projections that the other colour's domain solves wrote on
+// their faces) or, for the even-odd block solve, in k_sap_cross (from its
+// whole corrections).
 __device__ __forceinline__ cplx<float> h2f(half2_t v) { return {(float)v.x, (float)v.y}; }
 
 template <bool FWD>
@@ -1041,8 +1043,10 @@ __device__ __forceinline__ void hop_h(int mu, const cplx<float> (&psi)[12], cons
   hop_any<FWD>(mu, psi, u, coef, acc);
 }
 
-// The crossing-hop correction of a mixed-precision SAP half-sweep as a
-// kernel of its own, ahead of the domain solves: for every site x of the
+// The crossing-hop correction of a mixed-precision SAP half-sweep from whole
+// block corrections (the even-odd block solve's hand-over; the default path
+// uses k_sap_cross_face), as a kernel of its own ahead of the domain solves:
+// for every site x of the
 // active colour's domains and every right-hand side,
 //   r(x) = src(x) - sum_{hops x -> y leaving the domain} sign H delta(y)
 // with H the hop's FP16 matrix -kappa U (or its adjoint) spin-projected
