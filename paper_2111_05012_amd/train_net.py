@@ -101,16 +101,19 @@ def summarize(rows):
     return out
 
 
-def heatbath_configs(dims, beta, therm, sep, count, seed, device):
+def heatbath_configs(dims, beta, therm, sep, count, seed, device, log=None):
     """count configurations of one heat-bath chain (Wilson action, cold
     start): after therm sweeps, every sep-th sweep."""
     from synthetic import heatbath as hb
     out = []
+    total = therm + sep * (count - 1)
 
     def keep(n, U):
         if n + 1 >= therm and (n + 1 - therm) % sep == 0 and len(out) < count:
             out.append(U.clone())
-    hb.heatbath_field_torch(dims, beta, therm + sep * (count - 1), seed, device, record=keep)
+        if log and (n + 1) % 100 == 0:
+            log('heat-bath sweep %d of %d' % (n + 1, total))
+    hb.heatbath_field_torch(dims, beta, total, seed, device, record=keep)
     return out
 
 
@@ -161,8 +164,8 @@ def main(argv=None):
     held = list(range(args.eval[0], args.eval[1] + 1))
     if args.gauge == 'heatbath':
         t0 = time.perf_counter()
-        chain_t = heatbath_configs(dims, args.beta, args.therm, args.sep, len(train), train[0], dev)
-        chain_e = heatbath_configs(dims, args.beta, args.therm, args.sep, len(held), held[0], dev)
+        chain_t = heatbath_configs(dims, args.beta, args.therm, args.sep, len(train), train[0], dev, log)
+        chain_e = heatbath_configs(dims, args.beta, args.therm, args.sep, len(held), held[0], dev, log)
         fields = dict(zip(train, chain_t))
         fields.update(zip(held, chain_e))
         log('heat-bath configurations: %d + %d in %.1f s' % (len(train), len(held), time.perf_counter() - t0))
