@@ -258,6 +258,10 @@ typedef struct {
   int use_graph; /* capture the V-cycle in a HIP graph and replay it */
   int phase_times; /* nonzero: time the solve's phases (the info's t_precond ... t_outer) with HIP
                       events; the V-cycles then run without graphs */
+  int ortho;       /* orthogonalisation of the Arnoldi vectors: 0 = classical Gram-Schmidt twice
+                      with the second pass delayed into the next step (two sweeps over the basis
+                      per step; the last Hessenberg column of a cycle keeps its first-pass
+                      values), 1 = classical Gram-Schmidt twice (three sweeps per step) */
 } wcamg_solve_params;
 
 #define WCAMG_MAX_RHS 64

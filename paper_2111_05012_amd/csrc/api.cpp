@@ -1776,7 +1776,9 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
   double2* V = (double2*)c->W("fg_V", (size_t)(m + 1) * vs * sizeof(double2));
   void* Z = c->W("fg_Z", (size_t)m * vs * ct_size(zt));
   void* vin = prec == WCAMG_PREC_MIXED ? c->W("fg_vin", vs * sizeof(float2)) : nullptr;
-  double2* part = (double2*)c->W("fg_part", (size_t)nrhs * reduce_nwg(n) * 16 * sizeof(double2));
+  double2* part = (double2*)c->W("fg_part", (size_t)nrhs * reduce_nwg(n) * (2 * GS_CHUNK + 2) * sizeof(double2));
+  const bool delayed = p->ortho == 0;  // CGS2 with the second pass delayed into the next step
+  double2* coef = (double2*)c->W("fg_c", (size_t)2 * (m + 2 + m / GS_CHUNK) * nrhs * sizeof(double2));
   double2* h1 = (double2*)c->W("fg_h1", (size_t)(m + 1) * nrhs * sizeof(double2));
   double2* h2 = (double2*)c->W("fg_h2", (size_t)(m + 1) * nrhs * sizeof(double2));
   double* nrm = (double*)c->W("fg_nrm", (size_t)nrhs * sizeof(double));
@@ -1853,12 +1855,67 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
     HIPCHK(hipGraphLaunch(it->second, c->st));
   };
 
-  std::vector<cd> H((size_t)(m + 1) * m * nrhs), gvec((size_t)(m + 1) * nrhs), cs((size_t)m * nrhs),
-      sn((size_t)m * nrhs);
-  std::vector<double2> hh1((size_t)(m + 1) * nrhs), hh2((size_t)(m + 1) * nrhs);
+  // raw Hessenberg matrix H[i][j][r] of the current cycle; the least-squares
+  // problem is solved from it by Givens rotations after every step
+  std::vector<cd> H((size_t)(m + 1) * m * nrhs);
+  std::vector<double> beta(nrhs);
+  std::vector<double2> hh1((size_t)(m + 1) * nrhs), hh2((size_t)(m + 1) * nrhs), hc;
   std::vector<int> kcols(nrhs);
   std::vector<double2> yhost((size_t)m * nrhs);
   auto Hc = [&](int i, int j, int r) -> cd& { return H[((size_t)i * m + j) * nrhs + r]; };
+  // min_y || beta e_0 - H y || over the first k columns, rotations (c real,
+  // s complex) applied to a copy; returns the residual norm, y if asked
+  auto lsq = [&](int r, int k, std::vector<cd>* y) -> double {
+    std::vector<cd> R((size_t)(k + 1) * std::max(k, 1)), gv(k + 1, cd(0)), cs(k), sn(k);
+    auto Rc = [&](int i, int j) -> cd& { return R[(size_t)i * k + j]; };
+    gv[0] = beta[r];
+    for (int j = 0; j < k; ++j) {
+      for (int i = 0; i <= j + 1; ++i) Rc(i, j) = Hc(i, j, r);
+      for (int i = 0; i < j; ++i) {
+        cd t = cs[i] * Rc(i, j) + sn[i] * Rc(i + 1, j);
+        Rc(i + 1, j) = -std::conj(sn[i]) * Rc(i, j) + cs[i] * Rc(i + 1, j);
+        Rc(i, j) = t;
+      }
+      cd a = Rc(j, j), bq = Rc(j + 1, j);
+      double den = std::sqrt(std::norm(a) + std::norm(bq));
+      if (den == 0) {
+        cs[j] = 1;
+        sn[j] = 0;
+      } else if (std::abs(a) == 0) {
+        cs[j] = 0;
+        sn[j] = std::conj(bq) / std::abs(bq);
+      } else {
+        cs[j] = std::abs(a) / den;
+        sn[j] = (a / std::abs(a)) * std::conj(bq) / den;
+      }
+      Rc(j, j) = cs[j] * Rc(j, j) + sn[j] * Rc(j + 1, j);
+      Rc(j + 1, j) = 0;
+      gv[j + 1] = -std::conj(sn[j]) * gv[j];
+      gv[j] = cs[j] * gv[j];
+    }
+    if (y) {
+      y->assign(k, cd(0));
+      for (int i = k - 1; i >= 0; --i) {
+        cd sum = gv[i];
+        for (int l = i + 1; l < k; ++l) sum -= Rc(i, l) * (*y)[l];
+        (*y)[i] = Rc(i, i) != cd(0) ? sum / Rc(i, i) : cd(0);
+      }
+    }
+    return std::abs(gv[k]);
+  };
+  auto gs_args = [&](int k0, int nq, double2* pv, double2* w) {
+    GsArgs a;
+    a.Q = V + (size_t)k0 * vs;
+    a.vs = vs;
+    a.nq = nq;
+    a.p = pv;
+    a.w = w;
+    a.n = n;
+    a.rs = rs;
+    a.nrhs = nrhs;
+    a.part = part;
+    return a;
+  };
 
   while (true) {
     // r = b - D x (FP64), into V_0
@@ -1875,105 +1932,192 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
     }
     if (all) break;
     std::vector<double> sc(nrhs);
-    std::vector<int> act(nrhs);
+    std::fill(H.begin(), H.end(), cd(0));
     for (int r = 0; r < nrhs; ++r) {
-      act[r] = !done[r];
-      double beta = std::sqrt(rn2[r]);
-      sc[r] = act[r] && beta > 0 ? 1.0 / beta : 0.0;
-      for (int i = 0; i <= m; ++i) gvec[(size_t)i * nrhs + r] = 0;
-      gvec[r] = act[r] ? beta : 0.0;
+      bool act = !done[r];
+      beta[r] = act ? std::sqrt(rn2[r]) : 0.0;
+      sc[r] = act && beta[r] > 0 ? 1.0 / beta[r] : 0.0;
       kcols[r] = 0;
     }
     HIPCHK(hipMemcpyAsync(scl, sc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
     launch_scale(V, scl, V, (float2*)vin, n, rs, nrhs, c->st);
-    std::vector<int> ext = act;  // still extending its Krylov space in this cycle
+    std::vector<int> ext(nrhs);  // still extending its Krylov space in this cycle
+    for (int r = 0; r < nrhs; ++r) ext[r] = !done[r];
     for (int j = 0; j < m; ++j) {
       run_vcycle(j);
       *vcycles += 1;
       void* zj = (char*)Z + (size_t)j * vs * ct_size(zt);
+      double2* pj = V + (size_t)j * vs;
       double2* w = V + (size_t)(j + 1) * vs;
       c->dslash(zj, zt, w, C128, nrhs, OP_D, WCAMG_PREC_FP64);
-      // classical Gram-Schmidt twice; the update of the first pass and the
-      // projections of the second share one sweep over the basis.  Timed as
-      // the class "gs": algorithmic bytes = the j + 1 basis vectors read three
-      // times, w read three times and written twice (FP64, all RHS)
-      {
-        const double vb = (double)vs * sizeof(double2);
-        wcamg_ctx::Timed tg(c, "gs", vb * (3.0 * (j + 1) + 5.0), 8.0 * 3 * (j + 1) * (double)vs, nrhs);
-        launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h1, c->st);
-        if (j + 1 <= 16) {
-          launch_multiaxpy_dot(V, vs, j + 1, h1, w, n, rs, nrhs, part, h2, c->st);
-        } else {
-          launch_multiaxpy(V, vs, j + 1, h1, w, n, rs, nrhs, part, nullptr, c->st);
-          launch_multidot(V, vs, j + 1, w, n, rs, nrhs, part, h2, c->st);
+      const double vb = (double)vs * sizeof(double2);
+      std::vector<int> was = ext;
+      if (delayed) {
+        // Delayed classical Gram-Schmidt twice.  V_0..V_{j-1} are final and
+        // V_j = p holds the previous step's vector after one projection.
+        // Sweep 1: the projections of w and p on the basis and on p; from
+        // them the second projection of p (s, rho), the correction of
+        // column j-1 (H[i][j-1] += s_i, H[j][j-1] = rho) and column j.
+        // Sweep 2: V_j = (p - sum_i s_i V_i) / rho and the first projection
+        // of w on V_0..V_j; w becomes the next p.  Class "gs": the j + 1
+        // basis vectors and w read twice, w and V_j written.
+        wcamg_ctx::Timed tg(c, "gs", vb * (2.0 * (j + 1) + 2.0 + (j > 0 ? 2.0 : 1.0)),
+                            8.0 * (4.0 * (j + 1) + 1.0) * (double)vs, nrhs);
+        for (int k0 = 0; k0 == 0 || k0 < j; k0 += GS_CHUNK) {
+          GsArgs a = gs_args(k0, std::min(GS_CHUNK, j - k0), pj, w);
+          a.h1 = h1 + (size_t)k0 * nrhs;
+          a.h2 = h2 + (size_t)k0 * nrhs;
+          a.h1p = h1 + (size_t)j * nrhs;
+          a.h2p = h2 + (size_t)j * nrhs;
+          launch_gs(GS_DOT2, a, c->st);
         }
-        launch_multiaxpy(V, vs, j + 1, h2, w, n, rs, nrhs, part, nrm, c->st);
+        HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
+                              c->st));
+        sync_get(hh2.data(), h2, (size_t)(j + 1) * nrhs * sizeof(double2));
+        // coefficients of sweep 2 per chunk: c1 then c2, (nq + 1) x nrhs each
+        const int nch = j == 0 ? 1 : (j + GS_CHUNK - 1) / GS_CHUNK;
+        std::vector<std::vector<cd>> c1(nrhs), c2(nrhs);
+        std::vector<double> rho(nrhs, 1.0);
+        for (int r = 0; r < nrhs; ++r) {
+          c1[r].assign(j + 1, cd(0));
+          c2[r].assign(j + 1, cd(0));
+          if (!ext[r]) continue;
+          auto cx = [](double2 v) { return cd(v.x, v.y); };
+          std::vector<cd> s(j);
+          double ss = 0;
+          for (int i = 0; i < j; ++i) {
+            s[i] = cx(hh2[(size_t)i * nrhs + r]);
+            ss += std::norm(s[i]);
+          }
+          if (j > 0) {
+            double rho2 = hh2[(size_t)j * nrhs + r].x - ss;
+            require(std::isfinite(rho2), "non-finite Arnoldi norm", WCAMG_ENUMERIC);
+            for (int i = 0; i < j; ++i) Hc(i, j - 1, r) += s[i];
+            if (!(rho2 > 0)) {
+              // p lies in the span of V_0..V_{j-1}: the space is invariant
+              Hc(j, j - 1, r) = 0;
+              ext[r] = 0;
+              continue;
+            }
+            rho[r] = std::sqrt(rho2);
+            Hc(j, j - 1, r) = rho[r];
+          }
+          cd bj = cx(hh1[(size_t)j * nrhs + r]);
+          for (int i = 0; i < j; ++i) {
+            cd ai = cx(hh1[(size_t)i * nrhs + r]);
+            Hc(i, j, r) = ai;
+            bj -= std::conj(s[i]) * ai;
+          }
+          bj /= rho[r];
+          Hc(j, j, r) = bj;
+          for (int i = 0; i < j; ++i) {
+            c1[r][i] = -s[i] / rho[r];
+            c2[r][i] = Hc(i, j, r) - bj * s[i] / rho[r];
+          }
+          c1[r][j] = 1.0 / rho[r];
+          c2[r][j] = bj / rho[r];
+        }
+        hc.clear();
+        std::vector<size_t> co;
+        for (int ch = 0; ch < nch; ++ch) {
+          const int k0 = ch * GS_CHUNK, nq = std::min(GS_CHUNK, j - k0);
+          co.push_back(hc.size());
+          for (int half = 0; half < 2; ++half)
+            for (int k = 0; k <= nq; ++k)
+              for (int r = 0; r < nrhs; ++r) {
+                const std::vector<cd>& cc = half ? c2[r] : c1[r];
+                cd v = k < nq ? cc[k0 + k] : ch == 0 ? cc[j] : cd(half ? 0.0 : 1.0);
+                hc.push_back(make_double2(v.real(), v.imag()));
+              }
+        }
+        HIPCHK(hipMemcpyAsync(coef, hc.data(), hc.size() * sizeof(double2), hipMemcpyHostToDevice, c->st));
+        for (int ch = 0; ch < nch; ++ch) {
+          const int k0 = ch * GS_CHUNK, nq = std::min(GS_CHUNK, j - k0);
+          GsArgs a = gs_args(k0, nq, pj, w);
+          a.c1 = coef + co[ch];
+          a.c2 = a.c1 + (size_t)(nq + 1) * nrhs;
+          a.write_p = j > 0;
+          a.norm2 = ch == nch - 1 ? nrm : nullptr;
+          launch_gs(GS_COMB2, a, c->st);
+        }
+      } else {
+        // Classical Gram-Schmidt twice; the update of the first pass and the
+        // projections of the second share one sweep over the basis.  Class
+        // "gs": the j + 1 basis vectors read three times, w read three times
+        // and written twice
+        wcamg_ctx::Timed tg(c, "gs", vb * (3.0 * (j + 1) + 5.0), 8.0 * 3 * (j + 1) * (double)vs, nrhs);
+        const int nk = j + 1;
+        auto sweep = [&](int mode, const double2* cf, double2* out, double* norm2) {
+          for (int k0 = 0; k0 < nk; k0 += GS_CHUNK) {
+            GsArgs a = gs_args(k0, std::min(GS_CHUNK, nk - k0), nullptr, w);
+            a.c1 = cf ? cf + (size_t)k0 * nrhs : nullptr;
+            a.h1 = out ? out + (size_t)k0 * nrhs : nullptr;
+            a.norm2 = k0 + GS_CHUNK >= nk ? norm2 : nullptr;
+            launch_gs(mode, a, c->st);
+          }
+        };
+        sweep(GS_DOT, nullptr, h1, nullptr);
+        if (nk <= GS_CHUNK) {
+          sweep(GS_AXPY_DOT, h1, h2, nullptr);
+        } else {
+          sweep(GS_AXPY_NORM, h1, nullptr, nullptr);
+          sweep(GS_DOT, nullptr, h2, nullptr);
+        }
+        sweep(GS_AXPY_NORM, h2, nullptr, nrm);
+        HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)nk * nrhs * sizeof(double2), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(hh2.data(), h2, (size_t)nk * nrhs * sizeof(double2), hipMemcpyDeviceToHost, c->st));
+        for (int r = 0; r < nrhs; ++r)
+          if (ext[r])
+            for (int i = 0; i <= j; ++i) {
+              size_t o = (size_t)i * nrhs + r;
+              Hc(i, j, r) = cd(hh1[o].x + hh2[o].x, hh1[o].y + hh2[o].y);
+            }
       }
-      HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
-                            c->st));
-      HIPCHK(hipMemcpyAsync(hh2.data(), h2, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
-                            c->st));
+      std::fill(hs.begin(), hs.end(), 0.0);
       sync_get(hn.data(), nrm, nrhs * sizeof(double));
-      bool any = false;
+      bool any = false, died = false;
       for (int r = 0; r < nrhs; ++r) {
-        hs[r] = 0.0;
-        if (!ext[r]) continue;
-        for (int i = 0; i <= j; ++i) {
-          size_t o = (size_t)i * nrhs + r;
-          Hc(i, j, r) = cd(hh1[o].x + hh2[o].x, hh1[o].y + hh2[o].y);
+        if (!ext[r]) {
+          died = died || was[r];  // an invariant space found by the delayed pass
+          continue;
         }
         double hnr = std::sqrt(std::max(hn[r], 0.0));
         require(std::isfinite(hnr), "non-finite Arnoldi norm", WCAMG_ENUMERIC);
         Hc(j + 1, j, r) = hnr;
         hs[r] = hnr > 0 ? 1.0 / hnr : 0.0;
-        // apply previous rotations, then a new one (c real, s complex)
-        for (int i = 0; i < j; ++i) {
-          cd ci = cs[(size_t)i * nrhs + r], si = sn[(size_t)i * nrhs + r];
-          cd t = ci * Hc(i, j, r) + si * Hc(i + 1, j, r);
-          Hc(i + 1, j, r) = -std::conj(si) * Hc(i, j, r) + ci * Hc(i + 1, j, r);
-          Hc(i, j, r) = t;
-        }
-        cd a = Hc(j, j, r), bq = Hc(j + 1, j, r);
-        double den = std::sqrt(std::norm(a) + std::norm(bq));
-        cd cj_, sj;
-        if (den == 0) {
-          cj_ = 1;
-          sj = 0;
-        } else if (std::abs(a) == 0) {
-          cj_ = 0;
-          sj = std::conj(bq) / std::abs(bq);
-        } else {
-          cj_ = std::abs(a) / den;
-          sj = (a / std::abs(a)) * std::conj(bq) / den;
-        }
-        cs[(size_t)j * nrhs + r] = cj_;
-        sn[(size_t)j * nrhs + r] = sj;
-        Hc(j, j, r) = cj_ * Hc(j, j, r) + sj * Hc(j + 1, j, r);
-        Hc(j + 1, j, r) = 0;
-        cd gj = gvec[(size_t)j * nrhs + r];
-        gvec[(size_t)(j + 1) * nrhs + r] = -std::conj(sj) * gj;
-        gvec[(size_t)j * nrhs + r] = cj_ * gj;
         its[r] += 1;
         kcols[r] = j + 1;
-        double est = std::abs(gvec[(size_t)(j + 1) * nrhs + r]);
-        if (est <= p->tol * std::sqrt(bn2[r]) || hnr == 0 || its[r] >= p->max_iters) ext[r] = 0;
+        double est = lsq(r, j + 1, nullptr);
+        if (est <= p->tol * std::sqrt(bn2[r]) || hnr == 0 || its[r] >= p->max_iters) {
+          ext[r] = 0;
+          hs[r] = 0.0;
+          died = true;
+        }
         any = any || ext[r];
       }
       if (!any || j == m - 1) break;
-      HIPCHK(hipMemcpyAsync(scl, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
-      launch_scale(w, scl, w, (float2*)vin, n, rs, nrhs, c->st);
+      // the next V-cycle input: V_{j+1} normalised (CGS2), or w normalised
+      // into the FP32 input (delayed, mixed precision); right-hand sides that
+      // stopped get a zero input
+      if (!delayed) {
+        HIPCHK(hipMemcpyAsync(scl, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
+        launch_scale(w, scl, w, (float2*)vin, n, rs, nrhs, c->st);
+      } else if (vin) {
+        HIPCHK(hipMemcpyAsync(scl, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
+        launch_scale(w, scl, nullptr, (float2*)vin, n, rs, nrhs, c->st);
+      } else if (died) {
+        for (int r = 0; r < nrhs; ++r) hs[r] = ext[r] ? 1.0 : 0.0;
+        HIPCHK(hipMemcpyAsync(scl, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
+        launch_scale(w, scl, w, nullptr, n, rs, nrhs, c->st);
+      }
     }
-    // y = H^{-1} g per rhs, x += Z y
+    // y = argmin || beta e_0 - H y || per rhs, x += Z y
     int kmax = 0;
     for (int r = 0; r < nrhs; ++r) {
       int k = kcols[r];
       kmax = std::max(kmax, k);
-      std::vector<cd> y(k);
-      for (int i = k - 1; i >= 0; --i) {
-        cd s = gvec[(size_t)i * nrhs + r];
-        for (int l = i + 1; l < k; ++l) s -= Hc(i, l, r) * y[l];
-        y[i] = Hc(i, i, r) != cd(0) ? s / Hc(i, i, r) : cd(0);
-      }
+      std::vector<cd> y;
+      if (k > 0) lsq(r, k, &y);
       for (int i = 0; i < m; ++i) {
         cd v = i < k ? y[i] : cd(0);
         yhost[(size_t)i * nrhs + r] = make_double2(v.real(), v.imag());

@@ -7,6 +7,7 @@
 // then one workgroup per right-hand side adds them in index order): results
 // do not depend on scheduling.
 #include <stdexcept>
+#include <utility>
 
 #include "wc_kernels.h"
 
@@ -412,127 +413,153 @@ void launch_fbicg_x(double2* x, const void* mp, const void* ms, int zt, size_t n
 }
 
 // ---------------------------------------------------------------- FGMRES (FP64 basis)
-constexpr int KC = 8;  // basis vectors per multidot pass
-
-__global__ __launch_bounds__(RED_THREADS) void k_multidot(const double2* V, size_t vs, int k0, int nk,
-                                                          const double2* w, size_t n, size_t rs, double2* part) {
+// One Gram-Schmidt sweep over a chunk of NQ basis vectors Q_k (compile-time
+// count, so that all loads of an element are issued before the first use),
+// the new Arnoldi vector w and, in the two-vector modes, the pending vector p.
+// Each thread owns one complex number of one right-hand side per step of the
+// grid-stride loop; the partial sums of a workgroup go to part[r][block][NOUT].
+template <int NQ, int MODE>
+__global__ __launch_bounds__(RED_THREADS) void k_gs(GsArgs a) {
+  constexpr bool TWO = MODE == GS_DOT2 || MODE == GS_COMB2;
+  constexpr bool AXPY = MODE == GS_AXPY_DOT || MODE == GS_AXPY_NORM || MODE == GS_COMB2;
+  constexpr int NOUT = MODE == GS_DOT || MODE == GS_AXPY_DOT ? NQ : MODE == GS_DOT2 ? 2 * NQ + 2 : 1;
+  constexpr int NO = NOUT > 0 ? NOUT : 1;
+  constexpr int NC = NQ + (TWO ? 1 : 0);  // coefficients per right-hand side
   const int r = blockIdx.y;
-  const size_t off = r * rs;
-  double v[2 * KC];
+  const size_t off = r * a.rs;
+  // negated update coefficients of w (-c for the AXPY modes, -c2 for COMB2)
+  // and the coefficients of the new p (COMB2)
+  cplx<double> cw[NC > 0 ? NC : 1], cp[NC > 0 ? NC : 1];
+  if constexpr (AXPY) {
+    const double2* src = MODE == GS_COMB2 ? a.c2 : a.c1;
 #pragma unroll
-  for (int k = 0; k < 2 * KC; ++k) v[k] = 0;
-  for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (size_t)gridDim.x * RED_THREADS) {
-    double2 ww = w[off + i];
+    for (int k = 0; k < NC; ++k) {
+      double2 v = src[(size_t)k * a.nrhs + r];
+      cw[k] = {-v.x, -v.y};
+    }
+  }
+  if constexpr (MODE == GS_COMB2) {
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      if (k0 + k < nk) {
-        double2 a = V[(size_t)(k0 + k) * vs + off + i];
-        v[2 * k] += a.x * ww.x + a.y * ww.y;
-        v[2 * k + 1] += a.x * ww.y - a.y * ww.x;
+    for (int k = 0; k < NC; ++k) cp[k] = C(a.c1[(size_t)k * a.nrhs + r]);
+  }
+  double acc[2 * NO];
+#pragma unroll
+  for (int k = 0; k < 2 * NO; ++k) acc[k] = 0;
+  auto cjacc = [&](int k, cplx<double> u, cplx<double> v) {  // acc_k += conj(u) v
+    acc[2 * k] = fma(u.x, v.x, fma(u.y, v.y, acc[2 * k]));
+    acc[2 * k + 1] = fma(u.x, v.y, fma(-u.y, v.x, acc[2 * k + 1]));
+  };
+  const double2* Q = a.Q + off;
+  double2* P = a.p + off;
+  double2* W = a.w + off;
+  for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < a.n; i += (size_t)gridDim.x * RED_THREADS) {
+    cplx<double> q[NQ > 0 ? NQ : 1];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) q[k] = ld<double>(Q + (size_t)k * a.vs, i);
+    cplx<double> pv = {0, 0};
+    if constexpr (TWO) pv = ld<double>(P, i);
+    cplx<double> wv = ld<double>(W, i);
+    if constexpr (MODE == GS_DOT) {
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) cjacc(k, q[k], wv);
+    } else if constexpr (MODE == GS_DOT2) {
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) {
+        cjacc(k, q[k], wv);
+        cjacc(NQ + k, q[k], pv);
+      }
+      cjacc(2 * NQ, pv, wv);
+      cjacc(2 * NQ + 1, pv, pv);
+    } else {
+      if constexpr (MODE == GS_COMB2) {
+        cplx<double> pn = cp[NQ] * pv;
+        cmac(wv, cw[NQ], pv);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+          cmac(pn, cp[k], q[k]);
+          cmac(wv, cw[k], q[k]);
+        }
+        if (a.write_p) st(P, i, pn);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) cmac(wv, cw[k], q[k]);
+      }
+      st(W, i, wv);
+      if constexpr (MODE == GS_AXPY_DOT) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) cjacc(k, q[k], wv);
+      } else {
+        acc[0] = fma(wv.x, wv.x, fma(wv.y, wv.y, acc[0]));
       }
     }
   }
-  block_sum<2 * KC>(v);
-  if (threadIdx.x == 0)
+  block_sum<2 * NO>(acc);
+  if (threadIdx.x == 0) {
+    double2* out = a.part + ((size_t)r * gridDim.x + blockIdx.x) * NOUT;
 #pragma unroll
-    for (int k = 0; k < KC; ++k)
-      part[((size_t)r * gridDim.x + blockIdx.x) * KC + k] = make_double2(v[2 * k], v[2 * k + 1]);
-}
-
-__global__ void k_multidot_fin(const double2* part, int nwg, int k0, int nk, int nrhs, double2* h) {
-  int r = blockIdx.x;
-  int k = threadIdx.x;
-  if (k >= KC || k0 + k >= nk) return;
-  cplx<double> s = sum_parts(part, nwg, KC, r, k);
-  h[(size_t)(k0 + k) * nrhs + r] = D2(s);
-}
-
-void launch_multidot(const double2* V, size_t vs, int nk, const double2* w, size_t n, size_t rs, int nrhs,
-                     double2* part, double2* h, hipStream_t st) {
-  int nwg = reduce_nwg(n);
-  for (int k0 = 0; k0 < nk; k0 += KC) {
-    k_multidot<<<dim3(nwg, nrhs), RED_THREADS, 0, st>>>(V, vs, k0, nk, w, n, rs, part);
-    k_multidot_fin<<<nrhs, 64, 0, st>>>(part, nwg, k0, nk, nrhs, h);
+    for (int k = 0; k < NOUT; ++k) out[k] = make_double2(acc[2 * k], acc[2 * k + 1]);
   }
 }
 
-__global__ __launch_bounds__(RED_THREADS) void k_multiaxpy(const double2* V, size_t vs, int nk, const double2* h,
-                                                           double2* w, size_t n, size_t rs, int nrhs,
-                                                           double2* part) {
-  const int r = blockIdx.y;
-  const size_t off = r * rs;
-  double v[1] = {0};
-  for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (size_t)gridDim.x * RED_THREADS) {
-    cplx<double> acc = ld<double>(w + off, i);
-    for (int k = 0; k < nk; ++k) {
-      cplx<double> hk = C(h[(size_t)k * nrhs + r]);
-      acc = acc - hk * ld<double>(V + (size_t)k * vs + off, i);
+// Sum of the partial sums of k_gs in a fixed order: thread t adds output
+// t % 64 over the workgroups t / 64, t / 64 + 4, ... and the four groups are
+// added in order; one workgroup per right-hand side.
+__global__ __launch_bounds__(256) void k_gs_fin(GsArgs a, int mode, int nwg, int nout) {
+  __shared__ double2 red[4][64];
+  const int r = blockIdx.x, k = threadIdx.x & 63, g = threadIdx.x >> 6;
+  double2 s = make_double2(0.0, 0.0);
+  if (k < nout)
+    for (int w = g; w < nwg; w += 4) {
+      double2 v = a.part[((size_t)r * nwg + w) * nout + k];
+      s.x += v.x;
+      s.y += v.y;
     }
-    st(w + off, i, acc);
-    v[0] += acc.x * acc.x + acc.y * acc.y;
+  red[g][k] = s;
+  __syncthreads();
+  if (g != 0 || k >= nout) return;
+  for (int q = 1; q < 4; ++q) {
+    s.x += red[q][k].x;
+    s.y += red[q][k].y;
   }
-  if (part) {
-    block_sum<1>(v);
-    if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = make_double2(v[0], 0.0);
+  const size_t nr = a.nrhs;
+  if (mode == GS_AXPY_NORM || mode == GS_COMB2) {
+    if (a.norm2) a.norm2[r] = s.x;
+  } else if (k < a.nq) {
+    a.h1[k * nr + r] = s;
+  } else if (k < 2 * a.nq) {
+    a.h2[(k - a.nq) * nr + r] = s;
+  } else if (k == 2 * a.nq) {
+    a.h1p[r] = s;
+  } else {
+    a.h2p[r] = s;
   }
 }
 
-void launch_multiaxpy(const double2* V, size_t vs, int nk, const double2* h, double2* w, size_t n, size_t rs,
-                      int nrhs, double2* part, double* norm2, hipStream_t st) {
-  int nwg = reduce_nwg(n);
-  k_multiaxpy<<<dim3(nwg, nrhs), RED_THREADS, 0, st>>>(V, vs, nk, h, w, n, rs, nrhs, norm2 ? part : nullptr);
-  if (norm2) k_norm2_fin<<<nrhs, 64, 0, st>>>(part, nwg, norm2);
+template <int MODE, int... K>
+static void gs_launch(std::integer_sequence<int, K...>, const GsArgs& a, dim3 grid, hipStream_t st) {
+  using F = void (*)(GsArgs);
+  static const F tab[] = {&k_gs<K, MODE>...};
+  hipLaunchKernelGGL(tab[a.nq], grid, dim3(RED_THREADS), 0, st, a);
 }
 
-// Classical Gram-Schmidt, the update of the first pass fused with the
-// projections of the second: w -= sum_k h[k] V_k, and in the same sweep over
-// the basis the partial sums of conj(V_k) w (k < nk <= 16) for the second pass.
-constexpr int KM = 16;
-__global__ __launch_bounds__(RED_THREADS) void k_multiaxpy_dot(const double2* V, size_t vs, int nk, const double2* h,
-                                                               double2* w, size_t n, size_t rs, int nrhs,
-                                                               double2* part) {
-  const int r = blockIdx.y;
-  const size_t off = r * rs;
-  cplx<double> hk[KM];
-#pragma unroll
-  for (int k = 0; k < KM; ++k) hk[k] = k < nk ? C(h[(size_t)k * nrhs + r]) : cplx<double>{0, 0};
-  double v[2 * KM];
-#pragma unroll
-  for (int k = 0; k < 2 * KM; ++k) v[k] = 0;
-  for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (size_t)gridDim.x * RED_THREADS) {
-    cplx<double> acc = ld<double>(w + off, i);
-    cplx<double> a[KM];
-#pragma unroll
-    for (int k = 0; k < KM; ++k)
-      if (k < nk) {
-        a[k] = ld<double>(V + (size_t)k * vs + off, i);
-        acc = acc - hk[k] * a[k];
-      }
-    st(w + off, i, acc);
-#pragma unroll
-    for (int k = 0; k < KM; ++k)
-      if (k < nk) {
-        v[2 * k] += a[k].x * acc.x + a[k].y * acc.y;
-        v[2 * k + 1] += a[k].x * acc.y - a[k].y * acc.x;
-      }
+void launch_gs(int mode, const GsArgs& a, hipStream_t st) {
+  const bool two = mode == GS_DOT2 || mode == GS_COMB2;
+  if (a.nq < (two ? 0 : 1) || a.nq > GS_CHUNK) throw std::runtime_error("launch_gs: basis chunk out of range");
+  if (!a.part) throw std::runtime_error("launch_gs: no partial-sum buffer");
+  const int nwg = reduce_nwg(a.n);
+  const dim3 grid(nwg, a.nrhs);
+  auto seq = std::make_integer_sequence<int, GS_CHUNK + 1>{};
+  switch (mode) {
+    case GS_DOT: gs_launch<GS_DOT>(seq, a, grid, st); break;
+    case GS_AXPY_DOT: gs_launch<GS_AXPY_DOT>(seq, a, grid, st); break;
+    case GS_AXPY_NORM: gs_launch<GS_AXPY_NORM>(seq, a, grid, st); break;
+    case GS_DOT2: gs_launch<GS_DOT2>(seq, a, grid, st); break;
+    case GS_COMB2: gs_launch<GS_COMB2>(seq, a, grid, st); break;
+    default: throw std::runtime_error("launch_gs: unknown mode");
   }
-  block_sum<2 * KM>(v);
-  if (threadIdx.x == 0)
-    for (int k = 0; k < nk; ++k) part[((size_t)r * gridDim.x + blockIdx.x) * KM + k] = make_double2(v[2 * k], v[2 * k + 1]);
-}
-
-__global__ void k_multidot16_fin(const double2* part, int nwg, int nk, int nrhs, double2* h2) {
-  const int r = blockIdx.x, k = threadIdx.x;
-  if (k >= nk) return;
-  h2[(size_t)k * nrhs + r] = D2(sum_parts(part, nwg, KM, r, k));
-}
-
-void launch_multiaxpy_dot(const double2* V, size_t vs, int nk, const double2* h, double2* w, size_t n, size_t rs,
-                          int nrhs, double2* part, double2* h2, hipStream_t st) {
-  if (nk > KM) throw std::runtime_error("multiaxpy_dot: at most 16 basis vectors");
-  const int nwg = reduce_nwg(n);
-  k_multiaxpy_dot<<<dim3(nwg, nrhs), RED_THREADS, 0, st>>>(V, vs, nk, h, w, n, rs, nrhs, part);
-  k_multidot16_fin<<<nrhs, 64, 0, st>>>(part, nwg, nk, nrhs, h2);
+  const int nout = mode == GS_DOT || mode == GS_AXPY_DOT ? a.nq : mode == GS_DOT2 ? 2 * a.nq + 2 : 1;
+  if ((mode == GS_AXPY_NORM || mode == GS_COMB2) && !a.norm2) return;
+  k_gs_fin<<<a.nrhs, 256, 0, st>>>(a, mode, nwg, nout);
 }
 
 __global__ __launch_bounds__(256) void k_scale(const double2* w, const double* scale, double2* out, float2* out32,

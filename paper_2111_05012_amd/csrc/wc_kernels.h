@@ -215,16 +215,38 @@ void launch_bicg_xr(void* x, void* r, const void* p, const void* s, const void* 
                     size_t n, size_t rs, int nrhs, double2* part, BicgScal* sc, hipStream_t st);
 
 // FGMRES helpers (FP64 basis)
-// h[k][r] = <V_k[r], w[r]> for k < nk;  V_k at V + k*vs
-void launch_multidot(const double2* V, size_t vs, int nk, const double2* w, size_t n, size_t rs, int nrhs,
-                     double2* part, double2* h, hipStream_t st);
-// w[r] -= sum_k h[k][r] V_k[r]; then norm2[r] = ||w[r]||^2 (if norm2 != null)
-void launch_multiaxpy(const double2* V, size_t vs, int nk, const double2* h, double2* w, size_t n, size_t rs,
-                      int nrhs, double2* part, double* norm2, hipStream_t st);
-// w[r] -= sum_k h[k][r] V_k[r], and h2[k][r] = V_k[r]^H w[r] of the updated w in the
-// same sweep (nk <= 16; part holds nrhs * reduce_nwg(n) * 16 partial sums)
-void launch_multiaxpy_dot(const double2* V, size_t vs, int nk, const double2* h, double2* w, size_t n, size_t rs,
-                          int nrhs, double2* part, double2* h2, hipStream_t st);
+// One Gram-Schmidt sweep over a chunk of nq basis vectors Q_k = Q + k*vs
+// (nq <= GS_CHUNK) of every right-hand side (offset r*rs, n complex numbers
+// each), the new Arnoldi vector w and, in the two-vector modes, the pending
+// vector p.  Coefficient arrays are [k][nrhs]; in the two-vector modes index
+// nq is the coefficient of p.  Dot products conj(u) v are summed per
+// right-hand side in a fixed order and written to h1/h2 ([k][nrhs], chunk
+// offset applied by the caller), h1p/h2p ([nrhs]) and norm2 ([nrhs], skipped
+// when null).  part holds nrhs * reduce_nwg(n) * (2 GS_CHUNK + 2) partial sums.
+//   GS_DOT:       h1[k] = Q_k^H w                                 (nq >= 1)
+//   GS_AXPY_DOT:  w -= sum_k c1[k] Q_k, then h1[k] = Q_k^H w       (nq >= 1)
+//   GS_AXPY_NORM: w -= sum_k c1[k] Q_k, then norm2 = |w|^2         (nq >= 1)
+//   GS_DOT2:      h1[k] = Q_k^H w, h2[k] = Q_k^H p, h1p = p^H w, h2p = p^H p
+//   GS_COMB2:     p <- c1[nq] p + sum_k c1[k] Q_k (stored if write_p),
+//                 w <- w - c2[nq] p - sum_k c2[k] Q_k (old p), then norm2 = |w|^2
+enum GsMode { GS_DOT = 0, GS_AXPY_DOT = 1, GS_AXPY_NORM = 2, GS_DOT2 = 3, GS_COMB2 = 4 };
+constexpr int GS_CHUNK = 16;
+struct GsArgs {
+  const double2* Q = nullptr;
+  size_t vs = 0;
+  int nq = 0;
+  double2* p = nullptr;
+  double2* w = nullptr;
+  const double2* c1 = nullptr;
+  const double2* c2 = nullptr;
+  int write_p = 0;
+  size_t n = 0, rs = 0;
+  int nrhs = 0;
+  double2* part = nullptr;
+  double2 *h1 = nullptr, *h2 = nullptr, *h1p = nullptr, *h2p = nullptr;
+  double* norm2 = nullptr;
+};
+void launch_gs(int mode, const GsArgs& a, hipStream_t st);
 // out[r] = w[r] * scale[r]; optional FP32 copy out32
 void launch_scale(const double2* w, const double* scale, double2* out, float2* out32, size_t n, size_t rs, int nrhs,
                   hipStream_t st);

@@ -42,7 +42,8 @@ class SetupParams(ctypes.Structure):
 
 class SolveParams(ctypes.Structure):
     _fields_ = [('restart', ctypes.c_int), ('tol', ctypes.c_double), ('max_iters', ctypes.c_int),
-                ('rhs_chunk', ctypes.c_int), ('use_graph', ctypes.c_int), ('phase_times', ctypes.c_int)]
+                ('rhs_chunk', ctypes.c_int), ('use_graph', ctypes.c_int), ('phase_times', ctypes.c_int),
+                ('ortho', ctypes.c_int)]
 
 
 class BicgParams(ctypes.Structure):
@@ -300,13 +301,14 @@ class Context:
         w = _same_where(v, out)
         self._done(self.lib.wcamg_vcycle(self.h, _ptr(v)[0], _ptr(out)[0], nrhs, w), out)
 
-    def solve(self, b, x, nrhs, restart=16, tol=1e-10, max_iters=2000, rhs_chunk=0, use_graph=1, phase_times=0):
+    def solve(self, b, x, nrhs, restart=16, tol=1e-10, max_iters=2000, rhs_chunk=0, use_graph=1, phase_times=0,
+              ortho=0):
         """b, x: device tensors.  Returns (status, SolveInfo)."""
         pb, wb = _ptr(b)
         px, wx = _ptr(x)
         if wb != DEVICE or wx != DEVICE:
             raise ValueError('solve takes device tensors')
-        prm = SolveParams(restart, tol, max_iters, rhs_chunk, use_graph, phase_times)
+        prm = SolveParams(restart, tol, max_iters, rhs_chunk, use_graph, phase_times, ortho)
         info = SolveInfo()
         rc = self._chk(self.lib.wcamg_solve(self.h, pb, px, nrhs, ctypes.byref(prm), ctypes.byref(info)),
                        allow=(OK, NOT_CONVERGED))
