@@ -6,6 +6,7 @@
 // Reductions are two-stage and fixed-order (per-workgroup partial sums,
 // then one workgroup per right-hand side adds them in index order): results
 // do not depend on scheduling.
+#include <algorithm>
 #include <stdexcept>
 #include <utility>
 
@@ -418,6 +419,15 @@ void launch_fbicg_x(double2* x, const void* mp, const void* ms, int zt, size_t n
 // the new Arnoldi vector w and, in the two-vector modes, the pending vector p.
 // Each thread owns one complex number of one right-hand side per step of the
 // grid-stride loop; the partial sums of a workgroup go to part[r][block][NOUT].
+// Streaming accesses: every element of the sweeps is touched once per launch.
+__device__ __forceinline__ cplx<double> ld_nt(const double2* p) {
+  return {__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y)};
+}
+__device__ __forceinline__ void st_nt(double2* p, cplx<double> v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+
 template <int NQ, int MODE>
 __global__ __launch_bounds__(RED_THREADS) void k_gs(GsArgs a) {
   constexpr bool TWO = MODE == GS_DOT2 || MODE == GS_COMB2;
@@ -455,10 +465,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_gs(GsArgs a) {
   for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < a.n; i += (size_t)gridDim.x * RED_THREADS) {
     cplx<double> q[NQ > 0 ? NQ : 1];
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) q[k] = ld<double>(Q + (size_t)k * a.vs, i);
+    for (int k = 0; k < NQ; ++k) q[k] = ld_nt(Q + (size_t)k * a.vs + i);
     cplx<double> pv = {0, 0};
-    if constexpr (TWO) pv = ld<double>(P, i);
-    cplx<double> wv = ld<double>(W, i);
+    if constexpr (TWO) pv = ld_nt(P + i);
+    cplx<double> wv = ld_nt(W + i);
     if constexpr (MODE == GS_DOT) {
 #pragma unroll
       for (int k = 0; k < NQ; ++k) cjacc(k, q[k], wv);
@@ -479,12 +489,12 @@ __global__ __launch_bounds__(RED_THREADS) void k_gs(GsArgs a) {
           cmac(pn, cp[k], q[k]);
           cmac(wv, cw[k], q[k]);
         }
-        if (a.write_p) st(P, i, pn);
+        if (a.write_p) st_nt(P + i, pn);
       } else {
 #pragma unroll
         for (int k = 0; k < NQ; ++k) cmac(wv, cw[k], q[k]);
       }
-      st(W, i, wv);
+      st_nt(W + i, wv);
       if constexpr (MODE == GS_AXPY_DOT) {
 #pragma unroll
         for (int k = 0; k < NQ; ++k) cjacc(k, q[k], wv);
@@ -546,7 +556,9 @@ void launch_gs(int mode, const GsArgs& a, hipStream_t st) {
   const bool two = mode == GS_DOT2 || mode == GS_COMB2;
   if (a.nq < (two ? 0 : 1) || a.nq > GS_CHUNK) throw std::runtime_error("launch_gs: basis chunk out of range");
   if (!a.part) throw std::runtime_error("launch_gs: no partial-sum buffer");
-  const int nwg = reduce_nwg(a.n);
+  // 256 workgroups per right-hand side: measured the fastest for these
+  // read-write streams (512 and more cost 3-7%)
+  const int nwg = std::min(reduce_nwg(a.n), 256);
   const dim3 grid(nwg, a.nrhs);
   auto seq = std::make_integer_sequence<int, GS_CHUNK + 1>{};
   switch (mode) {
