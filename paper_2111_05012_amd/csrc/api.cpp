@@ -1917,12 +1917,17 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
     return a;
   };
 
+  bool x_zero = true;  // x = 0 until the first update: then r = b exactly
   while (true) {
     // r = b - D x (FP64), into V_0
-    c->dslash(xx, C128, V, C128, nrhs, OP_D, WCAMG_PREC_FP64, bb);
-    launch_norm2(V, C128, n, rs, nrhs, part, nrm, c->st);
     std::vector<double> rn2(nrhs);
-    sync_get(rn2.data(), nrm, nrhs * sizeof(double));
+    if (x_zero) {
+      rn2 = bn2;
+    } else {
+      c->dslash(xx, C128, V, C128, nrhs, OP_D, WCAMG_PREC_FP64, bb);
+      launch_norm2(V, C128, n, rs, nrhs, part, nrm, c->st);
+      sync_get(rn2.data(), nrm, nrhs * sizeof(double));
+    }
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
       require(std::isfinite(rn2[r]), "non-finite residual", WCAMG_ENUMERIC);
@@ -1940,7 +1945,7 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
       kcols[r] = 0;
     }
     HIPCHK(hipMemcpyAsync(scl, sc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
-    launch_scale(V, scl, V, (float2*)vin, n, rs, nrhs, c->st);
+    launch_scale(x_zero ? bb : V, scl, V, (float2*)vin, n, rs, nrhs, c->st);
     std::vector<int> ext(nrhs);  // still extending its Krylov space in this cycle
     for (int r = 0; r < nrhs; ++r) ext[r] = !done[r];
     for (int j = 0; j < m; ++j) {
@@ -2126,6 +2131,7 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
     if (kmax > 0) {
       HIPCHK(hipMemcpyAsync(ycoef, yhost.data(), (size_t)m * nrhs * sizeof(double2), hipMemcpyHostToDevice, c->st));
       launch_update_x(xx, Z, zt, vs, kmax, ycoef, n, rs, nrhs, c->st);
+      x_zero = false;
     }
   }
   for (int r = 0; r < nrhs; ++r) {
