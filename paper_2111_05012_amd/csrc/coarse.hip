@@ -140,6 +140,10 @@ __global__ __launch_bounds__(256) void k_restrict_mf64(Geo g, int nv, int nrhs, 
   const int X = lg >> 1, s = lg & 1;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int it = w & 1, rt = w >> 1;
+  // the Gram matrix V^H V (in is V): Hermitian, so V is staged once and the
+  // tile (i >= 16, r < 16) is written from its mirror (i < 16, r >= 16)
+  const bool gram = (const void*)in == (const void*)V && nrhs == nv && in_rs == (size_t)12 * g.V;
+  const bool skip = gram && it == 1 && rt == 0;
   f64x4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
   const size_t base = (size_t)X * 12 * g.Vb;  // plane 0 of block X
   for (int a6 = 0; a6 < 6; ++a6) {
@@ -153,17 +157,18 @@ __global__ __launch_bounds__(256) void k_restrict_mf64(Geo g, int nv, int nrhs, 
         cplx<double> v = {0, 0}, x = {0, 0};
         if (loc < g.Vb) {
           if (c < nv) v = ld<double>(V, (size_t)c * 12 * g.V + pl + loc);
-          if (c < nrhs) x = ld<double>(in, (size_t)c * in_rs + pl + loc);
+          if (c < nrhs && !gram) x = ld<double>(in, (size_t)c * in_rs + pl + loc);
         }
         sv[kk][c] = make_double2(v.x, v.y);
-        sx[kk][c] = make_double2(x.x, x.y);
+        if (!gram) sx[kk][c] = make_double2(x.x, x.y);
       }
       __syncthreads();
+      const double2(*sb)[33] = gram ? sv : sx;
 #pragma unroll 4
-      for (int kk = 0; kk < KC; kk += 4) {
+      for (int kk = 0; kk < KC && !skip; kk += 4) {
         const int k = kk + (lane >> 4);
         const double2 va = sv[k][16 * it + (lane & 15)];
-        const double2 xb = sx[k][16 * rt + (lane & 15)];
+        const double2 xb = sb[k][16 * rt + (lane & 15)];
         re = __builtin_amdgcn_mfma_f64_16x16x4f64(va.x, xb.x, re, 0, 0, 0);
         re = __builtin_amdgcn_mfma_f64_16x16x4f64(va.y, xb.y, re, 0, 0, 0);
         im = __builtin_amdgcn_mfma_f64_16x16x4f64(va.x, xb.y, im, 0, 0, 0);
@@ -172,11 +177,15 @@ __global__ __launch_bounds__(256) void k_restrict_mf64(Geo g, int nv, int nrhs, 
       __syncthreads();
     }
   }
+  if (skip) return;
   const int r = 16 * rt + (lane & 15);
+  const bool mirror = gram && it == 0 && rt == 1;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int i = 16 * it + (lane >> 4) + 4 * q;
     if (i < nv && r < nrhs) out[(size_t)r * out_rs + (size_t)X * out_xs + s * nv + i] = make_double2(re[q], im[q]);
+    if (mirror && r < nv && i < nrhs)
+      out[(size_t)i * out_rs + (size_t)X * out_xs + s * nv + r] = make_double2(re[q], -im[q]);
   }
 }
 

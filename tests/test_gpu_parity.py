@@ -78,10 +78,11 @@ def test_sap_mixed(prob):
     assert rel(prob.N(x), want) < 1e-2
 
 
-@pytest.mark.parametrize('nv', [6, 20])
+@pytest.mark.parametrize('nv', [6, 20, 32])
 def test_orthonormalize_fp64(prob, nv):
     """FP64 block orthonormalisation (Gram matrices on the FP64 matrix cores;
-    nv = 20 spans two 16-row output tiles)."""
+    nv = 20 and 32 span two 16-row output tiles, whose off-diagonal tile is
+    written from its Hermitian mirror)."""
     from paper_2111_05012_amd import PREC_FP64
     V = syn.gaussian_vectors(prob.dims, nv, 16)
     out = prob.zeros(V.shape)
@@ -90,7 +91,7 @@ def test_orthonormalize_fp64(prob, nv):
     assert rel(prob.N(out), want) < 1e-12
 
 
-@pytest.mark.parametrize('nv', [6, 20])
+@pytest.mark.parametrize('nv', [6, 20, 32])
 def test_orthonormalize_mixed(prob, nv):
     """Mixed precision (FP32 vectors, FP64 Gram on the matrix cores, FP32
     matrix-core update): the result of Cholesky-QR twice agrees with the
