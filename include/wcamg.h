@@ -261,7 +261,8 @@ typedef struct {
   int ortho;       /* orthogonalisation of the Arnoldi vectors: 0 = classical Gram-Schmidt twice
                       with the second pass delayed into the next step (two sweeps over the basis
                       per step; the last Hessenberg column of a cycle keeps its first-pass
-                      values), 1 = classical Gram-Schmidt twice (three sweeps per step) */
+                      values), 1 = classical Gram-Schmidt twice (three sweeps per step);
+                      other values: WCAMG_EINVAL */
 } wcamg_solve_params;
 
 #define WCAMG_MAX_RHS 64

@@ -2178,6 +2178,7 @@ int wcamg_solve(wcamg_ctx* c, const void* b, void* x, int nrhs, const wcamg_solv
     require(b && x && p, "null pointer");
     check_nrhs(nrhs);
     require(p->restart >= 1 && p->restart <= 32, "restart must be in [1, 32]");
+    require(p->ortho == 0 || p->ortho == 1, "ortho must be 0 (delayed CGS2) or 1 (CGS2)");
     require(std::isfinite(p->tol) && p->tol >= 0, "invalid tol");
     require(p->max_iters >= 0, "invalid max_iters");
     require(c->have_hier, "no hierarchy: call wcamg_setup first", WCAMG_ESTATE);

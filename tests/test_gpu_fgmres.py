@@ -86,3 +86,16 @@ def test_batch_members_solve_as_alone(p8, ortho):
         rc1, info1, x1, res1 = _solve(p8, b[src:src + 1], restart=32, ortho=ortho)
         assert rc1 == 0 and info1.iters[0] == its[k], (k, info1.iters[0], its[k])
         assert np.abs(x1[0] - xg[k]).max() / np.abs(x1[0]).max() < 1e-9
+
+
+def test_solve_rejects_unknown_orthogonalisation(p8):
+    """ortho takes 0 or 1; anything else is an argument error, raised before
+    any work."""
+    from paper_2111_05012_amd import PREC_FP64, WcamgError, EINVAL
+    _setup(p8, PREC_FP64)
+    b = _rhs(p8)[:1]
+    x = p8.zeros(b.shape)
+    for bad in (-1, 2):
+        with pytest.raises(WcamgError) as e:
+            p8.ctx.solve(p8.T(b), x, 1, ortho=bad)
+        assert e.value.code == EINVAL
