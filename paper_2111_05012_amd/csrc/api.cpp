@@ -1776,7 +1776,8 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
   double2* V = (double2*)c->W("fg_V", (size_t)(m + 1) * vs * sizeof(double2));
   void* Z = c->W("fg_Z", (size_t)m * vs * ct_size(zt));
   void* vin = prec == WCAMG_PREC_MIXED ? c->W("fg_vin", vs * sizeof(float2)) : nullptr;
-  double2* part = (double2*)c->W("fg_part", (size_t)nrhs * reduce_nwg(n) * (2 * GS_CHUNK + 2) * sizeof(double2));
+  double2* part = (double2*)c->W("fg_part", (size_t)nrhs * reduce_nwg(n) * (2 * GS_CHUNK + 3) * sizeof(double2));
+  double* wwd = (double*)c->W("fg_ww", (size_t)nrhs * sizeof(double));
   const bool delayed = p->ortho == 0;  // CGS2 with the second pass delayed into the next step
   double2* coef = (double2*)c->W("fg_c", (size_t)2 * (m + 2 + m / GS_CHUNK) * nrhs * sizeof(double2));
   double2* h1 = (double2*)c->W("fg_h1", (size_t)(m + 1) * nrhs * sizeof(double2));
@@ -1790,7 +1791,7 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
     HIPCHK(hipStreamSynchronize(c->st));
   };
 
-  std::vector<double> bn2(nrhs), hn(nrhs), hs(nrhs);
+  std::vector<double> bn2(nrhs), hn(nrhs), hs(nrhs), wwh(nrhs), vsc(nrhs);
   launch_norm2(bb, C128, n, rs, nrhs, part, nrm, c->st);
   sync_get(bn2.data(), nrm, nrhs * sizeof(double));
   for (int r = 0; r < nrhs; ++r) require(std::isfinite(bn2[r]), "non-finite right-hand side", WCAMG_ENUMERIC);
@@ -1946,6 +1947,7 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
     }
     HIPCHK(hipMemcpyAsync(scl, sc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
     launch_scale(x_zero ? bb : V, scl, V, (float2*)vin, n, rs, nrhs, c->st);
+    bool vin_done = false;       // sweep 2 wrote the next V-cycle input
     std::vector<int> ext(nrhs);  // still extending its Krylov space in this cycle
     for (int r = 0; r < nrhs; ++r) ext[r] = !done[r];
     for (int j = 0; j < m; ++j) {
@@ -1964,9 +1966,12 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
         // them the second projection of p (s, rho), the correction of
         // column j-1 (H[i][j-1] += s_i, H[j][j-1] = rho) and column j.
         // Sweep 2: V_j = (p - sum_i s_i V_i) / rho and the first projection
-        // of w on V_0..V_j; w becomes the next p.  Class "gs": the j + 1
-        // basis vectors and w read twice, w and V_j written.
-        wcamg_ctx::Timed tg(c, "gs", vb * (2.0 * (j + 1) + 2.0 + (j > 0 ? 2.0 : 1.0)),
+        // of w on V_0..V_j; w becomes the next p.  In mixed precision sweep 2
+        // also writes the next V-cycle's FP32 input, w normalised by the norm
+        // that sweep 1 predicts (|w|^2 minus the squared projections), unless
+        // that prediction cancels.  Class "gs": the j + 1 basis vectors and w
+        // read twice, w and V_j written, and the FP32 input (half a vector).
+        wcamg_ctx::Timed tg(c, "gs", vb * (2.0 * (j + 1) + 2.0 + (j > 0 ? 2.0 : 1.0) + (vin ? 0.5 : 0.0)),
                             8.0 * (4.0 * (j + 1) + 1.0) * (double)vs, nrhs);
         for (int k0 = 0; k0 == 0 || k0 < j; k0 += GS_CHUNK) {
           GsArgs a = gs_args(k0, std::min(GS_CHUNK, j - k0), pj, w);
@@ -1974,18 +1979,22 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
           a.h2 = h2 + (size_t)k0 * nrhs;
           a.h1p = h1 + (size_t)j * nrhs;
           a.h2p = h2 + (size_t)j * nrhs;
+          a.ww = wwd;
           launch_gs(GS_DOT2, a, c->st);
         }
         HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
                               c->st));
+        HIPCHK(hipMemcpyAsync(wwh.data(), wwd, (size_t)nrhs * sizeof(double), hipMemcpyDeviceToHost, c->st));
         sync_get(hh2.data(), h2, (size_t)(j + 1) * nrhs * sizeof(double2));
         // coefficients of sweep 2 per chunk: c1 then c2, (nq + 1) x nrhs each
         const int nch = j == 0 ? 1 : (j + GS_CHUNK - 1) / GS_CHUNK;
         std::vector<std::vector<cd>> c1(nrhs), c2(nrhs);
         std::vector<double> rho(nrhs, 1.0);
+        bool fused = vin != nullptr;
         for (int r = 0; r < nrhs; ++r) {
           c1[r].assign(j + 1, cd(0));
           c2[r].assign(j + 1, cd(0));
+          vsc[r] = 0.0;
           if (!ext[r]) continue;
           auto cx = [](double2 v) { return cd(v.x, v.y); };
           std::vector<cd> s(j);
@@ -2021,7 +2030,15 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
           }
           c1[r][j] = 1.0 / rho[r];
           c2[r][j] = bj / rho[r];
+          // |new w|^2 = |w|^2 - sum_i |H[i][j]|^2 (V_0..V_j orthonormal)
+          double est = wwh[r] - std::norm(bj);
+          for (int i = 0; i < j; ++i) est -= std::norm(Hc(i, j, r));
+          if (std::isfinite(est) && est > 1e-12 * wwh[r])
+            vsc[r] = 1.0 / std::sqrt(est);
+          else
+            fused = false;
         }
+        if (fused) HIPCHK(hipMemcpyAsync(scl, vsc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
         hc.clear();
         std::vector<size_t> co;
         for (int ch = 0; ch < nch; ++ch) {
@@ -2043,8 +2060,13 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
           a.c2 = a.c1 + (size_t)(nq + 1) * nrhs;
           a.write_p = j > 0;
           a.norm2 = ch == nch - 1 ? nrm : nullptr;
+          if (fused && ch == nch - 1) {
+            a.vin = (float2*)vin;
+            a.vscale = scl;
+          }
           launch_gs(GS_COMB2, a, c->st);
         }
+        vin_done = fused;
       } else {
         // Classical Gram-Schmidt twice; the update of the first pass and the
         // projections of the second share one sweep over the basis.  Class
@@ -2102,14 +2124,18 @@ static void fgmres_batch(wcamg_ctx* c, const double2* bb, double2* xx, int nrhs,
       }
       if (!any || j == m - 1) break;
       // the next V-cycle input: V_{j+1} normalised (CGS2), or w normalised
-      // into the FP32 input (delayed, mixed precision); right-hand sides that
-      // stopped get a zero input
+      // into the FP32 input (delayed, mixed precision; done by sweep 2 unless
+      // its norm prediction cancelled); right-hand sides that stopped get a
+      // zero input (after a fused write, those that stopped in this step keep
+      // theirs: its V-cycle output enters no solution, y being 0 there)
       if (!delayed) {
         HIPCHK(hipMemcpyAsync(scl, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
         launch_scale(w, scl, w, (float2*)vin, n, rs, nrhs, c->st);
       } else if (vin) {
-        HIPCHK(hipMemcpyAsync(scl, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
-        launch_scale(w, scl, nullptr, (float2*)vin, n, rs, nrhs, c->st);
+        if (!vin_done) {
+          HIPCHK(hipMemcpyAsync(scl, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
+          launch_scale(w, scl, nullptr, (float2*)vin, n, rs, nrhs, c->st);
+        }
       } else if (died) {
         for (int r = 0; r < nrhs; ++r) hs[r] = ext[r] ? 1.0 : 0.0;
         HIPCHK(hipMemcpyAsync(scl, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));

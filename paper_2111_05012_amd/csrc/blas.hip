@@ -432,7 +432,7 @@ template <int NQ, int MODE>
 __global__ __launch_bounds__(RED_THREADS) void k_gs(GsArgs a) {
   constexpr bool TWO = MODE == GS_DOT2 || MODE == GS_COMB2;
   constexpr bool AXPY = MODE == GS_AXPY_DOT || MODE == GS_AXPY_NORM || MODE == GS_COMB2;
-  constexpr int NOUT = MODE == GS_DOT || MODE == GS_AXPY_DOT ? NQ : MODE == GS_DOT2 ? 2 * NQ + 2 : 1;
+  constexpr int NOUT = MODE == GS_DOT || MODE == GS_AXPY_DOT ? NQ : MODE == GS_DOT2 ? 2 * NQ + 3 : 1;
   constexpr int NO = NOUT > 0 ? NOUT : 1;
   constexpr int NC = NQ + (TWO ? 1 : 0);  // coefficients per right-hand side
   const int r = blockIdx.y;
@@ -462,6 +462,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_gs(GsArgs a) {
   const double2* Q = a.Q + off;
   double2* P = a.p + off;
   double2* W = a.w + off;
+  // COMB2: the new w, times vscale, also as the FP32 input of the next V-cycle
+  float2* VI = a.vin ? a.vin + off : nullptr;
+  const double vsc = a.vin ? a.vscale[r] : 0.0;
   for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < a.n; i += (size_t)gridDim.x * RED_THREADS) {
     cplx<double> q[NQ > 0 ? NQ : 1];
 #pragma unroll
@@ -480,6 +483,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_gs(GsArgs a) {
       }
       cjacc(2 * NQ, pv, wv);
       cjacc(2 * NQ + 1, pv, pv);
+      acc[2 * (2 * NQ + 2)] = fma(wv.x, wv.x, fma(wv.y, wv.y, acc[2 * (2 * NQ + 2)]));
     } else {
       if constexpr (MODE == GS_COMB2) {
         cplx<double> pn = cp[NQ] * pv;
@@ -495,6 +499,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_gs(GsArgs a) {
         for (int k = 0; k < NQ; ++k) cmac(wv, cw[k], q[k]);
       }
       st_nt(W + i, wv);
+      if constexpr (MODE == GS_COMB2) {
+        if (VI) st(VI, i, vsc * wv);
+      }
       if constexpr (MODE == GS_AXPY_DOT) {
 #pragma unroll
         for (int k = 0; k < NQ; ++k) cjacc(k, q[k], wv);
@@ -540,8 +547,10 @@ __global__ __launch_bounds__(256) void k_gs_fin(GsArgs a, int mode, int nwg, int
     a.h2[(k - a.nq) * nr + r] = s;
   } else if (k == 2 * a.nq) {
     a.h1p[r] = s;
-  } else {
+  } else if (k == 2 * a.nq + 1) {
     a.h2p[r] = s;
+  } else if (a.ww) {
+    a.ww[r] = s.x;
   }
 }
 
@@ -569,7 +578,7 @@ void launch_gs(int mode, const GsArgs& a, hipStream_t st) {
     case GS_COMB2: gs_launch<GS_COMB2>(seq, a, grid, st); break;
     default: throw std::runtime_error("launch_gs: unknown mode");
   }
-  const int nout = mode == GS_DOT || mode == GS_AXPY_DOT ? a.nq : mode == GS_DOT2 ? 2 * a.nq + 2 : 1;
+  const int nout = mode == GS_DOT || mode == GS_AXPY_DOT ? a.nq : mode == GS_DOT2 ? 2 * a.nq + 3 : 1;
   if ((mode == GS_AXPY_NORM || mode == GS_COMB2) && !a.norm2) return;
   k_gs_fin<<<a.nrhs, 256, 0, st>>>(a, mode, nwg, nout);
 }

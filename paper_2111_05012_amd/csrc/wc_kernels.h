@@ -222,13 +222,15 @@ void launch_bicg_xr(void* x, void* r, const void* p, const void* s, const void* 
 // nq is the coefficient of p.  Dot products conj(u) v are summed per
 // right-hand side in a fixed order and written to h1/h2 ([k][nrhs], chunk
 // offset applied by the caller), h1p/h2p ([nrhs]) and norm2 ([nrhs], skipped
-// when null).  part holds nrhs * reduce_nwg(n) * (2 GS_CHUNK + 2) partial sums.
+// when null).  part holds nrhs * reduce_nwg(n) * (2 GS_CHUNK + 3) partial sums.
 //   GS_DOT:       h1[k] = Q_k^H w                                 (nq >= 1)
 //   GS_AXPY_DOT:  w -= sum_k c1[k] Q_k, then h1[k] = Q_k^H w       (nq >= 1)
 //   GS_AXPY_NORM: w -= sum_k c1[k] Q_k, then norm2 = |w|^2         (nq >= 1)
-//   GS_DOT2:      h1[k] = Q_k^H w, h2[k] = Q_k^H p, h1p = p^H w, h2p = p^H p
+//   GS_DOT2:      h1[k] = Q_k^H w, h2[k] = Q_k^H p, h1p = p^H w, h2p = p^H p,
+//                 ww = w^H w (when not null)
 //   GS_COMB2:     p <- c1[nq] p + sum_k c1[k] Q_k (stored if write_p),
-//                 w <- w - c2[nq] p - sum_k c2[k] Q_k (old p), then norm2 = |w|^2
+//                 w <- w - c2[nq] p - sum_k c2[k] Q_k (old p), then norm2 = |w|^2;
+//                 with vin set, also vin = vscale[r] * w (FP32, [rhs][n] at offset r*rs)
 enum GsMode { GS_DOT = 0, GS_AXPY_DOT = 1, GS_AXPY_NORM = 2, GS_DOT2 = 3, GS_COMB2 = 4 };
 constexpr int GS_CHUNK = 16;
 struct GsArgs {
@@ -245,6 +247,9 @@ struct GsArgs {
   double2* part = nullptr;
   double2 *h1 = nullptr, *h2 = nullptr, *h1p = nullptr, *h2p = nullptr;
   double* norm2 = nullptr;
+  double* ww = nullptr;
+  float2* vin = nullptr;
+  const double* vscale = nullptr;
 };
 void launch_gs(int mode, const GsArgs& a, hipStream_t st);
 // out[r] = w[r] * scale[r]; optional FP32 copy out32
