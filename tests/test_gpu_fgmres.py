@@ -43,8 +43,9 @@ def _solve(prob, b, **kw):
     return rc, info, xg, res
 
 
-@pytest.mark.parametrize('prec,weak,restart', [('fp64', False, 3), ('mixed', False, 16), ('fp64', True, 3),
-                                               ('fp64', True, 16), ('fp64', True, 32), ('mixed', True, 32)])
+@pytest.mark.parametrize('prec,weak,restart', [('fp64', False, 1), ('mixed', False, 2), ('fp64', False, 3),
+                                               ('mixed', False, 16), ('fp64', True, 3), ('fp64', True, 16),
+                                               ('fp64', True, 32), ('mixed', True, 32)])
 def test_delayed_and_classical_gram_schmidt_agree(p8, prec, weak, restart):
     from paper_2111_05012_amd import PREC_FP64, PREC_MIXED
     _setup(p8, PREC_FP64 if prec == 'fp64' else PREC_MIXED, **(WEAK if weak else {}))
