@@ -100,3 +100,22 @@ def test_solve_rejects_unknown_orthogonalisation(p8):
         with pytest.raises(WcamgError) as e:
             p8.ctx.solve(p8.T(b), x, 1, ortho=bad)
         assert e.value.code == EINVAL
+
+
+@pytest.mark.parametrize('prec', ['fp64', 'mixed'])
+def test_graph_replays_match_eager(p8, prec):
+    """The V-cycle replayed from its captured graphs, over three solves in a
+    row (the graphs of every Krylov slot replayed many times, with the outer
+    solver's eager kernels and synchronisations in between), gives the
+    eager V-cycle's iterations and solution (the kernels reduce in a fixed
+    order, so to rounding at most)."""
+    from paper_2111_05012_amd import PREC_FP64, PREC_MIXED
+    _setup(p8, PREC_FP64 if prec == 'fp64' else PREC_MIXED, **WEAK)
+    b = _rhs(p8)
+    rc, info, x_eager, _ = _solve(p8, b, restart=16, use_graph=0)
+    assert rc == 0
+    for rep in range(3):
+        rc, info_g, x_g, res = _solve(p8, b, restart=16, use_graph=1)
+        assert rc == 0 and max(res) <= 1e-10
+        assert list(info_g.iters[:3]) == list(info.iters[:3]), rep
+        assert np.abs(x_g - x_eager).max() / np.abs(x_eager).max() < 1e-12, rep
